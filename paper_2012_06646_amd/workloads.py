@@ -1,0 +1,215 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no spreading or interpolation arithmetic: it only draws positions,
+forces and grid fields, and builds red-blood-cell surface point sets.  All draws use
+``numpy.random.Generator(PCG64(seed))`` in the order documented per workload, so the GPU
+path and the CPU oracle see identical bytes.
+
+Grid descriptions are plain dicts:
+    dim, n (cells per dim), length (box edge per dim), stagger (list of xi_c), kernel
+"""
+import math
+
+import numpy as np
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def mac_stagger(dim):
+    """MAC staggering: component c at the cell centre minus h e_c / 2 (Sec. 2)."""
+    return [[0.0 if k == c else 0.5 for k in range(dim)] for c in range(dim)]
+
+
+def grid(dim, n, length, stagger=None, kernel="peskin4"):
+    if isinstance(n, int):
+        n = [n] * dim
+    if isinstance(length, (int, float)):
+        length = [float(length)] * dim
+    if stagger is None:
+        stagger = mac_stagger(dim)
+    return {"dim": dim, "n": list(n), "length": [float(v) for v in length],
+            "stagger": [list(map(float, s)) for s in stagger], "kernel": kernel}
+
+
+def grid_shape(g):
+    return [len(g["stagger"])] + [int(v) for v in g["n"]][::-1]
+
+
+def uniform_case(g, npts, seed, dtype=np.float64):
+    """Uniform points in the box, then N(0,1) forces (npts x ncomp), then N(0,1) grid field.
+
+    Draw order: X, F, u (C order)."""
+    r = rng(seed)
+    dim = g["dim"]
+    L = np.array(g["length"], dtype=np.float64)
+    X = r.random((npts, dim)) * L
+    F = r.standard_normal((npts, len(g["stagger"])))
+    u = r.standard_normal(grid_shape(g))
+    return X.astype(dtype), F.astype(dtype), u.astype(dtype)
+
+
+# ---- the named workloads ----------------------------------------------------------
+
+def config1():
+    """2-D periodic unit square, 32 x 32 collocated (cell-centred) grid with two components,
+    1000 uniform points, FP64; seed 1001."""
+    g = grid(2, 32, 1.0, stagger=[[0.5, 0.5], [0.5, 0.5]])
+    X, F, u = uniform_case(g, 1000, 1001)
+    return g, X, F, u
+
+
+def config2(dtype=np.float64, npts=1_000_000):
+    """3-D periodic unit cube, 128^3 MAC grid, 10^6 uniform points; seed 1002."""
+    g = grid(3, 128, 1.0)
+    X, F, u = uniform_case(g, npts, 1002, dtype)
+    return g, X, F, u
+
+
+# ---- red blood cells (Evans-Fung / Omori reference shape, Sec. 4.2) -----------------
+
+RBC_R0 = 3.91  # micrometres
+
+
+def rbc_p(r):
+    return 0.105 + r * r - 0.56 * r ** 4
+
+
+def icosphere(level):
+    """Unit-sphere vertices of an icosahedron subdivided `level` times (midpoints,
+    re-normalised).  Level 4 gives 2562 vertices."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    verts = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t),
+             (0, -1, -t), (0, 1, -t), (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(v, dtype=np.float64) / np.linalg.norm(v) for v in verts]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9),
+             (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2),
+             (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+             (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    return np.array(verts)
+
+
+def rbc_surface(level=4):
+    """Body-frame RBC vertices: each unit vector (a, b, c) maps to theta = atan2(b, a),
+    phi = asin(c), then x = R0 cos(theta) cos(phi), y = R0 sin(theta) cos(phi),
+    z = R0 p(cos(phi)) sin(phi)  (Sec. 4.2, reference configuration)."""
+    v = icosphere(level)
+    th = np.arctan2(v[:, 1], v[:, 0])
+    ph = np.arcsin(np.clip(v[:, 2], -1.0, 1.0))
+    x = RBC_R0 * np.cos(th) * np.cos(ph)
+    y = RBC_R0 * np.sin(th) * np.cos(ph)
+    z = RBC_R0 * rbc_p(np.cos(ph)) * np.sin(ph)
+    return np.stack([x, y, z], axis=1)
+
+
+def rbc_volume():
+    """Enclosed volume of the reference RBC, 2 pi R0^3 (0.105*2/3 + 4/15 - 0.56*16/105)."""
+    return 2.0 * math.pi * RBC_R0 ** 3 * (0.105 * 2.0 / 3.0 + 4.0 / 15.0 - 0.56 * 16.0 / 105.0)
+
+
+def random_rotations(r, k):
+    """k uniform random rotation matrices (Shoemake's quaternion method)."""
+    u1, u2, u3 = r.random(k), r.random(k), r.random(k)
+    q = np.stack([np.sqrt(1 - u1) * np.sin(2 * np.pi * u2), np.sqrt(1 - u1) * np.cos(2 * np.pi * u2),
+                  np.sqrt(u1) * np.sin(2 * np.pi * u3), np.sqrt(u1) * np.cos(2 * np.pi * u3)], 1)
+    x, y, z, w = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((k, 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z); R[:, 0, 1] = 2 * (x * y - z * w); R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w); R[:, 1, 1] = 1 - 2 * (x * x + z * z); R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w); R[:, 2, 1] = 2 * (y * z + x * w); R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def _inside_rbc(p, margin):
+    """Body-frame points p (m x 3) strictly inside the RBC grown by `margin`."""
+    rho = np.sqrt(p[:, 0] ** 2 + p[:, 1] ** 2)
+    R = RBC_R0 + margin
+    s = np.clip(rho / R, 0.0, 1.0)
+    half = R * rbc_p(s) * np.sqrt(np.clip(1.0 - s * s, 0.0, None)) + margin
+    return (rho < R) & (np.abs(p[:, 2]) < half)
+
+
+def place_rbcs(box, count, seed_pos, seed_rot, max_trials=200_000, margin=0.05):
+    """Random sequential addition of `count` RBCs in a periodic cube of edge `box`:
+    uniform centres (seed_pos) and uniform rotations (seed_rot); a trial is rejected when a
+    vertex of either cell lies inside the other (minimum periodic image, `margin` um).
+    When trials run out, the remaining cells are placed at the least-overlapping of a few
+    candidate positions.  Returns (centres, rotations, n_nonoverlapping)."""
+    rp, rr = rng(seed_pos), rng(seed_rot)
+    surf = rbc_surface(4)
+    sub = surf[:: max(1, len(surf) // 162)]  # coarse vertex subset for the overlap test
+    centres, rots = [], []
+    trials = 0
+    reach = 2.0 * (RBC_R0 + margin)
+    while len(centres) < count and trials < max_trials:
+        trials += 1
+        c = rp.random(3) * box
+        R = random_rotations(rr, 1)[0]
+        ok = True
+        if centres:
+            C = np.array(centres)
+            d = C - c
+            d -= box * np.round(d / box)
+            near = np.nonzero(np.einsum("ij,ij->i", d, d) < reach * reach)[0]
+            mine = sub @ R.T
+            for k in near:
+                Rk = rots[k]
+                # my vertices in k's body frame; k's vertices in my body frame
+                pk = (mine - d[k]) @ Rk
+                if _inside_rbc(pk, margin).any():
+                    ok = False
+                    break
+                pm = (sub @ Rk.T + d[k]) @ R
+                if _inside_rbc(pm, margin).any():
+                    ok = False
+                    break
+        if ok:
+            centres.append(c)
+            rots.append(R)
+    placed = len(centres)
+    while len(centres) < count:
+        centres.append(rp.random(3) * box)
+        rots.append(random_rotations(rr, 1)[0])
+    return np.array(centres), np.array(rots), placed
+
+
+def rbc_points(box, count, seed_pos, seed_rot, max_trials=200_000):
+    surf = rbc_surface(4)
+    C, R, placed = place_rbcs(box, count, seed_pos, seed_rot, max_trials)
+    pts = np.einsum("kij,vj->kvi", R, surf) + C[:, None, :]
+    pts = np.mod(pts, box)
+    return pts.reshape(-1, 3), placed
+
+
+def smooth_force(X, box, seed, modes=16):
+    """F_c(x) = sum_m a_cm cos(2 pi kappa_cm . x / L + psi_cm), a ~ N(0,1),
+    kappa in {-4..4}^3, psi ~ U[0, 2 pi); each component rescaled to max |F_c| = 1."""
+    r = rng(seed)
+    F = np.zeros((X.shape[0], 3))
+    for c in range(3):
+        a = r.standard_normal(modes)
+        kap = r.integers(-4, 5, size=(modes, 3))
+        psi = r.random(modes) * 2 * np.pi
+        arg = 2 * np.pi * (X @ kap.T) / box + psi
+        F[:, c] = np.cos(arg) @ a
+        m = np.abs(F[:, c]).max()
+        if m > 0:
+            F[:, c] /= m
+    return F

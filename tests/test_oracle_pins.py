@@ -1,0 +1,315 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by the mathematics.
+
+None of these tests retypes the oracle's formulas: they check closed-form values, the
+moment conditions that define the 4-point kernel, the worked example of Fig. 2, exact
+rational floors, conservation, exactness on constant and linear fields, the adjoint
+identity, translation invariance, an independent dense-matrix oracle, exact dyadic
+cases and finite differences.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import allpairs
+from paper_2012_06646_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---- phi -----------------------------------------------------------------------------
+
+def test_phi_closed_form_values(orc):
+    s2 = math.sqrt(2.0)
+    expect = {0.0: 0.5, 0.5: (2 + s2) / 8, 1.0: 0.25, 1.5: (2 - s2) / 8, 2.0: 0.0, 2.5: 0.0,
+              -0.5: (2 + s2) / 8, -1.5: (2 - s2) / 8}
+    for r, v in expect.items():
+        assert orc.phi(r) == pytest.approx(v, abs=1e-16), r
+
+
+def kernel_moments(phi_fn, r):
+    """Peskin's defining sums over the 4 integer offsets j = -1..2 at fractional r."""
+    j = np.arange(-1, 3)[None, :]
+    d = r[:, None] - j
+    w = phi_fn(d)
+    return dict(total=w.sum(1), even=w[:, 1::2].sum(1), odd=w[:, 0::2].sum(1),
+                first=(d * w).sum(1), square=(w * w).sum(1))
+
+
+def test_phi_moment_conditions(orc):
+    r = wl.rng(7).random(20000)
+    m = kernel_moments(orc.phi, r)
+    assert np.abs(m["total"] - 1.0).max() < 1e-15
+    assert np.abs(m["even"] - 0.5).max() < 1e-15
+    assert np.abs(m["odd"] - 0.5).max() < 1e-15
+    assert np.abs(m["first"]).max() < 1e-15
+    assert np.abs(m["square"] - 3.0 / 8.0).max() < 1e-15
+
+
+def test_cosine_kernel_misses_first_moment(orc):
+    """The paper's cosine kernel meets partition of unity but not the first-moment
+    condition (Sec. 2)."""
+    r = wl.rng(8).random(5000)
+    m = kernel_moments(lambda d: orc.phi(d, "cosine4"), r)
+    assert np.abs(m["total"] - 1.0).max() < 1e-15
+    assert np.abs(m["even"] - 0.5).max() < 1e-15
+    assert np.abs(m["first"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("mutant", ["sign", "drop_sqrt", "shift"])
+def test_moment_pins_reject_planted_kernel_mistakes(orc, mutant):
+    """A plausible slip in phi (sign of the root, a dropped term, an index shift) must
+    break at least one moment condition."""
+    def bad(d):
+        a = np.abs(d)
+        s_in = np.sqrt(np.clip(1 + 4 * a - 4 * a * a, 0, None))
+        s_out = np.sqrt(np.clip(-7 + 12 * a - 4 * a * a, 0, None))
+        if mutant == "sign":
+            s_out = -s_out
+        if mutant == "drop_sqrt":
+            s_in = 1.0
+        if mutant == "shift":
+            a = np.abs(d + 0.01)
+            s_in = np.sqrt(np.clip(1 + 4 * a - 4 * a * a, 0, None))
+            s_out = np.sqrt(np.clip(-7 + 12 * a - 4 * a * a, 0, None))
+        return np.where(a <= 1, (3 - 2 * a + s_in) / 8, np.where(a <= 2, (5 - 2 * a - s_out) / 8, 0))
+    r = wl.rng(9).random(2000)
+    m = kernel_moments(bad, r)
+    worst = max(np.abs(m["total"] - 1).max(), np.abs(m["first"]).max(),
+                np.abs(m["square"] - 0.375).max())
+    assert worst > 1e-6
+
+
+def test_dphi_matches_central_differences(orc):
+    r = np.concatenate([wl.rng(10).uniform(-2.2, 2.2, 4000)])
+    r = r[(np.abs(np.abs(r) - 1) > 1e-3) & (np.abs(np.abs(r) - 2) > 1e-3) & (np.abs(r) > 1e-3)]
+    for kern in ("peskin4", "cosine4"):
+        e = 1e-6
+        fd = (orc.phi(r + e, kern) - orc.phi(r - e, kern)) / (2 * e)
+        assert np.abs(fd - orc.dphi(r, kern)).max() < 1e-8
+
+
+# ---- keys and plan -----------------------------------------------------------------
+
+def test_fig2_worked_example(orc):
+    with open(os.path.join(GOLDEN, "fig2_keys.json")) as fh:
+        g2 = json.load(fh)
+    grid = {"dim": 2, "n": g2["n"], "length": g2["length"], "stagger": [g2["stagger"]]}
+    k, bad = orc.keys(grid, np.array(g2["points"]), g2["stagger"])
+    assert bad == 0
+    assert (k + 1).tolist() == g2["keys_1based"]
+    sk, perm, seg, q = orc.plan(k)
+    assert (sk + 1).tolist() == g2["sorted_keys_1based"]
+    assert (perm + 1).tolist() == g2["perm_1based"]
+    assert q == g2["q"]
+    assert (sk[seg[:-1]] + 1).tolist() == g2["unique_keys_1based"]
+    assert seg[-1] == len(k)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_keys_exact_rational_floor(orc, prec, dim):
+    """For power-of-two N/L the scaled coordinate is exact, so the key equals the exact
+    rational floor(X N / L - xi) mod N; checked with Python fractions, negative and
+    out-of-box coordinates included."""
+    r = wl.rng(11 + dim)
+    n = [32, 16, 64][:dim]
+    length = [1.0, 0.5, 2.0][:dim]
+    X = r.uniform(-3.0, 4.0, (3000, dim)) * np.array(length)
+    X[:50] = np.round(X[:50] * 64) / 64  # points exactly on cell faces
+    if prec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    grid = wl.grid(dim, n, length)
+    for xi in ([0.0] * dim, [0.5] * dim, wl.mac_stagger(dim)[0]):
+        k, bad = orc.keys(grid, X, xi, prec)
+        assert bad == 0
+        for j in range(0, len(X), 7):
+            key, stride = 0, 1
+            for d in range(dim):
+                t = Fraction(X[j, d]) * Fraction(n[d]) / Fraction(length[d]) - Fraction(xi[d])
+                c = math.floor(t) % n[d]
+                key += c * stride
+                stride *= n[d]
+            assert k[j] == key
+
+
+def test_keys_flag_invalid_points(orc):
+    grid = wl.grid(3, 8, 1.0)
+    X = np.array([[0.1, 0.2, 0.3], [np.nan, 0, 0], [0, np.inf, 0], [0, 0, 1e12]])
+    k, bad = orc.keys(grid, X, [0.5, 0.5, 0.5])
+    assert bad == 3 and k[0] >= 0 and (k[1:] == -1).all()
+
+
+def test_plan_is_the_stable_sort(orc):
+    r = wl.rng(12)
+    for npts, kmax in ((0, 5), (1, 5), (257, 3), (5000, 200), (5000, 100000)):
+        k = r.integers(0, kmax, npts).astype(np.int32)
+        sk, perm, seg, q = orc.plan(k)
+        ref = sorted(range(npts), key=lambda i: (k[i], i))
+        assert perm.tolist() == ref
+        assert q == len(set(k.tolist()))
+        assert seg[-1] == npts and len(seg) == q + 1
+        if npts:
+            assert (np.diff(sk[seg[:-1]]) > 0).all()
+            assert all((sk[seg[i]:seg[i + 1]] == sk[seg[i]]).all() for i in range(q))
+
+
+# ---- operators --------------------------------------------------------------------
+
+def tiny_cases():
+    out = []
+    for dim, n, L, stag in ((2, [4, 6], [1.0, 1.5], None), (2, [8, 5], [2.0, 1.0], [[0.5, 0.5]]),
+                            (3, [4, 5, 6], [1.0, 1.0, 1.2], None), (3, [6, 4, 4], [1.5, 1.0, 1.0],
+                                                                   [[0.25, 0.75, 0.0]])):
+        out.append(wl.grid(dim, n, L, stagger=stag))
+    return out
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_tiers_and_dense_matrix_agree(orc, gi):
+    g = tiny_cases()[gi]
+    r = wl.rng(20 + gi)
+    L = np.array(g["length"])
+    X = r.uniform(-1.0, 2.0, (23, g["dim"])) * L  # includes X < 0 and X >= L
+    F = r.standard_normal((23, len(g["stagger"])))
+    u = r.standard_normal(wl.grid_shape(g))
+    fa = orc.spread(g, X, F, tier=0)
+    fb = orc.spread(g, X, F, tier=1)
+    fd = allpairs.spread(g, X, F)
+    sc = np.abs(fd).max()
+    assert np.abs(fa - fd).max() <= 1e-14 * sc
+    assert np.abs(fb - fd).max() <= 1e-14 * sc
+    Ua = orc.interp(g, X, u, tier=0)
+    Ub = orc.interp(g, X, u, tier=1)
+    Ud = allpairs.interp(g, X, u)
+    sc = np.abs(Ud).max()
+    assert np.abs(Ua - Ud).max() <= 1e-14 * sc
+    assert np.abs(Ub - Ud).max() <= 1e-14 * sc
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interp_reproduces_constants(orc, dim):
+    g = wl.grid(dim, [8, 12, 10][:dim], [1.0, 1.5, 1.25][:dim])
+    X = wl.rng(30).uniform(-1, 3, (500, dim))
+    u = np.full(wl.grid_shape(g), 2.5)
+    U = orc.interp(g, X, u)
+    assert np.abs(U - 2.5).max() < 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_interp_reproduces_linear_fields(orc, dim):
+    """First-moment condition: linear fields are interpolated exactly away from the
+    periodic seam."""
+    n = [16, 20, 12][:dim]
+    L = [1.0, 1.25, 0.75][:dim]
+    g = wl.grid(dim, n, L)
+    h = np.array(L) / np.array(n)
+    r = wl.rng(31)
+    X = (3 * h + r.random((400, dim)) * (np.array(L) - 6 * h))
+    a = r.standard_normal((dim, dim))
+    b = r.standard_normal(dim)
+    u = np.zeros(wl.grid_shape(g))
+    for c in range(dim):
+        xs = allpairs.grid_points(g, c)
+        u[c] = (xs @ a[c] + b[c]).reshape(u.shape[1:])
+    U = orc.interp(g, X, u)
+    exact = X @ a.T + b
+    assert np.abs(U - exact).max() < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_spread_conserves_total_force(orc, dim):
+    g = wl.grid(dim, [8, 6, 10][:dim], [1.0, 0.75, 1.25][:dim])
+    r = wl.rng(32)
+    X = r.uniform(-2, 3, (300, dim))
+    F = r.standard_normal((300, dim))
+    f = orc.spread(g, X, F)
+    hd = np.prod(np.array(g["length"]) / np.array(g["n"]))
+    tot = f.reshape(dim, -1).sum(1) * hd
+    assert np.abs(tot - F.sum(0)).max() < 1e-12 * np.abs(F).sum()
+
+
+def test_spread_single_point_is_outer_product_of_1d_weights(orc):
+    g = wl.grid(3, [8, 8, 8], 1.0, stagger=[[0.5, 0.0, 0.25]])
+    h = 1.0 / 8
+    X = np.array([[0.31, 0.77, 0.05]])
+    f = orc.spread(g, X, np.array([[1.0]]))[0]
+    w = []
+    for k in range(3):
+        xs = h * (np.arange(8) + g["stagger"][0][k])
+        d = xs - X[0, k]
+        d -= np.round(d)
+        w.append(allpairs.phi_peskin4(d / h))
+    expect = np.einsum("z,y,x->zyx", w[2], w[1], w[0]) / h ** 3
+    assert np.abs(f - expect).max() < 1e-12 * np.abs(expect).max()
+    assert np.count_nonzero(f) == 64
+    assert ((f * h ** 3) ** 2).sum() == pytest.approx((3 / 8) ** 3, rel=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adjoint_identity(orc, dim):
+    """<S F, u>_h = <F, J u> with <a, b>_h = h^d sum a b on the grid."""
+    g = wl.grid(dim, [12, 10, 8][:dim], [1.0, 1.1, 0.9][:dim])
+    r = wl.rng(33)
+    X = r.uniform(-1, 2, (200, dim))
+    F = r.standard_normal((200, dim))
+    u = r.standard_normal(wl.grid_shape(g))
+    hd = np.prod(np.array(g["length"]) / np.array(g["n"]))
+    lhs = hd * (orc.spread(g, X, F) * u).sum()
+    rhs = (F * orc.interp(g, X, u)).sum()
+    assert abs(lhs - rhs) < 1e-13 * (abs(lhs) + 1)
+
+
+def test_translation_by_grid_vector(orc):
+    g = wl.grid(3, [8, 16, 8], [1.0, 2.0, 1.0])
+    r = wl.rng(34)
+    X = np.round(r.random((100, 3)) * 2.0 ** 40) / 2.0 ** 40  # so that X + m h is exact
+    F = r.standard_normal((100, 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    m = np.array([3, 5, 2])
+    Xs = X + m * 0.125
+    f0 = orc.spread(g, X, F)
+    f1 = orc.spread(g, Xs, F)
+    assert np.array_equal(np.roll(f0, shift=(2, 5, 3), axis=(1, 2, 3)), f1)
+    u1 = np.roll(u, shift=(2, 5, 3), axis=(1, 2, 3))
+    assert np.array_equal(orc.interp(g, X, u), orc.interp(g, Xs, u1))
+
+
+def test_dyadic_points_on_nodes_are_exact(orc):
+    """Points on a component's nodes have weights 1/4, 1/2, 1/4 per dimension, so every
+    spread value is an exact small rational; computed here with integer arithmetic."""
+    g = wl.grid(3, [8, 8, 8], 1.0, stagger=[[0.5, 0.5, 0.5]])
+    h = 1 / 8
+    r = wl.rng(35)
+    idx = r.integers(0, 8, (40, 3))
+    X = (idx + 0.5) * h
+    F = r.integers(-8, 9, (40, 1)).astype(np.float64)
+    f = orc.spread(g, X, F)[0]
+    acc = np.zeros((8, 8, 8), dtype=object)
+    w1 = {-1: Fraction(1, 4), 0: Fraction(1, 2), 1: Fraction(1, 4)}
+    for j in range(40):
+        for sz in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                for sx in (-1, 0, 1):
+                    z, y, x = (idx[j, 2] + sz) % 8, (idx[j, 1] + sy) % 8, (idx[j, 0] + sx) % 8
+                    acc[z, y, x] += w1[sx] * w1[sy] * w1[sz] * int(F[j, 0]) * 512
+    assert np.array_equal(f, acc.astype(np.float64))
+
+
+def test_interp_grad_matches_finite_differences(orc):
+    g = wl.grid(3, [8, 8, 8], 1.0)
+    r = wl.rng(36)
+    X = r.random((30, 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    W = r.standard_normal((30, 3))
+    dX = orc.interp_grad(g, X, u, W)
+    e = 1e-6
+    for k in range(3):
+        Xp, Xm = X.copy(), X.copy()
+        Xp[:, k] += e
+        Xm[:, k] -= e
+        fd = ((orc.interp(g, Xp, u) - orc.interp(g, Xm, u)) * W).sum(1) / (2 * e)
+        assert np.abs(fd - dX[:, k]).max() < 1e-6 * (np.abs(dX).max() + 1)

@@ -1,0 +1,128 @@
+/*
+ * ibops: immersed-boundary spreading and interpolation on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libibops.so.  All pointers named "device" are HIP device
+ * pointers owned by the caller; all calls are asynchronous and ordered on the given
+ * HIP stream (a hipStream_t passed as void*, NULL = the null stream) unless stated.
+ *
+ * Operations (Kassen, Shankar & Fogelson, arXiv 2012.06646):
+ *   spreading      f = S(X) F, eq. (disc-spread) of Sec. 2 in matrix form (matrix-spread):
+ *                  f_c(x_i) = sum_j delta_h(x_i - X_j) F_{j,c}, delta_h = prod_k h_k^-1 phi(./h_k)
+ *   interpolation  U = J(X) u, eq. (disc-interp):  U_{j,c} = sum_i delta_h(x_i - X_j) u_c(x_i) h^d
+ *   plan           cell keys, stable key/index sort, unique-key count and segment offsets,
+ *                  the preparatory steps of Alg. 4 (Sec. 3.3).
+ * Grid points of component c are x = h (i + xi_c), i taken modulo n (periodic box,
+ * Sec. 3.1); phi is Peskin's 4-point kernel or the cosine kernel (Sec. 2).
+ *
+ * Layouts:
+ *   points X, forces F, velocities U : row-major (npts x dim) and (npts x ncomp)
+ *   grid fields f, u                 : [ncomp][n2][n1][n0], x (index 0) fastest; 2-D: [ncomp][n1][n0]
+ *   keys                             : key = c0 + n0 * (c1 + n1 * c2), the x-fastest cell index
+ *                                      counted from 0 (Fig. 2 counts from 1)
+ * Dtype: one per plan, IB_F64 or IB_F32, shared by X, F, f, u and U.  Keys, permutations
+ * and offsets are int32.
+ *
+ * Errors: every call returns an ib_status; negative values are errors and leave outputs
+ * untouched (argument errors are detected on the host before any launch).  Data errors
+ * found on the device (a non-finite coordinate, or |X_k / h_k| >= 2^30) set a device flag
+ * reported by ib_plan_status; the results of that update are then unspecified but every
+ * memory access stays in bounds.
+ */
+#ifndef IBOPS_IB_H
+#define IBOPS_IB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IB_OK = 0,
+    IB_ERR_ARG = -1,          /* invalid argument (null pointer, bad size, bad descriptor) */
+    IB_ERR_OOM = -2,          /* workspace too small / host allocation failed */
+    IB_ERR_HIP = -3,          /* a HIP runtime call failed */
+    IB_ERR_UNSUPPORTED = -4,  /* n_k < 4, more than 2^31-1 cells, unsupported dtype/kernel */
+    IB_ERR_BUSY = -5,         /* server queue full */
+    IB_ERR_DEVICE_FLAG = -6,  /* a device-side data error was flagged (see above) */
+    IB_PENDING = 1            /* batch job not finished yet */
+} ib_status;
+
+typedef enum { IB_F64 = 0, IB_F32 = 1 } ib_dtype;
+
+typedef enum {
+    IB_KERNEL_PESKIN4 = 0,    /* Peskin's 4-point kernel */
+    IB_KERNEL_COSINE4 = 1     /* phi(r) = (1 + cos(pi r / 2)) / 4 on |r| <= 2 (the paper's choice) */
+} ib_kernel;
+
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t n[3];             /* cells per dimension, each >= 4; product <= 2^31 - 1 */
+    double  length[3];        /* periodic box edge per dimension (> 0); h_k = length_k / n_k */
+    int32_t ncomp;            /* grid components, 1..3 (a MAC velocity grid has ncomp = dim) */
+    double  stagger[3][3];    /* xi_c in [0,1)^dim per component; MAC: 0.5 - 0.5 e_c */
+    int32_t kernel;           /* ib_kernel */
+} ib_grid_desc;
+
+typedef struct ib_plan_s *ib_plan;
+
+/* Human-readable name of a status code (static string). */
+const char *ib_status_string(int32_t status);
+
+/* ---- plans: keys, stable sort, segments (Alg. 4, Sec. 3.3; Fig. 2) -------------------- */
+
+/* Bytes of device workspace a plan for `npts` points needs (0 on invalid arguments).
+ * npts may be 0. */
+size_t ib_plan_workspace_bytes(const ib_grid_desc *grid, int32_t dtype, int64_t npts);
+
+/* Create a plan.  `workspace` is caller-owned device memory of at least
+ * ib_plan_workspace_bytes() bytes (256-byte aligned), kept alive until ib_plan_destroy.
+ * The library never allocates device memory.  The host-side plan object is freed by
+ * ib_plan_destroy.  Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED, IB_ERR_OOM, IB_ERR_HIP. */
+int32_t ib_plan_create(const ib_grid_desc *grid, int32_t dtype, int64_t npts,
+                       void *workspace, size_t workspace_bytes, ib_plan *out);
+
+/* Number of distinct staggerings among the plan's components (each gets its own keys and
+ * sort), and the stagger index of component c. */
+int32_t ib_plan_num_staggers(ib_plan plan);
+int32_t ib_plan_stagger_of(ib_plan plan, int32_t comp);
+
+/* Recompute the plan for positions X (device, npts x dim, plan dtype): per distinct
+ * staggering, the cell key of every point, the stable ascending sort of the point indices
+ * by key (ties keep input order), the number q of distinct keys and the first sorted
+ * position of each run.  X is referenced, not copied: it must stay valid and unchanged
+ * until the last spread/interpolate/gradient call that uses this update. */
+int32_t ib_plan_update(ib_plan plan, const void *X, void *stream);
+
+/* Copy one staggering's plan arrays into caller device buffers (any may be NULL):
+ * keys[npts] (input order), sorted_keys[npts], perm[npts] (sorted position -> point index),
+ * seg_off[q+1] (seg_off[q] = npts; buffer must hold npts+1), q[1]. */
+int32_t ib_plan_export(ib_plan plan, int32_t stagger_id, int32_t *keys, int32_t *sorted_keys,
+                       int32_t *perm, int32_t *seg_off, int32_t *q, void *stream);
+
+/* Synchronize the plan's last stream and report IB_ERR_DEVICE_FLAG if the last update
+ * flagged a data error, else IB_OK (or IB_ERR_HIP).  Clears the flag. */
+int32_t ib_plan_status(ib_plan plan);
+
+void ib_plan_destroy(ib_plan plan);
+
+/* ---- operators ---------------------------------------------------------------------- */
+
+/* Spreading, eq. (disc-spread): f_c(x_i) = (prod_k h_k)^-1 sum_j W_{c,i,j} F_{j,c}, with
+ * W = prod_k phi((x_{i,k} - X_{j,k}) / h_k) taken at the nearest periodic image.  F is
+ * (npts x ncomp) device, already multiplied by the Lagrangian weights dtheta_j.  f is
+ * (ncomp x grid) device; overwritten, or added to when accumulate != 0.  Every grid value
+ * is written exactly once; no floating-point atomics are used and the result is bitwise
+ * reproducible run to run. */
+int32_t ib_spread(ib_plan plan, const void *F, void *f, int32_t accumulate, void *stream);
+
+/* Interpolation, eq. (disc-interp): U_{j,c} = sum_i W_{c,i,j} u_c(x_i).  u (ncomp x grid)
+ * device; U (npts x ncomp) device, overwritten. */
+int32_t ib_interpolate(ib_plan plan, const void *u, void *U, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBOPS_IB_H */

@@ -1,0 +1,128 @@
+// Device helpers shared by the HIP kernels: wave64 primitives, block scans, the cell /
+// fractional-offset computation and the 4-point kernel weights.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ib_internal.h"
+
+namespace ibk {
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    const int lane = lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, (unsigned)o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over a block of NT threads (NT a multiple of
+// 64, at most 1024).  `scratch` holds NT/64 + 1 words of LDS.  Returns the exclusive
+// prefix; *total receives the block sum.  Must be called by all threads.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* scratch,
+                                                        uint32_t* total)
+{
+    constexpr int NW = NT / 64;
+    const int lane = lane_id(), w = wave_id();
+    uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == 63) scratch[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < NW; ++i) {
+            uint32_t t = scratch[i];
+            scratch[i] = run;
+            run += t;
+        }
+        scratch[NW] = run;
+    }
+    __syncthreads();
+    uint32_t r = scratch[w] + incl - v;
+    *total = scratch[NW];
+    __syncthreads();
+    return r;
+}
+
+// ---- scaled coordinates, cells and fractional offsets ----------------------------------
+//
+// The cell of coordinate X on staggering xi is floor(t - xi) with t = X * inv_h rounded
+// once in the working precision and never fused with the subtraction, so that cell keys
+// are reproducible bit for bit.  The fractional offset r = (t - xi) - floor(t - xi) is then
+// corrected by the exact rounding residual of the product and by the residual of inv_h
+// itself, so the weights see X / h to working precision.
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    __device__ static double inv_h(const GeomArgs& g, int k) { return g.inv_h_d[k]; }
+    __device__ static double inv_lo(const GeomArgs& g, int k) { return g.inv_lo_d[k]; }
+};
+template <> struct Prec<float> {
+    __device__ static float inv_h(const GeomArgs& g, int k) { return g.inv_h_f[k]; }
+    __device__ static float inv_lo(const GeomArgs& g, int k) { return g.inv_lo_f[k]; }
+};
+
+template <typename T>
+__device__ __forceinline__ T shifted_scaled(T x, T inv_h, T xi)
+{
+#pragma clang fp contract(off)
+    T t = x * inv_h;
+    return t - xi;
+}
+
+template <typename T>
+__device__ __forceinline__ T product_residual(T x, T inv_h, T inv_lo)
+{
+#pragma clang fp contract(off)
+    T t = x * inv_h;
+    return fma(x, inv_h, -t) + x * inv_lo;
+}
+
+// ---- one-dimensional kernel weights for the four shifts sigma = -1, 0, 1, 2 --------------
+// w[k] = phi(sigma_k - r) for a point at fractional offset r in [0, 1) of its cell.
+
+template <typename T, int KERN>
+__device__ __forceinline__ void weights4(T r, T w[4])
+{
+    if constexpr (KERN == IB_KERNEL_COSINE4) {
+        T s, c;
+        if constexpr (sizeof(T) == 8) sincospi(0.5 * r, &s, &c);
+        else sincospif(0.5f * r, &s, &c);
+        const T q = T(0.25);
+        w[0] = q - q * s;
+        w[1] = q + q * c;
+        w[2] = q + q * s;
+        w[3] = q - q * c;
+    } else {
+        // Peskin 4-point: with s = sqrt(1 + 4r - 4r^2), phi(-1-r) = (1-r)^2 / (3 - 2r + s),
+        // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = r^2 / (1 + 2r + s).
+        const T s = sqrt(T(1) + T(4) * r * (T(1) - r));
+        const T a = T(3) - T(2) * r + s;
+        const T b = T(1) + T(2) * r + s;
+        const T om = T(1) - r;
+        w[0] = om * om / a;
+        w[1] = a * T(0.125);
+        w[2] = b * T(0.125);
+        w[3] = r * r / b;
+    }
+}
+
+__device__ __forceinline__ int emod(int a, int n)
+{
+    int m = a % n;
+    return m < 0 ? m + n : m;
+}
+
+}  // namespace ibk

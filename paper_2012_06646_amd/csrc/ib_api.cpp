@@ -1,0 +1,334 @@
+// Host runtime of libibops: argument checking, plan workspace layout and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "ib.h"
+#include "ib_internal.h"
+
+using namespace ibk;
+
+struct ib_plan_s {
+    ib_grid_desc grid;
+    int32_t dtype;
+    int64_t npts;
+    SortArgs sa;           // geometry, device pointers, radix configuration
+    int32_t* sorted_keys;  // final sort output (aliases kA or kB)
+    int32_t* perm;
+    const void* X;         // positions of the last update
+    hipStream_t last_stream;
+    int updated;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int bits_for(int64_t G)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < G) ++b;
+    return b;
+}
+
+struct Layout {
+    int nstag, npass, rbits, rows;
+    int64_t ntiles, nseg_tiles, G;
+    // byte offsets
+    size_t keys0, kA, vA, kB, vB, row_start, seg_off, q, zero_begin, hist, sort_status,
+        seg_status, counters, flag, zero_end, total;
+};
+
+// Validate a descriptor; fill the distinct staggerings.
+int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nstag,
+                   int comp_stag[3], double stag_xi[3][3])
+{
+    if (!g) return IB_ERR_ARG;
+    if (g->dim != 2 && g->dim != 3) return IB_ERR_UNSUPPORTED;
+    if (dtype != IB_F64 && dtype != IB_F32) return IB_ERR_UNSUPPORTED;
+    if (g->kernel != IB_KERNEL_PESKIN4 && g->kernel != IB_KERNEL_COSINE4) return IB_ERR_UNSUPPORTED;
+    if (g->ncomp < 1 || g->ncomp > 3) return IB_ERR_ARG;
+    if (npts < 0) return IB_ERR_ARG;
+    if (npts > MAX_POINTS) return IB_ERR_UNSUPPORTED;
+    int64_t G = 1;
+    for (int k = 0; k < g->dim; ++k) {
+        if (g->n[k] < 4) return IB_ERR_UNSUPPORTED;
+        if (!(g->length[k] > 0.0) || !std::isfinite(g->length[k])) return IB_ERR_ARG;
+        G *= g->n[k];
+        if (G > 2147483647LL) return IB_ERR_UNSUPPORTED;
+    }
+    int ns = 0;
+    for (int c = 0; c < g->ncomp; ++c) {
+        for (int k = 0; k < g->dim; ++k) {
+            const double xi = g->stagger[c][k];
+            if (!(xi >= 0.0 && xi < 1.0)) return IB_ERR_ARG;
+        }
+        int found = -1;
+        for (int s = 0; s < ns && found < 0; ++s) {
+            bool same = true;
+            for (int k = 0; k < g->dim; ++k) same &= (stag_xi[s][k] == g->stagger[c][k]);
+            if (same) found = s;
+        }
+        if (found < 0) {
+            for (int k = 0; k < 3; ++k) stag_xi[ns][k] = k < g->dim ? g->stagger[c][k] : 0.0;
+            found = ns++;
+        }
+        comp_stag[c] = found;
+    }
+    *nstag = ns;
+    return IB_OK;
+}
+
+void make_layout(const ib_grid_desc* g, int nstag, int64_t n, Layout* L)
+{
+    L->nstag = nstag;
+    L->G = 1;
+    for (int k = 0; k < g->dim; ++k) L->G *= g->n[k];
+    L->rows = (int)(L->G / g->n[0]);
+    const int bits = bits_for(L->G);
+    L->npass = (bits + MAX_RADIX_BITS - 1) / MAX_RADIX_BITS;
+    L->rbits = (bits + L->npass - 1) / L->npass;
+    if (L->rbits < 4) L->rbits = 4;
+    L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    L->nseg_tiles = L->ntiles > 0 ? L->ntiles : 1;
+    const int64_t R = int64_t(1) << L->rbits;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t kn = (size_t)nstag * (size_t)n * sizeof(int32_t);
+    L->keys0 = take(kn);
+    L->kA = take(kn);
+    L->vA = take(kn);
+    L->kB = take(kn);
+    L->vB = take(kn);
+    L->row_start = take((size_t)nstag * (L->rows + 1) * sizeof(int32_t));
+    L->seg_off = take((size_t)nstag * (size_t)(n + 1) * sizeof(int32_t));
+    L->q = take((size_t)nstag * sizeof(int32_t));
+    // Everything from here to zero_end is cleared at every update.
+    L->zero_begin = off;
+    L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
+    L->sort_status = take((size_t)L->npass * nstag * L->ntiles * R * sizeof(uint32_t));
+    L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
+    L->counters = take((size_t)(L->npass + 1) * sizeof(uint32_t));
+    L->flag = take(sizeof(uint32_t));
+    L->zero_end = off;
+    L->total = off;
+}
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? IB_OK : IB_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* ib_status_string(int32_t s)
+{
+    switch (s) {
+    case IB_OK: return "ok";
+    case IB_ERR_ARG: return "invalid argument";
+    case IB_ERR_OOM: return "out of memory (workspace too small or host allocation failed)";
+    case IB_ERR_HIP: return "HIP runtime error";
+    case IB_ERR_UNSUPPORTED: return "unsupported configuration";
+    case IB_ERR_BUSY: return "busy";
+    case IB_ERR_DEVICE_FLAG: return "device flagged a data error (non-finite or out-of-range position)";
+    case IB_PENDING: return "pending";
+    default: return "unknown status";
+    }
+}
+
+size_t ib_plan_workspace_bytes(const ib_grid_desc* grid, int32_t dtype, int64_t npts)
+{
+    int nstag, cs[3];
+    double sx[3][3];
+    if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
+    Layout L;
+    make_layout(grid, nstag, npts, &L);
+    return L.total;
+}
+
+int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* workspace,
+                       size_t workspace_bytes, ib_plan* out)
+{
+    if (!out) return IB_ERR_ARG;
+    *out = nullptr;
+    int nstag, cs[3];
+    double sx[3][3] = {{0}};
+    int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
+    if (st != IB_OK) return st;
+    Layout L;
+    make_layout(grid, nstag, npts, &L);
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
+    if (workspace_bytes < L.total) return IB_ERR_OOM;
+
+    ib_plan p = new (std::nothrow) ib_plan_s();
+    if (!p) return IB_ERR_OOM;
+    p->grid = *grid;
+    p->dtype = dtype;
+    p->npts = npts;
+    GeomArgs& g = p->sa.g;
+    std::memset(&g, 0, sizeof g);
+    g.dim = grid->dim;
+    g.ncomp = grid->ncomp;
+    g.nstag = nstag;
+    g.rows = L.rows;
+    g.npts = npts;
+    double hd = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = k < grid->dim ? grid->n[k] : 1;
+        if (k >= grid->dim) {
+            g.inv_h_d[k] = 1.0;
+            g.inv_h_f[k] = 1.0f;
+            continue;
+        }
+        const double N = grid->n[k], Lk = grid->length[k];
+        g.inv_h_d[k] = N / Lk;
+        g.inv_lo_d[k] = (double)((long double)N / (long double)Lk - (long double)g.inv_h_d[k]);
+        g.inv_h_f[k] = (float)grid->n[k] / (float)grid->length[k];
+        g.inv_lo_f[k] = (float)((long double)N / (long double)Lk - (long double)g.inv_h_f[k]);
+        hd *= Lk / N;
+    }
+    g.scale = 1.0 / hd;
+    for (int c = 0; c < grid->ncomp; ++c) {
+        g.comp_stag[c] = cs[c];
+        for (int k = 0; k < 3; ++k) g.comp_xi[c][k] = k < grid->dim ? grid->stagger[c][k] : 0.0;
+    }
+    for (int s = 0; s < nstag; ++s)
+        for (int k = 0; k < 3; ++k) g.stag_xi[s][k] = sx[s][k];
+
+    char* base = (char*)workspace;
+    PlanDev& d = p->sa.d;
+    d.keys0 = (int32_t*)(base + L.keys0);
+    d.kA = (int32_t*)(base + L.kA);
+    d.vA = (int32_t*)(base + L.vA);
+    d.kB = (int32_t*)(base + L.kB);
+    d.vB = (int32_t*)(base + L.vB);
+    d.row_start = (int32_t*)(base + L.row_start);
+    d.seg_off = (int32_t*)(base + L.seg_off);
+    d.q = (int32_t*)(base + L.q);
+    d.hist = (uint32_t*)(base + L.hist);
+    d.sort_status = (uint32_t*)(base + L.sort_status);
+    d.seg_status = (uint32_t*)(base + L.seg_status);
+    d.counters = (uint32_t*)(base + L.counters);
+    d.flag = (uint32_t*)(base + L.flag);
+    d.zero_begin = (uint32_t*)(base + L.zero_begin);
+    d.zero_words = (L.zero_end - L.zero_begin) / sizeof(uint32_t);
+    p->sa.npass = L.npass;
+    p->sa.rbits = L.rbits;
+    p->sa.ntiles = L.ntiles;
+    p->sa.nseg_tiles = L.nseg_tiles;
+    const bool in_a = (npts == 0) || (L.npass & 1);
+    p->sorted_keys = in_a ? d.kA : d.kB;
+    p->perm = in_a ? d.vA : d.vB;
+    p->X = nullptr;
+    p->last_stream = nullptr;
+    p->updated = 0;
+    *out = p;
+    return IB_OK;
+}
+
+int32_t ib_plan_num_staggers(ib_plan p) { return p ? p->sa.g.nstag : IB_ERR_ARG; }
+
+int32_t ib_plan_stagger_of(ib_plan p, int32_t comp)
+{
+    if (!p || comp < 0 || comp >= p->grid.ncomp) return IB_ERR_ARG;
+    return p->sa.g.comp_stag[comp];
+}
+
+int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
+{
+    if (!p) return IB_ERR_ARG;
+    if (!X && p->npts > 0) return IB_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t r = hip_status(launch_plan_update(p->sa, p->dtype, X, st));
+    if (r != IB_OK) return r;
+    p->X = X;
+    p->last_stream = st;
+    p->updated = 1;
+    return IB_OK;
+}
+
+int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_keys, int32_t* perm,
+                       int32_t* seg_off, int32_t* q, void* stream)
+{
+    if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n = (size_t)p->npts;
+    const PlanDev& d = p->sa.d;
+    hipError_t e = hipSuccess;
+    if (keys && n) e = hipMemcpyAsync(keys, d.keys0 + sid * n, n * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && sorted_keys && n)
+        e = hipMemcpyAsync(sorted_keys, p->sorted_keys + sid * n, n * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && perm && n)
+        e = hipMemcpyAsync(perm, p->perm + sid * n, n * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && seg_off)
+        e = hipMemcpyAsync(seg_off, d.seg_off + sid * (n + 1), (n + 1) * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && q) e = hipMemcpyAsync(q, d.q + sid, 4, hipMemcpyDeviceToDevice, st);
+    return hip_status(e);
+}
+
+int32_t ib_plan_status(ib_plan p)
+{
+    if (!p) return IB_ERR_ARG;
+    if (hipStreamSynchronize(p->last_stream) != hipSuccess) return IB_ERR_HIP;
+    if (!p->updated) return IB_OK;
+    uint32_t flag = 0;
+    if (hipMemcpy(&flag, p->sa.d.flag, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
+        return IB_ERR_HIP;
+    if (flag) {
+        const uint32_t zero = 0;
+        if (hipMemcpy(p->sa.d.flag, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+            return IB_ERR_HIP;
+        return IB_ERR_DEVICE_FLAG;
+    }
+    return IB_OK;
+}
+
+void ib_plan_destroy(ib_plan p) { delete p; }
+
+static void fill_op_args(ib_plan p, OpArgs* a)
+{
+    std::memset(a, 0, sizeof *a);
+    a->g = p->sa.g;
+    a->sorted_keys = p->sorted_keys;
+    a->perm = p->perm;
+    a->row_start = p->sa.d.row_start;
+    a->X = p->X;
+}
+
+int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
+{
+    if (!p || !f || !p->updated) return IB_ERR_ARG;
+    if (!F && p->npts > 0) return IB_ERR_ARG;
+    OpArgs a;
+    fill_op_args(p, &a);
+    a.F = F;
+    a.f = f;
+    a.accumulate = accumulate != 0;
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    return hip_status(launch_spread(a, p->dtype, p->grid.kernel, st));
+}
+
+int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
+{
+    if (!p || !u || !p->updated) return IB_ERR_ARG;
+    if (!U && p->npts > 0) return IB_ERR_ARG;
+    if (p->npts == 0) return IB_OK;
+    OpArgs a;
+    fill_op_args(p, &a);
+    a.u = u;
+    a.U = U;
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// Plan kernels: cell keys, stable LSD radix sort of (key, index) pairs, and segments.
+//
+// These are the preparatory steps of the parallel spreading algorithm (Alg. 4, Sec. 3.3):
+// one key per IB point from the cell it occupies, a key-value sort of the point indices
+// that groups equal keys, the count of distinct keys and where each run starts (Fig. 2).
+// The sort is stable, so the permutation is unique: ties keep input order.
+//
+// gfx950 design: every distinct staggering of the grid is sorted in the same launches
+// (one tile queue across staggerings).  Each radix pass is a single kernel: tiles of 4096
+// keys take a ticket from an atomic counter, rank their keys stably within the tile with
+// wave64 ballots, publish per-digit tile counts, and obtain the exclusive prefix over all
+// earlier tiles by decoupled look-back; keys are then staged in LDS in digit order so the
+// global writes are contiguous runs.  Digit histograms for every pass are accumulated by
+// the key kernel in the same sweep over X.  Only ceil(log2(#cells)) key bits are sorted.
+#include "device_common.h"
+
+namespace ibk {
+
+// ---- reset: clear histograms, look-back words, tickets and the error flag -------------
+__global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ---- keys: one per point and distinct staggering, plus all pass histograms ----------
+template <typename T>
+__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X)
+{
+    extern __shared__ uint32_t lhist[];  // [nstag][npass][R]
+    const GeomArgs& g = a.g;
+    const int R = 1 << a.rbits;
+    const int nh = g.nstag * a.npass * R;
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) lhist[i] = 0u;
+    __syncthreads();
+
+    const int64_t n = g.npts;
+    bool any_bad = false;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        T x[3];
+        for (int k = 0; k < g.dim; ++k) x[k] = X[j * g.dim + k];
+        bool bad = false;
+        for (int s = 0; s < g.nstag; ++s) {
+            int key = 0, stride = 1;
+            for (int k = 0; k < g.dim; ++k) {
+                const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
+                int c = 0;
+                if (fabs(y) < T(1073741824.0)) c = emod((int)floor(y), g.n[k]);
+                else bad = true;
+                key += c * stride;
+                stride *= g.n[k];
+            }
+            a.d.keys0[(int64_t)s * n + j] = key;
+            for (int p = 0; p < a.npass; ++p)
+                atomicAdd(&lhist[(s * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
+        }
+        any_bad |= bad;
+    }
+    if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nh; i += blockDim.x)
+        if (lhist[i]) atomicAdd(&a.d.hist[i], lhist[i]);
+}
+
+// ---- decoupled look-back over one counter per tile ------------------------------------
+// Tile `t` of a chain publishes its own count first (flag AGG; tile 0 publishes INC), then
+// walks back over earlier tiles, summing AGG counts until it meets an INC prefix.  Every
+// earlier tile already holds a ticket, so it is running or done and publishes without
+// waiting: the walk always ends.  A bounded spin guards against the impossible case.
+__device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t stride, int64_t t,
+                                                     uint32_t mine, uint32_t* flag)
+{
+    if (t == 0) {
+        __hip_atomic_store(&chain[0], LB_INC | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0u;
+    }
+    __hip_atomic_store(&chain[t * stride], LB_AGG | mine, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    int64_t j = t - 1;
+    uint32_t spins = 0;
+    while (true) {
+        uint32_t v = __hip_atomic_load(&chain[j * stride], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t f = v & ~LB_MASK;
+        if (f == 0u) {
+            if (++spins > (1u << 22)) {  // never expected; keep the kernel finite
+                atomicOr(flag, FLAG_LOOKBACK_STALL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += v & LB_MASK;
+        if (f == LB_INC || j == 0) break;
+        --j;
+    }
+    __hip_atomic_store(&chain[t * stride], LB_INC | (excl + mine), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
+// ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
+template <int RBITS>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int pass)
+{
+    constexpr int R = 1 << RBITS;
+    constexpr int NW = SORT_BLOCK / 64;
+    __shared__ int32_t s_key[SORT_TILE];
+    __shared__ int32_t s_val[SORT_TILE];
+    __shared__ uint32_t s_wcnt[NW][R];
+    __shared__ uint32_t s_tstart[R];
+    __shared__ uint32_t s_gbase[R];
+    __shared__ uint32_t s_excl[R];
+    __shared__ uint32_t s_scan[NW + 1];
+    __shared__ uint32_t s_ticket;
+
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[pass], 1u);
+    for (int i = tid; i < NW * R; i += SORT_BLOCK) (&s_wcnt[0][0])[i] = 0u;
+    __syncthreads();
+
+    const int64_t n = a.g.npts;
+    const int64_t ticket = s_ticket;
+    const int s = (int)(ticket / a.ntiles);
+    const int64_t t = ticket % a.ntiles;
+    const int64_t base = t * SORT_TILE;
+    const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
+
+    // Source and destination: pass 0 reads the unsorted keys and generates the indices.
+    const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
+    const int32_t* srcv = (pass & 1) ? a.d.vA : a.d.vB;
+    int32_t* dstk = (pass & 1) ? a.d.kB : a.d.kA;
+    int32_t* dstv = (pass & 1) ? a.d.vB : a.d.vA;
+    srck += (int64_t)s * n;
+    srcv += (int64_t)s * n;
+    dstk += (int64_t)s * n;
+    dstv += (int64_t)s * n;
+    const int shift = pass * RBITS;
+
+    // Stable in-tile ranking: wave w owns items [w*1024, (w+1)*1024) of the tile, in
+    // 16 steps of 64 consecutive items; the rank of an item among equal digits is the
+    // count in earlier steps of its wave plus the count of lower lanes in its step.
+    int32_t key[SORT_IPT], val[SORT_IPT];
+    uint32_t rank[SORT_IPT];
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
+        const bool valid = li < nvalid;
+        key[k] = valid ? srck[base + li] : 0;
+        val[k] = valid ? (pass == 0 ? (int32_t)(base + li) : srcv[base + li]) : 0;
+        const uint32_t digit = ((uint32_t)key[k] >> shift) & (R - 1);
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < RBITS; ++b) {
+            const bool bit = (digit >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t prior = 0;
+        if (valid) prior = s_wcnt[w][digit];
+        rank[k] = prior + (uint32_t)__popcll(m & below);
+        if (valid && lane == 63 - __clzll(m)) s_wcnt[w][digit] = prior + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+
+    // Per digit: wave offsets within the tile, the tile count, its exclusive prefix over
+    // earlier tiles (look-back), the digit's global base and its start inside the tile.
+    uint32_t cnt = 0, gcount = 0;
+    if (tid < R) {
+        for (int v = 0; v < NW; ++v) {
+            const uint32_t c = s_wcnt[v][tid];
+            s_wcnt[v][tid] = cnt;
+            cnt += c;
+        }
+        gcount = a.d.hist[((int64_t)s * a.npass + pass) * R + tid];
+    }
+    uint32_t tot;
+    const uint32_t tstart = block_excl_scan_u32<SORT_BLOCK>(tid < R ? cnt : 0u, s_scan, &tot);
+    const uint32_t gbase = block_excl_scan_u32<SORT_BLOCK>(tid < R ? gcount : 0u, s_scan, &tot);
+    if (tid < R) {
+        s_tstart[tid] = tstart;
+        s_gbase[tid] = gbase;
+        // Look-back column of this digit: tile-major, digit-minor words.
+        uint32_t* col = a.d.sort_status +
+                        ((int64_t)pass * a.g.nstag * a.ntiles + (int64_t)s * a.ntiles) * R + tid;
+        const uint32_t excl = lookback_strided(col, R, t, cnt, a.d.flag);
+        s_excl[tid] = excl;
+    }
+    __syncthreads();
+
+    // Stage the tile in digit order, then write contiguous runs per digit.
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
+        if (li < nvalid) {
+            const uint32_t digit = ((uint32_t)key[k] >> shift) & (R - 1);
+            const uint32_t pos = s_tstart[digit] + s_wcnt[w][digit] + rank[k];
+            s_key[pos] = key[k];
+            s_val[pos] = val[k];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nvalid; i += SORT_BLOCK) {
+        const int32_t kk = s_key[i];
+        const uint32_t digit = ((uint32_t)kk >> shift) & (R - 1);
+        const int64_t dst = (int64_t)s_gbase[digit] + s_excl[digit] + (i - (int64_t)s_tstart[digit]);
+        if (dst < n) {  // always true when the histograms and tile counts agree
+            dstk[dst] = kk;
+            dstv[dst] = s_val[i];
+        }
+    }
+}
+
+// ---- segments: run heads, q, seg_off and the per-row start table -----------------------
+__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, const int32_t* sk_all)
+{
+    constexpr int NW = SORT_BLOCK / 64;
+    __shared__ uint32_t s_wtot[NW];
+    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_excl;
+    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[a.npass], 1u);
+    __syncthreads();
+
+    const int64_t n = a.g.npts;
+    const int64_t ticket = s_ticket;
+    const int s = (int)(ticket / a.nseg_tiles);
+    const int64_t t = ticket % a.nseg_tiles;
+    const int64_t base = t * SORT_TILE;
+    const int32_t* sk = sk_all + (int64_t)s * n;
+    int32_t* seg = a.d.seg_off + (int64_t)s * (n + 1);
+    int32_t* rs = a.d.row_start + (int64_t)s * (a.g.rows + 1);
+    const int n0 = a.g.n[0];
+
+    uint32_t rank[SORT_IPT];
+    bool head[SORT_IPT];
+    uint32_t wrun = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+        bool hd = false;
+        if (i < n) {
+            const int32_t kc = sk[i];
+            const int32_t kp = i > 0 ? sk[i - 1] : -1;
+            hd = (i == 0) || (kc != kp);
+            // Row table: rows (row(i-1), row(i)] start at sorted position i.
+            const int rp = i > 0 ? min(max(kp / n0, -1), a.g.rows - 1) : -1;
+            const int rc = min(max(kc / n0, -1), a.g.rows - 1);
+            for (int r = rp + 1; r <= rc; ++r) rs[r] = (int32_t)i;
+        }
+        const unsigned long long m = __ballot(hd);
+        head[k] = hd;
+        rank[k] = wrun + (uint32_t)__popcll(m & below);
+        wrun += (uint32_t)__popcll(m);
+    }
+    if (lane == 0) s_wtot[w] = wrun;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int v = 0; v < NW; ++v) {
+            const uint32_t c = s_wtot[v];
+            s_wtot[v] = run;
+            run += c;
+        }
+        uint32_t* chain = a.d.seg_status + (int64_t)s * a.nseg_tiles;
+        const uint32_t excl = lookback_strided(chain, 1, t, run, a.d.flag);
+        s_excl = excl;
+        if (t == a.nseg_tiles - 1) {
+            const uint32_t q = excl + run;
+            a.d.q[s] = (int32_t)q;
+            seg[q] = (int32_t)n;
+            const int rlast = n > 0 ? min(max(sk[n - 1] / n0, -1), a.g.rows - 1) : -1;
+            for (int r = rlast + 1; r <= a.g.rows; ++r) rs[r] = (int32_t)n;
+        }
+    }
+    __syncthreads();
+    const uint32_t off = s_excl + s_wtot[w];
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+        if (head[k]) seg[off + rank[k]] = (int32_t)i;
+    }
+}
+
+// ---- host launcher ----------------------------------------------------------------------
+hipError_t launch_plan_update(const SortArgs& a, int dtype, const void* X, hipStream_t st)
+{
+    const GeomArgs& g = a.g;
+    {
+        const size_t nw = a.d.zero_words;
+        const int blocks = (int)min((size_t)1024, (nw + 255) / 256);
+        if (blocks > 0)
+            hipLaunchKernelGGL(plan_reset_kernel, dim3(blocks), dim3(256), 0, st, a.d.zero_begin, nw);
+    }
+    const int R = 1 << a.rbits;
+    const size_t lds = (size_t)g.nstag * a.npass * R * sizeof(uint32_t);
+    if (g.npts > 0) {
+        const int blocks = (int)min((int64_t)2048, (g.npts + 255) / 256);
+        if (dtype == IB_F64)
+            hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a,
+                               (const double*)X);
+        else
+            hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a,
+                               (const float*)X);
+        const unsigned tiles = (unsigned)(a.ntiles * g.nstag);
+        for (int p = 0; p < a.npass; ++p) {
+            switch (a.rbits) {
+            case 4: hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            case 5: hipLaunchKernelGGL(radix_pass_kernel<5>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            case 6: hipLaunchKernelGGL(radix_pass_kernel<6>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            case 7: hipLaunchKernelGGL(radix_pass_kernel<7>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            case 8: hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            default: return hipErrorInvalidValue;
+            }
+        }
+    }
+    // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
+    const int32_t* sk = (g.npts == 0) ? a.d.kA : ((a.npass & 1) ? a.d.kA : a.d.kB);
+    hipLaunchKernelGGL(segments_kernel, dim3((unsigned)(a.nseg_tiles * g.nstag)), dim3(SORT_BLOCK),
+                       0, st, a, sk);
+    return hipGetLastError();
+}
+
+}  // namespace ibk

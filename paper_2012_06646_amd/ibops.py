@@ -1,0 +1,218 @@
+"""Thin Python binding of libibops.so (the C ABI declared in include/ib.h).
+
+Argument marshalling only: every step of spreading, interpolation and plan construction
+runs in the library's HIP kernels.  PyTorch provides device memory and streams.  Importing
+this module loads the library and raises ImportError if it has not been built
+(``python -m paper_2012_06646_amd.build``); there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibops.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libibops.so not built ({LIB_PATH}); run python -m paper_2012_06646_amd.build")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+IB_F64, IB_F32 = 0, 1
+KERNELS = {"peskin4": 0, "cosine4": 1}
+STATUS = {0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_OOM", -3: "IB_ERR_HIP",
+          -4: "IB_ERR_UNSUPPORTED", -5: "IB_ERR_BUSY", -6: "IB_ERR_DEVICE_FLAG", 1: "IB_PENDING"}
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("length", ctypes.c_double * 3),
+                ("ncomp", ctypes.c_int32), ("stagger", (ctypes.c_double * 3) * 3),
+                ("kernel", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_lib.ib_status_string.restype = ctypes.c_char_p
+_lib.ib_status_string.argtypes = [_i32]
+_lib.ib_plan_workspace_bytes.restype = ctypes.c_size_t
+_lib.ib_plan_workspace_bytes.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64]
+_lib.ib_plan_create.restype = _i32
+_lib.ib_plan_create.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, ctypes.c_size_t,
+                                ctypes.POINTER(_vp)]
+_lib.ib_plan_num_staggers.restype = _i32
+_lib.ib_plan_num_staggers.argtypes = [_vp]
+_lib.ib_plan_stagger_of.restype = _i32
+_lib.ib_plan_stagger_of.argtypes = [_vp, _i32]
+_lib.ib_plan_update.restype = _i32
+_lib.ib_plan_update.argtypes = [_vp, _vp, _vp]
+_lib.ib_plan_export.restype = _i32
+_lib.ib_plan_export.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.ib_plan_status.restype = _i32
+_lib.ib_plan_status.argtypes = [_vp]
+_lib.ib_plan_destroy.restype = None
+_lib.ib_plan_destroy.argtypes = [_vp]
+_lib.ib_spread.restype = _i32
+_lib.ib_spread.argtypes = [_vp, _vp, _vp, _i32, _vp]
+_lib.ib_interpolate.restype = _i32
+_lib.ib_interpolate.argtypes = [_vp, _vp, _vp, _vp]
+
+EXPORTED = ["ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
+            "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
+            "ib_plan_destroy", "ib_spread", "ib_interpolate"]
+
+
+class IBError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({_lib.ib_status_string(code).decode()})")
+
+
+def _check(code, what):
+    if code < 0:
+        raise IBError(code, what)
+    return code
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def make_desc(grid):
+    """ib_grid_desc from a grid dict (dim, n, length, stagger, kernel)."""
+    d = GridDesc()
+    d.dim = int(grid["dim"])
+    for k in range(3):
+        d.n[k] = int(grid["n"][k]) if k < d.dim else 1
+        d.length[k] = float(grid["length"][k]) if k < d.dim else 1.0
+    d.ncomp = len(grid["stagger"])
+    for c, xi in enumerate(grid["stagger"]):
+        for k in range(3):
+            d.stagger[c][k] = float(xi[k]) if k < d.dim else 0.0
+    d.kernel = KERNELS[grid.get("kernel", "peskin4")]
+    return d
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float64:
+        return IB_F64
+    if dtype == torch.float32:
+        return IB_F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def workspace_bytes(grid, dtype, npts):
+    return int(_lib.ib_plan_workspace_bytes(ctypes.byref(make_desc(grid)), _dtype_code(dtype), int(npts)))
+
+
+class Plan:
+    """Cell keys, stable sort and segments of a point set (Alg. 4 preparation), resident on
+    the device.  `update(X)` recomputes them; spread/interpolate use the last update."""
+
+    def __init__(self, grid, npts, dtype=torch.float64, device="cuda"):
+        self.grid = grid
+        self.desc = make_desc(grid)
+        self.npts = int(npts)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.dim = self.desc.dim
+        self.ncomp = self.desc.ncomp
+        code = _dtype_code(dtype)
+        nbytes = int(_lib.ib_plan_workspace_bytes(ctypes.byref(self.desc), code, self.npts))
+        if nbytes == 0:
+            _check(-4, "ib_plan_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(_lib.ib_plan_create(ctypes.byref(self.desc), code, self.npts, _ptr(self.workspace),
+                                   nbytes, ctypes.byref(h)), "ib_plan_create")
+        self._h = h
+        self.X = None
+        self.nstag = _lib.ib_plan_num_staggers(h)
+        self.grid_shape = [self.ncomp] + [int(self.desc.n[k]) for k in range(self.dim)][::-1]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.ib_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stagger_of(self, c):
+        return _lib.ib_plan_stagger_of(self._h, c)
+
+    def update(self, X, stream=None):
+        X = self._pts(X, self.dim, "X")
+        _check(_lib.ib_plan_update(self._h, _ptr(X), _stream(stream)), "ib_plan_update")
+        self.X = X  # the library references X; keep it alive
+        return self
+
+    def export(self, stagger_id=0, stream=None):
+        n = self.npts
+        dev = self.device
+        out = dict(keys=torch.empty(n, dtype=torch.int32, device=dev),
+                   sorted_keys=torch.empty(n, dtype=torch.int32, device=dev),
+                   perm=torch.empty(n, dtype=torch.int32, device=dev),
+                   seg_off=torch.empty(n + 1, dtype=torch.int32, device=dev),
+                   q=torch.empty(1, dtype=torch.int32, device=dev))
+        _check(_lib.ib_plan_export(self._h, stagger_id, _ptr(out["keys"]), _ptr(out["sorted_keys"]),
+                                   _ptr(out["perm"]), _ptr(out["seg_off"]), _ptr(out["q"]),
+                                   _stream(stream)), "ib_plan_export")
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        q = int(out["q"].item())
+        out["q"] = q
+        out["seg_off"] = out["seg_off"][: q + 1]
+        return out
+
+    def status(self):
+        return _lib.ib_plan_status(self._h)
+
+    def _pts(self, t, cols, name):
+        if t.dtype != self.dtype or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a {self.dtype} CUDA tensor")
+        if t.shape != (self.npts, cols):
+            raise ValueError(f"{name} must have shape ({self.npts}, {cols}), got {tuple(t.shape)}")
+        return t.contiguous()
+
+    def _grid(self, t, name):
+        if t.dtype != self.dtype or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a {self.dtype} CUDA tensor")
+        if list(t.shape) != self.grid_shape:
+            raise ValueError(f"{name} must have shape {self.grid_shape}, got {list(t.shape)}")
+        return t.contiguous()
+
+    def spread(self, F, f=None, accumulate=False, stream=None):
+        F = self._pts(F, self.ncomp, "F")
+        if f is None:
+            f = torch.empty(self.grid_shape, dtype=self.dtype, device=self.device)
+            accumulate = False
+        else:
+            f = self._grid(f, "f")
+        _check(_lib.ib_spread(self._h, _ptr(F), _ptr(f), int(bool(accumulate)), _stream(stream)),
+               "ib_spread")
+        return f
+
+    def interpolate(self, u, U=None, stream=None):
+        u = self._grid(u, "u")
+        if U is None:
+            U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
+        _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
+        return U
+
+
+def spread(grid, X, F):
+    """f = S(X) F on `grid` (convenience: builds a plan)."""
+    p = Plan(grid, X.shape[0], X.dtype, X.device).update(X)
+    return p.spread(F)
+
+
+def interpolate(grid, X, u):
+    """U = J(X) u on `grid` (convenience: builds a plan)."""
+    p = Plan(grid, X.shape[0], X.dtype, X.device).update(X)
+    return p.interpolate(u)

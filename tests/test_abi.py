@@ -1,0 +1,79 @@
+"""The C-ABI library: it loads, exports every function include/ib.h declares, and its host
+logic (descriptor validation, workspace sizing) behaves as documented.  No device calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ib.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ib_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_2012_06646_amd import ibops
+    return ibops
+
+
+def test_library_exports_every_declared_function(ib):
+    names = declared_functions()
+    assert "ib_spread" in names and "ib_plan_create" in names
+    for name in names:
+        assert hasattr(ib._lib, name), f"{name} declared in include/ib.h but not exported"
+    assert set(ib.EXPORTED) <= set(names)
+
+
+def test_status_strings(ib):
+    for code in (0, -1, -2, -3, -4, -5, -6, 1):
+        assert ib._lib.ib_status_string(code)
+
+
+def test_workspace_bytes_and_validation(ib):
+    from paper_2012_06646_amd import workloads as wl
+    import torch
+    g = wl.grid(3, 128, 1.0)
+    nb = ib.workspace_bytes(g, torch.float64, 10**6)
+    # keys, two key/value pairs, run offsets: at least 6 int32 per point per staggering
+    assert nb >= 3 * 6 * 4 * 10**6
+    assert ib.workspace_bytes(g, torch.float64, 0) > 0
+    bad = wl.grid(3, [3, 8, 8], 1.0)  # fewer than 4 cells
+    assert ib.workspace_bytes(bad, torch.float64, 10) == 0
+    d = ib.make_desc(g)
+    h = ctypes.c_void_p()
+    # unaligned workspace pointer -> IB_ERR_ARG; too small -> IB_ERR_OOM (no device access)
+    assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 100, ctypes.c_void_p(4096 + 8), 1 << 30,
+                                  ctypes.byref(h)) == -1
+    assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 100, ctypes.c_void_p(4096), 16,
+                                  ctypes.byref(h)) == -2
+    d.kernel = 7
+    assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 100, ctypes.c_void_p(4096), 1 << 30,
+                                  ctypes.byref(h)) == -4
+    d = ib.make_desc(g)
+    d.stagger[0][0] = 1.0  # staggering must lie in [0, 1)
+    assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 100, ctypes.c_void_p(4096), 1 << 30,
+                                  ctypes.byref(h)) == -1
+    d = ib.make_desc(g)
+    d.n[0], d.n[1], d.n[2] = 2048, 2048, 1024  # more than 2^31 - 1 cells
+    assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 100, ctypes.c_void_p(4096), 1 << 30,
+                                  ctypes.byref(h)) == -4
+
+
+def test_mac_grid_has_three_staggers_collocated_one(ib):
+    from paper_2012_06646_amd import workloads as wl
+    h = ctypes.c_void_p()
+    for g, expect in ((wl.grid(3, 16, 1.0), 3), (wl.grid(2, 16, 1.0, stagger=[[.5, .5], [.5, .5]]), 1)):
+        d = ib.make_desc(g)
+        nb = ib._lib.ib_plan_workspace_bytes(ctypes.byref(d), 0, 1000)
+        # creation touches no device memory, so a fake aligned address is fine here
+        assert ib._lib.ib_plan_create(ctypes.byref(d), 0, 1000, ctypes.c_void_p(1 << 20), nb,
+                                      ctypes.byref(h)) == 0
+        assert ib._lib.ib_plan_num_staggers(h) == expect
+        ib._lib.ib_plan_destroy(h)

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Keys, sorted keys, permutations, run offsets and q must be bit-exact.  Spread and
+interpolated values must match the FP64 oracle to 1e-12 (FP64) or 2e-6 (FP32) in the
+normwise sense ||gpu - oracle||_inf / ||oracle||_inf; cases built from exactly
+representable data must match bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2012_06646_amd import workloads as wl
+from tests.gpu_util import TOL, normwise, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_06646_amd import ibops
+    return ibops
+
+
+def _prec(dtype):
+    return "f32" if dtype == torch.float32 else "f64"
+
+
+def _np_dtype(dtype):
+    return np.float32 if dtype == torch.float32 else np.float64
+
+
+def check_plan(ib, orc, g, X, dtype, label):
+    say(f"plan {label} n={X.shape[0]} grid={g['n']} dtype={dtype}")
+    p = ib.Plan(g, X.shape[0], dtype)
+    Xd = to_dev(X, dtype)
+    p.update(Xd)
+    assert p.status() == 0
+    Xh = np.asarray(X, dtype=_np_dtype(dtype)).astype(np.float64)
+    for c in range(len(g["stagger"])):
+        sid = p.stagger_of(c)
+        got = p.export(sid)
+        k_ref, bad = orc.keys(g, Xh, g["stagger"][c], _prec(dtype))
+        assert bad == 0
+        sk_ref, perm_ref, seg_ref, q_ref = orc.plan(k_ref)
+        assert np.array_equal(to_host(got["keys"]), k_ref), f"keys differ ({label}, comp {c})"
+        assert np.array_equal(to_host(got["sorted_keys"]), sk_ref)
+        assert np.array_equal(to_host(got["perm"]), perm_ref), f"perm differs ({label}, comp {c})"
+        assert got["q"] == q_ref
+        assert np.array_equal(to_host(got["seg_off"]), seg_ref)
+    return p
+
+
+def check_ops(ib, orc, g, X, F, u, dtype, label, tier=1):
+    say(f"ops {label} n={X.shape[0]} grid={g['n']} dtype={dtype}")
+    nd = _np_dtype(dtype)
+    Xc, Fc, uc = (np.asarray(a, dtype=nd) for a in (X, F, u))
+    p = ib.Plan(g, X.shape[0], dtype).update(to_dev(Xc, dtype))
+    f = to_host(p.spread(to_dev(Fc, dtype)))
+    U = to_host(p.interpolate(to_dev(uc, dtype)))
+    assert p.status() == 0
+    f_ref = orc.spread(g, Xc.astype(np.float64), Fc.astype(np.float64), tier=tier)
+    U_ref = orc.interp(g, Xc.astype(np.float64), uc.astype(np.float64), tier=tier)
+    ef, eU = normwise(f, f_ref), normwise(U, U_ref)
+    say(f"   spread err {ef:.3e}  interp err {eU:.3e}")
+    assert ef <= TOL[dtype], f"spread {label}: {ef}"
+    assert eU <= TOL[dtype], f"interp {label}: {eU}"
+    return p, f, U
+
+
+# ---- plans ----------------------------------------------------------------------------
+
+def test_plan_config1(ib, orc):
+    g, X, F, u = wl.config1()
+    check_plan(ib, orc, g, X, torch.float64, "config1")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("npts", [0, 1, 63, 4095, 4096, 4097, 20011])
+def test_plan_ragged_sizes(ib, orc, dtype, npts):
+    g = wl.grid(3, [24, 20, 16], [1.0, 0.9, 0.7])
+    X = wl.uniform_case(g, npts, 100 + npts)[0]
+    check_plan(ib, orc, g, X, dtype, f"ragged{npts}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_plan_degenerate_layouts(ib, orc, dtype):
+    r = wl.rng(5)
+    g = wl.grid(3, [4, 4, 4], [1.0, 1.0, 1.0])
+    X = np.tile(np.array([[0.3, 0.3, 0.3]]), (9000, 1))  # every point in one cell
+    check_plan(ib, orc, g, X, dtype, "one-cell")
+    g = wl.grid(3, [16, 12, 8], [2.0, 1.5, 1.0])
+    X = r.uniform(-5.0, 7.0, (6000, 3))  # far outside the box, both sides
+    X[:500] = np.round(X[:500] * 8.0) / 8.0  # exactly on cell faces
+    check_plan(ib, orc, g, X, dtype, "outside-box")
+
+
+def test_plan_non_power_of_two_scale_fp32(ib, orc):
+    """n/L = 96: the scaled coordinate is rounded, and the key follows that rounding."""
+    g = wl.grid(3, 96, 1.0)
+    X = wl.uniform_case(g, 50000, 96)[0]
+    check_plan(ib, orc, g, X, torch.float32, "96^3 fp32")
+
+
+def test_plan_2d_and_collocated(ib, orc):
+    g = wl.grid(2, [40, 28], [1.0, 0.7], stagger=[[0.5, 0.5], [0.5, 0.5]])
+    X = wl.uniform_case(g, 7000, 7)[0]
+    p = check_plan(ib, orc, g, X, torch.float64, "2d-collocated")
+    assert p.nstag == 1
+
+
+# ---- operators -------------------------------------------------------------------------
+
+def test_ops_config1(ib, orc):
+    g, X, F, u = wl.config1()
+    check_ops(ib, orc, g, X, F, u, torch.float64, "config1", tier=0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ops_3d_mac_several_tiles(ib, orc, dtype):
+    g = wl.grid(3, [72, 40, 30], [1.0, 0.6, 0.5])  # ragged tiles in every dimension
+    X, F, u = wl.uniform_case(g, 40000, 21)
+    check_ops(ib, orc, g, X, F, u, dtype, "72x40x30 MAC")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ops_small_grids_and_wrap(ib, orc, dtype):
+    g = wl.grid(3, [4, 5, 6], [1.0, 1.25, 1.5])  # grid smaller than a tile: stencils wrap
+    r = wl.rng(22)
+    X = r.uniform(-2, 3, (3000, 3))
+    F = r.standard_normal((3000, 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    check_ops(ib, orc, g, X, F, u, dtype, "4x5x6 wrap", tier=0)
+
+
+def test_ops_clustered_points(ib, orc):
+    """Many points per cell (long runs) and empty regions."""
+    g = wl.grid(3, [32, 32, 32], 1.0)
+    r = wl.rng(23)
+    centres = r.random((20, 3))
+    X = (centres[r.integers(0, 20, 30000)] + 0.01 * r.standard_normal((30000, 3))) % 1.0
+    F = r.standard_normal((30000, 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    check_ops(ib, orc, g, X, F, u, torch.float64, "clustered")
+
+
+def test_ops_2d(ib, orc):
+    g = wl.grid(2, [100, 36], [2.0, 0.72])
+    X, F, u = wl.uniform_case(g, 9000, 24)
+    check_ops(ib, orc, g, X, F, u, torch.float64, "2d MAC")
+
+
+def test_ops_empty_point_set(ib, orc):
+    g = wl.grid(3, 16, 1.0)
+    p = ib.Plan(g, 0, torch.float64).update(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
+    f = p.spread(torch.empty((0, 3), dtype=torch.float64, device="cuda"))
+    assert float(f.abs().max()) == 0.0
+    U = p.interpolate(torch.randn(p.grid_shape, dtype=torch.float64, device="cuda"))
+    assert U.shape == (0, 3)
+
+
+def test_ops_cosine_kernel(ib, orc):
+    g = wl.grid(3, [20, 16, 12], 1.0, kernel="cosine4")
+    X, F, u = wl.uniform_case(g, 8000, 25)
+    check_ops(ib, orc, g, X, F, u, torch.float64, "cosine")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_dyadic_case_is_bit_exact(ib, orc, dtype):
+    """Points on a component's nodes with small-integer forces: every weight product and
+    every partial sum is exact, so the GPU must equal the oracle bit for bit."""
+    g = wl.grid(3, [16, 16, 16], 1.0, stagger=[[0.5, 0.5, 0.5]])
+    r = wl.rng(26)
+    idx = r.integers(0, 16, (5000, 3))
+    X = (idx + 0.5) / 16.0
+    F = r.integers(-4, 5, (5000, 1)).astype(np.float64)
+    u = r.integers(-4, 5, wl.grid_shape(g)).astype(np.float64)
+    nd = _np_dtype(dtype)
+    p = ib.Plan(g, 5000, dtype).update(to_dev(X.astype(nd), dtype))
+    f = to_host(p.spread(to_dev(F.astype(nd), dtype))).astype(np.float64)
+    U = to_host(p.interpolate(to_dev(u.astype(nd), dtype))).astype(np.float64)
+    assert np.array_equal(f, orc.spread(g, X, F))
+    assert np.array_equal(U, orc.interp(g, X, u))
+
+
+def test_spread_accumulate_flag(ib, orc):
+    g = wl.grid(3, [16, 12, 20], 1.0)
+    X, F, u = wl.uniform_case(g, 5000, 27)
+    p = ib.Plan(g, 5000, torch.float64).update(to_dev(X, torch.float64))
+    base = to_dev(u, torch.float64)
+    f = p.spread(to_dev(F, torch.float64), f=base.clone(), accumulate=True)
+    ref = orc.spread(g, X, F) + u
+    assert normwise(to_host(f), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bitwise_run_to_run(ib, dtype):
+    g = wl.grid(3, [64, 48, 40], 1.0)
+    X, F, u = wl.uniform_case(g, 100000, 28)
+    say(f"determinism dtype={dtype}")
+    p = ib.Plan(g, X.shape[0], dtype)
+    Xd, Fd, ud = to_dev(X, dtype), to_dev(F, dtype), to_dev(u, dtype)
+    outs = []
+    for _ in range(4):
+        p.update(Xd)
+        outs.append((to_host(p.spread(Fd)), to_host(p.interpolate(ud))))
+    for f, U in outs[1:]:
+        assert np.array_equal(f, outs[0][0]) and np.array_equal(U, outs[0][1])
+
+
+# ---- the 128^3 / 10^6-point workload at full size ----------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_config2_full_size(ib, orc, dtype):
+    g, X, F, u = wl.config2()
+    nd = _np_dtype(dtype)
+    Xc = X.astype(nd)
+    check_plan(ib, orc, g, Xc, dtype, "config2")
+    check_ops(ib, orc, g, X, F, u, dtype, "config2")

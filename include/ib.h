@@ -121,6 +121,13 @@ int32_t ib_spread(ib_plan plan, const void *F, void *f, int32_t accumulate, void
  * device; U (npts x ncomp) device, overwritten. */
 int32_t ib_interpolate(ib_plan plan, const void *u, void *U, void *stream);
 
+/* Position update of the IB time step, steps (b)/(g) of Sec. 2 with the interpolated
+ * velocity: X <- X + dt * U, each coordinate wrapped back into [0, length_k).  X (npts x dim)
+ * device, updated in place; U (npts x ncomp) device with ncomp == dim; grid supplies dim and
+ * the box.  Errors: IB_ERR_ARG. */
+int32_t ib_advect(const ib_grid_desc *grid, int32_t dtype, int64_t npts, void *X, const void *U,
+                  double dt, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

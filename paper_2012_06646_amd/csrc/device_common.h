@@ -106,23 +106,49 @@ __device__ __forceinline__ void weights4(T r, T w[4])
         w[2] = q + q * s;
         w[3] = q - q * c;
     } else {
-        // Peskin 4-point: with s = sqrt(1 + 4r - 4r^2), phi(-1-r) = (1-r)^2 / (3 - 2r + s),
-        // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = r^2 / (1 + 2r + s).
+        // Peskin 4-point, with s = sqrt(1 + 4r - 4r^2): phi(-1-r) = (3 - 2r - s)/8,
+        // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = (1 + 2r - s)/8.
+        // The two differences lose relative (not absolute) accuracy when a weight is
+        // tiny, which leaves every weighted sum accurate to working precision.
         const T s = sqrt(T(1) + T(4) * r * (T(1) - r));
-        const T a = T(3) - T(2) * r + s;
-        const T b = T(1) + T(2) * r + s;
-        const T om = T(1) - r;
-        w[0] = om * om / a;
-        w[1] = a * T(0.125);
-        w[2] = b * T(0.125);
-        w[3] = r * r / b;
+        const T a = T(3) - T(2) * r;
+        const T b = T(1) + T(2) * r;
+        w[0] = (a - s) * T(0.125);
+        w[1] = (a + s) * T(0.125);
+        w[2] = (b + s) * T(0.125);
+        w[3] = (b - s) * T(0.125);
     }
 }
 
-__device__ __forceinline__ int emod(int a, int n)
+// a mod n for a in [-n, 2n) (unwrapped tile and halo coordinates), without division.
+__device__ __forceinline__ int wrap_small(int a, int n)
 {
-    int m = a % n;
-    return m < 0 ? m + n : m;
+    a = a < 0 ? a + n : a;
+    return a >= n ? a - n : a;
+}
+
+// Euclidean floor(y) mod n for |y| < 2^30: double arithmetic on exact integers, with a
+// one-step correction of the quotient.
+__device__ __forceinline__ int floor_mod(double fy, int n, double inv_n)
+{
+    const double q = floor(fy * inv_n);
+    double c = fy - q * (double)n;
+    c = c < 0.0 ? c + (double)n : c;
+    c = c >= (double)n ? c - (double)n : c;
+    return (int)c;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, FastDiv f)
+{
+    return (uint32_t)(((uint64_t)x * f.m) >> f.s);
+}
+
+// Flat index of the cell-block table entry of a key (row * (nbx + 1) + cx / 4).
+__device__ __forceinline__ int64_t cblk_index(int32_t key, const GeomArgs& g)
+{
+    const uint32_t row = fdiv((uint32_t)key, g.div_n0);
+    const int cx = key - (int)row * g.n[0];
+    return (int64_t)row * (g.nbx + 1) + (cx >> CBLK_SHIFT);
 }
 
 }  // namespace ibk

@@ -21,6 +21,7 @@ struct ib_plan_s {
     const void* X;         // positions of the last update
     hipStream_t last_stream;
     int updated;
+    uint32_t sorted_mask;  // staggerings sorted since the last update
 };
 
 namespace {
@@ -37,10 +38,10 @@ int bits_for(int64_t G)
 }
 
 struct Layout {
-    int nstag, npass, rbits, rows;
+    int nstag, npass, rbits, rows, nbx;
     int64_t ntiles, nseg_tiles, G;
     // byte offsets
-    size_t keys0, kA, vA, kB, vB, row_start, seg_off, q, zero_begin, hist, sort_status,
+    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, zero_begin, hist, sort_status,
         seg_status, counters, flag, zero_end, total;
 };
 
@@ -84,12 +85,13 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     return IB_OK;
 }
 
-void make_layout(const ib_grid_desc* g, int nstag, int64_t n, Layout* L)
+void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L)
 {
     L->nstag = nstag;
     L->G = 1;
     for (int k = 0; k < g->dim; ++k) L->G *= g->n[k];
     L->rows = (int)(L->G / g->n[0]);
+    L->nbx = (g->n[0] + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT;
     const int bits = bits_for(L->G);
     L->npass = (bits + MAX_RADIX_BITS - 1) / MAX_RADIX_BITS;
     L->rbits = (bits + L->npass - 1) / L->npass;
@@ -109,21 +111,35 @@ void make_layout(const ib_grid_desc* g, int nstag, int64_t n, Layout* L)
     L->vA = take(kn);
     L->kB = take(kn);
     L->vB = take(kn);
-    L->row_start = take((size_t)nstag * (L->rows + 1) * sizeof(int32_t));
+    L->cblk = take((size_t)nstag * L->rows * (L->nbx + 1) * sizeof(int32_t));
     L->seg_off = take((size_t)nstag * (size_t)(n + 1) * sizeof(int32_t));
     L->q = take((size_t)nstag * sizeof(int32_t));
+    const size_t b = dtype == IB_F64 ? 8 : 4;
+    L->Xs = take((size_t)n * g->dim * b);
+    L->Fs = take((size_t)n * g->ncomp * b);
     // Everything from here to zero_end is cleared at every update.
     L->zero_begin = off;
     L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
     L->sort_status = take((size_t)L->npass * nstag * L->ntiles * R * sizeof(uint32_t));
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
-    L->counters = take((size_t)(L->npass + 1) * sizeof(uint32_t));
+    L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
     L->zero_end = off;
     L->total = off;
 }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? IB_OK : IB_ERR_HIP; }
+
+FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    FastDiv f;
+    f.d = d;
+    f.s = 31 + l;
+    f.m = (uint32_t)(((uint64_t(1) << f.s) + d - 1) / d);
+    return f;
+}
 
 }  // namespace
 
@@ -150,7 +166,7 @@ size_t ib_plan_workspace_bytes(const ib_grid_desc* grid, int32_t dtype, int64_t 
     double sx[3][3];
     if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
     Layout L;
-    make_layout(grid, nstag, npts, &L);
+    make_layout(grid, dtype, nstag, npts, &L);
     return L.total;
 }
 
@@ -164,7 +180,7 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
     if (st != IB_OK) return st;
     Layout L;
-    make_layout(grid, nstag, npts, &L);
+    make_layout(grid, dtype, nstag, npts, &L);
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
     if (workspace_bytes < L.total) return IB_ERR_OOM;
 
@@ -179,6 +195,8 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     g.ncomp = grid->ncomp;
     g.nstag = nstag;
     g.rows = L.rows;
+    g.nbx = L.nbx;
+    g.div_n0 = make_fastdiv((uint32_t)grid->n[0]);
     g.npts = npts;
     double hd = 1.0;
     for (int k = 0; k < 3; ++k) {
@@ -189,6 +207,7 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
             continue;
         }
         const double N = grid->n[k], Lk = grid->length[k];
+        g.inv_n[k] = 1.0 / N;
         g.inv_h_d[k] = N / Lk;
         g.inv_lo_d[k] = (double)((long double)N / (long double)Lk - (long double)g.inv_h_d[k]);
         g.inv_h_f[k] = (float)grid->n[k] / (float)grid->length[k];
@@ -198,7 +217,13 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     g.scale = 1.0 / hd;
     for (int c = 0; c < grid->ncomp; ++c) {
         g.comp_stag[c] = cs[c];
-        for (int k = 0; k < 3; ++k) g.comp_xi[c][k] = k < grid->dim ? grid->stagger[c][k] : 0.0;
+        for (int k = 0; k < 3; ++k) {
+            g.comp_xi[c][k] = k < grid->dim ? grid->stagger[c][k] : 0.0;
+            // floor(t - xi_c) - floor(t - xi_0) lies in [dlo, dhi]
+            const double d = k < grid->dim ? grid->stagger[0][k] - grid->stagger[c][k] : 0.0;
+            g.dlo[c][k] = d < 0.0 ? -1 : 0;
+            g.dhi[c][k] = d > 0.0 ? 1 : 0;
+        }
     }
     for (int s = 0; s < nstag; ++s)
         for (int k = 0; k < 3; ++k) g.stag_xi[s][k] = sx[s][k];
@@ -210,9 +235,11 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     d.vA = (int32_t*)(base + L.vA);
     d.kB = (int32_t*)(base + L.kB);
     d.vB = (int32_t*)(base + L.vB);
-    d.row_start = (int32_t*)(base + L.row_start);
+    d.cblk = (int32_t*)(base + L.cblk);
     d.seg_off = (int32_t*)(base + L.seg_off);
     d.q = (int32_t*)(base + L.q);
+    d.Xs = base + L.Xs;
+    d.Fs = base + L.Fs;
     d.hist = (uint32_t*)(base + L.hist);
     d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
@@ -230,6 +257,7 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     p->X = nullptr;
     p->last_stream = nullptr;
     p->updated = 0;
+    p->sorted_mask = 0;
     *out = p;
     return IB_OK;
 }
@@ -247,11 +275,17 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     if (!p) return IB_ERR_ARG;
     if (!X && p->npts > 0) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
-    int32_t r = hip_status(launch_plan_update(p->sa, p->dtype, X, st));
+    hipError_t e = launch_plan_reset(p->sa, st);
+    if (e == hipSuccess) e = launch_keys(p->sa, p->dtype, X, st);
+    // The operators use the sort of staggering 0 (with the positions gathered into it);
+    // other staggerings are sorted when exported.
+    if (e == hipSuccess) e = launch_sort_stagger(p->sa, 0, p->dtype, X, true, st);
+    int32_t r = hip_status(e);
     if (r != IB_OK) return r;
     p->X = X;
     p->last_stream = st;
     p->updated = 1;
+    p->sorted_mask = 1u;
     return IB_OK;
 }
 
@@ -260,6 +294,11 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
 {
     if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
+    if (!(p->sorted_mask & (1u << sid))) {
+        int32_t r = hip_status(launch_sort_stagger(p->sa, sid, p->dtype, nullptr, false, st));
+        if (r != IB_OK) return r;
+        p->sorted_mask |= 1u << sid;
+    }
     const size_t n = (size_t)p->npts;
     const PlanDev& d = p->sa.d;
     hipError_t e = hipSuccess;
@@ -297,10 +336,12 @@ static void fill_op_args(ib_plan p, OpArgs* a)
 {
     std::memset(a, 0, sizeof *a);
     a->g = p->sa.g;
-    a->sorted_keys = p->sorted_keys;
+    a->sorted_keys = p->sorted_keys;  // staggering 0
     a->perm = p->perm;
-    a->row_start = p->sa.d.row_start;
+    a->cblk = p->sa.d.cblk;
     a->X = p->X;
+    a->Xs = p->sa.d.Xs;
+    a->Fs = p->sa.d.Fs;
 }
 
 int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
@@ -329,6 +370,19 @@ int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
     hipStream_t st = (hipStream_t)stream;
     p->last_stream = st;
     return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
+}
+
+int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X, const void* U,
+                  double dt, void* stream)
+{
+    int nstag, cs[3];
+    double sx[3][3];
+    int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
+    if (st != IB_OK) return st;
+    if (grid->ncomp != grid->dim || !std::isfinite(dt)) return IB_ERR_ARG;
+    if (npts > 0 && (!X || !U)) return IB_ERR_ARG;
+    return hip_status(launch_advect(grid->dim, grid->ncomp, npts, grid->length, dtype, X, U, dt,
+                                    (hipStream_t)stream));
 }
 
 }  // extern "C"

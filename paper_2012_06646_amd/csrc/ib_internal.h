@@ -8,9 +8,9 @@
 
 namespace ibk {
 
-// Sort configuration: 256-thread blocks, 16 keys per thread (one tile = 4096 keys).
+// Sort configuration: 256-thread blocks, SORT_IPT keys per thread.
 constexpr int SORT_BLOCK = 256;
-constexpr int SORT_IPT = 16;
+constexpr int SORT_IPT = 8;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
 constexpr int MAX_RADIX_BITS = 8;
 
@@ -31,26 +31,48 @@ struct PlanDev {
     int32_t* kB;
     int32_t* vB;
     uint32_t* hist;        // [nstag][npass][R] global digit counts
-    uint32_t* sort_status; // [npass][nstag * ntiles][R] look-back words
-    uint32_t* counters;    // [npass + 1] tile tickets (last one: segments kernel)
+    uint32_t* sort_status; // [nstag][npass][ntiles][R] look-back words
+    uint32_t* counters;    // [nstag][npass + 1] tile tickets (last: segments kernel)
     uint32_t* flag;        // device error flag
-    int32_t* row_start;    // [nstag][rows + 1]
+    int32_t* cblk;         // [nstag][rows * (nbx + 1)] cell-block start table (see GeomArgs)
     int32_t* seg_off;      // [nstag][n + 1]
     int32_t* q;            // [nstag]
-    uint32_t* seg_status;  // [nstag * nseg_tiles] look-back words
+    uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
+    void* Xs;              // [n][dim] positions in the sorted order of staggering 0
+    void* Fs;              // [n][ncomp] forces in that order (filled by each spread call)
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
 
+// Exact division of non-negative 31-bit integers by a fixed divisor d >= 1:
+// q = (n * m) >> s with s = 31 + ceil(log2 d) and m = ceil(2^s / d) (m < 2^32).
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
 // Geometry and per-call arguments passed by value to every kernel.
+//
+// Cell-block start table: each x-row of cells is cut into blocks of 4 cells; entry
+// (row r, block b), at flat index r * (nbx + 1) + b, holds the first sorted position whose
+// cell lies in row r at x >= 4 b (b = nbx: the start of the next row).  A sorted range of
+// cells [xa, xb) of one row is then bracketed in O(1) by entries xa / 4 and ceil(xb / 4).
+//
+// Staggering 0 (that of component 0) orders the points for spreading and interpolation.
+// For component c, cell_c - cell_0 lies in [dlo, dhi] per dimension (each in {-1, 0, 1}).
+constexpr int CBLK_SHIFT = 2;
 struct GeomArgs {
     int dim;
     int ncomp;
     int nstag;
     int n[3];
     int rows;              // n1 * n2 (3-D) or n1 (2-D): number of x-rows
+    int nbx;               // ceil(n0 / 4): cell blocks per x-row
+    FastDiv div_n0;        // division by n0 (key -> row)
+    double inv_n[3];       // 1 / n_k (periodic wrap of cell indices)
     int64_t npts;
     int comp_stag[3];      // component -> distinct-stagger index
+    int dlo[3][3];         // per component and dimension
+    int dhi[3][3];
     double inv_h_d[3];     // fl64(n_k / L_k) and its residual (n_k / L_k - inv_h_d)
     double inv_lo_d[3];
     float inv_h_f[3];      // fl32(n_k / L_k) and its residual
@@ -71,11 +93,13 @@ struct SortArgs {
 
 struct OpArgs {
     GeomArgs g;
-    const int32_t* sorted_keys;  // [nstag][n]
-    const int32_t* perm;         // [nstag][n]
-    const int32_t* row_start;    // [nstag][rows + 1]
-    const void* X;
+    const int32_t* sorted_keys;  // staggering 0: [n]
+    const int32_t* perm;         // staggering 0: [n]
+    const int32_t* cblk;         // staggering 0: [rows * (nbx + 1)]
+    const void* X;               // input order
+    const void* Xs;              // staggering-0 order
     const void* F;
+    void* Fs;
     void* f;
     const void* u;
     void* U;
@@ -84,8 +108,15 @@ struct OpArgs {
 };
 
 // Host launchers (stream-ordered; return hipError_t).
-hipError_t launch_plan_update(const SortArgs& a, int dtype, const void* X, hipStream_t st);
+hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st);
+hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st);
+// Sort staggering s, build its segments and cell-block table; with gather_x, also write
+// the positions in that order (used for staggering 0 only).
+hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,
+                               hipStream_t st);
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st);
 hipError_t launch_interp(const OpArgs& a, int dtype, int kernel, hipStream_t st);
+hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
+                         void* X, const void* U, double dt, hipStream_t st);
 
 }  // namespace ibk

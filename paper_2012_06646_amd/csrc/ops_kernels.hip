@@ -1,29 +1,35 @@
 // Spreading and interpolation kernels.
 //
+// Both operators visit the points in the sorted order of staggering 0 (the staggering of
+// component 0): the plan stores the positions in that order, each spread call first
+// gathers the forces into it, and interpolation writes each point's values once.  So the
+// only scattered memory accesses per call are one gather of F (spreading) and one scatter
+// of U (interpolation); everything else streams.  A point's cell for component c differs
+// from its staggering-0 cell by at most one per dimension, so the tiles below widen their
+// halos by that offset.
+//
 // Spreading (eq. disc-spread, Sec. 2; parallel algorithm Alg. 4, Sec. 3.3).  Each block
 // owns a tile of one component's grid and produces every value of it exactly once.  It
-// reads the sorted points whose cells lie in the tile grown by the stencil reach (cells
-// x0-2 .. x0+ext+1 per dimension; contiguous sorted ranges per x-row because keys are
-// x-fastest).  Within a wave, each lane takes one run of equal keys -- one occupied cell --
-// and reduces the contributions of all its points to the 4^d shifts in registers (the
-// segmented reduce of Alg. 4 for all shifts at once).  Lanes of one wave hold distinct
-// cells, so for any shift their targets differ and the 4^d read-add-writes into the LDS
-// tile never collide.  The four waves of a block work on source slices (planes in 3-D,
-// rows in 2-D) whose indices differ by multiples of 4, so their targets are disjoint; the
-// slices are visited in 4 phases separated by barriers.  The order in which every grid
-// value receives its contributions is therefore fixed by the data alone: no atomics, and
-// the result is bitwise reproducible.
+// reads the sorted points whose cells can reach the tile (contiguous sorted ranges per
+// x-row, since keys are x-fastest).  A wave takes 64 consecutive points, computes their
+// weights, then sorts the 64 lanes by component-c cell (a bitonic network across the
+// wave), so equal cells form runs; the first lane of each run sums the run's
+// contributions to all 4^d shifts in registers -- the segmented reduce of Alg. 4, for all
+// shifts at once.  Run heads of one wave hold distinct cells, so for any shift their
+// targets differ and the read-add-writes into the LDS tile never collide.  The waves of a
+// block take source slices (planes in 3-D, rows in 2-D) far enough apart that their
+// targets are disjoint, in phases separated by barriers.  The order in which every grid
+// value receives its contributions is fixed by the data alone: no atomics, and the result
+// is bitwise reproducible.
 //
-// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  Each block owns a tile of cells of
-// one component, stages the grid values of the tile plus its stencil halo in LDS with
-// coalesced loads, and gives one thread to each sorted point in those cells; the thread
-// accumulates the 4^d products in registers in tensor-product order and writes its value.
+// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  Each block owns a tile of
+// staggering-0 cells; for each component in turn it stages that component's grid values
+// over the tile plus halo in LDS with coalesced loads; one thread per point accumulates
+// the 4^d products in registers in tensor-product order, and finally writes all of the
+// point's components together.
 #include "device_common.h"
 
 namespace ibk {
-
-template <typename T>
-__device__ __forceinline__ T ld(const void* p, int64_t i) { return ((const T*)p)[i]; }
 
 // Point index from a permutation entry, kept inside [0, n) so that no data can steer a
 // load or store out of bounds (a valid permutation is never changed by this).
@@ -32,101 +38,95 @@ __device__ __forceinline__ int64_t clamp_index(int32_t p, int64_t n)
     return (uint32_t)p < (uint64_t)n ? (int64_t)p : 0;
 }
 
-// First position in sk[lo, hi) whose key is >= v (keys ascending).
-__device__ __forceinline__ int64_t lower_bound_key(const int32_t* __restrict__ sk, int64_t lo,
-                                                   int64_t hi, int32_t v)
-{
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (sk[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Fractional offsets of point p for component c and the 1-D weights per dimension.
+// Weights of a point at coordinates x for component c, and the offset of its component-c
+// cell from its staggering-0 cell per dimension.  The cells follow the key rule exactly
+// (t = x * inv_h rounded once, minus the staggering, floored).
 template <typename T, int DIM, int KERN>
-__device__ __forceinline__ void point_weights(const GeomArgs& g, int c, const T* __restrict__ X,
-                                              int64_t p, T w[DIM][4])
+__device__ __forceinline__ void comp_weights(const GeomArgs& g, int c, const T x[DIM],
+                                             T w[DIM][4], int delta[DIM])
 {
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const T x = X[p * DIM + k];
         const T ih = Prec<T>::inv_h(g, k);
-        const T y = shifted_scaled<T>(x, ih, (T)g.comp_xi[c][k]);
-        T r = y - floor(y);
-        r += product_residual<T>(x, ih, Prec<T>::inv_lo(g, k));
+        const T yc = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
+        const T fc = floor(yc);
+        const T y0 = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
+        delta[k] = min(max((int)(fc - floor(y0)), g.dlo[c][k]), g.dhi[c][k]);
+        T r = yc - fc;
+        r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
         weights4<T, KERN>(r, w[k]);
     }
 }
 
-// ---------------------------------------------------------------------------------------
-// Spreading
-// ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-// A source slice (an x-y plane of cells in 3-D, one x-row in 2-D) as a list of sorted
-// ranges: one per x-row piece (at most 3 pieces per row, since a tile is never wider than
-// the grid).  Each range carries the unwrapped tile offsets of its cells.
+// ---------------------------------------------------------------------------------------
+// Spreading
+// ---------------------------------------------------------------------------------------
+
+// A source slice (an x-y plane of staggering-0 cells in 3-D, one x-row in 2-D) as a list
+// of sorted ranges, one per x-row piece (at most 3 pieces per row, since a tile is never
+// wider than the grid).  A range may include a few points of neighbouring cells (the
+// cell-block table brackets ranges in blocks of 4 cells); such points map outside the
+// tile and are dropped.
 template <int MAXR>
 struct SliceTable {
     int32_t lo[MAXR];
     int32_t hi[MAXR];
-    int32_t xoff[MAXR];   // unwrapped x position (relative to x0 - 2) = key % n0 + xoff
-    int32_t uy[MAXR];     // unwrapped y position relative to y0 - 2
+    int32_t xo[MAXR];     // source-frame x of a key: key + xo
+    int32_t uy[MAXR];     // source-frame y of the row
     int32_t pref[MAXR + 1];
 };
 
+constexpr uint32_t NO_CELL = 0xFFFFFFu;
+
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 struct SpreadTile {
-    static constexpr int NZ = (DIM == 3) ? 4 : 1;          // stencil extent in z
-    static constexpr int MAXROWS = (DIM == 3) ? TY + 3 : 1; // x-rows per slice
+    static constexpr int PXS = TX + 6;  // padded row pitch of the LDS tile (x from -3 to TX + 2)
+    static constexpr int NZ = (DIM == 3) ? 4 : 1;            // stencil extent in z
+    static constexpr int MAXROWS = (DIM == 3) ? TY + 5 : 1;   // x-rows per slice
     static constexpr int MAXR = 3 * MAXROWS;
     using Table = SliceTable<MAXR>;
 
-    // Build the range table of slice (cz or cy) for this wave; returns the point count.
-    __device__ static int build(const OpArgs& a, const int32_t* __restrict__ sk,
-                                const int32_t* __restrict__ rs, int qslice, int x0, int y0,
-                                int z0, int ex, int ey, Table& tb)
+    // Range table of source slice q (frame origin ox, oy, oz; lenx cells per row, nrows
+    // rows); returns the slice's point count.
+    __device__ static int build(const GeomArgs& g, const int32_t* __restrict__ cb, int q, int ox,
+                                int oy, int oz, int lenx, int nrows, Table& tb)
     {
-        const GeomArgs& g = a.g;
         const int lane = lane_id();
         const int n0 = g.n[0];
-        const int nrows = (DIM == 3) ? ey + 3 : 1;
         int count = 0;
         if (lane < nrows) {
-            int cy, r, uy;
+            int r, uy;
             if (DIM == 3) {
-                const int cz = emod(z0 - 2 + qslice, g.n[2]);
+                const int cz = wrap_small(oz + q, g.n[2]);
                 uy = lane;
-                cy = emod(y0 - 2 + lane, g.n[1]);
-                r = cz * g.n[1] + cy;
+                r = cz * g.n[1] + wrap_small(oy + lane, g.n[1]);
             } else {
-                uy = qslice;
-                cy = emod(y0 - 2 + qslice, g.n[1]);
-                r = cy;
+                uy = q;
+                r = wrap_small(oy + q, g.n[1]);
             }
-            const int32_t rlo = rs[r], rhi = rs[r + 1];
+            const int64_t rb = (int64_t)r * (g.nbx + 1);
             const int32_t rowbase = r * n0;
-            const int total = ex + 3;
             int done = 0;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
-                int32_t lo = 0, hi = 0, xoff = 0;
-                if (done < total && rlo < rhi) {
-                    const int xa = emod(x0 - 2 + done, n0);
-                    const int len = min(total - done, n0 - xa);
-                    lo = (int32_t)lower_bound_key(sk, rlo, rhi, rowbase + xa);
-                    hi = (int32_t)lower_bound_key(sk, lo, rhi, rowbase + xa + len);
-                    xoff = done - xa;
+                int32_t lo = 0, hi = 0, xo = 0;
+                if (done < lenx) {
+                    const int xa = wrap_small(ox + done, n0);
+                    const int len = min(lenx - done, n0 - xa);
+                    lo = cb[rb + (xa >> CBLK_SHIFT)];
+                    hi = cb[rb + ((xa + len + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT)];
+                    xo = done - xa - rowbase;
                     done += len;
                 }
                 tb.lo[lane * 3 + k] = lo;
                 tb.hi[lane * 3 + k] = hi;
-                tb.xoff[lane * 3 + k] = xoff;
+                tb.xo[lane * 3 + k] = xo;
                 tb.uy[lane * 3 + k] = uy;
                 count += hi - lo;
             }
@@ -134,6 +134,7 @@ struct SpreadTile {
         const uint32_t incl = wave_incl_scan_u32((uint32_t)count);
         if (lane < nrows) {
             int run = (int)incl - count;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 tb.pref[lane * 3 + k] = run;
                 run += tb.hi[lane * 3 + k] - tb.lo[lane * 3 + k];
@@ -145,20 +146,113 @@ struct SpreadTile {
         return total_pts;
     }
 
-    // Reduce every run of equal keys of the slice in registers (one lane per run) and add
-    // the 4^d sums into the tile.  uz: the slice's unwrapped z offset (3-D).
+    __device__ static void accumulate(T acc[NZ][4][4], const T w[DIM][4])
+    {
+#pragma unroll
+        for (int iz = 0; iz < NZ; ++iz)
+#pragma unroll
+            for (int iy = 0; iy < 4; ++iy) {
+                const T cyz = (DIM == 3) ? w[1][iy] * w[2][iz] : w[1][iy];
+#pragma unroll
+                for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = fma(w[0][ix], cyz, acc[iz][iy][ix]);
+            }
+    }
+
+    static constexpr int bits_for(int v) { return v <= 1 ? 1 : 1 + bits_for((v + 1) / 2); }
+    static constexpr int XB = bits_for(TX + 6);
+    static constexpr int YB = bits_for(TY + 6);
+    static constexpr int ZB = (DIM == 3) ? bits_for(TZ + 6) : 0;
+    static constexpr int CB = XB + YB + ZB;
+    static_assert(CB <= 24, "cell code too wide");
+
+    // Lanes holding the same (tile-relative) cell as this lane, by matching the cell code
+    // bit by bit with ballots; lanes without a cell match nothing.
+    __device__ static unsigned long long match_code(uint32_t code, bool has)
+    {
+        unsigned long long m = __ballot(has);
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const bool bit = (code >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        return has ? m : 0ull;
+    }
+
+    // Add a leader's 4^d sums into the tile.  For one shift the leaders of a wave hit
+    // distinct targets, but for different shifts they may not, so each read-add-write must
+    // complete before the next shift's read -- except for shifts whose slice-axis offsets
+    // (z in 3-D, y in 2-D) differ by more than `span`, the largest difference between the
+    // leaders' cells along that axis: those never share a target and go in one batch.
+    // Add a leader's 4^d sums into the tile.  The tile rows are padded in x (PXS = TX + 6,
+    // target x from -3 to TX + 2), so only whole rows can fall outside the tile; such rows,
+    // and every row of a lane that is not a leader, go to the lane's own dummy row.
+    // For one shift the leaders of a wave hit distinct targets, but for different shifts
+    // they may not, so each read-add-write must complete before the next shift's read --
+    // except for shifts whose slice-axis offsets (z in 3-D, y in 2-D) differ by more than
+    // `span`, the largest difference between the leaders' cells along that axis: those
+    // never share a target and go in one batch.
+    __device__ static void add_to_tile(const T acc[NZ][4][4], bool leader, int cx, int cy,
+                                       int cz, int ey, int ez, int span, T* drow, T* tile)
+    {
+        // Row pointer for (slice-axis offset ia, in-plane offset ib).
+        T* rowp[4][4];
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                int ty, tz;
+                if (DIM == 3) { tz = cz - 1 + ia; ty = cy - 1 + ib; }
+                else { tz = 0; ty = cy - 1 + ia; }
+                const bool ok = leader && (unsigned)ty < (unsigned)ey && (unsigned)tz < (unsigned)ez &&
+                                (DIM == 3 || ib == 0);
+                rowp[ia][ib] = ok ? tile + (tz * TY + ty) * PXS + (cx + 2) : drow;
+            }
+        constexpr int NB = (DIM == 3) ? 4 : 1;
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib) {
+#pragma unroll
+            for (int ix = 0; ix < 4; ++ix) {
+                T val[4];
+#pragma unroll
+                for (int ia = 0; ia < 4; ++ia) val[ia] = (DIM == 3) ? acc[ia][ib][ix] : acc[0][ia][ix];
+                if (span == 0) {
+                    T old[4];
+#pragma unroll
+                    for (int ia = 0; ia < 4; ++ia) old[ia] = rowp[ia][ib][ix];
+#pragma unroll
+                    for (int ia = 0; ia < 4; ++ia) rowp[ia][ib][ix] = old[ia] + val[ia];
+                } else if (span == 1) {  // pairs (-1, +1) and (0, +2) along the slice axis
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const T o0 = rowp[h][ib][ix], o1 = rowp[h + 2][ib][ix];
+                        rowp[h][ib][ix] = o0 + val[h];
+                        rowp[h + 2][ib][ix] = o1 + val[h + 2];
+                    }
+                } else {
+#pragma unroll
+                    for (int ia = 0; ia < 4; ++ia) rowp[ia][ib][ix] = rowp[ia][ib][ix] + val[ia];
+                }
+            }
+        }
+    }
+
+    // Reduce the slice in chunks of 64 points and add the sums into the tile.
+    // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
+    // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
+    // group; its lowest lane (the leader) sums the group's contributions to all 4^d shifts
+    // in registers, pulling each member's offsets and force from the member's lane.
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
-                                  const int32_t* __restrict__ perm, const Table& tb,
-                                  int nranges, int total, int uz, int ex, int ey, int ez,
+                                  const Table& tb, int nranges, int total, int q, const int off[3],
+                                  int ex, int ey, int ez, bool same0, int span, T* drow,
                                   T* tile)
     {
         const GeomArgs& g = a.g;
-        const T* __restrict__ X = (const T*)a.X;
-        const T* __restrict__ F = (const T*)a.F;
+        const T* __restrict__ Xs = (const T*)a.Xs;
+        const T* __restrict__ Fs = (const T*)a.Fs;
         const int lane = lane_id();
-        const int n0 = g.n[0];
-        int v0 = 0;
-        while (v0 < total) {
+        const unsigned long long below = (1ull << lane) - 1ull;
+        for (int v0 = 0; v0 < total; v0 += 64) {
             const int v = v0 + lane;
             const bool valid = v < total;
             int rr = 0;
@@ -171,11 +265,53 @@ struct SpreadTile {
                 }
                 rr = lo;
             }
-            const int32_t rlo = tb.lo[rr], rhi = tb.hi[rr], rpref = tb.pref[rr];
-            const int64_t j = (int64_t)rlo + (v - rpref);
-            const int32_t key = valid ? sk[j] : -1;
-            const bool head = valid && (v == rpref || sk[j - 1] != key);
-            int seg_end = valid ? v : v0;
+            T w[DIM][4];
+            int cx = 0, cy = 0, cz = 0;
+            bool has = false;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[k][i] = T(0);
+            if (valid) {
+                const int64_t j = (int64_t)tb.lo[rr] + (v - tb.pref[rr]);
+                T x[DIM];
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+                const T Fc = Fs[j * g.ncomp + c];
+                int delta[DIM];
+                comp_weights<T, DIM, KERN>(g, c, x, w, delta);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[DIM - 1][i] *= Fc;
+                cx = sk[j] + tb.xo[rr] + delta[0] - off[0];
+                cy = tb.uy[rr] + delta[1] - off[1];
+                cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
+                has = cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
+                      (DIM == 2 || (cz >= -2 && cz <= ez));
+            }
+            // Tile-relative cell code: x + 4, y + 4 and z + 4 in fields of XB, YB, ZB bits.
+            const uint32_t code = (uint32_t)(cx + 4) | ((uint32_t)(cy + 4) << XB) |
+                                  ((uint32_t)(cz + 4) << (XB + YB));
+            unsigned long long grp;
+            bool leader;
+            if (same0) {
+                // Cells of staggering 0 itself: a cell's points are adjacent in sorted order,
+                // so a group runs from its first lane to the next change of cell.
+                const uint32_t prev = (uint32_t)__shfl_up((int)code, 1u, 64);
+                const int hprev = __shfl_up((int)has, 1u, 64);
+                leader = has && (lane == 0 || !hprev || prev != code);
+                const unsigned long long heads = __ballot(leader);
+                const unsigned long long holes = ~__ballot(has);
+                const unsigned long long stop = (heads | holes) & ~((2ull << lane) - 1ull);
+                const int end = stop ? __ffsll((long long)stop) - 1 : 64;
+                const unsigned long long upto = (end == 64) ? ~0ull : ((1ull << end) - 1ull);
+                grp = leader ? (upto & ~below) : 0ull;
+            } else {
+                grp = match_code(code, has);
+                leader = has && (grp & below) == 0ull;
+            }
+            unsigned long long rest = leader ? (grp & ~(1ull << lane)) : 0ull;
+            const int cnt = __popcll(rest);
+            const int maxc = wave_max_i32(cnt);
             T acc[NZ][4][4];
 #pragma unroll
             for (int iz = 0; iz < NZ; ++iz)
@@ -183,50 +319,30 @@ struct SpreadTile {
                 for (int iy = 0; iy < 4; ++iy)
 #pragma unroll
                     for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = T(0);
-            if (head) {
-                int64_t jj = j;
-                do {
-                    const int64_t p = clamp_index(perm[jj], g.npts);
-                    T w[DIM][4];
-                    point_weights<T, DIM, KERN>(g, c, X, p, w);
-                    const T Fc = F[p * g.ncomp + c];
+            {
+                T wl[DIM][4];
 #pragma unroll
-                    for (int iz = 0; iz < NZ; ++iz) {
-                        const T wzF = (DIM == 3) ? w[DIM - 1][iz] * Fc : Fc;
+                for (int d = 0; d < DIM; ++d)
 #pragma unroll
-                        for (int iy = 0; iy < 4; ++iy) {
-                            const T cyz = w[1][iy] * wzF;
-#pragma unroll
-                            for (int ix = 0; ix < 4; ++ix)
-                                acc[iz][iy][ix] = fma(w[0][ix], cyz, acc[iz][iy][ix]);
-                        }
-                    }
-                    ++jj;
-                } while (jj < rhi && sk[jj] == key);
-                seg_end = rpref + (int)(jj - rlo);
+                    for (int i = 0; i < 4; ++i) wl[d][i] = leader ? w[d][i] : T(0);
+                accumulate(acc, wl);
             }
-            const int next = wave_max_i32(seg_end);
-            if (head) {
-                const int ux = tb.xoff[rr] + (key % n0);
-                const int uy = tb.uy[rr];
+            for (int k = 0; k < maxc; ++k) {  // the group's other points, from their lanes
+                const int src = rest ? __ffsll((long long)rest) - 1 : lane;
+                rest &= rest - 1ull;
+                const bool use = k < cnt;
+                T wk[DIM][4];
 #pragma unroll
-                for (int iz = 0; iz < NZ; ++iz) {
-                    const int tz = (DIM == 3) ? uz - 3 + iz : 0;
-                    if (tz < 0 || tz >= ez) continue;
+                for (int d = 0; d < DIM; ++d)
 #pragma unroll
-                    for (int iy = 0; iy < 4; ++iy) {
-                        const int ty = uy - 3 + iy;
-                        if (ty < 0 || ty >= ey) continue;
-                        T* row = tile + (tz * TY + ty) * TX;
-#pragma unroll
-                        for (int ix = 0; ix < 4; ++ix) {
-                            const int tx = ux - 3 + ix;
-                            if (tx >= 0 && tx < ex) row[tx] += acc[iz][iy][ix];
-                        }
+                    for (int i = 0; i < 4; ++i) {
+                        const T t = __shfl(w[d][i], src, 64);
+                        wk[d][i] = use ? t : T(0);
                     }
-                }
+                accumulate(acc, wk);
             }
-            v0 = next;
+            add_to_tile(acc, leader, cx, cy, cz, ey, ez, span, drow, tile);
+            wave_sync();
         }
     }
 };
@@ -235,7 +351,8 @@ template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
-    __shared__ T tile[TX * TY * TZ];
+    // Tile rows padded in x (3 before, 3 after); then one 4-wide dummy row per thread.
+    __shared__ T tile[ST::PXS * TY * TZ + 4 * 256];
     __shared__ typename ST::Table tables[4];
     const GeomArgs& g = a.g;
     int b = blockIdx.x;
@@ -243,30 +360,38 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
     const int by = b % a.tiles[1]; b /= a.tiles[1];
     const int bz = b % a.tiles[2]; b /= a.tiles[2];
     const int c = b;
-    const int s = g.comp_stag[c];
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
 
-    for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) tile[i] = T(0);
+    for (int i = threadIdx.x; i < ST::PXS * TY * TZ; i += blockDim.x) tile[i] = T(0);
     __syncthreads();
 
-    const int32_t* sk = a.sorted_keys + (int64_t)s * g.npts;
-    const int32_t* perm = a.perm + (int64_t)s * g.npts;
-    const int32_t* rs = a.row_start + (int64_t)s * (g.rows + 1);
+    // Source frame: staggering-0 cells that can reach the tile for this component.
+    const int hx = g.dhi[c][0] - g.dlo[c][0], hy = g.dhi[c][1] - g.dlo[c][1];
+    const int hz = (DIM == 3) ? g.dhi[c][2] - g.dlo[c][2] : 0;
+    const int off[3] = {2 + g.dhi[c][0], 2 + g.dhi[c][1], (DIM == 3) ? 2 + g.dhi[c][2] : 0};
+    const int ox = x0 - off[0], oy = y0 - off[1], oz = (DIM == 3) ? z0 - off[2] : 0;
+    const int lenx = ex + 3 + hx;
+    const int nrows = (DIM == 3) ? ey + 3 + hy : 1;
+    const int nslices = (DIM == 3) ? ez + 3 + hz : ey + 3 + hy;
+    const int nphase = 4 + ((DIM == 3) ? hz : hy);
+    const int nranges = 3 * nrows;
+    const bool same0 = hx == 0 && hy == 0 && hz == 0;
+    const int span = (DIM == 3) ? hz : hy;  // spread of leader cells along the slice axis
     const int w = wave_id();
-    const int nslices = (DIM == 3) ? ez + 3 : ey + 3;
-    const int nranges = 3 * ((DIM == 3) ? ey + 3 : 1);
     typename ST::Table& tb = tables[w];
 
-    // Slices q and q + 4 feed disjoint target slices, so the four waves take slices
-    // q = phase + 4m concurrently and the phases are separated by barriers.
-    for (int phase = 0; phase < 4; ++phase) {
+    // Slices q and q + nphase feed disjoint target slices, so the four waves take slices
+    // of one residue class concurrently and the phases are separated by barriers.
+    for (int phase = 0; phase < nphase; ++phase) {
         for (int m = w;; m += 4) {
-            const int q = phase + 4 * m;
+            const int q = phase + nphase * m;
             if (q >= nslices) break;
-            const int total = ST::build(a, sk, rs, q, x0, y0, z0, ex, ey, tb);
-            if (total > 0) ST::reduce(a, c, sk, perm, tb, nranges, total, q, ex, ey, ez, tile);
+            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb);
+            if (total > 0)
+                ST::reduce(a, c, a.sorted_keys, tb, nranges, total, q, off, ex, ey, ez, same0,
+                           span, tile + ST::PXS * TY * TZ + 4 * threadIdx.x, tile);
             wave_sync();
         }
         __syncthreads();
@@ -275,122 +400,150 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
     T* f = (T*)a.f;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
     const T scale = (T)g.scale;
-    const int cnt = ex * ey * ez;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int xr = i % ex, yr = (i / ex) % ey, zr = i / (ex * ey);
+    for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+        const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
+        if (xr >= ex || yr >= ey || zr >= ez) continue;
         const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
-        const T v = tile[(zr * TY + yr) * TX + xr] * scale;
+        const T v = tile[(zr * TY + yr) * ST::PXS + xr + 3] * scale;
         T* dst = f + (int64_t)c * G + gi;
         *dst = a.accumulate ? *dst + v : v;
+    }
+}
+
+// Forces into the sorted order of staggering 0 (one gather of whole rows).
+template <typename T>
+__global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int ncols,
+                                                          const int32_t* __restrict__ perm,
+                                                          const T* __restrict__ src,
+                                                          T* __restrict__ dst)
+{
+    const int64_t total = n * ncols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / ncols;
+        const int k = (int)(e - i * ncols);
+        dst[e] = src[clamp_index(perm[i], n) * ncols + k];
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // Interpolation
 // ---------------------------------------------------------------------------------------
-template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
+// One thread per point, in the sorted order of staggering 0: neighbouring lanes hold
+// neighbouring cells, so the 4^d gathers of a wave share cache lines.  All components of a
+// point are accumulated in registers and written together.
+template <typename T, int DIM, int KERN>
 __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 {
-    constexpr int PX = TX + 3, PY = TY + 3, PZ = (DIM == 3) ? TZ + 3 : 1;
-    constexpr int NROWS = TY * TZ;
-    static_assert(NROWS <= 256, "row table sized for one block");
-    __shared__ T ut[PX * PY * PZ];
-    __shared__ int64_t s_lo[NROWS];
-    __shared__ uint32_t s_pref[NROWS + 1];
-    __shared__ uint32_t s_scan[5];
-
     const GeomArgs& g = a.g;
-    int b = blockIdx.x;
-    const int bx = b % a.tiles[0]; b /= a.tiles[0];
-    const int by = b % a.tiles[1]; b /= a.tiles[1];
-    const int bz = b % a.tiles[2]; b /= a.tiles[2];
-    const int c = b;
-    const int s = g.comp_stag[c];
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-    const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
-    const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
+    const int64_t n = g.npts;
     const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
     const int64_t G = (int64_t)n0 * n1 * n2;
-    const T* __restrict__ u = (const T*)a.u + (int64_t)c * G;
-
-    // Grid values of cells x0-1 .. x0+ex+1 (and likewise in y, z), periodic.
-    const int lx = ex + 3, ly = ey + 3, lz = (DIM == 3) ? ez + 3 : 1;
-    for (int i = threadIdx.x; i < lx * ly * lz; i += blockDim.x) {
-        const int xr = i % lx, yr = (i / lx) % ly, zr = i / (lx * ly);
-        const int gx = emod(x0 - 1 + xr, n0), gy = emod(y0 - 1 + yr, n1);
-        const int gz = (DIM == 3) ? emod(z0 - 1 + zr, n2) : 0;
-        ut[(zr * PY + yr) * PX + xr] = u[((int64_t)gz * n1 + gy) * n0 + gx];
-    }
-
-    // Sorted ranges of the tile's x-rows.
-    const int32_t* sk = a.sorted_keys + (int64_t)s * g.npts;
-    const int32_t* perm = a.perm + (int64_t)s * g.npts;
-    const int32_t* rs = a.row_start + (int64_t)s * (g.rows + 1);
-    const int nrows = ey * ez;
-    uint32_t cnt = 0;
-    if ((int)threadIdx.x < nrows) {
-        const int yr = threadIdx.x % ey, zr = threadIdx.x / ey;
-        const int r = (DIM == 3) ? (z0 + zr) * n1 + (y0 + yr) : (y0 + yr);
-        const int32_t rowbase = r * n0;
-        const int64_t lo = lower_bound_key(sk, rs[r], rs[r + 1], rowbase + x0);
-        const int64_t hi = lower_bound_key(sk, lo, rs[r + 1], rowbase + x0 + ex);
-        s_lo[threadIdx.x] = lo;
-        cnt = (uint32_t)(hi - lo);
-    }
-    uint32_t total;
-    const uint32_t pre = block_excl_scan_u32<256>(cnt, s_scan, &total);
-    if ((int)threadIdx.x < nrows) s_pref[threadIdx.x] = pre;
-    if (threadIdx.x == 0) s_pref[nrows] = total;
-    __syncthreads();
-
-    const T* __restrict__ X = (const T*)a.X;
-    T* U = (T*)a.U;
-    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) {
-        int lo = 0, hi = nrows;  // find the row: s_pref[row] <= i < s_pref[row+1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pref[mid] <= i) lo = mid;
-            else hi = mid;
-        }
-        const int row = lo;
-        const int64_t j = s_lo[row] + (i - s_pref[row]);
-        const int yr = row % ey, zr = row / ey;
-        const int xr = min(max(sk[j] % n0 - x0, 0), ex - 1);
-        const int64_t p = clamp_index(perm[j], g.npts);
-        T w[DIM][4];
-        point_weights<T, DIM, KERN>(g, c, X, p, w);
-        T sum = T(0);
+    const T* __restrict__ Xs = (const T*)a.Xs;
+    const T* __restrict__ u = (const T*)a.u;
+    T* __restrict__ U = (T*)a.U;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        T x[DIM];
 #pragma unroll
-        for (int iz = 0; iz < ((DIM == 3) ? 4 : 1); ++iz) {
-            T sy = T(0);
+        for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+        const int64_t p = clamp_index(a.perm[j], n);
+        T res[3] = {T(0), T(0), T(0)};
+        for (int c = 0; c < g.ncomp; ++c) {
+            T w[DIM][4];
+            int cell[DIM];
 #pragma unroll
-            for (int iy = 0; iy < 4; ++iy) {
-                const T* line = ut + ((zr + iz) * PY + (yr + iy)) * PX + xr;
-                T sx = T(0);
-#pragma unroll
-                for (int ix = 0; ix < 4; ++ix) sx = fma(w[0][ix], line[ix], sx);
-                sy = fma(w[1][iy], sx, sy);
+            for (int k = 0; k < DIM; ++k) {
+                const T ih = Prec<T>::inv_h(g, k);
+                const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
+                const T fy = floor(y);
+                T r = y - fy;
+                r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
+                weights4<T, KERN>(r, w[k]);
+                const double fyd = (double)fy;
+                cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
             }
-            sum = (DIM == 3) ? fma(w[DIM - 1][iz], sy, sum) : sy;
+            int xi[4];
+#pragma unroll
+            for (int ix = 0; ix < 4; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+            const T* __restrict__ uc = u + (int64_t)c * G;
+            T sum = T(0);
+#pragma unroll
+            for (int iz = 0; iz < ((DIM == 3) ? 4 : 1); ++iz) {
+                const int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
+                T sy = T(0);
+#pragma unroll
+                for (int iy = 0; iy < 4; ++iy) {
+                    const int yy = wrap_small(cell[1] - 1 + iy, n1);
+                    const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
+                    T sx = T(0);
+#pragma unroll
+                    for (int ix = 0; ix < 4; ++ix) sx = fma(w[0][ix], line[xi[ix]], sx);
+                    sy = fma(w[1][iy], sx, sy);
+                }
+                sum = (DIM == 3) ? fma(w[DIM - 1][iz], sy, sum) : sy;
+            }
+            res[c] = sum;
         }
-        U[p * g.ncomp + c] = sum;
+        for (int c = 0; c < g.ncomp; ++c) U[p * g.ncomp + c] = res[c];
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// Position update: X <- wrap(X + dt U) into [0, L) per coordinate.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void advect_kernel(int dim, int ncomp, int64_t npts, T L0, T L1,
+                                                     T L2, T* __restrict__ X,
+                                                     const T* __restrict__ U, T dt)
+{
+    const int64_t total = npts * dim;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = i / dim;
+        const int k = (int)(i - j * dim);
+        const T L = k == 0 ? L0 : (k == 1 ? L1 : L2);
+        T y = fma(dt, U[j * ncomp + k], X[i]);
+        y -= L * floor(y / L);
+        if (y >= L || y < T(0)) y = T(0);
+        X[i] = y;
+    }
+}
+
+hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
+                         void* X, const void* U, double dt, hipStream_t st)
+{
+    if (npts == 0) return hipSuccess;
+    const int64_t total = npts * dim;
+    const unsigned blocks = (unsigned)min((int64_t)4096, (total + 255) / 256);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(advect_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, ncomp, npts,
+                           length[0], length[1], length[2], (double*)X, (const double*)U, dt);
+    else
+        hipLaunchKernelGGL(advect_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, ncomp, npts,
+                           (float)length[0], (float)length[1], (float)length[2], (float*)X,
+                           (const float*)U, (float)dt);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
 namespace {
-constexpr int SP_TX = 32, SP_TY = 16, SP_TZ = 13;   // spreading tile (3-D)
+constexpr int SP_TX = 32, SP_TY = 16, SP_TZ = 12;   // spreading tile (3-D)
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
-constexpr int IN_TX = 64, IN_TY = 8, IN_TZ = 2;     // interpolation tile (3-D)
-constexpr int IN2_TX = 64, IN2_TY = 16;             // interpolation tile (2-D)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 {
+    const int64_t nel = a.g.npts * a.g.ncomp;
+    if (nel > 0) {
+        const unsigned gb = (unsigned)min((int64_t)8192, (nel + 255) / 256);
+        hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(gb), dim3(256), 0, st, a.g.npts, a.g.ncomp,
+                           a.perm, (const T*)a.F, (T*)a.Fs);
+    }
     if (a.g.dim == 3) {
         a.tiles[0] = cdiv(a.g.n[0], SP_TX);
         a.tiles[1] = cdiv(a.g.n[1], SP_TY);
@@ -412,21 +565,11 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 template <typename T, int KERN>
 hipError_t interp_dispatch(OpArgs a, hipStream_t st)
 {
-    if (a.g.dim == 3) {
-        a.tiles[0] = cdiv(a.g.n[0], IN_TX);
-        a.tiles[1] = cdiv(a.g.n[1], IN_TY);
-        a.tiles[2] = cdiv(a.g.n[2], IN_TZ);
-        const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp);
-        hipLaunchKernelGGL((interp_kernel<T, 3, KERN, IN_TX, IN_TY, IN_TZ>), dim3(nb), dim3(256),
-                           0, st, a);
-    } else {
-        a.tiles[0] = cdiv(a.g.n[0], IN2_TX);
-        a.tiles[1] = cdiv(a.g.n[1], IN2_TY);
-        a.tiles[2] = 1;
-        const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.g.ncomp);
-        hipLaunchKernelGGL((interp_kernel<T, 2, KERN, IN2_TX, IN2_TY, 1>), dim3(nb), dim3(256),
-                           0, st, a);
-    }
+    const unsigned nb = (unsigned)min((int64_t)65536, (a.g.npts + 255) / 256);
+    if (a.g.dim == 3)
+        hipLaunchKernelGGL((interp_kernel<T, 3, KERN>), dim3(nb), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((interp_kernel<T, 2, KERN>), dim3(nb), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 }  // namespace

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restri
             for (int k = 0; k < g.dim; ++k) {
                 const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
                 int c = 0;
-                if (fabs(y) < T(1073741824.0)) c = emod((int)floor(y), g.n[k]);
+                if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
                 else bad = true;
                 key += c * stride;
                 stride *= g.n[k];
@@ -104,7 +104,7 @@ __device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t st
 
 // ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
 template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int pass)
+__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int s, int pass)
 {
     constexpr int R = 1 << RBITS;
     constexpr int NW = SORT_BLOCK / 64;
@@ -118,14 +118,12 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[pass], 1u);
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
     for (int i = tid; i < NW * R; i += SORT_BLOCK) (&s_wcnt[0][0])[i] = 0u;
     __syncthreads();
 
     const int64_t n = a.g.npts;
-    const int64_t ticket = s_ticket;
-    const int s = (int)(ticket / a.ntiles);
-    const int64_t t = ticket % a.ntiles;
+    const int64_t t = s_ticket;
     const int64_t base = t * SORT_TILE;
     const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
 
@@ -140,8 +138,8 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
     dstv += (int64_t)s * n;
     const int shift = pass * RBITS;
 
-    // Stable in-tile ranking: wave w owns items [w*1024, (w+1)*1024) of the tile, in
-    // 16 steps of 64 consecutive items; the rank of an item among equal digits is the
+    // Stable in-tile ranking: wave w owns items [w*64*IPT, (w+1)*64*IPT) of the tile, in
+    // IPT steps of 64 consecutive items; the rank of an item among equal digits is the
     // count in earlier steps of its wave plus the count of lower lanes in its step.
     int32_t key[SORT_IPT], val[SORT_IPT];
     uint32_t rank[SORT_IPT];
@@ -186,7 +184,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
         s_gbase[tid] = gbase;
         // Look-back column of this digit: tile-major, digit-minor words.
         uint32_t* col = a.d.sort_status +
-                        ((int64_t)pass * a.g.nstag * a.ntiles + (int64_t)s * a.ntiles) * R + tid;
+                        (((int64_t)s * a.npass + pass) * a.ntiles) * R + tid;
         const uint32_t excl = lookback_strided(col, R, t, cnt, a.d.flag);
         s_excl[tid] = excl;
     }
@@ -215,26 +213,28 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
     }
 }
 
-// ---- segments: run heads, q, seg_off and the per-row start table -----------------------
-__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, const int32_t* sk_all)
+// ---- segments: run heads, q, seg_off and the cell-block start table -------------------
+template <typename T>
+__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s, const int32_t* sk_all,
+                                                              const int32_t* perm_all,
+                                                              const T* __restrict__ X, T* __restrict__ Xs)
 {
     constexpr int NW = SORT_BLOCK / 64;
     __shared__ uint32_t s_wtot[NW];
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_excl;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[a.npass], 1u);
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + a.npass], 1u);
     __syncthreads();
 
-    const int64_t n = a.g.npts;
-    const int64_t ticket = s_ticket;
-    const int s = (int)(ticket / a.nseg_tiles);
-    const int64_t t = ticket % a.nseg_tiles;
+    const GeomArgs& g = a.g;
+    const int64_t n = g.npts;
+    const int64_t t = s_ticket;
     const int64_t base = t * SORT_TILE;
     const int32_t* sk = sk_all + (int64_t)s * n;
     int32_t* seg = a.d.seg_off + (int64_t)s * (n + 1);
-    int32_t* rs = a.d.row_start + (int64_t)s * (a.g.rows + 1);
-    const int n0 = a.g.n[0];
+    const int64_t nent = (int64_t)g.rows * (g.nbx + 1);
+    int32_t* cb = a.d.cblk + (int64_t)s * nent;
 
     uint32_t rank[SORT_IPT];
     bool head[SORT_IPT];
@@ -248,10 +248,10 @@ __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, const 
             const int32_t kc = sk[i];
             const int32_t kp = i > 0 ? sk[i - 1] : -1;
             hd = (i == 0) || (kc != kp);
-            // Row table: rows (row(i-1), row(i)] start at sorted position i.
-            const int rp = i > 0 ? min(max(kp / n0, -1), a.g.rows - 1) : -1;
-            const int rc = min(max(kc / n0, -1), a.g.rows - 1);
-            for (int r = rp + 1; r <= rc; ++r) rs[r] = (int32_t)i;
+            // Table entries (block(i-1), block(i)] start at sorted position i.
+            const int64_t bp = i > 0 ? min(cblk_index(kp, g), nent - 1) : -1;
+            const int64_t bc = min(cblk_index(kc, g), nent - 1);
+            for (int64_t e = bp + 1; e <= bc; ++e) cb[e] = (int32_t)i;
         }
         const unsigned long long m = __ballot(hd);
         head[k] = hd;
@@ -274,9 +274,12 @@ __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, const 
             const uint32_t q = excl + run;
             a.d.q[s] = (int32_t)q;
             seg[q] = (int32_t)n;
-            const int rlast = n > 0 ? min(max(sk[n - 1] / n0, -1), a.g.rows - 1) : -1;
-            for (int r = rlast + 1; r <= a.g.rows; ++r) rs[r] = (int32_t)n;
         }
+    }
+    // The last tile fills the table entries after the last key with n.
+    if (t == a.nseg_tiles - 1) {
+        const int64_t blast = n > 0 ? min(cblk_index(sk[n - 1], g), nent - 1) : -1;
+        for (int64_t e = blast + 1 + tid; e < nent; e += SORT_BLOCK) cb[e] = (int32_t)n;
     }
     __syncthreads();
     const uint32_t off = s_excl + s_wtot[w];
@@ -285,44 +288,74 @@ __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, const 
         const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
         if (head[k]) seg[off + rank[k]] = (int32_t)i;
     }
+    // Positions in this sorted order (staggering 0 only): coalesced writes, one gather.
+    if (Xs != nullptr) {
+        const int32_t* perm = perm_all + (int64_t)s * n;
+        const int dim = g.dim;
+        for (int e = tid; e < SORT_TILE * dim; e += SORT_BLOCK) {
+            const int64_t i = base + e / dim;
+            if (i < n) {
+                const int k = e - (e / dim) * dim;
+                const int64_t p = (uint32_t)perm[i] < (uint64_t)n ? perm[i] : 0;
+                Xs[i * dim + k] = X[p * dim + k];
+            }
+        }
+    }
 }
 
-// ---- host launcher ----------------------------------------------------------------------
-hipError_t launch_plan_update(const SortArgs& a, int dtype, const void* X, hipStream_t st)
+// ---- host launchers ---------------------------------------------------------------------
+hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
+{
+    const size_t nw = a.d.zero_words;
+    const int blocks = (int)min((size_t)1024, (nw + 255) / 256);
+    if (blocks > 0)
+        hipLaunchKernelGGL(plan_reset_kernel, dim3(blocks), dim3(256), 0, st, a.d.zero_begin, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st)
 {
     const GeomArgs& g = a.g;
-    {
-        const size_t nw = a.d.zero_words;
-        const int blocks = (int)min((size_t)1024, (nw + 255) / 256);
-        if (blocks > 0)
-            hipLaunchKernelGGL(plan_reset_kernel, dim3(blocks), dim3(256), 0, st, a.d.zero_begin, nw);
-    }
+    if (g.npts == 0) return hipSuccess;
     const int R = 1 << a.rbits;
     const size_t lds = (size_t)g.nstag * a.npass * R * sizeof(uint32_t);
+    // Few blocks: each adds its LDS histograms to the global ones with atomics.
+    const int blocks = (int)min((int64_t)512, (g.npts + 255) / 256);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a, (const double*)X);
+    else
+        hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a, (const float*)X);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,
+                               hipStream_t st)
+{
+    const GeomArgs& g = a.g;
     if (g.npts > 0) {
-        const int blocks = (int)min((int64_t)2048, (g.npts + 255) / 256);
-        if (dtype == IB_F64)
-            hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a,
-                               (const double*)X);
-        else
-            hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a,
-                               (const float*)X);
-        const unsigned tiles = (unsigned)(a.ntiles * g.nstag);
+        const unsigned tiles = (unsigned)a.ntiles;
         for (int p = 0; p < a.npass; ++p) {
             switch (a.rbits) {
-            case 4: hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
-            case 5: hipLaunchKernelGGL(radix_pass_kernel<5>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
-            case 6: hipLaunchKernelGGL(radix_pass_kernel<6>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
-            case 7: hipLaunchKernelGGL(radix_pass_kernel<7>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
-            case 8: hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, p); break;
+            case 4: hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
+            case 5: hipLaunchKernelGGL(radix_pass_kernel<5>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
+            case 6: hipLaunchKernelGGL(radix_pass_kernel<6>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
+            case 7: hipLaunchKernelGGL(radix_pass_kernel<7>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
+            case 8: hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
             default: return hipErrorInvalidValue;
             }
         }
     }
     // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
-    const int32_t* sk = (g.npts == 0) ? a.d.kA : ((a.npass & 1) ? a.d.kA : a.d.kB);
-    hipLaunchKernelGGL(segments_kernel, dim3((unsigned)(a.nseg_tiles * g.nstag)), dim3(SORT_BLOCK),
-                       0, st, a, sk);
+    const bool in_a = (g.npts == 0) || (a.npass & 1);
+    const int32_t* sk = in_a ? a.d.kA : a.d.kB;
+    const int32_t* pv = in_a ? a.d.vA : a.d.vB;
+    const dim3 grid((unsigned)a.nseg_tiles);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(segments_kernel<double>, grid, dim3(SORT_BLOCK), 0, st, a, s, sk, pv,
+                           (const double*)X, gather_x ? (double*)a.d.Xs : nullptr);
+    else
+        hipLaunchKernelGGL(segments_kernel<float>, grid, dim3(SORT_BLOCK), 0, st, a, s, sk, pv,
+                           (const float*)X, gather_x ? (float*)a.d.Xs : nullptr);
     return hipGetLastError();
 }
 

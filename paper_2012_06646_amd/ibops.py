@@ -56,7 +56,10 @@ _lib.ib_spread.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.ib_interpolate.restype = _i32
 _lib.ib_interpolate.argtypes = [_vp, _vp, _vp, _vp]
 
-EXPORTED = ["ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
+_lib.ib_advect.restype = _i32
+_lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
+
+EXPORTED = ["ib_advect", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
 
@@ -204,6 +207,15 @@ class Plan:
             U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
         _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
         return U
+
+
+def advect(grid, X, U, dt, stream=None):
+    """In place: X <- X + dt U, wrapped into the periodic box (IB step position update)."""
+    if X.shape[0] != U.shape[0] or X.dtype != U.dtype or not X.is_contiguous() or not U.is_contiguous():
+        raise ValueError("X and U must be contiguous with matching rows and dtype")
+    _check(_lib.ib_advect(ctypes.byref(make_desc(grid)), _dtype_code(X.dtype), X.shape[0], _ptr(X),
+                          _ptr(U), float(dt), _stream(stream)), "ib_advect")
+    return X
 
 
 def spread(grid, X, F):

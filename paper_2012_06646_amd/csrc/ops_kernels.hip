@@ -242,50 +242,69 @@ struct SpreadTile {
     // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
     // group; its lowest lane (the leader) sums the group's contributions to all 4^d shifts
     // in registers, pulling each member's offsets and force from the member's lane.
+    // Sorted position v of the slice: its range, key, coordinates and force (zeros past
+    // the end).
+    __device__ static void load(const OpArgs& a, int c, const int32_t* __restrict__ sk,
+                                const Table& tb, int nranges, int total, int v, int& rr,
+                                int32_t& key, T x[DIM], T& F)
+    {
+        rr = 0;
+        key = 0;
+        F = T(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) x[k] = T(0);
+        if (v < total) {
+            int lo = 0, hi = nranges;  // last range whose prefix is <= v (it is non-empty)
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tb.pref[mid] <= v) lo = mid;
+                else hi = mid;
+            }
+            rr = lo;
+            const int64_t j = (int64_t)tb.lo[rr] + (v - tb.pref[rr]);
+            const T* __restrict__ Xs = (const T*)a.Xs;
+            key = sk[j];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+            F = ((const T*)a.Fs)[j * a.g.ncomp + c];
+        }
+    }
+
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
                                   const Table& tb, int nranges, int total, int q, const int off[3],
                                   int ex, int ey, int ez, bool same0, int span, T* drow,
                                   T* tile)
     {
         const GeomArgs& g = a.g;
-        const T* __restrict__ Xs = (const T*)a.Xs;
-        const T* __restrict__ Fs = (const T*)a.Fs;
         const int lane = lane_id();
         const unsigned long long below = (1ull << lane) - 1ull;
+        // Chunk data is loaded one chunk ahead, so its latency overlaps the current chunk.
+        int nrr = 0;
+        int32_t nkey = 0;
+        T nx[DIM], nF = T(0);
+        load(a, c, sk, tb, nranges, total, lane, nrr, nkey, nx, nF);
         for (int v0 = 0; v0 < total; v0 += 64) {
             const int v = v0 + lane;
             const bool valid = v < total;
-            int rr = 0;
-            if (valid) {  // last range whose prefix is <= v (it is non-empty)
-                int lo = 0, hi = nranges;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (tb.pref[mid] <= v) lo = mid;
-                    else hi = mid;
-                }
-                rr = lo;
-            }
+            const int rr = nrr;
+            const int32_t key = nkey;
+            T x[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) x[k] = nx[k];
+            const T Fc = nF;
+            if (v0 + 64 < total) load(a, c, sk, tb, nranges, total, v + 64, nrr, nkey, nx, nF);
             T w[DIM][4];
             int cx = 0, cy = 0, cz = 0;
             bool has = false;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) w[k][i] = T(0);
-            if (valid) {
-                const int64_t j = (int64_t)tb.lo[rr] + (v - tb.pref[rr]);
-                T x[DIM];
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
-                const T Fc = Fs[j * g.ncomp + c];
+            {
                 int delta[DIM];
                 comp_weights<T, DIM, KERN>(g, c, x, w, delta);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) w[DIM - 1][i] *= Fc;
-                cx = sk[j] + tb.xo[rr] + delta[0] - off[0];
+                cx = key + tb.xo[rr] + delta[0] - off[0];
                 cy = tb.uy[rr] + delta[1] - off[1];
                 cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
-                has = cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
+                has = valid && cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
                       (DIM == 2 || (cz >= -2 && cz <= ez));
             }
             // Tile-relative cell code: x + 4, y + 4 and z + 4 in fields of XB, YB, ZB bits.
@@ -330,15 +349,16 @@ struct SpreadTile {
             for (int k = 0; k < maxc; ++k) {  // the group's other points, from their lanes
                 const int src = rest ? __ffsll((long long)rest) - 1 : lane;
                 rest &= rest - 1ull;
-                const bool use = k < cnt;
+                T xm[DIM];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) xm[d] = __shfl(x[d], src, 64);
+                const T Fm = __shfl(Fc, src, 64);
                 T wk[DIM][4];
+                int dd[DIM];
+                comp_weights<T, DIM, KERN>(g, c, xm, wk, dd);
+                const T fk = (k < cnt) ? Fm : T(0);
 #pragma unroll
-                for (int d = 0; d < DIM; ++d)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const T t = __shfl(w[d][i], src, 64);
-                        wk[d][i] = use ? t : T(0);
-                    }
+                for (int i = 0; i < 4; ++i) wk[DIM - 1][i] *= fk;
                 accumulate(acc, wk);
             }
             add_to_tile(acc, leader, cx, cy, cz, ey, ez, span, drow, tile);
@@ -351,8 +371,9 @@ template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
-    // Tile rows padded in x (3 before, 3 after); then one 4-wide dummy row per thread.
-    __shared__ T tile[ST::PXS * TY * TZ + 4 * 256];
+    // Tile rows padded in x (3 before, 3 after); then one 4-wide dummy row per thread,
+    // 5 elements apart so that the dummy rows of 16 consecutive lanes use distinct banks.
+    __shared__ T tile[ST::PXS * TY * TZ + 5 * 256];
     __shared__ typename ST::Table tables[4];
     const GeomArgs& g = a.g;
     int b = blockIdx.x;
@@ -391,7 +412,7 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
             const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb);
             if (total > 0)
                 ST::reduce(a, c, a.sorted_keys, tb, nranges, total, q, off, ex, ey, ez, same0,
-                           span, tile + ST::PXS * TY * TZ + 4 * threadIdx.x, tile);
+                           span, tile + ST::PXS * TY * TZ + 5 * threadIdx.x, tile);
             wave_sync();
         }
         __syncthreads();
@@ -530,7 +551,7 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // Launchers
 // ---------------------------------------------------------------------------------------
 namespace {
-constexpr int SP_TX = 32, SP_TY = 16, SP_TZ = 12;   // spreading tile (3-D)
+constexpr int SP_TX = 32, SP_TY = 16, SP_TZ = 13;   // spreading tile (3-D): 960 blocks at 128^3
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }

@@ -121,6 +121,16 @@ int32_t ib_spread(ib_plan plan, const void *F, void *f, int32_t accumulate, void
  * device; U (npts x ncomp) device, overwritten. */
 int32_t ib_interpolate(ib_plan plan, const void *u, void *U, void *stream);
 
+/* Position gradient of interpolation, for differentiating through J(X):
+ * dX_{j,k} (+)= sum_c W_{j,c} dU_{j,c}/dX_{j,k}, U = J(X) u as in ib_interpolate, where
+ * dW/dX_k = (1/h_k) phi'-term: the derivative of the tensor-product weight along axis k.
+ * With W = U this is the X-gradient of (1/2)|J(X)u|^2; with u = g and W = F it is the
+ * X-gradient of <S(X)F, g>_h (the adjoint pair of eqs. (matrix-interp), (matrix-spread)).
+ * u (ncomp x grid), W (npts x ncomp), dX (npts x dim): device, plan dtype.  dX is
+ * overwritten, or added to when accumulate != 0. */
+int32_t ib_interpolate_grad(ib_plan plan, const void *u, const void *W, void *dX,
+                            int32_t accumulate, void *stream);
+
 /* Position update of the IB time step, steps (b)/(g) of Sec. 2 with the interpolated
  * velocity: X <- X + dt * U, each coordinate wrapped back into [0, length_k).  X (npts x dim)
  * device, updated in place; U (npts x ncomp) device with ncomp == dim; grid supplies dim and

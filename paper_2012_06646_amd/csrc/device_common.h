@@ -121,6 +121,30 @@ __device__ __forceinline__ void weights4(T r, T w[4])
 }
 
 // a mod n for a in [-n, 2n) (unwrapped tile and halo coordinates), without division.
+// Derivatives d w[k] / d r of the four weights of weights4 (r increases with X).
+template <typename T, int KERN>
+__device__ __forceinline__ void dweights4(T r, T dw[4])
+{
+    if constexpr (KERN == IB_KERNEL_COSINE4) {
+        T s, c;
+        if constexpr (sizeof(T) == 8) sincospi(0.5 * r, &s, &c);
+        else sincospif(0.5f * r, &s, &c);
+        const T q = T(3.14159265358979323846 / 8.0);
+        dw[0] = -q * c;
+        dw[1] = -q * s;
+        dw[2] = q * c;
+        dw[3] = q * s;
+    } else {
+        // with s = sqrt(1 + 4r - 4r^2), ds/dr = (2 - 4r) / s
+        const T s = sqrt(T(1) + T(4) * r * (T(1) - r));
+        const T ds = (T(2) - T(4) * r) / s;
+        dw[0] = (T(-2) - ds) * T(0.125);
+        dw[1] = (T(-2) + ds) * T(0.125);
+        dw[2] = (T(2) + ds) * T(0.125);
+        dw[3] = (T(2) - ds) * T(0.125);
+    }
+}
+
 __device__ __forceinline__ int wrap_small(int a, int n)
 {
     a = a < 0 ? a + n : a;

@@ -372,6 +372,20 @@ int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
     return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
 }
 
+int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, int32_t accumulate,
+                            void* stream)
+{
+    if (!p || !u || !p->updated) return IB_ERR_ARG;
+    if ((!W || !dX) && p->npts > 0) return IB_ERR_ARG;
+    if (p->npts == 0) return IB_OK;
+    OpArgs a;
+    fill_op_args(p, &a);
+    a.u = u;
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    return hip_status(launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st));
+}
+
 int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X, const void* U,
                   double dt, void* stream)
 {

@@ -116,6 +116,8 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
                                hipStream_t st);
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st);
 hipError_t launch_interp(const OpArgs& a, int dtype, int kernel, hipStream_t st);
+hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
+                              int accumulate, hipStream_t st);
 hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
                          void* X, const void* U, double dt, hipStream_t st);
 

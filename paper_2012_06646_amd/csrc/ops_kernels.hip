@@ -511,6 +511,120 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
+// Position gradient of interpolation: dX_j += sum_c W_{j,c} dU_{j,c} / dX_j, U = J(X) u.
+// dW/dX_k = (1/h_k) dw_k(r_k) prod_{l != k} w_l(r_l); one thread per sorted point.
+// ---------------------------------------------------------------------------------------
+template <typename T, int DIM, int KERN>
+__global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __restrict__ W,
+                                                          T* __restrict__ dX, int accumulate)
+{
+    const GeomArgs& g = a.g;
+    const int64_t n = g.npts;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
+    const int64_t G = (int64_t)n0 * n1 * n2;
+    const T* __restrict__ Xs = (const T*)a.Xs;
+    const T* __restrict__ u = (const T*)a.u;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        T x[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+        const int64_t p = clamp_index(a.perm[j], n);
+        T grad[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) grad[k] = T(0);
+        for (int c = 0; c < g.ncomp; ++c) {
+            const T wc = W[p * g.ncomp + c];
+            T w[DIM][4], dw[DIM][4];
+            int cell[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const T ih = Prec<T>::inv_h(g, k);
+                const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
+                const T fy = floor(y);
+                T r = y - fy;
+                r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
+                weights4<T, KERN>(r, w[k]);
+                dweights4<T, KERN>(r, dw[k]);
+                const double fyd = (double)fy;
+                cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
+            }
+            int xi[4];
+#pragma unroll
+            for (int ix = 0; ix < 4; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+            const T* __restrict__ uc = a.u ? u + (int64_t)c * G : u;
+            // s_* : sums with w in every axis except the one differentiated
+            T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+            for (int iz = 0; iz < ((DIM == 3) ? 4 : 1); ++iz) {
+                const int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
+                T ay = T(0), by = T(0), cy = T(0);
+#pragma unroll
+                for (int iy = 0; iy < 4; ++iy) {
+                    const int yy = wrap_small(cell[1] - 1 + iy, n1);
+                    const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
+                    T sx = T(0), dsx = T(0);
+#pragma unroll
+                    for (int ix = 0; ix < 4; ++ix) {
+                        const T v = line[xi[ix]];
+                        sx = fma(w[0][ix], v, sx);
+                        dsx = fma(dw[0][ix], v, dsx);
+                    }
+                    ay = fma(w[1][iy], dsx, ay);   // d/dx
+                    by = fma(dw[1][iy], sx, by);   // d/dy
+                    cy = fma(w[1][iy], sx, cy);    // for d/dz
+                }
+                if (DIM == 3) {
+                    gx = fma(w[2][iz], ay, gx);
+                    gy = fma(w[2][iz], by, gy);
+                    gz = fma(dw[2][iz], cy, gz);
+                } else {
+                    gx = ay;
+                    gy = by;
+                }
+            }
+            grad[0] = fma(wc, gx * Prec<T>::inv_h(g, 0), grad[0]);
+            grad[1] = fma(wc, gy * Prec<T>::inv_h(g, 1), grad[1]);
+            if (DIM == 3) grad[2] = fma(wc, gz * Prec<T>::inv_h(g, 2), grad[2]);
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            T* d = dX + p * DIM + k;
+            *d = accumulate ? *d + grad[k] : grad[k];
+        }
+    }
+}
+
+hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
+                              int accumulate, hipStream_t st)
+{
+    if (a.g.npts == 0) return hipSuccess;
+    const unsigned nb = (unsigned)min((int64_t)65536, (a.g.npts + 255) / 256);
+#define IBK_GRAD_LAUNCH(T, D, K)                                                              \
+    hipLaunchKernelGGL((interp_grad_kernel<T, D, K>), dim3(nb), dim3(256), 0, st, a,           \
+                       (const T*)W, (T*)dX, accumulate)
+    if (dtype == IB_F64) {
+        if (a.g.dim == 3) {
+            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(double, 3, IB_KERNEL_COSINE4);
+            else IBK_GRAD_LAUNCH(double, 3, IB_KERNEL_PESKIN4);
+        } else {
+            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(double, 2, IB_KERNEL_COSINE4);
+            else IBK_GRAD_LAUNCH(double, 2, IB_KERNEL_PESKIN4);
+        }
+    } else {
+        if (a.g.dim == 3) {
+            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(float, 3, IB_KERNEL_COSINE4);
+            else IBK_GRAD_LAUNCH(float, 3, IB_KERNEL_PESKIN4);
+        } else {
+            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(float, 2, IB_KERNEL_COSINE4);
+            else IBK_GRAD_LAUNCH(float, 2, IB_KERNEL_PESKIN4);
+        }
+    }
+#undef IBK_GRAD_LAUNCH
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Position update: X <- wrap(X + dt U) into [0, L) per coordinate.
 // ---------------------------------------------------------------------------------------
 template <typename T>

@@ -56,10 +56,12 @@ _lib.ib_spread.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.ib_interpolate.restype = _i32
 _lib.ib_interpolate.argtypes = [_vp, _vp, _vp, _vp]
 
+_lib.ib_interpolate_grad.restype = _i32
+_lib.ib_interpolate_grad.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
 
-EXPORTED = ["ib_advect", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
+EXPORTED = ["ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
 
@@ -207,6 +209,20 @@ class Plan:
             U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
         _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
         return U
+
+
+def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None):
+    u = plan._grid(u, "u")
+    W = plan._pts(W, plan.ncomp, "W")
+    if dX is None:
+        dX = torch.empty((plan.npts, plan.dim), dtype=plan.dtype, device=plan.device)
+        accumulate = False
+    _check(_lib.ib_interpolate_grad(plan._h, _ptr(u), _ptr(W), _ptr(dX), int(bool(accumulate)),
+                                    _stream(stream)), "ib_interpolate_grad")
+    return dX
+
+
+Plan.interpolate_grad = _interp_grad
 
 
 def advect(grid, X, U, dt, stream=None):

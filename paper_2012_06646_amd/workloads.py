@@ -150,8 +150,8 @@ def place_rbcs(box, count, seed_pos, seed_rot, max_trials=200_000, margin=0.05):
     """Random sequential addition of `count` RBCs in a periodic cube of edge `box`:
     uniform centres (seed_pos) and uniform rotations (seed_rot); a trial is rejected when a
     vertex of either cell lies inside the other (minimum periodic image, `margin` um).
-    When trials run out, the remaining cells are placed at the least-overlapping of a few
-    candidate positions.  Returns (centres, rotations, n_nonoverlapping)."""
+    When trials run out, the remaining cells are placed at random positions (they may
+    overlap).  Returns (centres, rotations, number placed without overlap)."""
     rp, rr = rng(seed_pos), rng(seed_rot)
     surf = rbc_surface(4)
     sub = surf[:: max(1, len(surf) // 162)]  # coarse vertex subset for the overlap test
@@ -213,3 +213,51 @@ def smooth_force(X, box, seed, modes=16):
         if m > 0:
             F[:, c] /= m
     return F
+
+
+def _cached(name, builder):
+    """Deterministic generator output, cached under $IBOPS_CACHE (default /tmp/ibops_cache)."""
+    import os
+    d = os.environ.get("IBOPS_CACHE", "/tmp/ibops_cache")
+    path = os.path.join(d, name + ".npz")
+    try:
+        with np.load(path) as z:
+            return {k: z[k] for k in z.files}
+    except (OSError, ValueError, KeyError):
+        pass
+    out = builder()
+    try:
+        os.makedirs(d, exist_ok=True)
+        np.savez(path + ".tmp.npz", **out)
+        os.replace(path + ".tmp.npz", path)
+    except OSError:
+        pass
+    return out
+
+
+def rbc_case(box, n, count, seeds, dtype, max_trials):
+    """RBC surface points (count cells, 2562 vertices each) in a periodic cube of edge `box`
+    on an n^3 MAC grid; seeds = (positions, rotations, forces, grid field)."""
+    def build():
+        X, placed = rbc_points(box, count, seeds[0], seeds[1], max_trials)
+        F = smooth_force(X, box, seeds[2])
+        u = rng(seeds[3]).standard_normal((3, n, n, n))
+        return {"X": X, "F": F, "u": u, "placed": np.array(placed)}
+    z = _cached(f"rbc_{box}_{n}_{count}_{'_'.join(map(str, seeds))}_{max_trials}", build)
+    g = grid(3, n, box)
+    return g, z["X"].astype(dtype), z["F"].astype(dtype), z["u"].astype(dtype), int(z["placed"])
+
+
+def config3(dtype=np.float32):
+    """256^3 MAC grid in a 64 um periodic box (h = 0.25 um), 1111 RBCs of 2562 vertices
+    (40% volume fraction), seeds 3001-3004.  Random sequential addition jams below 40%; the
+    cells that do not fit without overlap are placed at random (count returned)."""
+    return rbc_case(64.0, 256, 1111, (3001, 3002, 3003, 3004), dtype, 40000)
+
+
+def config5(dtype=np.float64):
+    """128^3 MAC grid in a 32 um periodic box (h = 0.25 um), 78 RBCs (about 2 x 10^5 points),
+    seeds 5001-5004; the loss's grid field g is drawn with seed 5005."""
+    g, X, F, u, placed = rbc_case(32.0, 128, 78, (5001, 5002, 5003, 5004), dtype, 200000)
+    gfield = rng(5005).standard_normal((3, 128, 128, 128)).astype(dtype)
+    return g, X, F, u, gfield, placed

@@ -36,6 +36,40 @@ def algorithmic_bytes(npts, dim, ncomp, G, b):
     }
 
 
+# Kernels behind each operator call (the roofline's unit is one operator call).
+OP_KERNELS = {"spread": "ib_spread = gather_rows_kernel (F into sorted order) + spread_kernel",
+              "interp": "ib_interpolate = interp_kernel"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cube_1e6pts.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2012_06646_amd", "csrc", f)
+                  for f in ("ops_kernels.hip", "device_common.h", "ib_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(op, dtype):
+    """HBM bytes per operator call from the committed FETCH_SIZE/WRITE_SIZE summary, scaled
+    by the copy calibration; None when the summary is missing or the operator kernels'
+    sources changed after the counters were taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    want = f"traffic {dtype} {op}:"
+    src = None
+    for line in text.splitlines():
+        if line.startswith("kernel sources sha256:"):
+            src = line.split(":", 1)[1].strip()
+        if line.startswith(want) and src == kernel_source_hash():
+            return int(line.split(":", 1)[1].split()[0])
+    return None
+
+
 def cpu_baseline(g, X, F, u, sample):
     """The CPU oracle as it stands (single thread) on the first `sample` points of the same
     workload: keys + stable sort for each staggering, spreading, interpolation."""
@@ -60,8 +94,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--npts", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=250_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the step captured once in a HIP graph and replayed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy 5 times (the reference "
                          "kernel for scaling HBM byte counters)")
@@ -112,47 +148,61 @@ def main():
         plan.interpolate(ud, U)
         ibops.advect(g, X, U, 0.1 * h)
 
+    def timed(fn, K):
+        """Average ms per call of fn over K back-to-back calls, from two HIP events on the
+        stream the library launches on (torch's current stream)."""
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s0.record(stream)
+        for _ in range(K):
+            fn()
+        s1.record(stream)
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / K
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
+    # The timed region: K whole steps, no host synchronisation inside.
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_host0 = time.perf_counter()
-    start.record(stream)
-    for k in range(K):
-        e = ev[k]
-        e[0].record(stream)
-        plan.update(X)
-        e[1].record(stream)
-        plan.spread(Fd, f)
-        e[2].record(stream)
-        plan.interpolate(ud, U)
-        e[3].record(stream)
-        ibops.advect(g, X, U, 0.1 * h)
-        e[4].record(stream)
-    end.record(stream)
-    torch.cuda.synchronize()
+    ms_step = timed(step, K)
     t_host = time.perf_counter() - t_host0
     if plan.status() != 0:
         print("bench.py: device flagged a data error", file=sys.stderr)
         sys.exit(1)
+    value = npts / (ms_step / 1e3)
 
-    ms_total = start.elapsed_time(end)
-    ms_step = ms_total / K
-    stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
-                for i, name in enumerate(["plan", "spread", "interp", "advect"])}
-    value = npts * K / (ms_total / 1e3)
+    # Per-operator averages: each operator alone, K calls back to back on the positions the
+    # steps left (the dominant operator's duration feeds the roofline).
+    stage_ms = {
+        "plan": timed(lambda: plan.update(X), K),
+        "spread": timed(lambda: plan.spread(Fd, f), K),
+        "interp": timed(lambda: plan.interpolate(ud, U), K),
+    }
+
+    graph_ms = None
+    if args.graph:
+        gr = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(stream)
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(gr, stream=cap):
+                step()
+        stream.wait_stream(cap)
+        gr.replay()
+        torch.cuda.synchronize()
+        graph_ms = timed(gr.replay, K)
 
     algo = algorithmic_bytes(npts, dim, ncomp, G, b)
     dom = max(("spread", "interp"), key=lambda s: stage_ms[s])
     achieved = algo[dom] / (stage_ms[dom] / 1e3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+    traffic = measured_traffic(dom, args.dtype)
+    roofline = {"bound": "hbm", "kernel": OP_KERNELS[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": traffic,
                 "algorithmic_bytes_per_launch": algo[dom]}
 
     out = {
@@ -163,6 +213,7 @@ def main():
         "steps": K,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_graph": graph_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -172,7 +223,7 @@ def main():
                                "N(0,1) forces and grid velocities, Peskin 4-point; step = plan + "
                                "spread + interpolate + advect (dt = 0.1 h)",
                    "grid": [128, 128, 128], "npts": npts, "seed": 1002},
-        "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "operator_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "step_algorithmic_bytes": sum(algo.values()),
         "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "host_wall_s": round(t_host, 4),

@@ -9,6 +9,18 @@
 
 namespace ibk {
 
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), and each XCD has its own L2.  xcd_block renumbers the workgroups so that each
+// XCD runs one contiguous range of logical blocks: neighbouring work then shares an L2.
+// A bijection of [0, nblk) for every nblk.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblk)
+{
+    const int x = b % NUM_XCD, i = b / NUM_XCD;
+    const int q = nblk / NUM_XCD, r = nblk % NUM_XCD;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 

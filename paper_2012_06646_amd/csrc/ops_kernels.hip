@@ -11,22 +11,23 @@
 // Spreading (eq. disc-spread, Sec. 2; parallel algorithm Alg. 4, Sec. 3.3).  Each block
 // owns a tile of one component's grid and produces every value of it exactly once.  It
 // reads the sorted points whose cells can reach the tile (contiguous sorted ranges per
-// x-row, since keys are x-fastest).  A wave takes 64 consecutive points, computes their
-// weights, then sorts the 64 lanes by component-c cell (a bitonic network across the
-// wave), so equal cells form runs; the first lane of each run sums the run's
-// contributions to all 4^d shifts in registers -- the segmented reduce of Alg. 4, for all
-// shifts at once.  Run heads of one wave hold distinct cells, so for any shift their
-// targets differ and the read-add-writes into the LDS tile never collide.  The waves of a
-// block take source slices (planes in 3-D, rows in 2-D) far enough apart that their
-// targets are disjoint, in phases separated by barriers.  The order in which every grid
-// value receives its contributions is fixed by the data alone: no atomics, and the result
-// is bitwise reproducible.
+// x-row, since keys are x-fastest), one source plane at a time.  A wave takes 64
+// consecutive points of a plane and computes their weights; lanes holding the same
+// component-c cell form a group (adjacent lanes for staggering 0, found by matching cell
+// codes with ballots otherwise), and the group's lowest lane, its leader, sums the
+// group's contributions to all 4^d shifts in registers -- the segmented reduce of Alg. 4,
+// for all shifts at once.  Leaders of one wave hold distinct cells, so for any one shift
+// their targets differ and the read-add-writes into the LDS tile never collide.  The
+// waves of a block take source planes far enough apart that their targets are disjoint,
+// in phases separated by barriers.  The order in which every grid value receives its
+// contributions is fixed by the data alone: no atomics, and the result is bitwise
+// reproducible.
 //
-// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  Each block owns a tile of
-// staggering-0 cells; for each component in turn it stages that component's grid values
-// over the tile plus halo in LDS with coalesced loads; one thread per point accumulates
-// the 4^d products in registers in tensor-product order, and finally writes all of the
-// point's components together.
+// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  One thread per point in the sorted
+// order of staggering 0, gathering the 4^d grid values of each component directly
+// (neighbouring lanes hold neighbouring cells, so a wave's gathers share cache lines);
+// the point's components are accumulated in registers in tensor-product order and
+// written together.
 #include "device_common.h"
 
 namespace ibk {
@@ -179,11 +180,6 @@ struct SpreadTile {
         return has ? m : 0ull;
     }
 
-    // Add a leader's 4^d sums into the tile.  For one shift the leaders of a wave hit
-    // distinct targets, but for different shifts they may not, so each read-add-write must
-    // complete before the next shift's read -- except for shifts whose slice-axis offsets
-    // (z in 3-D, y in 2-D) differ by more than `span`, the largest difference between the
-    // leaders' cells along that axis: those never share a target and go in one batch.
     // Add a leader's 4^d sums into the tile.  The tile rows are padded in x (PXS = TX + 6,
     // target x from -3 to TX + 2), so only whole rows can fall outside the tile; such rows,
     // and every row of a lane that is not a leader, go to the lane's own dummy row.
@@ -237,11 +233,6 @@ struct SpreadTile {
         }
     }
 
-    // Reduce the slice in chunks of 64 points and add the sums into the tile.
-    // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
-    // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
-    // group; its lowest lane (the leader) sums the group's contributions to all 4^d shifts
-    // in registers, pulling each member's offsets and force from the member's lane.
     // Sorted position v of the slice: its range, key, coordinates and force (zeros past
     // the end).
     __device__ static void load(const OpArgs& a, int c, const int32_t* __restrict__ sk,
@@ -270,6 +261,11 @@ struct SpreadTile {
         }
     }
 
+    // Reduce the slice in chunks of 64 points and add the sums into the tile.
+    // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
+    // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
+    // group; its lowest lane (the leader) sums the group's contributions to all 4^d shifts
+    // in registers, pulling each member's offsets and force from the member's lane.
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
                                   const Table& tb, int nranges, int total, int q, const int off[3],
                                   int ex, int ey, int ez, bool same0, int span, T* drow,
@@ -368,7 +364,7 @@ struct SpreadTile {
 };
 
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
+__device__ void spread_body(const OpArgs& a, int bid)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
     // Tile rows padded in x (3 before, 3 after); then one 4-wide dummy row per thread,
@@ -376,7 +372,7 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
     __shared__ T tile[ST::PXS * TY * TZ + 5 * 256];
     __shared__ typename ST::Table tables[4];
     const GeomArgs& g = a.g;
-    int b = blockIdx.x;
+    int b = bid;
     const int bx = b % a.tiles[0]; b /= a.tiles[0];
     const int by = b % a.tiles[1]; b /= a.tiles[1];
     const int bz = b % a.tiles[2]; b /= a.tiles[2];
@@ -431,20 +427,32 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
     }
 }
 
+template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
+{
+    spread_body<T, DIM, KERN, TX, TY, TZ>(a, blockIdx.x);
+}
+
 // Forces into the sorted order of staggering 0 (one gather of whole rows).
+template <typename T>
+__device__ void gather_rows_body(int64_t n, int ncols, const int32_t* __restrict__ perm,
+                                 const T* __restrict__ src, T* __restrict__ dst, int bid, int nblk)
+{
+    const int64_t total = n * ncols;
+    for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
+        const int64_t i = e / ncols;
+        const int k = (int)(e - i * ncols);
+        dst[e] = src[clamp_index(perm[i], n) * ncols + k];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int ncols,
                                                           const int32_t* __restrict__ perm,
                                                           const T* __restrict__ src,
                                                           T* __restrict__ dst)
 {
-    const int64_t total = n * ncols;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / ncols;
-        const int k = (int)(e - i * ncols);
-        dst[e] = src[clamp_index(perm[i], n) * ncols + k];
-    }
+    gather_rows_body<T>(n, ncols, perm, src, dst, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int ncols,
 // neighbouring cells, so the 4^d gathers of a wave share cache lines.  All components of a
 // point are accumulated in registers and written together.
 template <typename T, int DIM, int KERN>
-__global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
+__device__ void interp_body(const OpArgs& a, int bid, int nblk)
 {
     const GeomArgs& g = a.g;
     const int64_t n = g.npts;
@@ -463,8 +471,7 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
     const T* __restrict__ Xs = (const T*)a.Xs;
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)nblk * blockDim.x) {
         T x[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
@@ -510,6 +517,12 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
     }
 }
 
+template <typename T, int DIM, int KERN>
+__global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
+{
+    interp_body<T, DIM, KERN>(a, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+}
+
 // ---------------------------------------------------------------------------------------
 // Position gradient of interpolation: dX_j += sum_c W_{j,c} dU_{j,c} / dX_j, U = J(X) u.
 // dW/dX_k = (1/h_k) dw_k(r_k) prod_{l != k} w_l(r_l); one thread per sorted point.
@@ -524,8 +537,8 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
     const int64_t G = (int64_t)n0 * n1 * n2;
     const T* __restrict__ Xs = (const T*)a.Xs;
     const T* __restrict__ u = (const T*)a.u;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         T x[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];

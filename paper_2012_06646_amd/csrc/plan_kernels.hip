@@ -17,16 +17,20 @@
 namespace ibk {
 
 // ---- reset: clear histograms, look-back words, tickets and the error flag -------------
+__device__ void plan_reset_body(uint32_t* __restrict__ p, size_t nwords, int bid, int nblk)
+{
+    for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < nwords; i += (size_t)nblk * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
-         i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
+    plan_reset_body(p, nwords, blockIdx.x, gridDim.x);
 }
 
 // ---- keys: one per point and distinct staggering, plus all pass histograms ----------
 template <typename T>
-__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X)
+__device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk)
 {
     extern __shared__ uint32_t lhist[];  // [nstag][npass][R]
     const GeomArgs& g = a.g;
@@ -37,8 +41,7 @@ __global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restri
 
     const int64_t n = g.npts;
     bool any_bad = false;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)nblk * blockDim.x) {
         T x[3];
         for (int k = 0; k < g.dim; ++k) x[k] = X[j * g.dim + k];
         bool bad = false;
@@ -62,6 +65,12 @@ __global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restri
     __syncthreads();
     for (int i = threadIdx.x; i < nh; i += blockDim.x)
         if (lhist[i]) atomicAdd(&a.d.hist[i], lhist[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X)
+{
+    keys_body<T>(a, X, blockIdx.x, gridDim.x);
 }
 
 // ---- decoupled look-back over one counter per tile ------------------------------------
@@ -104,7 +113,7 @@ __device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t st
 
 // ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
 template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int s, int pass)
+__device__ void radix_pass_body(const SortArgs& a, int s, int pass)
 {
     constexpr int R = 1 << RBITS;
     constexpr int NW = SORT_BLOCK / 64;
@@ -213,12 +222,20 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
     }
 }
 
+template <int RBITS>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int s, int pass)
+{
+    radix_pass_body<RBITS>(a, s, pass);
+}
+
 // ---- segments: run heads, q, seg_off and the cell-block start table -------------------
 template <typename T>
-__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s, const int32_t* sk_all,
-                                                              const int32_t* perm_all,
-                                                              const T* __restrict__ X, T* __restrict__ Xs)
+__device__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
 {
+    // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
+    const bool in_a = (a.g.npts == 0) || (a.npass & 1);
+    const int32_t* sk_all = in_a ? a.d.kA : a.d.kB;
+    const int32_t* perm_all = in_a ? a.d.vA : a.d.vB;
     constexpr int NW = SORT_BLOCK / 64;
     __shared__ uint32_t s_wtot[NW];
     __shared__ uint32_t s_ticket;
@@ -303,6 +320,13 @@ __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s,
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s, const T* __restrict__ X,
+                                                              T* __restrict__ Xs)
+{
+    segments_body<T>(a, s, X, Xs);
+}
+
 // ---- host launchers ---------------------------------------------------------------------
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
 {
@@ -345,16 +369,12 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
             }
         }
     }
-    // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
-    const bool in_a = (g.npts == 0) || (a.npass & 1);
-    const int32_t* sk = in_a ? a.d.kA : a.d.kB;
-    const int32_t* pv = in_a ? a.d.vA : a.d.vB;
     const dim3 grid((unsigned)a.nseg_tiles);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(segments_kernel<double>, grid, dim3(SORT_BLOCK), 0, st, a, s, sk, pv,
+        hipLaunchKernelGGL(segments_kernel<double>, grid, dim3(SORT_BLOCK), 0, st, a, s,
                            (const double*)X, gather_x ? (double*)a.d.Xs : nullptr);
     else
-        hipLaunchKernelGGL(segments_kernel<float>, grid, dim3(SORT_BLOCK), 0, st, a, s, sk, pv,
+        hipLaunchKernelGGL(segments_kernel<float>, grid, dim3(SORT_BLOCK), 0, st, a, s,
                            (const float*)X, gather_x ? (float*)a.d.Xs : nullptr);
     return hipGetLastError();
 }

@@ -14,14 +14,15 @@
 // x-row, since keys are x-fastest), one source plane at a time.  A wave takes 64
 // consecutive points of a plane and computes their weights; lanes holding the same
 // component-c cell form a group (adjacent lanes for staggering 0, found by matching cell
-// codes with ballots otherwise), and the group's lowest lane, its leader, sums the
-// group's contributions to all 4^d shifts in registers -- the segmented reduce of Alg. 4,
-// for all shifts at once.  Leaders of one wave hold distinct cells, so for any one shift
-// their targets differ and the read-add-writes into the LDS tile never collide.  The
-// waves of a block take source planes far enough apart that their targets are disjoint,
-// in phases separated by barriers.  The order in which every grid value receives its
-// contributions is fixed by the data alone: no atomics, and the result is bitwise
-// reproducible.
+// codes with ballots otherwise).  The group's sum over its points of the 4^d weight
+// products -- the segmented reduce of Alg. 4, for all shifts at once -- is formed in
+// registers (by one lane, or for a crowded cell by several lanes combined in a tree), and
+// its first lane adds it into an FP64 LDS copy of the tile with LDS atomic adds.  Those
+// lanes hold distinct cells, so for one shift the active lanes of an instruction hit
+// distinct addresses; the waves of a block take source planes far enough apart that their
+// targets are disjoint, in phases separated by barriers.  The order in which every grid
+// value receives its contributions is therefore fixed by the data alone, and the result is
+// bitwise reproducible; no global atomics are used.
 //
 // Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  One thread per point in the sorted
 // order of staggering 0, gathering the 4^d grid values of each component directly
@@ -180,57 +181,34 @@ struct SpreadTile {
         return has ? m : 0ull;
     }
 
-    // Add a leader's 4^d sums into the tile.  The tile rows are padded in x (PXS = TX + 6,
-    // target x from -3 to TX + 2), so only whole rows can fall outside the tile; such rows,
-    // and every row of a lane that is not a leader, go to the lane's own dummy row.
-    // For one shift the leaders of a wave hit distinct targets, but for different shifts
-    // they may not, so each read-add-write must complete before the next shift's read --
-    // except for shifts whose slice-axis offsets (z in 3-D, y in 2-D) differ by more than
-    // `span`, the largest difference between the leaders' cells along that axis: those
-    // never share a target and go in one batch.
+    // Add a leader's 4^d sums into the tile with LDS atomic adds (ds_add), which apply the
+    // read-add-write inside the LDS unit, so no lane waits for a value.  The order of the
+    // additions into any tile value is still fixed: the leaders of one wave hold distinct
+    // cells, so for one shift the active lanes of an instruction hit distinct addresses;
+    // a wave's LDS instructions execute in program order; and waves working at the same
+    // time own disjoint target regions.  Tile rows are padded in x (PXS = TX + 6, target
+    // x from -3 to TX + 2), so only whole rows can fall outside the tile; those are skipped.
     __device__ static void add_to_tile(const T acc[NZ][4][4], bool leader, int cx, int cy,
-                                       int cz, int ey, int ez, int span, T* drow, T* tile)
+                                       int cz, int ey, int ez, double* tile)
     {
-        // Row pointer for (slice-axis offset ia, in-plane offset ib).
-        T* rowp[4][4];
 #pragma unroll
         for (int ia = 0; ia < 4; ++ia)
 #pragma unroll
-            for (int ib = 0; ib < 4; ++ib) {
+            for (int ib = 0; ib < ((DIM == 3) ? 4 : 1); ++ib) {
                 int ty, tz;
                 if (DIM == 3) { tz = cz - 1 + ia; ty = cy - 1 + ib; }
                 else { tz = 0; ty = cy - 1 + ia; }
-                const bool ok = leader && (unsigned)ty < (unsigned)ey && (unsigned)tz < (unsigned)ez &&
-                                (DIM == 3 || ib == 0);
-                rowp[ia][ib] = ok ? tile + (tz * TY + ty) * PXS + (cx + 2) : drow;
-            }
-        constexpr int NB = (DIM == 3) ? 4 : 1;
+                const bool ok = leader && (unsigned)ty < (unsigned)ey && (unsigned)tz < (unsigned)ez;
+                if (ok) {
+                    double* row = tile + (tz * TY + ty) * PXS + (cx + 2);
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-#pragma unroll
-            for (int ix = 0; ix < 4; ++ix) {
-                T val[4];
-#pragma unroll
-                for (int ia = 0; ia < 4; ++ia) val[ia] = (DIM == 3) ? acc[ia][ib][ix] : acc[0][ia][ix];
-                if (span == 0) {
-                    T old[4];
-#pragma unroll
-                    for (int ia = 0; ia < 4; ++ia) old[ia] = rowp[ia][ib][ix];
-#pragma unroll
-                    for (int ia = 0; ia < 4; ++ia) rowp[ia][ib][ix] = old[ia] + val[ia];
-                } else if (span == 1) {  // pairs (-1, +1) and (0, +2) along the slice axis
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const T o0 = rowp[h][ib][ix], o1 = rowp[h + 2][ib][ix];
-                        rowp[h][ib][ix] = o0 + val[h];
-                        rowp[h + 2][ib][ix] = o1 + val[h + 2];
+                    for (int ix = 0; ix < 4; ++ix) {
+                        const double v = (DIM == 3) ? acc[ia][ib][ix] : acc[0][ia][ix];
+                        __hip_atomic_fetch_add(row + ix, v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                } else {
-#pragma unroll
-                    for (int ia = 0; ia < 4; ++ia) rowp[ia][ib][ix] = rowp[ia][ib][ix] + val[ia];
                 }
             }
-        }
     }
 
     // Sorted position v of the slice: its range, key, coordinates and force (zeros past
@@ -268,8 +246,8 @@ struct SpreadTile {
     // in registers, pulling each member's offsets and force from the member's lane.
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
                                   const Table& tb, int nranges, int total, int q, const int off[3],
-                                  int ex, int ey, int ez, bool same0, int span, T* drow,
-                                  T* tile)
+                                  int ex, int ey, int ez, bool same0, double* tile,
+                                  int32_t* ltab)
     {
         const GeomArgs& g = a.g;
         const int lane = lane_id();
@@ -316,17 +294,42 @@ struct SpreadTile {
                 leader = has && (lane == 0 || !hprev || prev != code);
                 const unsigned long long heads = __ballot(leader);
                 const unsigned long long holes = ~__ballot(has);
-                const unsigned long long stop = (heads | holes) & ~((2ull << lane) - 1ull);
+                // This lane's run starts at the highest head at or below it and ends at the
+                // next head or hole above that.
+                const unsigned long long hb = heads & ((2ull << lane) - 1ull);
+                const int head = hb ? 63 - __clzll((long long)hb) : lane;
+                const unsigned long long stop = (heads | holes) & ~((2ull << head) - 1ull);
                 const int end = stop ? __ffsll((long long)stop) - 1 : 64;
                 const unsigned long long upto = (end == 64) ? ~0ull : ((1ull << end) - 1ull);
-                grp = leader ? (upto & ~below) : 0ull;
+                grp = has ? (upto & ~((1ull << head) - 1ull)) : 0ull;
             } else {
                 grp = match_code(code, has);
                 leader = has && (grp & below) == 0ull;
             }
-            unsigned long long rest = leader ? (grp & ~(1ull << lane)) : 0ull;
-            const int cnt = __popcll(rest);
-            const int maxc = wave_max_i32(cnt);
+            // Group layout: each group gets a contiguous range of the wave's lane table, in
+            // rank order (the rank of a lane is the number of group lanes below it), so any
+            // member's lane is found from (group offset, rank).
+            const int rank = __popcll(grp & below);
+            const int gk = __popcll(grp);
+            const int maxk = wave_max_i32(gk);
+            int gbase;
+            {
+                const uint32_t kl = leader ? (uint32_t)gk : 0u;
+                const int goff_l = (int)(wave_incl_scan_u32(kl) - kl);
+                const int lead_lane = has ? __ffsll((long long)grp) - 1 : lane;
+                const int goff = __shfl(goff_l, lead_lane, 64);
+                if (has) ltab[goff + rank] = lane;
+                wave_sync();
+                gbase = goff;
+            }
+            // The first P members of a group (sub-leaders) each sum every P-th member, then
+            // a tree over the sub-leaders folds their sums into the leader.  P grows with
+            // the largest group of the wave, so a crowded cell costs O(k / P + log P)
+            // rounds instead of O(k); a tree step moves all 4^d sums between lanes and costs
+            // about five member rounds, which sets the thresholds.  P is uniform across the
+            // wave and depends only on the data, so the order of every sum is fixed.
+            const int P = maxk > 40 ? 8 : maxk > 20 ? 4 : maxk > 10 ? 2 : 1;
+            const bool sub = has && rank < P;
             T acc[NZ][4][4];
 #pragma unroll
             for (int iz = 0; iz < NZ; ++iz)
@@ -339,25 +342,40 @@ struct SpreadTile {
 #pragma unroll
                 for (int d = 0; d < DIM; ++d)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) wl[d][i] = leader ? w[d][i] : T(0);
+                    for (int i = 0; i < 4; ++i) wl[d][i] = sub ? w[d][i] : T(0);
                 accumulate(acc, wl);
             }
-            for (int k = 0; k < maxc; ++k) {  // the group's other points, from their lanes
-                const int src = rest ? __ffsll((long long)rest) - 1 : lane;
-                rest &= rest - 1ull;
-                T xm[DIM];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) xm[d] = __shfl(x[d], src, 64);
-                const T Fm = __shfl(Fc, src, 64);
+            const int iters = (maxk + P - 1) / P - 1;
+            for (int j = 1; j <= iters; ++j) {
+                const int mr = rank + j * P;
+                const bool ok = sub && mr < gk;
+                const int src = ok ? ltab[(gbase + mr) & 63] : lane;
                 T wk[DIM][4];
-                int dd[DIM];
-                comp_weights<T, DIM, KERN>(g, c, xm, wk, dd);
-                const T fk = (k < cnt) ? Fm : T(0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) wk[DIM - 1][i] *= fk;
+                for (int d = 0; d < DIM; ++d)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) wk[d][i] = __shfl(w[d][i], src, 64);
+                const T on = ok ? T(1) : T(0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) wk[DIM - 1][i] *= on;
                 accumulate(acc, wk);
             }
-            add_to_tile(acc, leader, cx, cy, cz, ey, ez, span, drow, tile);
+            for (int st = 1; st < P; st <<= 1) {
+                const int pr = rank + st;
+                const bool ok = sub && (rank & (2 * st - 1)) == 0 && pr < gk && pr < P;
+                const int src = ok ? ltab[(gbase + pr) & 63] : lane;
+#pragma unroll
+                for (int iz = 0; iz < NZ; ++iz)
+#pragma unroll
+                    for (int iy = 0; iy < 4; ++iy)
+#pragma unroll
+                        for (int ix = 0; ix < 4; ++ix) {
+                            const T v = __shfl(acc[iz][iy][ix], src, 64);
+                            acc[iz][iy][ix] += ok ? v : T(0);
+                        }
+            }
+            wave_sync();
+            add_to_tile(acc, leader, cx, cy, cz, ey, ez, tile);
             wave_sync();
         }
     }
@@ -367,10 +385,11 @@ template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __device__ void spread_body(const OpArgs& a, int bid)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
-    // Tile rows padded in x (3 before, 3 after); then one 4-wide dummy row per thread,
-    // 5 elements apart so that the dummy rows of 16 consecutive lanes use distinct banks.
-    __shared__ T tile[ST::PXS * TY * TZ + 5 * 256];
+    // Tile rows padded in x (3 before, 3 after).  The tile accumulates in FP64 for both
+    // precisions: FP64 LDS atomic adds run at full LDS rate on gfx950, FP32 ones do not.
+    __shared__ double tile[ST::PXS * TY * TZ];
     __shared__ typename ST::Table tables[4];
+    __shared__ int32_t ltabs[4][64];  // per wave: lanes of each group in rank order
     const GeomArgs& g = a.g;
     int b = bid;
     const int bx = b % a.tiles[0]; b /= a.tiles[0];
@@ -381,7 +400,7 @@ __device__ void spread_body(const OpArgs& a, int bid)
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
 
-    for (int i = threadIdx.x; i < ST::PXS * TY * TZ; i += blockDim.x) tile[i] = T(0);
+    for (int i = threadIdx.x; i < ST::PXS * TY * TZ; i += blockDim.x) tile[i] = 0.0;
     __syncthreads();
 
     // Source frame: staggering-0 cells that can reach the tile for this component.
@@ -395,7 +414,6 @@ __device__ void spread_body(const OpArgs& a, int bid)
     const int nphase = 4 + ((DIM == 3) ? hz : hy);
     const int nranges = 3 * nrows;
     const bool same0 = hx == 0 && hy == 0 && hz == 0;
-    const int span = (DIM == 3) ? hz : hy;  // spread of leader cells along the slice axis
     const int w = wave_id();
     typename ST::Table& tb = tables[w];
 
@@ -408,7 +426,7 @@ __device__ void spread_body(const OpArgs& a, int bid)
             const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb);
             if (total > 0)
                 ST::reduce(a, c, a.sorted_keys, tb, nranges, total, q, off, ex, ey, ez, same0,
-                           span, tile + ST::PXS * TY * TZ + 5 * threadIdx.x, tile);
+                           tile, ltabs[w]);
             wave_sync();
         }
         __syncthreads();
@@ -416,12 +434,11 @@ __device__ void spread_body(const OpArgs& a, int bid)
 
     T* f = (T*)a.f;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
-    const T scale = (T)g.scale;
     for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
         const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
         if (xr >= ex || yr >= ey || zr >= ez) continue;
         const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
-        const T v = tile[(zr * TY + yr) * ST::PXS + xr + 3] * scale;
+        const T v = (T)(tile[(zr * TY + yr) * ST::PXS + xr + 3] * g.scale);
         T* dst = f + (int64_t)c * G + gi;
         *dst = a.accumulate ? *dst + v : v;
     }

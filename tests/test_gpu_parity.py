@@ -145,6 +145,41 @@ def test_ops_clustered_points(ib, orc):
     check_ops(ib, orc, g, X, F, u, torch.float64, "clustered")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ops_mixed_cell_crowding(ib, orc, dtype):
+    """Cells holding 1 to 90 points side by side, so the waves see every group size that
+    changes how a crowded cell is summed, plus scattered single points."""
+    g = wl.grid(3, [40, 36, 32], 1.0)
+    r = wl.rng(31)
+    h = 1.0 / np.array(g["n"], dtype=np.float64)
+    parts = []
+    for k in list(range(1, 41)) + [47, 55, 64, 65, 90]:
+        cell = r.integers(0, g["n"]) * h
+        parts.append(cell + r.random((k, 3)) * h)          # k points in one cell
+    parts.append(r.random((3000, 3)))
+    X = np.concatenate(parts) % 1.0
+    X = X[r.permutation(X.shape[0])]
+    F = r.standard_normal((X.shape[0], 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    check_ops(ib, orc, g, X, F, u, dtype, "mixed crowding")
+
+
+def test_clustered_bitwise_run_to_run(ib):
+    g = wl.grid(3, [32, 32, 32], 1.0)
+    r = wl.rng(37)
+    centres = r.random((12, 3))
+    X = (centres[r.integers(0, 12, 40000)] + 0.02 * r.standard_normal((40000, 3))) % 1.0
+    F = r.standard_normal((40000, 3))
+    p = ib.Plan(g, X.shape[0], torch.float64)
+    Xd, Fd = to_dev(X, torch.float64), to_dev(F, torch.float64)
+    outs = []
+    for _ in range(3):
+        p.update(Xd)
+        outs.append(to_host(p.spread(Fd)))
+    for f in outs[1:]:
+        assert np.array_equal(f, outs[0])
+
+
 def test_ops_2d(ib, orc):
     g = wl.grid(2, [100, 36], [2.0, 0.72])
     X, F, u = wl.uniform_case(g, 9000, 24)
@@ -218,3 +253,21 @@ def test_config2_full_size(ib, orc, dtype):
     Xc = X.astype(nd)
     check_plan(ib, orc, g, Xc, dtype, "config2")
     check_ops(ib, orc, g, X, F, u, dtype, "config2")
+
+
+def test_config2_after_advection(ib, orc):
+    """The 128^3 / 10^6 workload after 50 steps of its own advection (points have gathered
+    into crowded cells): plan and operators against the oracle on the GPU's positions."""
+    g, X, F, u = wl.config2()
+    dtype = torch.float64
+    h = 1.0 / 128
+    Xd, Fd, ud = to_dev(X, dtype), to_dev(F, dtype), to_dev(u, dtype)
+    p = ib.Plan(g, X.shape[0], dtype)
+    for _ in range(50):
+        p.update(Xd)
+        U = p.interpolate(ud)
+        ib.advect(g, Xd, U, 0.1 * h)
+    assert p.status() == 0
+    Xk = to_host(Xd)
+    check_plan(ib, orc, g, Xk, dtype, "config2 step 50")
+    check_ops(ib, orc, g, Xk, F, u, dtype, "config2 step 50")

@@ -138,6 +138,52 @@ int32_t ib_interpolate_grad(ib_plan plan, const void *u, const void *W, void *dX
 int32_t ib_advect(const ib_grid_desc *grid, int32_t dtype, int64_t npts, void *X, const void *U,
                   double dt, void *stream);
 
+/* ---- batches of independent jobs ---------------------------------------------------- */
+
+/* One job of a batch: a point set on its own grid, with spreading (F -> f) and/or
+ * interpolation (u -> U) requested.  Pointers are device pointers in the batch's dtype,
+ * with the layouts of ib_spread / ib_interpolate; f == NULL skips spreading, u == NULL
+ * skips interpolation.  f and U are overwritten. */
+typedef struct {
+    ib_grid_desc grid;
+    int64_t npts;
+    const void *X;   /* npts x dim */
+    const void *F;   /* npts x ncomp (may be NULL when f is NULL or npts == 0) */
+    void *f;         /* ncomp x grid, or NULL */
+    const void *u;   /* ncomp x grid, or NULL */
+    void *U;         /* npts x ncomp (may be NULL when u is NULL or npts == 0) */
+} ib_job;
+
+#define IB_BATCH_MAX_JOBS 128
+
+/* Bytes of device workspace for a batch (0 on invalid arguments).  All jobs share the
+ * dtype, the dimension and the kernel; grids and point counts may differ. */
+size_t ib_batch_workspace_bytes(const ib_job *jobs, int32_t njobs, int32_t dtype);
+
+/* Bytes of host staging memory ib_batch_run uses for the job table (0 if njobs is out of
+ * range). */
+size_t ib_batch_staging_bytes(int32_t njobs);
+
+/* Run the plan (Alg. 4 preparation: keys, stable sort, segments), the spreading and the
+ * interpolation of every job of the batch, with one launch per stage for all jobs: each
+ * launch covers the blocks of every job, mapped through a job table in the workspace.
+ * Results equal those of ib_plan_update + ib_spread + ib_interpolate per job, bit for bit.
+ * workspace: caller-owned device memory, >= ib_batch_workspace_bytes, 256-byte aligned,
+ * not touched by anyone else until the batch has finished.  host_staging: pinned host
+ * memory of ib_batch_staging_bytes(njobs) bytes, left unchanged until the batch has
+ * finished; or NULL, in which case the table is uploaded from pageable memory, which makes
+ * this call wait for earlier work on the stream.  Asynchronous otherwise.
+ * Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED (njobs > IB_BATCH_MAX_JOBS, mixed dimension or
+ * kernel, a bad grid), IB_ERR_OOM (workspace too small), IB_ERR_HIP. */
+int32_t ib_batch_run(const ib_job *jobs, int32_t njobs, int32_t dtype, void *workspace,
+                     size_t workspace_bytes, void *host_staging, void *stream);
+
+/* Synchronise the stream, then report per job (job_status[j], may be NULL) whether the
+ * device flagged a data error in its positions; returns IB_ERR_DEVICE_FLAG if any did.
+ * The jobs and workspace must be those of the last ib_batch_run on that workspace. */
+int32_t ib_batch_status(const ib_job *jobs, int32_t njobs, int32_t dtype, const void *workspace,
+                        int32_t *job_status, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libibops.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["ib_api.cpp", "plan_kernels.hip", "ops_kernels.hip"]
+SOURCES = ["ib_api.cpp", "ib_batch.cpp", "plan_kernels.hip", "ops_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("IBOPS_ARCH", "gfx950")
 

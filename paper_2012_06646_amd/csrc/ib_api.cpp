@@ -7,26 +7,12 @@
 #include <new>
 
 #include "ib.h"
+#include "ib_host.h"
 #include "ib_internal.h"
 
 using namespace ibk;
 
-struct ib_plan_s {
-    ib_grid_desc grid;
-    int32_t dtype;
-    int64_t npts;
-    SortArgs sa;           // geometry, device pointers, radix configuration
-    int32_t* sorted_keys;  // final sort output (aliases kA or kB)
-    int32_t* perm;
-    const void* X;         // positions of the last update
-    hipStream_t last_stream;
-    int updated;
-    uint32_t sorted_mask;  // staggerings sorted since the last update
-};
-
-namespace {
-
-constexpr size_t ALIGN = 256;
+namespace ibk {
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -36,14 +22,6 @@ int bits_for(int64_t G)
     while ((int64_t(1) << b) < G) ++b;
     return b;
 }
-
-struct Layout {
-    int nstag, npass, rbits, rows, nbx;
-    int64_t ntiles, nseg_tiles, G;
-    // byte offsets
-    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, zero_begin, hist, sort_status,
-        seg_status, counters, flag, zero_end, total;
-};
 
 // Validate a descriptor; fill the distinct staggerings.
 int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nstag,
@@ -85,7 +63,8 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     return IB_OK;
 }
 
-void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L)
+void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
+                 int rbits_fixed)
 {
     L->nstag = nstag;
     L->G = 1;
@@ -96,6 +75,11 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->npass = (bits + MAX_RADIX_BITS - 1) / MAX_RADIX_BITS;
     L->rbits = (bits + L->npass - 1) / L->npass;
     if (L->rbits < 4) L->rbits = 4;
+    if (rbits_fixed > 0) {
+        L->rbits = rbits_fixed;
+        L->npass = (bits + rbits_fixed - 1) / rbits_fixed;
+        if (L->npass < 1) L->npass = 1;
+    }
     L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
     L->nseg_tiles = L->ntiles > 0 ? L->ntiles : 1;
     const int64_t R = int64_t(1) << L->rbits;
@@ -141,7 +125,7 @@ FastDiv make_fastdiv(uint32_t d)
     return f;
 }
 
-}  // namespace
+}  // namespace ibk
 
 extern "C" {
 
@@ -170,22 +154,13 @@ size_t ib_plan_workspace_bytes(const ib_grid_desc* grid, int32_t dtype, int64_t 
     return L.total;
 }
 
-int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* workspace,
-                       size_t workspace_bytes, ib_plan* out)
-{
-    if (!out) return IB_ERR_ARG;
-    *out = nullptr;
-    int nstag, cs[3];
-    double sx[3][3] = {{0}};
-    int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
-    if (st != IB_OK) return st;
-    Layout L;
-    make_layout(grid, dtype, nstag, npts, &L);
-    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
-    if (workspace_bytes < L.total) return IB_ERR_OOM;
+}  // extern "C"
 
-    ib_plan p = new (std::nothrow) ib_plan_s();
-    if (!p) return IB_ERR_OOM;
+namespace ibk {
+
+void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t npts, int nstag,
+                const int cs[3], const double sx[3][3], const Layout& L, void* workspace)
+{
     p->grid = *grid;
     p->dtype = dtype;
     p->npts = npts;
@@ -258,6 +233,29 @@ int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, vo
     p->last_stream = nullptr;
     p->updated = 0;
     p->sorted_mask = 0;
+}
+
+}  // namespace ibk
+
+extern "C" {
+
+int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* workspace,
+                       size_t workspace_bytes, ib_plan* out)
+{
+    if (!out) return IB_ERR_ARG;
+    *out = nullptr;
+    int nstag, cs[3];
+    double sx[3][3] = {{0}};
+    int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
+    if (st != IB_OK) return st;
+    Layout L;
+    make_layout(grid, dtype, nstag, npts, &L);
+    if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
+    if (workspace_bytes < L.total) return IB_ERR_OOM;
+
+    ib_plan p = new (std::nothrow) ib_plan_s();
+    if (!p) return IB_ERR_OOM;
+    plan_setup(p, grid, dtype, npts, nstag, cs, sx, L, workspace);
     *out = p;
     return IB_OK;
 }

@@ -1,0 +1,54 @@
+// Host-side internals of libibops shared by the plan and batch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ib.h"
+#include "ib_internal.h"
+
+struct ib_plan_s {
+    ib_grid_desc grid;
+    int32_t dtype;
+    int64_t npts;
+    ibk::SortArgs sa;      // geometry, device pointers, radix configuration
+    int32_t* sorted_keys;  // final sort output (aliases kA or kB)
+    int32_t* perm;
+    const void* X;         // positions of the last update
+    hipStream_t last_stream;
+    int updated;
+    uint32_t sorted_mask;  // staggerings sorted since the last update
+};
+
+namespace ibk {
+
+constexpr size_t ALIGN = 256;  // alignment of every workspace region
+
+size_t align_up(size_t v);
+
+// Byte layout of one plan's workspace.
+struct Layout {
+    int nstag, npass, rbits, rows, nbx;
+    int64_t ntiles, nseg_tiles, G;
+    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, zero_begin, hist, sort_status,
+        seg_status, counters, flag, zero_end, total;
+};
+
+// Validate a descriptor; find the distinct staggerings (count, component -> stagger index,
+// their offsets).  Returns an ib_status.
+int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nstag,
+                   int comp_stag[3], double stag_xi[3][3]);
+
+// Workspace layout of a plan; rbits_fixed > 0 forces that radix digit width (batched plans
+// share one sort kernel), else the digit width spreads the key bits evenly over passes.
+void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
+                 int rbits_fixed = 0);
+
+// Fill a plan object for a validated descriptor over a workspace of layout L.
+void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t npts, int nstag,
+                const int cs[3], const double sx[3][3], const Layout& L, void* workspace);
+
+int32_t hip_status(hipError_t e);
+
+}  // namespace ibk

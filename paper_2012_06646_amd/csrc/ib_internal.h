@@ -107,6 +107,57 @@ struct OpArgs {
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
 };
 
+// ---- batches: many independent jobs, one launch per stage ------------------------------
+//
+// Every stage kernel of a batch runs the virtual blocks of all jobs: virtual block vb of a
+// stage belongs to job j when starts[stage][j] <= vb < starts[stage][j + 1], as block
+// vb - starts[stage][j] of that job's own launch.  A launch's blocks stride over the
+// virtual blocks, so a launch of any size (e.g. a fixed grid replayed in a graph) covers a
+// batch of any shape.
+constexpr int BATCH_MAX_JOBS = 128;
+constexpr int BATCH_RBITS = 8;       // one radix digit width for every job of a batch
+constexpr int BATCH_MAX_PASSES = 4;  // ceil(31 / 8)
+enum BatchStage {
+    BS_RESET = 0,
+    BS_KEYS,
+    BS_SORT0,  // BS_SORT0 + p: radix pass p
+    BS_SEG = BS_SORT0 + BATCH_MAX_PASSES,
+    BS_GATHER,
+    BS_SPREAD,
+    BS_INTERP,
+    BS_COUNT
+};
+
+struct BatchJob {
+    SortArgs sa;  // the job's plan (staggering 0 is sorted)
+    OpArgs op;    // its operators (F/f and u/U null when not requested)
+};
+
+struct BatchTable {
+    int32_t njobs;
+    int32_t starts[BS_COUNT][BATCH_MAX_JOBS + 1];
+};
+
+// Host-side view of a batch resident in device memory.
+struct BatchLaunch {
+    const BatchJob* jobs;      // device
+    const BatchTable* table;   // device
+    int dtype, dim, kernel;
+    int grid[BS_COUNT];        // blocks to launch per stage (0: skip the stage)
+    size_t keys_lds;           // dynamic LDS of the keys stage (largest job)
+};
+
+// Virtual-block counts of one job (host side).
+int reset_blocks(const SortArgs& a);
+int keys_blocks(const SortArgs& a);
+size_t keys_lds_bytes(const SortArgs& a);
+int gather_blocks(int64_t npts, int ncomp);
+int interp_blocks(int64_t npts);
+void spread_tiles(const GeomArgs& g, int tiles[3]);
+
+hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st);
+hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st);
+
 // Host launchers (stream-ordered; return hipError_t).
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st);
 hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st);

@@ -703,41 +703,138 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 {
-    const int64_t nel = a.g.npts * a.g.ncomp;
-    if (nel > 0) {
-        const unsigned gb = (unsigned)min((int64_t)8192, (nel + 255) / 256);
+    const int gb = gather_blocks(a.g.npts, a.g.ncomp);
+    if (gb > 0)
         hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(gb), dim3(256), 0, st, a.g.npts, a.g.ncomp,
                            a.perm, (const T*)a.F, (T*)a.Fs);
-    }
-    if (a.g.dim == 3) {
-        a.tiles[0] = cdiv(a.g.n[0], SP_TX);
-        a.tiles[1] = cdiv(a.g.n[1], SP_TY);
-        a.tiles[2] = cdiv(a.g.n[2], SP_TZ);
-        const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp);
+    spread_tiles(a.g, a.tiles);
+    const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp);
+    if (a.g.dim == 3)
         hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_TX, SP_TY, SP_TZ>), dim3(nb), dim3(256),
                            0, st, a);
-    } else {
-        a.tiles[0] = cdiv(a.g.n[0], SP2_TX);
-        a.tiles[1] = cdiv(a.g.n[1], SP2_TY);
-        a.tiles[2] = 1;
-        const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.g.ncomp);
+    else
         hipLaunchKernelGGL((spread_kernel<T, 2, KERN, SP2_TX, SP2_TY, 1>), dim3(nb), dim3(256),
                            0, st, a);
-    }
     return hipGetLastError();
 }
 
 template <typename T, int KERN>
 hipError_t interp_dispatch(OpArgs a, hipStream_t st)
 {
-    const unsigned nb = (unsigned)min((int64_t)65536, (a.g.npts + 255) / 256);
+    const unsigned nb = (unsigned)interp_blocks(a.g.npts);
     if (a.g.dim == 3)
         hipLaunchKernelGGL((interp_kernel<T, 3, KERN>), dim3(nb), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((interp_kernel<T, 2, KERN>), dim3(nb), dim3(256), 0, st, a);
     return hipGetLastError();
 }
+
+// ---- batched operator stages ----------------------------------------------------------
+
+__device__ __forceinline__ int batch_job_of(const int32_t* starts, int njobs, int vb)
+{
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (starts[mid] <= vb) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* jobs, const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_GATHER];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job_of(st, nj, vb);
+        const OpArgs& a = jobs[j].op;
+        gather_rows_body<T>(a.g.npts, a.g.ncomp, a.perm, (const T*)a.F, (T*)a.Fs, vb - st[j],
+                            st[j + 1] - st[j]);
+    }
+}
+
+template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void batch_spread_kernel(const BatchJob* jobs, const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_SPREAD];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job_of(st, nj, vb);
+        spread_body<T, DIM, KERN, TX, TY, TZ>(jobs[j].op, vb - st[j]);
+        __syncthreads();
+    }
+}
+
+template <typename T, int DIM, int KERN>
+__global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* jobs, const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_INTERP];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job_of(st, nj, vb);
+        interp_body<T, DIM, KERN>(jobs[j].op, vb - st[j], st[j + 1] - st[j]);
+    }
+}
+
+template <typename T, int DIM, int KERN>
+void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
+{
+    constexpr int TX = DIM == 3 ? SP_TX : SP2_TX, TY = DIM == 3 ? SP_TY : SP2_TY;
+    constexpr int TZ = DIM == 3 ? SP_TZ : 1;
+    if (b.grid[BS_GATHER] > 0)
+        hipLaunchKernelGGL(batch_gather_kernel<T>, dim3(b.grid[BS_GATHER]), dim3(256), 0, st, b.jobs,
+                           b.table);
+    if (b.grid[BS_SPREAD] > 0)
+        hipLaunchKernelGGL((batch_spread_kernel<T, DIM, KERN, TX, TY, TZ>), dim3(b.grid[BS_SPREAD]),
+                           dim3(256), 0, st, b.jobs, b.table);
+    if (b.grid[BS_INTERP] > 0)
+        hipLaunchKernelGGL((batch_interp_kernel<T, DIM, KERN>), dim3(b.grid[BS_INTERP]), dim3(256), 0,
+                           st, b.jobs, b.table);
+}
+
+template <typename T>
+void batch_ops_by_shape(const BatchLaunch& b, hipStream_t st)
+{
+    const bool cos = b.kernel == IB_KERNEL_COSINE4;
+    if (b.dim == 3) cos ? batch_ops_dispatch<T, 3, IB_KERNEL_COSINE4>(b, st)
+                        : batch_ops_dispatch<T, 3, IB_KERNEL_PESKIN4>(b, st);
+    else cos ? batch_ops_dispatch<T, 2, IB_KERNEL_COSINE4>(b, st)
+             : batch_ops_dispatch<T, 2, IB_KERNEL_PESKIN4>(b, st);
+}
 }  // namespace
+
+int gather_blocks(int64_t npts, int ncomp)
+{
+    const int64_t nel = npts * ncomp;
+    return nel > 0 ? (int)min((int64_t)8192, (nel + 255) / 256) : 0;
+}
+
+int interp_blocks(int64_t npts)
+{
+    return npts > 0 ? (int)min((int64_t)65536, (npts + 255) / 256) : 0;
+}
+
+void spread_tiles(const GeomArgs& g, int tiles[3])
+{
+    if (g.dim == 3) {
+        tiles[0] = cdiv(g.n[0], SP_TX);
+        tiles[1] = cdiv(g.n[1], SP_TY);
+        tiles[2] = cdiv(g.n[2], SP_TZ);
+    } else {
+        tiles[0] = cdiv(g.n[0], SP2_TX);
+        tiles[1] = cdiv(g.n[1], SP2_TY);
+        tiles[2] = 1;
+    }
+}
+
+hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st)
+{
+    if (b.dtype == IB_F64) batch_ops_by_shape<double>(b, st);
+    else batch_ops_by_shape<float>(b, st);
+    return hipGetLastError();
+}
 
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st)
 {

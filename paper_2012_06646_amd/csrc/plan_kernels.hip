@@ -328,23 +328,129 @@ __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s,
 }
 
 // ---- host launchers ---------------------------------------------------------------------
+// ---- batched plan stages --------------------------------------------------------------
+
+// Job of virtual block vb: the last j with starts[j] <= vb (jobs without blocks in a stage
+// have starts[j] == starts[j + 1] and are passed over).
+__device__ __forceinline__ int batch_job(const int32_t* starts, int njobs, int vb)
+{
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (starts[mid] <= vb) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* jobs, const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_RESET];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job(st, nj, vb);
+        const PlanDev& d = jobs[j].sa.d;
+        plan_reset_body(d.zero_begin, d.zero_words, vb - st[j], st[j + 1] - st[j]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* jobs, const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_KEYS];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job(st, nj, vb);
+        keys_body<T>(jobs[j].sa, (const T*)jobs[j].op.X, vb - st[j], st[j + 1] - st[j]);
+        __syncthreads();
+    }
+}
+
+// Radix pass p of every job with more than p passes.  Blocks take tiles by ticket inside
+// the body, so only the number of virtual blocks per job (its tile count) matters.
+__global__ __launch_bounds__(SORT_BLOCK) void batch_sort_kernel(const BatchJob* jobs,
+                                                                const BatchTable* bt, int pass)
+{
+    const int32_t* st = bt->starts[BS_SORT0 + pass];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job(st, nj, vb);
+        radix_pass_body<BATCH_RBITS>(jobs[j].sa, 0, pass);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SORT_BLOCK) void batch_segments_kernel(const BatchJob* jobs,
+                                                                    const BatchTable* bt)
+{
+    const int32_t* st = bt->starts[BS_SEG];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job(st, nj, vb);
+        const BatchJob& J = jobs[j];
+        segments_body<T>(J.sa, 0, (const T*)J.op.X, (T*)J.sa.d.Xs);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st)
+{
+    if (b.grid[BS_RESET] > 0)
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(b.grid[BS_RESET]), dim3(256), 0, st, b.jobs, b.table);
+    if (b.grid[BS_KEYS] > 0) {
+        if (b.dtype == IB_F64)
+            hipLaunchKernelGGL(batch_keys_kernel<double>, dim3(b.grid[BS_KEYS]), dim3(256), b.keys_lds,
+                               st, b.jobs, b.table);
+        else
+            hipLaunchKernelGGL(batch_keys_kernel<float>, dim3(b.grid[BS_KEYS]), dim3(256), b.keys_lds,
+                               st, b.jobs, b.table);
+    }
+    for (int p = 0; p < BATCH_MAX_PASSES; ++p)
+        if (b.grid[BS_SORT0 + p] > 0)
+            hipLaunchKernelGGL(batch_sort_kernel, dim3(b.grid[BS_SORT0 + p]), dim3(SORT_BLOCK), 0, st,
+                               b.jobs, b.table, p);
+    if (b.grid[BS_SEG] > 0) {
+        if (b.dtype == IB_F64)
+            hipLaunchKernelGGL(batch_segments_kernel<double>, dim3(b.grid[BS_SEG]), dim3(SORT_BLOCK), 0,
+                               st, b.jobs, b.table);
+        else
+            hipLaunchKernelGGL(batch_segments_kernel<float>, dim3(b.grid[BS_SEG]), dim3(SORT_BLOCK), 0,
+                               st, b.jobs, b.table);
+    }
+    return hipGetLastError();
+}
+
+int reset_blocks(const SortArgs& a)
+{
+    return (int)min((size_t)1024, (a.d.zero_words + 255) / 256);
+}
+
+// Few blocks: each adds its LDS histograms to the global ones with atomics.
+int keys_blocks(const SortArgs& a)
+{
+    return a.g.npts > 0 ? (int)min((int64_t)512, (a.g.npts + 255) / 256) : 0;
+}
+
+size_t keys_lds_bytes(const SortArgs& a)
+{
+    return (size_t)a.g.nstag * a.npass * ((size_t)1 << a.rbits) * sizeof(uint32_t);
+}
+
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
 {
-    const size_t nw = a.d.zero_words;
-    const int blocks = (int)min((size_t)1024, (nw + 255) / 256);
+    const int blocks = reset_blocks(a);
     if (blocks > 0)
-        hipLaunchKernelGGL(plan_reset_kernel, dim3(blocks), dim3(256), 0, st, a.d.zero_begin, nw);
+        hipLaunchKernelGGL(plan_reset_kernel, dim3(blocks), dim3(256), 0, st, a.d.zero_begin,
+                           a.d.zero_words);
     return hipGetLastError();
 }
 
 hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st)
 {
-    const GeomArgs& g = a.g;
-    if (g.npts == 0) return hipSuccess;
-    const int R = 1 << a.rbits;
-    const size_t lds = (size_t)g.nstag * a.npass * R * sizeof(uint32_t);
-    // Few blocks: each adds its LDS histograms to the global ones with atomics.
-    const int blocks = (int)min((int64_t)512, (g.npts + 255) / 256);
+    const int blocks = keys_blocks(a);
+    if (blocks == 0) return hipSuccess;
+    const size_t lds = keys_lds_bytes(a);
     if (dtype == IB_F64)
         hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a, (const double*)X);
     else

@@ -58,10 +58,25 @@ _lib.ib_interpolate.argtypes = [_vp, _vp, _vp, _vp]
 
 _lib.ib_interpolate_grad.restype = _i32
 _lib.ib_interpolate_grad.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp]
+class JobDesc(ctypes.Structure):
+    _fields_ = [("grid", GridDesc), ("npts", ctypes.c_int64), ("X", ctypes.c_void_p),
+                ("F", ctypes.c_void_p), ("f", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("U", ctypes.c_void_p)]
+
+
+_lib.ib_batch_workspace_bytes.restype = ctypes.c_size_t
+_lib.ib_batch_workspace_bytes.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32]
+_lib.ib_batch_staging_bytes.restype = ctypes.c_size_t
+_lib.ib_batch_staging_bytes.argtypes = [_i32]
+_lib.ib_batch_run.restype = _i32
+_lib.ib_batch_run.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.ib_batch_status.restype = _i32
+_lib.ib_batch_status.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.POINTER(_i32), _vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
 
-EXPORTED = ["ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
+EXPORTED = ["ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
+            "ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
 
@@ -244,3 +259,77 @@ def interpolate(grid, X, u):
     """U = J(X) u on `grid` (convenience: builds a plan)."""
     p = Plan(grid, X.shape[0], X.dtype, X.device).update(X)
     return p.interpolate(u)
+
+
+BATCH_MAX_JOBS = 128
+
+
+class Batch:
+    """Independent spread/interpolate jobs run together, one launch per stage for all jobs
+    (ib_batch_run).  Each job is a dict with keys grid, X and optionally F (spread) and u
+    (interpolate); all share a dtype, dimension and kernel.  Outputs (f and U per job) and
+    the workspace are allocated once; `run()` may be called again after the inputs'
+    contents change (same shapes)."""
+
+    def __init__(self, jobs, dtype=torch.float64, device="cuda"):
+        if not 1 <= len(jobs) <= BATCH_MAX_JOBS:
+            raise ValueError(f"a batch holds 1..{BATCH_MAX_JOBS} jobs")
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.code = _dtype_code(dtype)
+        self.jobs = []
+        arr = (JobDesc * len(jobs))()
+        for j, job in enumerate(jobs):
+            g = job["grid"]
+            d = make_desc(g)
+            X = job["X"]
+            if X.dtype != dtype or X.dim() != 2 or X.shape[1] != d.dim:
+                raise ValueError(f"job {j}: X must be (n, {d.dim}) {dtype}")
+            X = X.contiguous()
+            n = X.shape[0]
+            shape = [d.ncomp] + [int(d.n[k]) for k in range(d.dim)][::-1]
+            F = job.get("F")
+            u = job.get("u")
+            rec = {"grid": g, "X": X, "npts": n, "F": None, "f": None, "u": None, "U": None}
+            if F is not None:
+                if F.dtype != dtype or tuple(F.shape) != (n, d.ncomp):
+                    raise ValueError(f"job {j}: F must be ({n}, {d.ncomp}) {dtype}")
+                rec["F"] = F.contiguous()
+                rec["f"] = torch.empty(shape, dtype=dtype, device=self.device)
+            if u is not None:
+                if u.dtype != dtype or list(u.shape) != shape:
+                    raise ValueError(f"job {j}: u must be {shape} {dtype}")
+                rec["u"] = u.contiguous()
+                rec["U"] = torch.empty((n, d.ncomp), dtype=dtype, device=self.device)
+            arr[j].grid = d
+            arr[j].npts = n
+            arr[j].X = X.data_ptr() if n else None
+            arr[j].F = rec["F"].data_ptr() if rec["F"] is not None and n else None
+            arr[j].f = rec["f"].data_ptr() if rec["f"] is not None else None
+            arr[j].u = rec["u"].data_ptr() if rec["u"] is not None else None
+            arr[j].U = rec["U"].data_ptr() if rec["U"] is not None and n else None
+            self.jobs.append(rec)
+        self._arr = arr
+        nbytes = int(_lib.ib_batch_workspace_bytes(arr, len(jobs), self.code))
+        if nbytes == 0:
+            _check(-4, "ib_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        nst = int(_lib.ib_batch_staging_bytes(len(jobs)))
+        self.staging = torch.empty(nst, dtype=torch.uint8, pin_memory=True)
+
+    def run(self, stream=None):
+        _check(_lib.ib_batch_run(self._arr, len(self.jobs), self.code, _ptr(self.workspace),
+                                 self.workspace.numel(), ctypes.c_void_p(self.staging.data_ptr()),
+                                 _stream(stream)), "ib_batch_run")
+        return self
+
+    def status(self, stream=None):
+        out = (_i32 * len(self.jobs))()
+        r = _lib.ib_batch_status(self._arr, len(self.jobs), self.code, _ptr(self.workspace), out,
+                                 _stream(stream))
+        if r < 0 and r != -6:
+            _check(r, "ib_batch_status")
+        return [int(v) for v in out]
+
+    def results(self):
+        return [(rec["f"], rec["U"]) for rec in self.jobs]

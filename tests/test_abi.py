@@ -77,3 +77,32 @@ def test_mac_grid_has_three_staggers_collocated_one(ib):
                                       ctypes.byref(h)) == 0
         assert ib._lib.ib_plan_num_staggers(h) == expect
         ib._lib.ib_plan_destroy(h)
+
+
+def test_batch_workspace_sizing_and_validation(ib):
+    from paper_2012_06646_amd import workloads as wl
+    g3, g2 = ib.make_desc(wl.grid(3, 32, 1.0)), ib.make_desc(wl.grid(2, 32, 1.0))
+    arr = (ib.JobDesc * 3)()
+    for j in range(3):
+        arr[j].grid = g3
+        arr[j].npts = 1000 * (j + 1)
+        arr[j].X = 4096
+        arr[j].F = 4096
+        arr[j].f = 4096
+    one = ib._lib.ib_plan_workspace_bytes(ctypes.byref(g3), 0, 3000)
+    total = ib._lib.ib_batch_workspace_bytes(arr, 3, 0)
+    assert total > one  # three plans and the job table
+    assert ib._lib.ib_batch_staging_bytes(3) > 0
+    assert ib._lib.ib_batch_staging_bytes(0) == 0
+    assert ib._lib.ib_batch_staging_bytes(ib.BATCH_MAX_JOBS + 1) == 0
+    assert ib._lib.ib_batch_workspace_bytes(arr, 0, 0) == 0
+    arr[1].grid = g2  # mixed dimensions are not batched together
+    assert ib._lib.ib_batch_workspace_bytes(arr, 3, 0) == 0
+    arr[1].grid = g3
+    arr[2].F = None  # spreading requested without forces
+    assert ib._lib.ib_batch_workspace_bytes(arr, 3, 0) == 0
+    arr[2].F = 4096
+    # argument errors are found before any device work
+    assert ib._lib.ib_batch_run(arr, 3, 0, ctypes.c_void_p(4096 + 8), total, None, None) == -1
+    assert ib._lib.ib_batch_run(arr, 3, 0, ctypes.c_void_p(4096), total - 1, None, None) == -2
+    assert ib._lib.ib_batch_run(arr, 3, 7, ctypes.c_void_p(4096), total, None, None) == -4

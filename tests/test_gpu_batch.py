@@ -1,0 +1,120 @@
+"""Batched jobs (ib_batch_run) against the same jobs run one by one through the plan API
+(bit for bit: the same kernels on the same data) and against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2012_06646_amd import workloads as wl
+from tests.gpu_util import TOL, normwise, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_06646_amd import ibops
+    return ibops
+
+
+def make_jobs(specs, dtype, seed):
+    """specs: (grid, npts, spread?, interp?) -> job dicts on the device, plus host copies."""
+    jobs, host = [], []
+    for i, (g, n, sp, it) in enumerate(specs):
+        X, F, u = wl.uniform_case(g, n, seed + i)
+        job = {"grid": g, "X": to_dev(X, dtype)}
+        if sp:
+            job["F"] = to_dev(F, dtype)
+        if it:
+            job["u"] = to_dev(u, dtype)
+        jobs.append(job)
+        host.append((X, F, u))
+    return jobs, host
+
+
+def one_by_one(ib, job, dtype):
+    p = ib.Plan(job["grid"], job["X"].shape[0], dtype).update(job["X"])
+    f = p.spread(job["F"]) if "F" in job else None
+    U = p.interpolate(job["u"]) if "u" in job else None
+    return f, U
+
+
+MIXED_3D = [
+    (wl.grid(3, 32, 1.0), 1000, True, True),
+    (wl.grid(3, 64, 1.0), 40000, True, True),
+    (wl.grid(3, 96, 1.0), 150000, True, False),
+    (wl.grid(3, [20, 24, 28], [1.0, 1.2, 1.4]), 5000, False, True),
+    (wl.grid(3, 128, 1.0), 300000, True, True),
+    (wl.grid(3, 32, 1.0), 0, True, True),
+    (wl.grid(3, 16, 2.0), 1, True, True),
+    (wl.grid(3, 48, 1.0), 4097, True, True),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_matches_one_by_one_bitwise(ib, dtype):
+    jobs, _ = make_jobs(MIXED_3D, dtype, 4100)
+    say(f"batch of {len(jobs)} mixed 3-D jobs dtype={dtype}")
+    b = ib.Batch(jobs, dtype).run()
+    assert b.status() == [0] * len(jobs)
+    for j, ((f, U), job) in enumerate(zip(b.results(), jobs)):
+        f1, U1 = one_by_one(ib, job, dtype)
+        if f1 is not None:
+            assert torch.equal(f, f1), f"job {j}: spread differs"
+        else:
+            assert f is None
+        if U1 is not None:
+            assert torch.equal(U, U1), f"job {j}: interpolation differs"
+
+
+def test_batch_against_oracle(ib, orc):
+    dtype = torch.float64
+    specs = [(wl.grid(3, 24, 1.0), 3000, True, True), (wl.grid(3, [16, 20, 12], 1.0), 2500, True, True),
+             (wl.grid(3, 32, 2.0), 6000, True, True)]
+    jobs, host = make_jobs(specs, dtype, 4200)
+    b = ib.Batch(jobs, dtype).run()
+    for (g, n, _, _), (f, U), (X, F, u) in zip(specs, b.results(), host):
+        ef = normwise(to_host(f), orc.spread(g, X, F))
+        eU = normwise(to_host(U), orc.interp(g, X, u))
+        say(f"   grid {g['n']} n={n}: spread err {ef:.2e} interp err {eU:.2e}")
+        assert ef <= TOL[dtype] and eU <= TOL[dtype]
+
+
+def test_batch_2d_and_reuse(ib, orc):
+    dtype = torch.float64
+    specs = [(wl.grid(2, 32, 1.0, stagger=[[0.5, 0.5], [0.5, 0.5]]), 1000, True, True),
+             (wl.grid(2, [64, 40], 1.0), 7000, True, True)]
+    jobs, host = make_jobs(specs, dtype, 4300)
+    b = ib.Batch(jobs, dtype)
+    b.run()
+    first = [(f.clone(), U.clone()) for f, U in b.results()]
+    b.run()  # the same batch again: identical results
+    for (f0, U0), (f, U) in zip(first, b.results()):
+        assert torch.equal(f0, f) and torch.equal(U0, U)
+    for (g, n, _, _), (f, U), (X, F, u) in zip(specs, b.results(), host):
+        assert normwise(to_host(f), orc.spread(g, X, F, tier=0)) <= TOL[dtype]
+        assert normwise(to_host(U), orc.interp(g, X, u, tier=0)) <= TOL[dtype]
+
+
+def test_batch_flags_bad_points_per_job(ib):
+    dtype = torch.float64
+    g = wl.grid(3, 16, 1.0)
+    X0, F0, _ = wl.uniform_case(g, 100, 4400)
+    Xbad = X0.copy()
+    Xbad[7, 1] = np.nan
+    jobs = [{"grid": g, "X": to_dev(X0, dtype), "F": to_dev(F0, dtype)},
+            {"grid": g, "X": to_dev(Xbad, dtype), "F": to_dev(F0, dtype)}]
+    b = ib.Batch(jobs, dtype).run()
+    assert b.status() == [0, -6]
+
+
+def test_max_jobs_batch(ib):
+    dtype = torch.float32
+    specs = [(wl.grid(3, 16 + 4 * (i % 5), 1.0), 200 + 37 * i, True, True) for i in range(128)]
+    jobs, _ = make_jobs(specs, dtype, 5000)
+    b = ib.Batch(jobs, dtype).run()
+    res = b.results()
+    for j in (0, 1, 63, 127):
+        f1, U1 = one_by_one(ib, jobs[j], dtype)
+        assert torch.equal(res[j][0], f1) and torch.equal(res[j][1], U1)

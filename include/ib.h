@@ -184,6 +184,61 @@ int32_t ib_batch_run(const ib_job *jobs, int32_t njobs, int32_t dtype, void *wor
 int32_t ib_batch_status(const ib_job *jobs, int32_t njobs, int32_t dtype, const void *workspace,
                         int32_t *job_status, void *stream);
 
+/* ---- serving loop ------------------------------------------------------------------- */
+
+/* A server takes independent jobs one at a time (ib_batch_submit), queues them, and runs
+ * them in batches as ib_batch_run does, on a HIP stream of its own (default priority),
+ * from a worker thread.  Jobs are admitted into a batch in arrival order while they share
+ * the first queued job's dimension and kernel, the batch holds at most
+ * max_jobs_per_batch jobs, and the batch's whole device footprint (its plans and job
+ * table) fits in the free part of the arena: the caller-owned device memory given at
+ * creation, handed out to batches in order and returned as they finish.  At most
+ * max_inflight batches are queued on the GPU at once; a new batch takes every compatible
+ * job waiting, so batches grow with the load.  A job's latency runs from its arrival (the
+ * submit time, or a scheduled arrival time given by the caller) to the moment the worker
+ * sees its batch finished.  The server allocates pinned host memory for job tables and
+ * flags, and no device memory. */
+typedef struct ib_server_s *ib_server;
+
+typedef struct {
+    int32_t dtype;               /* ib_dtype of every job */
+    int32_t max_jobs_per_batch;  /* 1 .. IB_BATCH_MAX_JOBS (1: one job per launch sequence) */
+    int32_t max_inflight;        /* 1 .. 4 batches queued on the GPU at once */
+    int32_t max_queue;           /* jobs waiting; ib_batch_submit returns IB_ERR_BUSY beyond */
+} ib_server_opts;
+
+typedef struct {
+    uint64_t jobs_done;
+    uint64_t batches;
+    uint64_t points;
+} ib_server_stats;
+
+/* arena: device memory (256-byte aligned) of arena_bytes, kept alive until destroy.  The
+ * current HIP device is the server's.  Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED, IB_ERR_HIP. */
+int32_t ib_server_create(const ib_server_opts *opts, void *arena, size_t arena_bytes,
+                         ib_server *out);
+
+/* Microseconds since the server was created (the clock of arrival times and latencies). */
+double ib_server_clock_us(ib_server server);
+
+/* Queue a job (non-blocking).  arrival_us < 0 means now.  The job's buffers must stay valid
+ * and unchanged until ib_batch_poll reports it finished.  Errors: IB_ERR_ARG (bad job),
+ * IB_ERR_OOM (its footprint exceeds the whole arena), IB_ERR_BUSY (queue full). */
+int32_t ib_batch_submit(ib_server server, const ib_job *job, double arrival_us, uint64_t *ticket);
+
+/* IB_PENDING while the job waits or runs; then, once, its final status (IB_OK,
+ * IB_ERR_DEVICE_FLAG, IB_ERR_HIP) with its latency in microseconds.  IB_ERR_ARG for an
+ * unknown or already reported ticket. */
+int32_t ib_batch_poll(ib_server server, uint64_t ticket, double *latency_us);
+
+/* Block until every submitted job has finished. */
+int32_t ib_server_drain(ib_server server);
+
+int32_t ib_server_get_stats(ib_server server, ib_server_stats *out);
+
+/* Finish all queued and running jobs, then free the server. */
+void ib_server_destroy(ib_server server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libibops.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["ib_api.cpp", "ib_batch.cpp", "plan_kernels.hip", "ops_kernels.hip"]
+SOURCES = ["ib_api.cpp", "ib_batch.cpp", "ib_server.cpp", "plan_kernels.hip", "ops_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("IBOPS_ARCH", "gfx950")
 
@@ -49,7 +49,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         for f in futs:
             f.result()
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -3,6 +3,7 @@
 // force gather, spreading, interpolation).
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -75,6 +76,8 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         BatchJob& b = hj[j];
         std::memset(&b, 0, sizeof b);
         b.sa = p.sa;
+        // All error flags of the batch sit in the table, so one copy reads them back.
+        b.sa.d.flag = (uint32_t*)(workspace + B.table_off + offsetof(BatchTable, flags)) + j;
         OpArgs& a = b.op;
         a.g = p.sa.g;
         a.sorted_keys = p.sorted_keys;
@@ -114,35 +117,38 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
 
 }  // namespace
 
-extern "C" {
+namespace ibk {
 
-size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype)
+size_t batch_header_bytes(int32_t njobs)
 {
-    BatchLayout B;
-    if (batch_layout(jobs, njobs, dtype, &B) != IB_OK) return 0;
-    return B.total;
+    return align_up(sizeof(BatchTable)) + align_up((size_t)njobs * sizeof(BatchJob));
 }
 
-size_t ib_batch_staging_bytes(int32_t njobs)
+size_t batch_flags_offset() { return offsetof(BatchTable, flags); }
+
+size_t batch_job_bytes(const ib_job* job, int32_t dtype)
 {
-    if (njobs < 1 || njobs > BATCH_MAX_JOBS) return 0;
-    return align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
+    int nstag, cs[3];
+    double sx[3][3];
+    if (!job || check_grid(&job->grid, dtype, job->npts, &nstag, cs, sx) != IB_OK) return 0;
+    Layout L;
+    make_layout(&job->grid, dtype, nstag, job->npts, &L, BATCH_RBITS);
+    return L.total;
 }
 
-int32_t ib_batch_run(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
-                     size_t workspace_bytes, void* host_staging, void* stream)
+int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
+                     size_t workspace_bytes, void* host_staging, hipStream_t hs)
 {
     BatchLayout B;
     int32_t st = batch_layout(jobs, njobs, dtype, &B);
     if (st != IB_OK) return st;
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
     if (workspace_bytes < B.total) return IB_ERR_OOM;
-    hipStream_t hs = (hipStream_t)stream;
     char* base = (char*)workspace;
 
     // The table and the job array go up in one copy: [table | pad | jobs], the same
     // arrangement as at the head of the workspace.
-    const size_t nbytes = ib_batch_staging_bytes(njobs);
+    const size_t nbytes = align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
     std::vector<char> pageable;
     char* stage = (char*)host_staging;
     if (!stage) {
@@ -160,6 +166,31 @@ int32_t ib_batch_run(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
     return hip_status(e);
 }
 
+}  // namespace ibk
+
+extern "C" {
+
+size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype)
+{
+    BatchLayout B;
+    if (batch_layout(jobs, njobs, dtype, &B) != IB_OK) return 0;
+    return B.total;
+}
+
+size_t ib_batch_staging_bytes(int32_t njobs)
+{
+    if (njobs < 1 || njobs > BATCH_MAX_JOBS) return 0;
+    return align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
+}
+
+
+int32_t ib_batch_run(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
+                     size_t workspace_bytes, void* host_staging, void* stream)
+{
+    return ibk::batch_launch(jobs, njobs, dtype, workspace, workspace_bytes, host_staging,
+                             (hipStream_t)stream);
+}
+
 int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const void* workspace,
                         int32_t* job_status, void* stream)
 {
@@ -168,12 +199,13 @@ int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const 
     if (st != IB_OK) return st;
     if (!workspace) return IB_ERR_ARG;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return IB_ERR_HIP;
+    std::vector<uint32_t> flags(njobs);
+    const char* fp = (const char*)workspace + B.table_off + offsetof(BatchTable, flags);
+    if (hipMemcpy(flags.data(), fp, njobs * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return IB_ERR_HIP;
     int32_t worst = IB_OK;
     for (int j = 0; j < njobs; ++j) {
-        uint32_t flag = 0;
-        const char* fp = (const char*)workspace + B.jobs[j].off + B.jobs[j].L.flag;
-        if (hipMemcpy(&flag, fp, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess) return IB_ERR_HIP;
-        const int32_t s = flag ? IB_ERR_DEVICE_FLAG : IB_OK;
+        const int32_t s = flags[j] ? IB_ERR_DEVICE_FLAG : IB_OK;
         if (job_status) job_status[j] = s;
         if (s != IB_OK) worst = s;
     }

@@ -51,4 +51,12 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
 
 int32_t hip_status(hipError_t e);
 
+// Batches (ib_batch.cpp).  Workspace of a batch: header (table and job array), then one
+// plan region per job of batch_job_bytes bytes, each 256-byte aligned.
+size_t batch_header_bytes(int32_t njobs);
+size_t batch_job_bytes(const ib_job* job, int32_t dtype);  // 0 for an invalid job
+size_t batch_flags_offset();                               // of the per-job flags in the header
+int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
+                     size_t workspace_bytes, void* host_staging, hipStream_t stream);
+
 }  // namespace ibk

@@ -136,6 +136,7 @@ struct BatchJob {
 struct BatchTable {
     int32_t njobs;
     int32_t starts[BS_COUNT][BATCH_MAX_JOBS + 1];
+    uint32_t flags[BATCH_MAX_JOBS];  // each job's device error flag (cleared by the upload)
 };
 
 // Host-side view of a batch resident in device memory.

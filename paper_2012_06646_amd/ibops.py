@@ -72,10 +72,35 @@ _lib.ib_batch_run.restype = _i32
 _lib.ib_batch_run.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.c_size_t, _vp, _vp]
 _lib.ib_batch_status.restype = _i32
 _lib.ib_batch_status.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.POINTER(_i32), _vp]
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("dtype", _i32), ("max_jobs_per_batch", _i32), ("max_inflight", _i32),
+                ("max_queue", _i32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("jobs_done", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("points", ctypes.c_uint64)]
+
+
+_lib.ib_server_create.restype = _i32
+_lib.ib_server_create.argtypes = [ctypes.POINTER(ServerOpts), _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]
+_lib.ib_server_clock_us.restype = ctypes.c_double
+_lib.ib_server_clock_us.argtypes = [_vp]
+_lib.ib_batch_submit.restype = _i32
+_lib.ib_batch_submit.argtypes = [_vp, ctypes.POINTER(JobDesc), ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
+_lib.ib_batch_poll.restype = _i32
+_lib.ib_batch_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+_lib.ib_server_drain.restype = _i32
+_lib.ib_server_drain.argtypes = [_vp]
+_lib.ib_server_get_stats.restype = _i32
+_lib.ib_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.ib_server_destroy.restype = None
+_lib.ib_server_destroy.argtypes = [_vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
 
-EXPORTED = ["ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
+EXPORTED = ["ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
+            "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
             "ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
@@ -333,3 +358,83 @@ class Batch:
 
     def results(self):
         return [(rec["f"], rec["U"]) for rec in self.jobs]
+
+
+IB_PENDING = 1
+
+
+def job_desc(job, dtype):
+    """ib_job for a dict with grid, X and optionally F + f (spread) and u + U (interpolate);
+    f and U are caller-allocated outputs."""
+    d = make_desc(job["grid"])
+    X = job["X"]
+    n = X.shape[0]
+    if X.dtype != dtype or not X.is_contiguous() or X.shape[1] != d.dim:
+        raise ValueError(f"X must be a contiguous (n, {d.dim}) {dtype} tensor")
+    jd = JobDesc()
+    jd.grid = d
+    jd.npts = n
+    jd.X = X.data_ptr() if n else None
+    shape = [d.ncomp] + [int(d.n[k]) for k in range(d.dim)][::-1]
+    for name, t, shp in (("F", job.get("F"), (n, d.ncomp)), ("f", job.get("f"), tuple(shape)),
+                         ("u", job.get("u"), tuple(shape)), ("U", job.get("U"), (n, d.ncomp))):
+        if t is None:
+            continue
+        if t.dtype != dtype or tuple(t.shape) != shp or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {shp} {dtype} tensor")
+        setattr(jd, name, t.data_ptr() if t.numel() else None)
+    return jd
+
+
+class Server:
+    """The serving loop (ib_server_*): submit jobs one at a time, poll their tickets.  The
+    device arena (the server's HBM budget) is allocated here with torch and handed over."""
+
+    def __init__(self, dtype=torch.float32, arena_bytes=16 << 30, max_jobs_per_batch=BATCH_MAX_JOBS,
+                 max_inflight=2, max_queue=1 << 20, device="cuda"):
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        o = ServerOpts(_dtype_code(dtype), int(max_jobs_per_batch), int(max_inflight), int(max_queue))
+        h = ctypes.c_void_p()
+        _check(_lib.ib_server_create(ctypes.byref(o), _ptr(self.arena), self.arena.numel(),
+                                     ctypes.byref(h)), "ib_server_create")
+        self._h = h
+        self._live = {}
+
+    def clock_us(self):
+        return _lib.ib_server_clock_us(self._h)
+
+    def submit(self, job, arrival_us=-1.0):
+        jd = job_desc(job, self.dtype)
+        t = ctypes.c_uint64()
+        _check(_lib.ib_batch_submit(self._h, ctypes.byref(jd), float(arrival_us), ctypes.byref(t)),
+               "ib_batch_submit")
+        self._live[t.value] = job  # keep the job's tensors alive until it is reported
+        return t.value
+
+    def poll(self, ticket):
+        """(status, latency_us): status IB_PENDING (1) while unfinished."""
+        lat = ctypes.c_double(0.0)
+        r = _lib.ib_batch_poll(self._h, ticket, ctypes.byref(lat))
+        if r != IB_PENDING:
+            self._live.pop(ticket, None)
+        return r, lat.value
+
+    def drain(self):
+        _check(_lib.ib_server_drain(self._h), "ib_server_drain")
+
+    def stats(self):
+        st = ServerStats()
+        _check(_lib.ib_server_get_stats(self._h, ctypes.byref(st)), "ib_server_get_stats")
+        return {"jobs_done": st.jobs_done, "batches": st.batches, "points": st.points}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.ib_server_destroy(h)
+            self._h = None
+        self._live.clear()
+
+    def __del__(self):
+        self.close()

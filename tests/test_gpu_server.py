@@ -1,0 +1,97 @@
+"""The serving loop: jobs submitted one by one come back with the same results as the
+same jobs run alone (bit for bit), under batching, arena pressure and bad inputs."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2012_06646_amd import workloads as wl
+from tests.gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_06646_amd import ibops
+    return ibops
+
+
+def serving_jobs(k, dtype, seed, sizes=(16, 24, 32, 48), nmax=20000):
+    r = wl.rng(seed)
+    jobs = []
+    for i in range(k):
+        g = wl.grid(3, int(r.choice(sizes)), 1.0)
+        n = int(round(np.exp(r.uniform(np.log(10), np.log(nmax)))))
+        X, F, u = wl.uniform_case(g, n, seed + 1 + i)
+        shape = wl.grid_shape(g)
+        jobs.append({"grid": g, "X": to_dev(X, dtype), "F": to_dev(F, dtype), "u": to_dev(u, dtype),
+                     "f": torch.empty(shape, dtype=dtype, device="cuda"),
+                     "U": torch.empty((n, 3), dtype=dtype, device="cuda")})
+    return jobs
+
+
+def alone(ib, job, dtype):
+    p = ib.Plan(job["grid"], job["X"].shape[0], dtype).update(job["X"])
+    return p.spread(job["F"]), p.interpolate(job["u"])
+
+
+def run_all(srv, jobs):
+    tickets = [srv.submit(j) for j in jobs]
+    srv.drain()
+    out = [srv.poll(t) for t in tickets]
+    return out
+
+
+@pytest.mark.parametrize("max_batch", [1, 5, 128])
+def test_server_results_match_jobs_run_alone(ib, max_batch):
+    dtype = torch.float32
+    jobs = serving_jobs(40, dtype, 6000)
+    say(f"server max_batch={max_batch}: 40 jobs")
+    srv = ib.Server(dtype, arena_bytes=256 << 20, max_jobs_per_batch=max_batch)
+    out = run_all(srv, jobs)
+    st = srv.stats()
+    srv.close()
+    assert all(s == 0 for s, _ in out), out
+    assert all(lat > 0 for _, lat in out)
+    assert st["jobs_done"] == 40 and st["batches"] >= (40 + max_batch - 1) // max_batch
+    for j in range(40):
+        f1, U1 = alone(ib, jobs[j], dtype)
+        assert torch.equal(jobs[j]["f"], f1) and torch.equal(jobs[j]["U"], U1), f"job {j}"
+
+
+def test_server_small_arena_wraps(ib):
+    """An arena that holds only a few jobs at a time: batches stay small, the ring wraps."""
+    dtype = torch.float64
+    jobs = serving_jobs(30, dtype, 6100, sizes=(32,), nmax=30000)
+    sizes = [ib.workspace_bytes(j["grid"], dtype, j["X"].shape[0]) for j in jobs]
+    arena = 3 * max(sizes) + (1 << 20)
+    srv = ib.Server(dtype, arena_bytes=arena, max_jobs_per_batch=128)
+    out = run_all(srv, jobs)
+    st = srv.stats()
+    srv.close()
+    assert all(s == 0 for s, _ in out)
+    assert st["batches"] >= -(-sum(sizes) // arena)  # no batch outgrows the arena
+    for j in range(30):
+        f1, U1 = alone(ib, jobs[j], dtype)
+        assert torch.equal(jobs[j]["f"], f1) and torch.equal(jobs[j]["U"], U1)
+
+
+def test_server_rejects_and_flags(ib):
+    dtype = torch.float32
+    jobs = serving_jobs(3, dtype, 6200, sizes=(16,), nmax=500)
+    bad = serving_jobs(1, dtype, 6300, sizes=(16,), nmax=500)[0]
+    Xh = bad["X"].cpu()
+    Xh[0, 0] = float("inf")
+    bad["X"] = Xh.to("cuda")
+    srv = ib.Server(dtype, arena_bytes=64 << 20)
+    big = {"grid": wl.grid(3, 128, 1.0), "X": torch.zeros((4_000_000, 3), dtype=dtype, device="cuda")}
+    with pytest.raises(ib.IBError):
+        srv.submit(big)  # larger than the whole arena
+    t = [srv.submit(j) for j in jobs[:2]] + [srv.submit(bad)] + [srv.submit(jobs[2])]
+    srv.drain()
+    st = [srv.poll(x)[0] for x in t]
+    assert st == [0, 0, -6, 0]
+    assert srv.poll(t[0])[0] == -1  # reported once
+    srv.close()

@@ -87,6 +87,116 @@ def cpu_baseline(g, X, F, u, sample):
                       f"staggering, spread, interpolate), single thread, {dt:.1f} s"}
 
 
+def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
+                  rhos=(0.5, 0.8, 0.95, 1.2)):
+    """The serving mix: independent FP32 jobs on {32,64,96,128}^3 MAC grids with
+    log-uniform point counts in [1e3, 1e6] (spread + interpolate each).  mu1 is the
+    closed-loop job rate of one job per launch sequence (plan update, spread, interpolate
+    through the plan API, jobs back to back); the batched rate submits the same jobs to the
+    server at once.  Then open-loop Poisson arrivals at rho * mu1 go to a server with
+    batches of one job and to one with batches of up to 128, and the measured jobs' latency
+    (scheduled arrival to observed completion) gives p50 / p99."""
+    dt = torch.float32
+    dev = torch.device("cuda:0")
+    sizes = wl.serving_job_sizes(pool_size)
+    fields = {N: torch.from_numpy(wl.serving_field(N)).to(dev) for N in sorted({N for N, _ in sizes})}
+    pool = []
+    for j, (N, n) in enumerate(sizes):
+        X, F = wl.serving_job(N, n, j)
+        pool.append({"grid": wl.grid(3, N, 1.0), "X": torch.from_numpy(X).to(dev),
+                     "F": torch.from_numpy(F).to(dev), "u": fields[N],
+                     "f": torch.empty((3, N, N, N), dtype=dt, device=dev),
+                     "U": torch.empty((n, 3), dtype=dt, device=dev)})
+    pool_pts = sum(n for _, n in sizes)
+    stream = torch.cuda.current_stream()
+
+    # closed loop, one job per launch sequence
+    plans = [ibops.Plan(jb["grid"], jb["X"].shape[0], dt, dev) for jb in pool]
+
+    def one_pass():
+        for p, jb in zip(plans, pool):
+            p.update(jb["X"])
+            p.spread(jb["F"], jb["f"])
+            p.interpolate(jb["u"], jb["U"])
+    one_pass()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    one_pass()
+    one_pass()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = e0.elapsed_time(e1) / 1e3
+    mu1 = 2 * pool_size / t1
+    del plans
+
+    def closed_batched():
+        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=128)
+        for jb in pool:
+            srv.submit(jb)
+        srv.drain()
+        c0 = srv.clock_us()
+        for _ in range(2):
+            for jb in pool:
+                srv.submit(jb)
+        srv.drain()
+        tb = (srv.clock_us() - c0) / 1e6
+        st = srv.stats()
+        srv.close()
+        return 2 * pool_size / tb, st
+
+    muB, stB = closed_batched()
+
+    def open_loop(max_batch, rate):
+        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=max_batch)
+        total = warm + measured
+        arr = wl.poisson_arrivals(total, rate)
+        start = srv.clock_us() + 2000.0
+        tickets, targets = [], []
+        for i in range(total):
+            target = start + arr[i] * 1e6
+            while True:
+                now = srv.clock_us()
+                if now >= target:
+                    break
+                if target - now > 400.0:
+                    time.sleep((target - now - 300.0) / 1e6)
+            tickets.append(srv.submit(pool[i % pool_size], arrival_us=target))
+            targets.append(target)
+        srv.drain()
+        res = [srv.poll(t) for t in tickets]
+        st = srv.stats()
+        srv.close()
+        bad = sum(1 for s_, _ in res if s_ != 0)
+        lat = np.array([l for _, l in res[warm:]])
+        done = np.array(targets[warm:]) + lat
+        span = (done.max() - targets[warm]) / 1e6
+        pts = sum(pool[i % pool_size]["X"].shape[0] for i in range(warm, total))
+        return {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "jobs_per_s": round(measured / span, 1), "points_per_s": round(pts / span, 1),
+                "mean_batch": round(st["jobs_done"] / max(st["batches"], 1), 2), "errors": bad}
+
+    runs = {}
+    for rho in rhos:
+        rate = rho * mu1
+        runs[str(rho)] = {"arrival_jobs_per_s": round(rate, 1),
+                          "one_job_per_launch": open_loop(1, rate),
+                          "batched": open_loop(128, rate)}
+    return {
+        "workload": "independent FP32 jobs, N^3 MAC grid with N uniform on {32,64,96,128}, "
+                    "n log-uniform in [1e3,1e6] uniform points, spread + interpolate each; "
+                    f"pool of {pool_size} distinct jobs (seeds 4000+j) cycled; Poisson arrivals "
+                    f"(seed 4008), {warm} warm-up + {measured} measured jobs per load",
+        "one_job_per_launch_jobs_per_s": round(mu1, 1),
+        "one_job_per_launch_points_per_s": round(mu1 * pool_pts / pool_size, 1),
+        "batched_closed_loop_jobs_per_s": round(muB, 1),
+        "batched_closed_loop_points_per_s": round(muB * pool_pts / pool_size, 1),
+        "batched_closed_loop_mean_batch": round(stB["jobs_done"] / max(stB["batches"], 1), 2),
+        "open_loop_by_load": runs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +206,9 @@ def main():
     ap.add_argument("--npts", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the batched-serving measurement (Poisson job stream)")
+    ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once in a HIP graph and replayed")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -124,6 +237,11 @@ def main():
 
     import torch
     from paper_2012_06646_amd import ibops, workloads as wl
+
+    if args.serving_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving_bench(torch, ibops, wl)}), flush=True)
+        return
 
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     b = 8 if args.dtype == "f64" else 4
@@ -229,7 +347,10 @@ def main():
         "host_wall_s": round(t_host, 4),
         "roofline": roofline,
         "cpu_baseline": None,
+        "serving": None,
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, X0.astype(np.float32 if b == 4 else np.float64)
                                            .astype(np.float64), F, u, min(args.cpu_sample, npts))

@@ -261,3 +261,41 @@ def config5(dtype=np.float64):
     g, X, F, u, placed = rbc_case(32.0, 128, 78, (5001, 5002, 5003, 5004), dtype, 200000)
     gfield = rng(5005).standard_normal((3, 128, 128, 128)).astype(dtype)
     return g, X, F, u, gfield, placed
+
+
+# ---- the serving mix: independent jobs of mixed grid and point counts -----------------
+
+SERVE_GRIDS = (32, 64, 96, 128)
+
+
+def serving_job_sizes(count, seed=4001):
+    """Grid edge N_j uniform on {32, 64, 96, 128} and point count n_j = round(exp(U(ln 1e3,
+    ln 1e6))) for jobs j = 0..count-1, drawn in that order per job from one stream."""
+    r = rng(seed)
+    out = []
+    for _ in range(count):
+        N = int(SERVE_GRIDS[int(r.integers(0, len(SERVE_GRIDS)))])
+        n = int(round(math.exp(r.uniform(math.log(1e3), math.log(1e6)))))
+        out.append((N, n))
+    return out
+
+
+def serving_job(N, n, j, dtype=np.float32):
+    """Job j's points and forces on the unit-cube N^3 MAC grid: X ~ U[0,1)^3 then F ~ N(0,1),
+    seed 4000 + j."""
+    r = rng(4000 + j)
+    X = r.random((n, 3))
+    F = r.standard_normal((n, 3))
+    return X.astype(dtype), F.astype(dtype)
+
+
+def serving_field(N, dtype=np.float32):
+    """The grid velocity interpolated by every job on an N^3 grid: u ~ N(0,1), seed 4000 + N
+    (read-only, so jobs on one grid size share it)."""
+    return rng(4000 + N).standard_normal((3, N, N, N)).astype(dtype)
+
+
+def poisson_arrivals(count, rate_per_s, seed=4001):
+    """Open-loop arrival times (seconds from the start) of a Poisson stream."""
+    r = rng(seed + 7)
+    return np.cumsum(r.exponential(1.0 / rate_per_s, count))

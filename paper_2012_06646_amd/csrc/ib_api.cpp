@@ -101,6 +101,13 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     const size_t b = dtype == IB_F64 ? 8 : 4;
     L->Xs = take((size_t)n * g->dim * b);
     L->Fs = take((size_t)n * g->ncomp * b);
+    int tiles[3];
+    spread_tiles(g->dim, g->n, tiles);
+    L->sp_tiles = tiles[0] * tiles[1] * tiles[2] * g->ncomp;
+    L->split = spread_split(n, L->sp_tiles);
+    L->partial = take(L->split > 1 ? (size_t)L->split * L->sp_tiles * spread_tile_cells(g->dim) *
+                                         sizeof(double)
+                                   : 0);
     // Everything from here to zero_end is cleared at every update.
     L->zero_begin = off;
     L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
@@ -108,6 +115,7 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
     L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
+    L->tile_count = take((size_t)L->sp_tiles * sizeof(uint32_t));
     L->zero_end = off;
     L->total = off;
 }
@@ -190,6 +198,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
         hd *= Lk / N;
     }
     g.scale = 1.0 / hd;
+    g.split = L.split;
     for (int c = 0; c < grid->ncomp; ++c) {
         g.comp_stag[c] = cs[c];
         for (int k = 0; k < 3; ++k) {
@@ -215,6 +224,8 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     d.q = (int32_t*)(base + L.q);
     d.Xs = base + L.Xs;
     d.Fs = base + L.Fs;
+    d.partial = (double*)(base + L.partial);
+    d.tile_count = (uint32_t*)(base + L.tile_count);
     d.hist = (uint32_t*)(base + L.hist);
     d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
@@ -340,6 +351,8 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->X = p->X;
     a->Xs = p->sa.d.Xs;
     a->Fs = p->sa.d.Fs;
+    a->partial = p->sa.d.partial;
+    a->tile_count = p->sa.d.tile_count;
 }
 
 int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)

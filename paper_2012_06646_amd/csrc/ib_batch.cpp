@@ -87,11 +87,13 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.Xs = p.sa.d.Xs;
         a.F = J.F;
         a.Fs = p.sa.d.Fs;
+        a.partial = p.sa.d.partial;
+        a.tile_count = p.sa.d.tile_count;
         a.f = J.f;
         a.u = J.u;
         a.U = J.U;
         a.accumulate = 0;
-        spread_tiles(a.g, a.tiles);
+        spread_tiles(a.g.dim, a.g.n, a.tiles);
 
         const SortArgs& sa = b.sa;
         const int64_t n = J.npts;
@@ -101,7 +103,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
             counts[BS_SORT0 + q] = (n > 0 && q < sa.npass) ? (int)sa.ntiles : 0;
         counts[BS_SEG] = (int)sa.nseg_tiles;
         counts[BS_GATHER] = J.f ? gather_blocks(n, a.g.ncomp) : 0;
-        counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp : 0;
+        counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;
         counts[BS_INTERP] = J.u ? interp_blocks(n) : 0;
         for (int s = 0; s < BS_COUNT; ++s) ht->starts[s][j + 1] = ht->starts[s][j] + counts[s];
         if (counts[BS_KEYS] > 0 && keys_lds_bytes(sa) > keys_lds) keys_lds = keys_lds_bytes(sa);

@@ -31,8 +31,9 @@ size_t align_up(size_t v);
 struct Layout {
     int nstag, npass, rbits, rows, nbx;
     int64_t ntiles, nseg_tiles, G;
-    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, zero_begin, hist, sort_status,
-        seg_status, counters, flag, zero_end, total;
+    int sp_tiles, split;  // spreading tiles (x components) and blocks per tile
+    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, partial, zero_begin, hist,
+        sort_status, seg_status, counters, flag, tile_count, zero_end, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

@@ -40,6 +40,8 @@ struct PlanDev {
     uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
     void* Fs;              // [n][ncomp] forces in that order (filled by each spread call)
+    double* partial;       // [tiles][split][tile cells] partial tile sums (split > 1 only)
+    uint32_t* tile_count;  // [tiles] blocks of a split tile done (in the cleared region)
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
@@ -80,6 +82,7 @@ struct GeomArgs {
     double stag_xi[3][3];  // per distinct stagger
     double comp_xi[3][3];  // per component
     double scale;          // (prod_k h_k)^-1 for spreading
+    int split;             // blocks per spreading tile (see spread_split)
 };
 
 struct SortArgs {
@@ -105,6 +108,8 @@ struct OpArgs {
     void* U;
     int accumulate;
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
+    double* partial;             // split spreading: partial tile sums
+    uint32_t* tile_count;        // split spreading: arrivals per tile
 };
 
 // ---- batches: many independent jobs, one launch per stage ------------------------------
@@ -154,7 +159,12 @@ int keys_blocks(const SortArgs& a);
 size_t keys_lds_bytes(const SortArgs& a);
 int gather_blocks(int64_t npts, int ncomp);
 int interp_blocks(int64_t npts);
-void spread_tiles(const GeomArgs& g, int tiles[3]);
+void spread_tiles(int dim, const int n[3], int tiles[3]);
+// Cells of one spreading tile, and the number of blocks that share a tile (1 .. 16) for
+// npts points over ntiles (tiles x components) tiles: a dense point set on a small grid
+// would otherwise leave most of the GPU idle.
+size_t spread_tile_cells(int dim);
+int spread_split(int64_t npts, int ntiles);
 
 hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st);
 hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st);

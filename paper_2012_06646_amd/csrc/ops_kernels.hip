@@ -247,7 +247,7 @@ struct SpreadTile {
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
                                   const Table& tb, int nranges, int total, int q, const int off[3],
                                   int ex, int ey, int ez, bool same0, double* tile,
-                                  int32_t* ltab)
+                                  int32_t* ltab, int k0, int kstride)
     {
         const GeomArgs& g = a.g;
         const int lane = lane_id();
@@ -256,8 +256,11 @@ struct SpreadTile {
         int nrr = 0;
         int32_t nkey = 0;
         T nx[DIM], nF = T(0);
-        load(a, c, sk, tb, nranges, total, lane, nrr, nkey, nx, nF);
-        for (int v0 = 0; v0 < total; v0 += 64) {
+        // This block's chunks of the slice: k0, k0 + kstride, ... (all of them unless the
+        // tile is split over several blocks).
+        const int step = 64 * kstride;
+        load(a, c, sk, tb, nranges, total, 64 * k0 + lane, nrr, nkey, nx, nF);
+        for (int v0 = 64 * k0; v0 < total; v0 += step) {
             const int v = v0 + lane;
             const bool valid = v < total;
             const int rr = nrr;
@@ -266,7 +269,7 @@ struct SpreadTile {
 #pragma unroll
             for (int k = 0; k < DIM; ++k) x[k] = nx[k];
             const T Fc = nF;
-            if (v0 + 64 < total) load(a, c, sk, tb, nranges, total, v + 64, nrr, nkey, nx, nF);
+            if (v0 + step < total) load(a, c, sk, tb, nranges, total, v + step, nrr, nkey, nx, nF);
             T w[DIM][4];
             int cx = 0, cy = 0, cz = 0;
             bool has = false;
@@ -391,7 +394,11 @@ __device__ void spread_body(const OpArgs& a, int bid)
     __shared__ typename ST::Table tables[4];
     __shared__ int32_t ltabs[4][64];  // per wave: lanes of each group in rank order
     const GeomArgs& g = a.g;
-    int b = bid;
+    // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
+    // chunk of its points and add their partial tiles at the end.
+    const int split = g.split;
+    const int tile_id = bid / split, ksub = bid - tile_id * split;
+    int b = tile_id;
     const int bx = b % a.tiles[0]; b /= a.tiles[0];
     const int by = b % a.tiles[1]; b /= a.tiles[1];
     const int bz = b % a.tiles[2]; b /= a.tiles[2];
@@ -426,7 +433,7 @@ __device__ void spread_body(const OpArgs& a, int bid)
             const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb);
             if (total > 0)
                 ST::reduce(a, c, a.sorted_keys, tb, nranges, total, q, off, ex, ey, ez, same0,
-                           tile, ltabs[w]);
+                           tile, ltabs[w], ksub, split);
             wave_sync();
         }
         __syncthreads();
@@ -434,7 +441,40 @@ __device__ void spread_body(const OpArgs& a, int bid)
 
     T* f = (T*)a.f;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
-    for (int i = threadIdx.x; i < TX * TY * TZ; i += blockDim.x) {
+    constexpr int CELLS = TX * TY * TZ;
+    if (split > 1) {
+        // Publish this block's partial tile; the last of the tile's blocks to arrive adds
+        // the partials in block order (a fixed order) and writes the grid values.
+        __shared__ int s_last;
+        double* part = a.partial + (int64_t)tile_id * split * CELLS;
+        for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
+            const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
+            part[(int64_t)ksub * CELLS + i] = tile[(zr * TY + yr) * ST::PXS + xr + 3];
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t prev = __hip_atomic_fetch_add(&a.tile_count[tile_id], 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            s_last = prev == (uint32_t)(split - 1);
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
+            const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
+            if (xr >= ex || yr >= ey || zr >= ez) continue;
+            double sum = 0.0;
+            for (int kk = 0; kk < split; ++kk) sum += part[(int64_t)kk * CELLS + i];
+            const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
+            const T v = (T)(sum * g.scale);
+            T* dst = f + (int64_t)c * G + gi;
+            *dst = a.accumulate ? *dst + v : v;
+        }
+        if (threadIdx.x == 0) a.tile_count[tile_id] = 0u;  // ready for the next call
+        return;
+    }
+    for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
         const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
         if (xr >= ex || yr >= ey || zr >= ez) continue;
         const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
@@ -707,8 +747,8 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
     if (gb > 0)
         hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(gb), dim3(256), 0, st, a.g.npts, a.g.ncomp,
                            a.perm, (const T*)a.F, (T*)a.Fs);
-    spread_tiles(a.g, a.tiles);
-    const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp);
+    spread_tiles(a.g.dim, a.g.n, a.tiles);
+    const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split);
     if (a.g.dim == 3)
         hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_TX, SP_TY, SP_TZ>), dim3(nb), dim3(256),
                            0, st, a);
@@ -816,17 +856,31 @@ int interp_blocks(int64_t npts)
     return npts > 0 ? (int)min((int64_t)65536, (npts + 255) / 256) : 0;
 }
 
-void spread_tiles(const GeomArgs& g, int tiles[3])
+void spread_tiles(int dim, const int n[3], int tiles[3])
 {
-    if (g.dim == 3) {
-        tiles[0] = cdiv(g.n[0], SP_TX);
-        tiles[1] = cdiv(g.n[1], SP_TY);
-        tiles[2] = cdiv(g.n[2], SP_TZ);
+    if (dim == 3) {
+        tiles[0] = cdiv(n[0], SP_TX);
+        tiles[1] = cdiv(n[1], SP_TY);
+        tiles[2] = cdiv(n[2], SP_TZ);
     } else {
-        tiles[0] = cdiv(g.n[0], SP2_TX);
-        tiles[1] = cdiv(g.n[1], SP2_TY);
+        tiles[0] = cdiv(n[0], SP2_TX);
+        tiles[1] = cdiv(n[1], SP2_TY);
         tiles[2] = 1;
     }
+}
+
+size_t spread_tile_cells(int dim)
+{
+    return dim == 3 ? (size_t)SP_TX * SP_TY * SP_TZ : (size_t)SP2_TX * SP2_TY;
+}
+
+// About 2048 points per block at least; the 128^3 grid with 10^6 points keeps one block
+// per tile, a 32^3 grid with 10^6 points gets 16.
+int spread_split(int64_t npts, int ntiles)
+{
+    if (ntiles <= 0) return 1;
+    const int64_t s = npts / ((int64_t)ntiles * 2048);
+    return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
 }
 
 hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st)

@@ -49,6 +49,7 @@ MIXED_3D = [
     (wl.grid(3, 32, 1.0), 0, True, True),
     (wl.grid(3, 16, 2.0), 1, True, True),
     (wl.grid(3, 48, 1.0), 4097, True, True),
+    (wl.grid(3, 32, 1.0), 150000, True, True),   # dense: split spreading tiles
 ]
 
 

@@ -164,6 +164,37 @@ def test_ops_mixed_cell_crowding(ib, orc, dtype):
     check_ops(ib, orc, g, X, F, u, dtype, "mixed crowding")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_ops_dense_small_grid_split_tiles(ib, orc, dtype):
+    """Many points per cell on a small grid: each spreading tile is shared by several
+    blocks whose partial tiles are added in a fixed order."""
+    g = wl.grid(3, 32, 1.0)
+    X, F, u = wl.uniform_case(g, 200000, 41)
+    check_ops(ib, orc, g, X, F, u, dtype, "dense 32^3 (split tiles)")
+
+
+def test_ops_dense_2d_split_tiles(ib, orc):
+    g = wl.grid(2, 32, 1.0)
+    X, F, u = wl.uniform_case(g, 120000, 43)
+    check_ops(ib, orc, g, X, F, u, torch.float64, "dense 2-D (split tiles)")
+
+
+def test_split_tiles_bitwise_run_to_run(ib):
+    g = wl.grid(3, 32, 1.0)
+    r = wl.rng(47)
+    X = (r.random((6, 3))[r.integers(0, 6, 250000)] + 0.05 * r.standard_normal((250000, 3))) % 1.0
+    F = r.standard_normal((250000, 3))
+    p = ib.Plan(g, X.shape[0], torch.float64)
+    Xd, Fd = to_dev(X, torch.float64), to_dev(F, torch.float64)
+    outs = []
+    for _ in range(3):
+        p.update(Xd)
+        outs.append(to_host(p.spread(Fd)))
+        outs.append(to_host(p.spread(Fd)))  # a second call reuses the per-tile counters
+    for f in outs[1:]:
+        assert np.array_equal(f, outs[0])
+
+
 def test_clustered_bitwise_run_to_run(ib):
     g = wl.grid(3, [32, 32, 32], 1.0)
     r = wl.rng(37)

@@ -266,40 +266,43 @@ def main():
         plan.interpolate(ud, U)
         ibops.advect(g, X, U, 0.1 * h)
 
-    def timed(fn, K):
-        """Average ms per call of fn over K back-to-back calls, from two HIP events on the
-        stream the library launches on (torch's current stream)."""
-        s0 = torch.cuda.Event(enable_timing=True)
-        s1 = torch.cuda.Event(enable_timing=True)
+    X0d = X.clone()
+
+    def restart():
+        """Every timed region starts from the initial positions, so all of them follow the
+        same trajectory (the points gather in crowded cells as they are advected)."""
+        X.copy_(X0d)
         torch.cuda.synchronize()
-        s0.record(stream)
-        for _ in range(K):
-            fn()
-        s1.record(stream)
-        torch.cuda.synchronize()
-        return s0.elapsed_time(s1) / K
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+    restart()
 
-    # The timed region: K whole steps, no host synchronisation inside.
+    # The timed region: K whole steps, no host synchronisation inside; HIP events between
+    # the stages of every step give each stage's average duration over the same region.
     K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
     t_host0 = time.perf_counter()
-    ms_step = timed(step, K)
+    for k in range(K):
+        e = ev[k]
+        e[0].record(stream)
+        plan.update(X)
+        e[1].record(stream)
+        plan.spread(Fd, f)
+        e[2].record(stream)
+        plan.interpolate(ud, U)
+        e[3].record(stream)
+        ibops.advect(g, X, U, 0.1 * h)
+        e[4].record(stream)
+    torch.cuda.synchronize()
     t_host = time.perf_counter() - t_host0
     if plan.status() != 0:
         print("bench.py: device flagged a data error", file=sys.stderr)
         sys.exit(1)
+    ms_step = ev[0][0].elapsed_time(ev[K - 1][4]) / K
     value = npts / (ms_step / 1e3)
-
-    # Per-operator averages: each operator alone, K calls back to back on the positions the
-    # steps left (the dominant operator's duration feeds the roofline).
-    stage_ms = {
-        "plan": timed(lambda: plan.update(X), K),
-        "spread": timed(lambda: plan.spread(Fd, f), K),
-        "interp": timed(lambda: plan.interpolate(ud, U), K),
-    }
+    stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
+                for i, name in enumerate(["plan", "spread", "interp", "advect"])}
 
     graph_ms = None
     if args.graph:
@@ -310,9 +313,15 @@ def main():
             with torch.cuda.graph(gr, stream=cap):
                 step()
         stream.wait_stream(cap)
-        gr.replay()
+        restart()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for _ in range(K):
+            gr.replay()
+        g1.record(stream)
         torch.cuda.synchronize()
-        graph_ms = timed(gr.replay, K)
+        graph_ms = g0.elapsed_time(g1) / K
 
     algo = algorithmic_bytes(npts, dim, ncomp, G, b)
     dom = max(("spread", "interp"), key=lambda s: stage_ms[s])
@@ -341,7 +350,7 @@ def main():
                                "N(0,1) forces and grid velocities, Peskin 4-point; step = plan + "
                                "spread + interpolate + advect (dt = 0.1 h)",
                    "grid": [128, 128, 128], "npts": npts, "seed": 1002},
-        "operator_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "step_algorithmic_bytes": sum(algo.values()),
         "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "host_wall_s": round(t_host, 4),

@@ -102,6 +102,23 @@ __device__ __forceinline__ T product_residual(T x, T inv_h, T inv_lo)
     return fma(x, inv_h, -t) + x * inv_lo;
 }
 
+// Square root of x in [1, 2] (the argument of the Peskin weights): the hardware reciprocal
+// square root refined by one Goldschmidt step and one Newton correction, accurate to one
+// ulp on that interval without the range handling of the general routine.  FP32 uses the
+// hardware square root (one ulp).
+__device__ __forceinline__ double sqrt_1to2(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
+__device__ __forceinline__ float sqrt_1to2(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---- one-dimensional kernel weights for the four shifts sigma = -1, 0, 1, 2 --------------
 // w[k] = phi(sigma_k - r) for a point at fractional offset r in [0, 1) of its cell.
 
@@ -122,7 +139,7 @@ __device__ __forceinline__ void weights4(T r, T w[4])
         // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = (1 + 2r - s)/8.
         // The two differences lose relative (not absolute) accuracy when a weight is
         // tiny, which leaves every weighted sum accurate to working precision.
-        const T s = sqrt(T(1) + T(4) * r * (T(1) - r));
+        const T s = sqrt_1to2(T(1) + T(4) * r * (T(1) - r));
         const T a = T(3) - T(2) * r;
         const T b = T(1) + T(2) * r;
         w[0] = (a - s) * T(0.125);

@@ -285,9 +285,9 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     if (!X && p->npts > 0) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_plan_reset(p->sa, st);
-    if (e == hipSuccess) e = launch_keys(p->sa, p->dtype, X, st);
-    // The operators use the sort of staggering 0 (with the positions gathered into it);
-    // other staggerings are sorted when exported.
+    // The operators use the keys and sort of staggering 0 (with the positions gathered into
+    // that order); other staggerings get theirs when exported.
+    if (e == hipSuccess) e = launch_keys(p->sa, p->dtype, X, 0, st);
     if (e == hipSuccess) e = launch_sort_stagger(p->sa, 0, p->dtype, X, true, st);
     int32_t r = hip_status(e);
     if (r != IB_OK) return r;
@@ -304,7 +304,9 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
     if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (!(p->sorted_mask & (1u << sid))) {
-        int32_t r = hip_status(launch_sort_stagger(p->sa, sid, p->dtype, nullptr, false, st));
+        hipError_t e0 = launch_keys(p->sa, p->dtype, p->X, sid, st);
+        if (e0 == hipSuccess) e0 = launch_sort_stagger(p->sa, sid, p->dtype, nullptr, false, st);
+        int32_t r = hip_status(e0);
         if (r != IB_OK) return r;
         p->sorted_mask |= 1u << sid;
     }

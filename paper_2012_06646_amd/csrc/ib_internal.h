@@ -171,7 +171,8 @@ hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st);
 
 // Host launchers (stream-ordered; return hipError_t).
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st);
-hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st);
+// Keys of staggering s and its digit histograms.
+hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, int s, hipStream_t st);
 // Sort staggering s, build its segments and cell-block table; with gather_x, also write
 // the positions in that order (used for staggering 0 only).
 hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,

@@ -191,16 +191,24 @@ struct SpreadTile {
     __device__ static void add_to_tile(const T acc[NZ][4][4], bool leader, int cx, int cy,
                                        int cz, int ey, int ez, double* tile)
     {
+        // Rows of the stencil: slice-axis offset ia (z in 3-D, y in 2-D), in-plane offset ib
+        // (y in 3-D); row (ia, ib) starts `base + (ia * TY + ib) * PXS` (3-D) or
+        // `base + ia * PXS` (2-D) elements into the tile.
+        const int zb = (DIM == 3) ? cz - 1 : 0, yb = cy - 1;
+        const int base = (zb * TY + yb) * PXS + (cx + 2);
+        bool oka[4], okb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            oka[i] = leader && ((DIM == 3) ? (unsigned)(zb + i) < (unsigned)ez
+                                           : (unsigned)(yb + i) < (unsigned)ey);
+            okb[i] = (DIM == 3) ? (unsigned)(yb + i) < (unsigned)ey : i == 0;
+        }
 #pragma unroll
         for (int ia = 0; ia < 4; ++ia)
 #pragma unroll
             for (int ib = 0; ib < ((DIM == 3) ? 4 : 1); ++ib) {
-                int ty, tz;
-                if (DIM == 3) { tz = cz - 1 + ia; ty = cy - 1 + ib; }
-                else { tz = 0; ty = cy - 1 + ia; }
-                const bool ok = leader && (unsigned)ty < (unsigned)ey && (unsigned)tz < (unsigned)ez;
-                if (ok) {
-                    double* row = tile + (tz * TY + ty) * PXS + (cx + 2);
+                if (oka[ia] && okb[ib]) {
+                    double* row = tile + base + ((DIM == 3) ? (ia * TY + ib) * PXS : ia * PXS);
 #pragma unroll
                     for (int ix = 0; ix < 4; ++ix) {
                         const double v = (DIM == 3) ? acc[ia][ib][ix] : acc[0][ia][ix];

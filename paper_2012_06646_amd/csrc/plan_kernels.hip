@@ -29,13 +29,15 @@ __global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
 }
 
 // ---- keys: one per point and distinct staggering, plus all pass histograms ----------
+// Keys of staggerings [s0, s1) and their digit histograms for every pass.
 template <typename T>
-__device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk)
+__device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk, int s0,
+                          int s1)
 {
-    extern __shared__ uint32_t lhist[];  // [nstag][npass][R]
+    extern __shared__ uint32_t lhist[];  // [s1 - s0][npass][R]
     const GeomArgs& g = a.g;
     const int R = 1 << a.rbits;
-    const int nh = g.nstag * a.npass * R;
+    const int nh = (s1 - s0) * a.npass * R;
     for (int i = threadIdx.x; i < nh; i += blockDim.x) lhist[i] = 0u;
     __syncthreads();
 
@@ -45,7 +47,7 @@ __device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, i
         T x[3];
         for (int k = 0; k < g.dim; ++k) x[k] = X[j * g.dim + k];
         bool bad = false;
-        for (int s = 0; s < g.nstag; ++s) {
+        for (int s = s0; s < s1; ++s) {
             int key = 0, stride = 1;
             for (int k = 0; k < g.dim; ++k) {
                 const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
@@ -57,20 +59,21 @@ __device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, i
             }
             a.d.keys0[(int64_t)s * n + j] = key;
             for (int p = 0; p < a.npass; ++p)
-                atomicAdd(&lhist[(s * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
+                atomicAdd(&lhist[((s - s0) * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
         }
         any_bad |= bad;
     }
     if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
     __syncthreads();
+    uint32_t* gh = a.d.hist + (size_t)s0 * a.npass * R;
     for (int i = threadIdx.x; i < nh; i += blockDim.x)
-        if (lhist[i]) atomicAdd(&a.d.hist[i], lhist[i]);
+        if (lhist[i]) atomicAdd(&gh[i], lhist[i]);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X)
+__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X, int s0, int s1)
 {
-    keys_body<T>(a, X, blockIdx.x, gridDim.x);
+    keys_body<T>(a, X, blockIdx.x, gridDim.x, s0, s1);
 }
 
 // ---- decoupled look-back over one counter per tile ------------------------------------
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* jobs, c
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
-        keys_body<T>(jobs[j].sa, (const T*)jobs[j].op.X, vb - st[j], st[j + 1] - st[j]);
+        keys_body<T>(jobs[j].sa, (const T*)jobs[j].op.X, vb - st[j], st[j + 1] - st[j], 0, 1);
         __syncthreads();
     }
 }
@@ -432,9 +435,9 @@ int keys_blocks(const SortArgs& a)
     return a.g.npts > 0 ? (int)min((int64_t)512, (a.g.npts + 255) / 256) : 0;
 }
 
-size_t keys_lds_bytes(const SortArgs& a)
+size_t keys_lds_bytes(const SortArgs& a)  // one staggering at a time
 {
-    return (size_t)a.g.nstag * a.npass * ((size_t)1 << a.rbits) * sizeof(uint32_t);
+    return (size_t)a.npass * ((size_t)1 << a.rbits) * sizeof(uint32_t);
 }
 
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
@@ -446,15 +449,17 @@ hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, hipStream_t st)
+hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, int s, hipStream_t st)
 {
     const int blocks = keys_blocks(a);
     if (blocks == 0) return hipSuccess;
     const size_t lds = keys_lds_bytes(a);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a, (const double*)X);
+        hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a, (const double*)X,
+                           s, s + 1);
     else
-        hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a, (const float*)X);
+        hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a, (const float*)X,
+                           s, s + 1);
     return hipGetLastError();
 }
 

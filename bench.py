@@ -130,8 +130,8 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
     mu1 = 2 * pool_size / t1
     del plans
 
-    def closed_batched():
-        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=128)
+    def closed_batched(graph=False):
+        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=128, use_graph=graph)
         for jb in pool:
             srv.submit(jb)
         srv.drain()
@@ -146,9 +146,10 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         return 2 * pool_size / tb, st
 
     muB, stB = closed_batched()
+    muG, _ = closed_batched(True)
 
-    def open_loop(max_batch, rate):
-        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=max_batch)
+    def open_loop(max_batch, rate, graph=False):
+        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=max_batch, use_graph=graph)
         total = warm + measured
         arr = wl.poisson_arrivals(total, rate)
         start = srv.clock_us() + 2000.0
@@ -182,7 +183,8 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         rate = rho * mu1
         runs[str(rho)] = {"arrival_jobs_per_s": round(rate, 1),
                           "one_job_per_launch": open_loop(1, rate),
-                          "batched": open_loop(128, rate)}
+                          "batched": open_loop(128, rate),
+                          "batched_graph": open_loop(128, rate, True)}
     return {
         "workload": "independent FP32 jobs, N^3 MAC grid with N uniform on {32,64,96,128}, "
                     "n log-uniform in [1e3,1e6] uniform points, spread + interpolate each; "
@@ -193,6 +195,7 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         "batched_closed_loop_jobs_per_s": round(muB, 1),
         "batched_closed_loop_points_per_s": round(muB * pool_pts / pool_size, 1),
         "batched_closed_loop_mean_batch": round(stB["jobs_done"] / max(stB["batches"], 1), 2),
+        "batched_graph_closed_loop_jobs_per_s": round(muG, 1),
         "open_loop_by_load": runs,
     }
 

@@ -205,6 +205,8 @@ typedef struct {
     int32_t max_jobs_per_batch;  /* 1 .. IB_BATCH_MAX_JOBS (1: one job per launch sequence) */
     int32_t max_inflight;        /* 1 .. 4 batches queued on the GPU at once */
     int32_t max_queue;           /* jobs waiting; ib_batch_submit returns IB_ERR_BUSY beyond */
+    int32_t use_graph;           /* nonzero: each batch is one replay of a captured HIP graph
+                                    (fixed grids that loop over the batch's blocks) */
 } ib_server_opts;
 
 typedef struct {
@@ -213,8 +215,10 @@ typedef struct {
     uint64_t points;
 } ib_server_stats;
 
-/* arena: device memory (256-byte aligned) of arena_bytes, kept alive until destroy.  The
- * current HIP device is the server's.  Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED, IB_ERR_HIP. */
+/* arena: device memory (256-byte aligned) of arena_bytes, kept alive until destroy; its
+ * first 4 job-table slots (about 0.6 MB) are reserved, the rest holds the batches' plans.
+ * The current HIP device is the server's.  Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED,
+ * IB_ERR_OOM (arena too small for the tables), IB_ERR_HIP. */
 int32_t ib_server_create(const ib_server_opts *opts, void *arena, size_t arena_bytes,
                          ib_server *out);
 

@@ -20,27 +20,25 @@ struct JobGeom {
     int cs[3];
     double sx[3][3];
     Layout L;
-    size_t off;  // byte offset of the job's plan region in the workspace
+    size_t off;  // byte offset of the job's plan region from the start of the plan regions
 };
 
 struct BatchLayout {
-    size_t table_off, jobs_off, total;
+    size_t header;  // table and job array
+    size_t plans;   // all plan regions
     std::vector<JobGeom> jobs;
 };
 
-// Validate the jobs and lay out the workspace: the table, the job array, then one plan
-// region per job (radix digits of BATCH_RBITS bits for all).
+// Validate the jobs and lay out their plan regions (radix digits of BATCH_RBITS bits for
+// all), one after another from offset 0.
 int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayout* B)
 {
     if (!jobs || njobs < 1) return IB_ERR_ARG;
     if (njobs > BATCH_MAX_JOBS) return IB_ERR_UNSUPPORTED;
     if (dtype != IB_F64 && dtype != IB_F32) return IB_ERR_UNSUPPORTED;
     B->jobs.resize(njobs);
+    B->header = batch_header_bytes(njobs);
     size_t off = 0;
-    B->table_off = off;
-    off += align_up(sizeof(BatchTable));
-    B->jobs_off = off;
-    off += align_up((size_t)njobs * sizeof(BatchJob));
     for (int j = 0; j < njobs; ++j) {
         const ib_job& J = jobs[j];
         JobGeom& G = B->jobs[j];
@@ -56,28 +54,33 @@ int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayo
         G.off = off;
         off += G.L.total;
     }
-    B->total = off;
+    B->plans = off;
     return IB_OK;
 }
 
-// Host copies of the job array and the table for jobs laid out by B over `workspace`.
+// Fill the host copy of the header (table, then job array, as batch_header_bytes lays them
+// out) for jobs whose header will live at `header_dev` and whose plan regions start at
+// `plans_dev`; and the launch description with exact grids.
 void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLayout& B,
-                 char* workspace, BatchJob* hj, BatchTable* ht, BatchLaunch* bl)
+                 char* header_dev, char* plans_dev, char* host_header, BatchLaunch* bl)
 {
+    BatchTable* ht = (BatchTable*)host_header;
+    BatchJob* hj = (BatchJob*)(host_header + align_up(sizeof(BatchTable)));
     std::memset(ht, 0, sizeof *ht);
     ht->njobs = njobs;
     int counts[BS_COUNT];
     size_t keys_lds = 0;
+    uint32_t* flags_dev = (uint32_t*)(header_dev + offsetof(BatchTable, flags));
     for (int j = 0; j < njobs; ++j) {
         const ib_job& J = jobs[j];
         const JobGeom& G = B.jobs[j];
         ib_plan_s p;
-        plan_setup(&p, &J.grid, dtype, J.npts, G.nstag, G.cs, G.sx, G.L, workspace + G.off);
+        plan_setup(&p, &J.grid, dtype, J.npts, G.nstag, G.cs, G.sx, G.L, plans_dev + G.off);
         BatchJob& b = hj[j];
         std::memset(&b, 0, sizeof b);
         b.sa = p.sa;
         // All error flags of the batch sit in the table, so one copy reads them back.
-        b.sa.d.flag = (uint32_t*)(workspace + B.table_off + offsetof(BatchTable, flags)) + j;
+        b.sa.d.flag = flags_dev + j;
         OpArgs& a = b.op;
         a.g = p.sa.g;
         a.sorted_keys = p.sorted_keys;
@@ -108,8 +111,8 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         for (int s = 0; s < BS_COUNT; ++s) ht->starts[s][j + 1] = ht->starts[s][j] + counts[s];
         if (counts[BS_KEYS] > 0 && keys_lds_bytes(sa) > keys_lds) keys_lds = keys_lds_bytes(sa);
     }
-    bl->jobs = (const BatchJob*)(workspace + B.jobs_off);
-    bl->table = (const BatchTable*)(workspace + B.table_off);
+    bl->jobs = (const BatchJob*)(header_dev + align_up(sizeof(BatchTable)));
+    bl->table = (const BatchTable*)header_dev;
     bl->dtype = dtype;
     bl->dim = jobs[0].grid.dim;
     bl->kernel = jobs[0].grid.kernel;
@@ -138,6 +141,19 @@ size_t batch_job_bytes(const ib_job* job, int32_t dtype)
     return L.total;
 }
 
+int32_t batch_prepare(const ib_job* jobs, int32_t njobs, int32_t dtype, void* header_dev,
+                      void* plans_dev, size_t plans_bytes, void* host_header, BatchLaunch* bl)
+{
+    BatchLayout B;
+    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    if (st != IB_OK) return st;
+    if (!header_dev || !plans_dev || !host_header) return IB_ERR_ARG;
+    if (((uintptr_t)header_dev % ALIGN) != 0 || ((uintptr_t)plans_dev % ALIGN) != 0) return IB_ERR_ARG;
+    if (plans_bytes < B.plans) return IB_ERR_OOM;
+    batch_build(jobs, njobs, dtype, B, (char*)header_dev, (char*)plans_dev, (char*)host_header, bl);
+    return IB_OK;
+}
+
 int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
                      size_t workspace_bytes, void* host_staging, hipStream_t hs)
 {
@@ -145,11 +161,9 @@ int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
     int32_t st = batch_layout(jobs, njobs, dtype, &B);
     if (st != IB_OK) return st;
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
-    if (workspace_bytes < B.total) return IB_ERR_OOM;
+    if (workspace_bytes < B.header + B.plans) return IB_ERR_OOM;
     char* base = (char*)workspace;
-
-    // The table and the job array go up in one copy: [table | pad | jobs], the same
-    // arrangement as at the head of the workspace.
+    // The header goes up in one copy from host memory laid out like its device copy.
     const size_t nbytes = align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
     std::vector<char> pageable;
     char* stage = (char*)host_staging;
@@ -157,10 +171,8 @@ int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
         pageable.resize(nbytes);
         stage = pageable.data();
     }
-    BatchTable* ht = (BatchTable*)stage;
-    BatchJob* hj = (BatchJob*)(stage + B.jobs_off);
     BatchLaunch bl;
-    batch_build(jobs, njobs, dtype, B, base, hj, ht, &bl);
+    batch_build(jobs, njobs, dtype, B, base, base + B.header, stage, &bl);
     if (hipMemcpyAsync(base, stage, nbytes, hipMemcpyHostToDevice, hs) != hipSuccess)
         return IB_ERR_HIP;
     hipError_t e = launch_batch_plan(bl, hs);
@@ -176,7 +188,7 @@ size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype
 {
     BatchLayout B;
     if (batch_layout(jobs, njobs, dtype, &B) != IB_OK) return 0;
-    return B.total;
+    return B.header + B.plans;
 }
 
 size_t ib_batch_staging_bytes(int32_t njobs)
@@ -202,7 +214,7 @@ int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const 
     if (!workspace) return IB_ERR_ARG;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return IB_ERR_HIP;
     std::vector<uint32_t> flags(njobs);
-    const char* fp = (const char*)workspace + B.table_off + offsetof(BatchTable, flags);
+    const char* fp = (const char*)workspace + offsetof(BatchTable, flags);
     if (hipMemcpy(flags.data(), fp, njobs * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return IB_ERR_HIP;
     int32_t worst = IB_OK;

@@ -59,5 +59,10 @@ size_t batch_job_bytes(const ib_job* job, int32_t dtype);  // 0 for an invalid j
 size_t batch_flags_offset();                               // of the per-job flags in the header
 int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
                      size_t workspace_bytes, void* host_staging, hipStream_t stream);
+// Build a batch whose header lives at header_dev (batch_header_bytes(njobs)) and whose plan
+// regions start at plans_dev: writes the header's host copy (to be uploaded) and the launch
+// description with exact grids.  Launches nothing.
+int32_t batch_prepare(const ib_job* jobs, int32_t njobs, int32_t dtype, void* header_dev,
+                      void* plans_dev, size_t plans_bytes, void* host_header, BatchLaunch* bl);
 
 }  // namespace ibk

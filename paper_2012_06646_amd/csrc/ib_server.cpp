@@ -27,6 +27,7 @@ using namespace ibk;
 namespace {
 
 constexpr int MAX_INFLIGHT = 4;
+constexpr int GRAPH_GRID = 1024;  // blocks per stage in a captured batch graph
 
 struct QueuedJob {
     ib_job job;
@@ -50,7 +51,9 @@ struct Flight {
 
 struct ib_server_s {
     ib_server_opts opts;
-    char* arena;
+    char* arena;         // slot headers, then the ring of plan regions
+    char* plans;         // start of the ring
+    size_t header_bytes; // one slot's header (job table for max_jobs_per_batch jobs)
     Ring ring;
     int device;
     hipStream_t stream;
@@ -59,6 +62,9 @@ struct ib_server_s {
     size_t slot_bytes;
     hipEvent_t events[MAX_INFLIGHT];
     bool slot_busy[MAX_INFLIGHT];
+    // With use_graph: one graph per slot and (dimension, kernel), captured on first use; its
+    // grids are fixed and its kernels loop over the batch's virtual blocks.
+    hipGraphExec_t graphs[MAX_INFLIGHT][2][2];
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -115,7 +121,7 @@ struct ib_server_s {
             if (!slot_busy[s]) { slot = s; break; }
         if (slot < 0) return false;
         // Admit jobs in arrival order while they share the first job's dimension and kernel
-        // and the batch's whole footprint still fits in the arena.
+        // and their plan regions still fit in the free part of the arena.
         const ib_job& j0 = queue.front().job;
         size_t body = 0, off = 0;
         int k = 0;
@@ -123,7 +129,7 @@ struct ib_server_s {
             const ib_job& jk = queue[k].job;
             if (jk.grid.dim != j0.grid.dim || jk.grid.kernel != j0.grid.kernel) break;
             size_t o;
-            if (!ring.place(batch_header_bytes(k + 1) + body + queue[k].bytes, &o)) break;
+            if (!ring.place(body + queue[k].bytes, &o)) break;
             body += queue[k].bytes;
             off = o;
             ++k;
@@ -138,14 +144,26 @@ struct ib_server_s {
             jobs[i] = queue.front().job;
             queue.pop_front();
         }
-        const size_t total = batch_header_bytes(k) + body;
-        char* ws = arena + off;
+        const size_t total = body;
+        char* header = arena + (size_t)slot * header_bytes;
         char* stage = staging + (size_t)slot * slot_bytes;
-        int32_t st = batch_launch(jobs.data(), k, opts.dtype, ws, total, stage, stream);
-        if (st == IB_OK &&
-            hipMemcpyAsync(flags + (size_t)slot * BATCH_MAX_JOBS, ws + batch_flags_offset(),
-                           k * sizeof(uint32_t), hipMemcpyDeviceToHost, stream) != hipSuccess)
-            st = IB_ERR_HIP;
+        uint32_t* fl = flags + (size_t)slot * BATCH_MAX_JOBS;
+        BatchLaunch bl;
+        int32_t st = batch_prepare(jobs.data(), k, opts.dtype, header, plans + off, total, stage, &bl);
+        if (st == IB_OK) {
+            if (opts.use_graph) {
+                st = graph_launch(slot, bl);
+            } else {
+                const size_t nb = align_up(sizeof(BatchTable)) + (size_t)k * sizeof(BatchJob);
+                hipError_t e = hipMemcpyAsync(header, stage, nb, hipMemcpyHostToDevice, stream);
+                if (e == hipSuccess) e = launch_batch_plan(bl, stream);
+                if (e == hipSuccess) e = launch_batch_ops(bl, stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(fl, header + batch_flags_offset(), k * sizeof(uint32_t),
+                                       hipMemcpyDeviceToHost, stream);
+                st = hip_status(e);
+            }
+        }
         if (st == IB_OK && hipEventRecord(F.done, stream) != hipSuccess) st = IB_ERR_HIP;
         if (st != IB_OK) {
             const double t = now_us();
@@ -162,6 +180,42 @@ struct ib_server_s {
         flight.push_back(std::move(F));
         stats.batches += 1;
         return true;
+    }
+
+    // Replay the slot's graph for this batch's dimension and kernel (capturing it first if
+    // needed): upload of the whole slot header, every stage with fixed grids, download of
+    // the flags.  The header's host copy is already in the slot's staging buffer.
+    int32_t graph_launch(int slot, const BatchLaunch& exact)
+    {
+        const int di = exact.dim == 3 ? 1 : 0, ki = exact.kernel == IB_KERNEL_COSINE4 ? 1 : 0;
+        hipGraphExec_t& ge = graphs[slot][di][ki];
+        if (!ge) {
+            char* header = arena + (size_t)slot * header_bytes;
+            BatchLaunch bl = exact;
+            for (int s = 0; s < BS_COUNT; ++s) bl.grid[s] = GRAPH_GRID;
+            bl.keys_lds = (size_t)BATCH_MAX_PASSES * ((size_t)1 << BATCH_RBITS) * sizeof(uint32_t);
+            const size_t nb = align_up(sizeof(BatchTable)) +
+                              (size_t)opts.max_jobs_per_batch * sizeof(BatchJob);
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return IB_ERR_HIP;
+            hipError_t e = hipMemcpyAsync(header, staging + (size_t)slot * slot_bytes, nb,
+                                          hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = launch_batch_plan(bl, stream);
+            if (e == hipSuccess) e = launch_batch_ops(bl, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(flags + (size_t)slot * BATCH_MAX_JOBS, header + batch_flags_offset(),
+                                   BATCH_MAX_JOBS * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+            const hipError_t e2 = hipStreamEndCapture(stream, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ge = nullptr;
+                return IB_ERR_HIP;
+            }
+        }
+        return hip_status(hipGraphLaunch(ge, stream));
     }
 
     void run()
@@ -199,9 +253,17 @@ int32_t ib_server_create(const ib_server_opts* opts, void* arena, size_t arena_b
     if (!s) return IB_ERR_OOM;
     s->opts = *opts;
     s->arena = (char*)arena;
-    s->ring.cap = arena_bytes;
+    s->header_bytes = batch_header_bytes(BATCH_MAX_JOBS);
+    const size_t reserved = MAX_INFLIGHT * s->header_bytes;
+    if (arena_bytes <= reserved) {
+        delete s;
+        return IB_ERR_OOM;
+    }
+    s->plans = s->arena + reserved;
+    s->ring.cap = arena_bytes - reserved;
+    std::memset(s->graphs, 0, sizeof s->graphs);
     std::memset(&s->stats, 0, sizeof s->stats);
-    s->slot_bytes = align_up(ib_batch_staging_bytes(opts->max_jobs_per_batch));
+    s->slot_bytes = s->header_bytes;
     bool ok = hipGetDevice(&s->device) == hipSuccess &&
               hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
     s->staging = nullptr;
@@ -238,7 +300,7 @@ int32_t ib_batch_submit(ib_server s, const ib_job* job, double arrival_us, uint6
     if (job->npts > 0 && !job->X) return IB_ERR_ARG;
     if (job->f && job->npts > 0 && !job->F) return IB_ERR_ARG;
     if (job->u && job->npts > 0 && !job->U) return IB_ERR_ARG;
-    if (batch_header_bytes(1) + bytes > s->ring.cap) return IB_ERR_OOM;  // can never be admitted
+    if (bytes > s->ring.cap) return IB_ERR_OOM;  // can never be admitted
     std::lock_guard<std::mutex> lk(s->mu);
     if ((int64_t)s->queue.size() >= s->opts.max_queue) return IB_ERR_BUSY;
     QueuedJob q;
@@ -292,7 +354,12 @@ void ib_server_destroy(ib_server s)
     s->cv.notify_all();
     s->worker.join();
     (void)hipStreamSynchronize(s->stream);
-    for (int i = 0; i < MAX_INFLIGHT; ++i) (void)hipEventDestroy(s->events[i]);
+    for (int i = 0; i < MAX_INFLIGHT; ++i) {
+        (void)hipEventDestroy(s->events[i]);
+        for (int d = 0; d < 2; ++d)
+            for (int k = 0; k < 2; ++k)
+                if (s->graphs[i][d][k]) (void)hipGraphExecDestroy(s->graphs[i][d][k]);
+    }
     (void)hipStreamDestroy(s->stream);
     (void)hipHostFree(s->staging);
     (void)hipHostFree(s->flags);

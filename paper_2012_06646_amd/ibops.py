@@ -74,7 +74,7 @@ _lib.ib_batch_status.restype = _i32
 _lib.ib_batch_status.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.POINTER(_i32), _vp]
 class ServerOpts(ctypes.Structure):
     _fields_ = [("dtype", _i32), ("max_jobs_per_batch", _i32), ("max_inflight", _i32),
-                ("max_queue", _i32)]
+                ("max_queue", _i32), ("use_graph", _i32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -391,11 +391,12 @@ class Server:
     device arena (the server's HBM budget) is allocated here with torch and handed over."""
 
     def __init__(self, dtype=torch.float32, arena_bytes=16 << 30, max_jobs_per_batch=BATCH_MAX_JOBS,
-                 max_inflight=2, max_queue=1 << 20, device="cuda"):
+                 max_inflight=2, max_queue=1 << 20, use_graph=False, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
-        o = ServerOpts(_dtype_code(dtype), int(max_jobs_per_batch), int(max_inflight), int(max_queue))
+        o = ServerOpts(_dtype_code(dtype), int(max_jobs_per_batch), int(max_inflight), int(max_queue),
+                       int(bool(use_graph)))
         h = ctypes.c_void_p()
         _check(_lib.ib_server_create(ctypes.byref(o), _ptr(self.arena), self.arena.numel(),
                                      ctypes.byref(h)), "ib_server_create")

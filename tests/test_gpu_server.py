@@ -44,12 +44,15 @@ def run_all(srv, jobs):
     return out
 
 
-@pytest.mark.parametrize("max_batch", [1, 5, 128])
-def test_server_results_match_jobs_run_alone(ib, max_batch):
+@pytest.mark.parametrize("max_batch,graph", [(1, False), (5, False), (128, False), (1, True),
+                                             (5, True), (128, True)])
+def test_server_results_match_jobs_run_alone(ib, max_batch, graph):
+    """Every batch (with graphs: every replay of the slot's graph, with other work and
+    synchronisations between replays) against the same jobs run alone, bit for bit."""
     dtype = torch.float32
     jobs = serving_jobs(40, dtype, 6000)
-    say(f"server max_batch={max_batch}: 40 jobs")
-    srv = ib.Server(dtype, arena_bytes=256 << 20, max_jobs_per_batch=max_batch)
+    say(f"server max_batch={max_batch} graph={graph}: 40 jobs")
+    srv = ib.Server(dtype, arena_bytes=256 << 20, max_jobs_per_batch=max_batch, use_graph=graph)
     out = run_all(srv, jobs)
     st = srv.stats()
     srv.close()
@@ -61,13 +64,14 @@ def test_server_results_match_jobs_run_alone(ib, max_batch):
         assert torch.equal(jobs[j]["f"], f1) and torch.equal(jobs[j]["U"], U1), f"job {j}"
 
 
-def test_server_small_arena_wraps(ib):
+@pytest.mark.parametrize("graph", [False, True])
+def test_server_small_arena_wraps(ib, graph):
     """An arena that holds only a few jobs at a time: batches stay small, the ring wraps."""
     dtype = torch.float64
     jobs = serving_jobs(30, dtype, 6100, sizes=(32,), nmax=30000)
     sizes = [ib.workspace_bytes(j["grid"], dtype, j["X"].shape[0]) for j in jobs]
-    arena = 3 * max(sizes) + (1 << 20)
-    srv = ib.Server(dtype, arena_bytes=arena, max_jobs_per_batch=128)
+    arena = 3 * max(sizes) + (4 << 20)
+    srv = ib.Server(dtype, arena_bytes=arena, max_jobs_per_batch=128, use_graph=graph)
     out = run_all(srv, jobs)
     st = srv.stats()
     srv.close()

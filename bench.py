@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--npts", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", choices=["auto", "none"], default="auto",
+                    help="pick the plan tuning (spreading tile, tile sharing, radix digits) with "
+                         "the autotuner on the initial positions, or use the built-in choices")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the batched-serving measurement (Poisson job stream)")
     ap.add_argument("--serving-only", action="store_true")
@@ -260,7 +263,12 @@ def main():
     ud = torch.from_numpy(u).to(dev, dtype)
     f = torch.empty([3, 128, 128, 128], dtype=dtype, device=dev)
     U = torch.empty((npts, 3), dtype=dtype, device=dev)
-    plan = ibops.Plan(g, npts, dtype, dev)
+    tuning, tune_info = None, None
+    if args.tune == "auto":
+        from paper_2012_06646_amd import tune
+        tuning, tried = tune.autotune(g, X, Fd, ud, reps=5, store=False)
+        tune_info = {"chosen": tuning, "candidates_ms": tried}
+    plan = ibops.Plan(g, npts, dtype, dev, tuning=tuning)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -354,6 +362,7 @@ def main():
                                "spread + interpolate + advect (dt = 0.1 h)",
                    "grid": [128, 128, 128], "npts": npts, "seed": 1002},
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "tuning": tune_info,
         "step_algorithmic_bytes": sum(algo.values()),
         "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "host_wall_s": round(t_host, 4),

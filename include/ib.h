@@ -67,6 +67,21 @@ typedef struct {
 
 typedef struct ib_plan_s *ib_plan;
 
+/* Tuning of a plan; all-zero fields select the built-in choices.
+ *   spread_tile   3-D spreading tile (x*y*z cells owned by one block): 0 = 32x16x13,
+ *                 1 = 32x8x13, 2 = 64x8x8 (2-D grids always use 64x32)
+ *   split_points  points per block before a spreading tile is shared by several blocks
+ *                 (at most 16): 0 = 2048, < 0 = never share
+ *   radix_bits    radix digit width of the key sort, 4..8: 0 = the key bits spread evenly
+ *                 over the fewest passes of at most 8 bits
+ * Results do not depend on the tuning beyond rounding: keys, permutations and offsets are
+ * identical, and spread values may differ in the order of their additions. */
+typedef struct {
+    int32_t spread_tile;
+    int32_t split_points;
+    int32_t radix_bits;
+} ib_tuning;
+
 /* Human-readable name of a status code (static string). */
 const char *ib_status_string(int32_t status);
 
@@ -106,6 +121,14 @@ int32_t ib_plan_export(ib_plan plan, int32_t stagger_id, int32_t *keys, int32_t 
 int32_t ib_plan_status(ib_plan plan);
 
 void ib_plan_destroy(ib_plan plan);
+
+/* As ib_plan_workspace_bytes / ib_plan_create, with a tuning (NULL = defaults).  An
+ * out-of-range tuning field gives 0 bytes / IB_ERR_ARG. */
+size_t ib_plan_workspace_bytes_tuned(const ib_grid_desc *grid, int32_t dtype, int64_t npts,
+                                     const ib_tuning *tuning);
+int32_t ib_plan_create_tuned(const ib_grid_desc *grid, int32_t dtype, int64_t npts,
+                             const ib_tuning *tuning, void *workspace, size_t workspace_bytes,
+                             ib_plan *out);
 
 /* ---- operators ---------------------------------------------------------------------- */
 

@@ -63,9 +63,18 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     return IB_OK;
 }
 
-void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed)
+int32_t check_tuning(const ib_tuning* t)
 {
+    if (!t) return IB_OK;
+    if (t->spread_tile < 0 || t->spread_tile >= SPREAD_TILE_SHAPES) return IB_ERR_ARG;
+    if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > MAX_RADIX_BITS)) return IB_ERR_ARG;
+    return IB_OK;
+}
+
+void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
+                 int rbits_fixed, const ib_tuning* tuning)
+{
+    if (rbits_fixed == 0 && tuning && tuning->radix_bits) rbits_fixed = tuning->radix_bits;
     L->nstag = nstag;
     L->G = 1;
     for (int k = 0; k < g->dim; ++k) L->G *= g->n[k];
@@ -102,11 +111,12 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->Xs = take((size_t)n * g->dim * b);
     L->Fs = take((size_t)n * g->ncomp * b);
     int tiles[3];
-    spread_tiles(g->dim, g->n, tiles);
+    L->sp_tile = (tuning && g->dim == 3) ? tuning->spread_tile : 0;
+    spread_tiles(g->dim, L->sp_tile, g->n, tiles);
     L->sp_tiles = tiles[0] * tiles[1] * tiles[2] * g->ncomp;
-    L->split = spread_split(n, L->sp_tiles);
-    L->partial = take(L->split > 1 ? (size_t)L->split * L->sp_tiles * spread_tile_cells(g->dim) *
-                                         sizeof(double)
+    L->split = spread_split(n, L->sp_tiles, tuning ? tuning->split_points : 0);
+    L->partial = take(L->split > 1 ? (size_t)L->split * L->sp_tiles *
+                                         spread_tile_cells(g->dim, L->sp_tile) * sizeof(double)
                                    : 0);
     // Everything from here to zero_end is cleared at every update.
     L->zero_begin = off;
@@ -199,6 +209,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     }
     g.scale = 1.0 / hd;
     g.split = L.split;
+    g.sp_tile = L.sp_tile;
     for (int c = 0; c < grid->ncomp; ++c) {
         g.comp_stag[c] = cs[c];
         for (int k = 0; k < 3; ++k) {
@@ -253,14 +264,35 @@ extern "C" {
 int32_t ib_plan_create(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* workspace,
                        size_t workspace_bytes, ib_plan* out)
 {
+    return ib_plan_create_tuned(grid, dtype, npts, nullptr, workspace, workspace_bytes, out);
+}
+
+size_t ib_plan_workspace_bytes_tuned(const ib_grid_desc* grid, int32_t dtype, int64_t npts,
+                                     const ib_tuning* tuning)
+{
+    int nstag, cs[3];
+    double sx[3][3];
+    if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
+    if (check_tuning(tuning) != IB_OK) return 0;
+    Layout L;
+    make_layout(grid, dtype, nstag, npts, &L, 0, tuning);
+    return L.total;
+}
+
+int32_t ib_plan_create_tuned(const ib_grid_desc* grid, int32_t dtype, int64_t npts,
+                             const ib_tuning* tuning, void* workspace, size_t workspace_bytes,
+                             ib_plan* out)
+{
     if (!out) return IB_ERR_ARG;
     *out = nullptr;
     int nstag, cs[3];
     double sx[3][3] = {{0}};
     int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
     if (st != IB_OK) return st;
+    st = check_tuning(tuning);
+    if (st != IB_OK) return st;
     Layout L;
-    make_layout(grid, dtype, nstag, npts, &L);
+    make_layout(grid, dtype, nstag, npts, &L, 0, tuning);
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
     if (workspace_bytes < L.total) return IB_ERR_OOM;
 

@@ -31,7 +31,7 @@ size_t align_up(size_t v);
 struct Layout {
     int nstag, npass, rbits, rows, nbx;
     int64_t ntiles, nseg_tiles, G;
-    int sp_tiles, split;  // spreading tiles (x components) and blocks per tile
+    int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, partial, zero_begin, hist,
         sort_status, seg_status, counters, flag, tile_count, zero_end, total;
 };
@@ -44,7 +44,9 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
 // Workspace layout of a plan; rbits_fixed > 0 forces that radix digit width (batched plans
 // share one sort kernel), else the digit width spreads the key bits evenly over passes.
 void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed = 0);
+                 int rbits_fixed = 0, const ib_tuning* tuning = nullptr);
+// IB_OK if every field of a (possibly null) tuning is in range.
+int32_t check_tuning(const ib_tuning* t);
 
 // Fill a plan object for a validated descriptor over a workspace of layout L.
 void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t npts, int nstag,

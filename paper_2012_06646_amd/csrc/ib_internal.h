@@ -83,6 +83,7 @@ struct GeomArgs {
     double comp_xi[3][3];  // per component
     double scale;          // (prod_k h_k)^-1 for spreading
     int split;             // blocks per spreading tile (see spread_split)
+    int sp_tile;           // spreading tile shape (ib_tuning.spread_tile)
 };
 
 struct SortArgs {
@@ -159,12 +160,13 @@ int keys_blocks(const SortArgs& a);
 size_t keys_lds_bytes(const SortArgs& a);
 int gather_blocks(int64_t npts, int ncomp);
 int interp_blocks(int64_t npts);
-void spread_tiles(int dim, const int n[3], int tiles[3]);
+constexpr int SPREAD_TILE_SHAPES = 3;
+void spread_tiles(int dim, int shape, const int n[3], int tiles[3]);
 // Cells of one spreading tile, and the number of blocks that share a tile (1 .. 16) for
 // npts points over ntiles (tiles x components) tiles: a dense point set on a small grid
-// would otherwise leave most of the GPU idle.
-size_t spread_tile_cells(int dim);
-int spread_split(int64_t npts, int ntiles);
+// would otherwise leave most of the GPU idle.  split_points as in ib_tuning.
+size_t spread_tile_cells(int dim, int shape);
+int spread_split(int64_t npts, int ntiles, int split_points);
 
 hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st);
 hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st);

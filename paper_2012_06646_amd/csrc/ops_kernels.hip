@@ -743,7 +743,9 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // Launchers
 // ---------------------------------------------------------------------------------------
 namespace {
-constexpr int SP_TX = 32, SP_TY = 16, SP_TZ = 13;   // spreading tile (3-D): 960 blocks at 128^3
+// Spreading tiles (3-D) selectable per plan; shape 0 is the default (960 blocks at 128^3).
+constexpr int SP_SHAPE[SPREAD_TILE_SHAPES][3] = {{32, 16, 13}, {32, 8, 13}, {64, 8, 8}};
+constexpr int SP_TX = SP_SHAPE[0][0], SP_TY = SP_SHAPE[0][1], SP_TZ = SP_SHAPE[0][2];
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -755,12 +757,22 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
     if (gb > 0)
         hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(gb), dim3(256), 0, st, a.g.npts, a.g.ncomp,
                            a.perm, (const T*)a.F, (T*)a.Fs);
-    spread_tiles(a.g.dim, a.g.n, a.tiles);
+    spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles);
     const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split);
-    if (a.g.dim == 3)
-        hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_TX, SP_TY, SP_TZ>), dim3(nb), dim3(256),
-                           0, st, a);
-    else
+    if (a.g.dim == 3) {
+        switch (a.g.sp_tile) {
+#define IBK_SPREAD_SHAPE(i)                                                                       \
+    case i:                                                                                       \
+        hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_SHAPE[i][0], SP_SHAPE[i][1], SP_SHAPE[i][2]>), \
+                           dim3(nb), dim3(256), 0, st, a);                                        \
+        break;
+            IBK_SPREAD_SHAPE(0)
+            IBK_SPREAD_SHAPE(1)
+            IBK_SPREAD_SHAPE(2)
+#undef IBK_SPREAD_SHAPE
+        default: return hipErrorInvalidValue;
+        }
+    } else
         hipLaunchKernelGGL((spread_kernel<T, 2, KERN, SP2_TX, SP2_TY, 1>), dim3(nb), dim3(256),
                            0, st, a);
     return hipGetLastError();
@@ -864,12 +876,13 @@ int interp_blocks(int64_t npts)
     return npts > 0 ? (int)min((int64_t)65536, (npts + 255) / 256) : 0;
 }
 
-void spread_tiles(int dim, const int n[3], int tiles[3])
+void spread_tiles(int dim, int shape, const int n[3], int tiles[3])
 {
     if (dim == 3) {
-        tiles[0] = cdiv(n[0], SP_TX);
-        tiles[1] = cdiv(n[1], SP_TY);
-        tiles[2] = cdiv(n[2], SP_TZ);
+        const int* t = SP_SHAPE[(shape >= 0 && shape < SPREAD_TILE_SHAPES) ? shape : 0];
+        tiles[0] = cdiv(n[0], t[0]);
+        tiles[1] = cdiv(n[1], t[1]);
+        tiles[2] = cdiv(n[2], t[2]);
     } else {
         tiles[0] = cdiv(n[0], SP2_TX);
         tiles[1] = cdiv(n[1], SP2_TY);
@@ -877,17 +890,20 @@ void spread_tiles(int dim, const int n[3], int tiles[3])
     }
 }
 
-size_t spread_tile_cells(int dim)
+size_t spread_tile_cells(int dim, int shape)
 {
-    return dim == 3 ? (size_t)SP_TX * SP_TY * SP_TZ : (size_t)SP2_TX * SP2_TY;
+    if (dim != 3) return (size_t)SP2_TX * SP2_TY;
+    const int* t = SP_SHAPE[(shape >= 0 && shape < SPREAD_TILE_SHAPES) ? shape : 0];
+    return (size_t)t[0] * t[1] * t[2];
 }
 
-// About 2048 points per block at least; the 128^3 grid with 10^6 points keeps one block
-// per tile, a 32^3 grid with 10^6 points gets 16.
-int spread_split(int64_t npts, int ntiles)
+// By default about 2048 points per block at least: the 128^3 grid with 10^6 points keeps
+// one block per tile, a 32^3 grid with 10^6 points gets 16.
+int spread_split(int64_t npts, int ntiles, int split_points)
 {
-    if (ntiles <= 0) return 1;
-    const int64_t s = npts / ((int64_t)ntiles * 2048);
+    if (ntiles <= 0 || split_points < 0) return 1;
+    const int64_t per = split_points > 0 ? split_points : 2048;
+    const int64_t s = npts / ((int64_t)ntiles * per);
     return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
 }
 

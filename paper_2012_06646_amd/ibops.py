@@ -30,6 +30,19 @@ class GridDesc(ctypes.Structure):
                 ("kernel", ctypes.c_int32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("spread_tile", ctypes.c_int32), ("split_points", ctypes.c_int32),
+                ("radix_bits", ctypes.c_int32)]
+
+
+def make_tuning(t):
+    """ib_tuning from None (defaults) or a dict with any of spread_tile, split_points,
+    radix_bits."""
+    if t is None:
+        return None
+    return Tuning(int(t.get("spread_tile", 0)), int(t.get("split_points", 0)), int(t.get("radix_bits", 0)))
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _lib.ib_status_string.restype = ctypes.c_char_p
@@ -39,6 +52,11 @@ _lib.ib_plan_workspace_bytes.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.
 _lib.ib_plan_create.restype = _i32
 _lib.ib_plan_create.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, ctypes.c_size_t,
                                 ctypes.POINTER(_vp)]
+_lib.ib_plan_workspace_bytes_tuned.restype = ctypes.c_size_t
+_lib.ib_plan_workspace_bytes_tuned.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, ctypes.POINTER(Tuning)]
+_lib.ib_plan_create_tuned.restype = _i32
+_lib.ib_plan_create_tuned.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, ctypes.POINTER(Tuning), _vp,
+                                      ctypes.c_size_t, ctypes.POINTER(_vp)]
 _lib.ib_plan_num_staggers.restype = _i32
 _lib.ib_plan_num_staggers.argtypes = [_vp]
 _lib.ib_plan_stagger_of.restype = _i32
@@ -99,7 +117,7 @@ _lib.ib_server_destroy.argtypes = [_vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
 
-EXPORTED = ["ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
+EXPORTED = ["ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
             "ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
@@ -158,7 +176,9 @@ class Plan:
     """Cell keys, stable sort and segments of a point set (Alg. 4 preparation), resident on
     the device.  `update(X)` recomputes them; spread/interpolate use the last update."""
 
-    def __init__(self, grid, npts, dtype=torch.float64, device="cuda"):
+    def __init__(self, grid, npts, dtype=torch.float64, device="cuda", tuning=None):
+        """tuning: None (built-in choices), a dict of ib_tuning fields, or "auto" (the
+        cached autotuner result for this grid, dtype and point count, if any)."""
         self.grid = grid
         self.desc = make_desc(grid)
         self.npts = int(npts)
@@ -166,14 +186,20 @@ class Plan:
         self.device = torch.device(device)
         self.dim = self.desc.dim
         self.ncomp = self.desc.ncomp
+        if tuning == "auto":
+            from . import tune
+            tuning = tune.cached(grid, dtype, self.npts)
+        self.tuning = tuning
+        tz = make_tuning(tuning)
+        tp = ctypes.byref(tz) if tz is not None else None
         code = _dtype_code(dtype)
-        nbytes = int(_lib.ib_plan_workspace_bytes(ctypes.byref(self.desc), code, self.npts))
+        nbytes = int(_lib.ib_plan_workspace_bytes_tuned(ctypes.byref(self.desc), code, self.npts, tp))
         if nbytes == 0:
             _check(-4, "ib_plan_workspace_bytes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
-        _check(_lib.ib_plan_create(ctypes.byref(self.desc), code, self.npts, _ptr(self.workspace),
-                                   nbytes, ctypes.byref(h)), "ib_plan_create")
+        _check(_lib.ib_plan_create_tuned(ctypes.byref(self.desc), code, self.npts, tp,
+                                         _ptr(self.workspace), nbytes, ctypes.byref(h)), "ib_plan_create")
         self._h = h
         self.X = None
         self.nstag = _lib.ib_plan_num_staggers(h)

@@ -106,3 +106,21 @@ def test_batch_workspace_sizing_and_validation(ib):
     assert ib._lib.ib_batch_run(arr, 3, 0, ctypes.c_void_p(4096 + 8), total, None, None) == -1
     assert ib._lib.ib_batch_run(arr, 3, 0, ctypes.c_void_p(4096), total - 1, None, None) == -2
     assert ib._lib.ib_batch_run(arr, 3, 7, ctypes.c_void_p(4096), total, None, None) == -4
+
+
+def test_tuned_workspace_and_validation(ib):
+    from paper_2012_06646_amd import workloads as wl
+    g = ib.make_desc(wl.grid(3, 32, 1.0))
+    T = ib.Tuning
+    base = ib._lib.ib_plan_workspace_bytes(ctypes.byref(g), 0, 10**6)
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, None) == base
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(0, 0, 0))) == base
+    # a dense point set shares tiles between blocks (partial tiles); never sharing needs less
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(0, -1, 0))) < base
+    for shape in (1, 2):
+        assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(shape, 0, 0))) > 0
+    for bad in (T(3, 0, 0), T(-1, 0, 0), T(0, 0, 3), T(0, 0, 9)):
+        assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 1000, ctypes.byref(bad)) == 0
+        h = ctypes.c_void_p()
+        assert ib._lib.ib_plan_create_tuned(ctypes.byref(g), 0, 1000, ctypes.byref(bad),
+                                            ctypes.c_void_p(4096), 1 << 30, ctypes.byref(h)) == -1

@@ -65,12 +65,13 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
                  char* header_dev, char* plans_dev, char* host_header, BatchLaunch* bl)
 {
     BatchTable* ht = (BatchTable*)host_header;
-    BatchJob* hj = (BatchJob*)(host_header + align_up(sizeof(BatchTable)));
+    BatchJob* hj = (BatchJob*)(host_header + batch_jobs_offset());
     std::memset(ht, 0, sizeof *ht);
+    std::memset(host_header + batch_flags_offset(), 0, BATCH_MAX_JOBS * sizeof(uint32_t));
     ht->njobs = njobs;
     int counts[BS_COUNT];
     size_t keys_lds = 0;
-    uint32_t* flags_dev = (uint32_t*)(header_dev + offsetof(BatchTable, flags));
+    uint32_t* flags_dev = (uint32_t*)(header_dev + batch_flags_offset());
     for (int j = 0; j < njobs; ++j) {
         const ib_job& J = jobs[j];
         const JobGeom& G = B.jobs[j];
@@ -111,7 +112,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         for (int s = 0; s < BS_COUNT; ++s) ht->starts[s][j + 1] = ht->starts[s][j] + counts[s];
         if (counts[BS_KEYS] > 0 && keys_lds_bytes(sa) > keys_lds) keys_lds = keys_lds_bytes(sa);
     }
-    bl->jobs = (const BatchJob*)(header_dev + align_up(sizeof(BatchTable)));
+    bl->jobs = (const BatchJob*)(header_dev + batch_jobs_offset());
     bl->table = (const BatchTable*)header_dev;
     bl->dtype = dtype;
     bl->dim = jobs[0].grid.dim;
@@ -124,12 +125,14 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
 
 namespace ibk {
 
+size_t batch_flags_offset() { return align_up(sizeof(BatchTable)); }
+
+size_t batch_jobs_offset() { return batch_flags_offset() + align_up(BATCH_MAX_JOBS * sizeof(uint32_t)); }
+
 size_t batch_header_bytes(int32_t njobs)
 {
-    return align_up(sizeof(BatchTable)) + align_up((size_t)njobs * sizeof(BatchJob));
+    return batch_jobs_offset() + align_up((size_t)njobs * sizeof(BatchJob));
 }
-
-size_t batch_flags_offset() { return offsetof(BatchTable, flags); }
 
 size_t batch_job_bytes(const ib_job* job, int32_t dtype)
 {
@@ -164,7 +167,7 @@ int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
     if (workspace_bytes < B.header + B.plans) return IB_ERR_OOM;
     char* base = (char*)workspace;
     // The header goes up in one copy from host memory laid out like its device copy.
-    const size_t nbytes = align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
+    const size_t nbytes = batch_jobs_offset() + (size_t)njobs * sizeof(BatchJob);
     std::vector<char> pageable;
     char* stage = (char*)host_staging;
     if (!stage) {
@@ -194,7 +197,7 @@ size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype
 size_t ib_batch_staging_bytes(int32_t njobs)
 {
     if (njobs < 1 || njobs > BATCH_MAX_JOBS) return 0;
-    return align_up(sizeof(BatchTable)) + (size_t)njobs * sizeof(BatchJob);
+    return batch_jobs_offset() + (size_t)njobs * sizeof(BatchJob);
 }
 
 
@@ -214,7 +217,7 @@ int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const 
     if (!workspace) return IB_ERR_ARG;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return IB_ERR_HIP;
     std::vector<uint32_t> flags(njobs);
-    const char* fp = (const char*)workspace + offsetof(BatchTable, flags);
+    const char* fp = (const char*)workspace + batch_flags_offset();
     if (hipMemcpy(flags.data(), fp, njobs * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)
         return IB_ERR_HIP;
     int32_t worst = IB_OK;

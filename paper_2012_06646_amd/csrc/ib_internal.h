@@ -139,10 +139,11 @@ struct BatchJob {
     OpArgs op;    // its operators (F/f and u/U null when not requested)
 };
 
+// Read-only during a batch.  The header of a batch in device memory is the table, then
+// the jobs' error flags (uint32_t[BATCH_MAX_JOBS], cleared by the upload), then the jobs.
 struct BatchTable {
     int32_t njobs;
     int32_t starts[BS_COUNT][BATCH_MAX_JOBS + 1];
-    uint32_t flags[BATCH_MAX_JOBS];  // each job's device error flag (cleared by the upload)
 };
 
 // Host-side view of a batch resident in device memory.

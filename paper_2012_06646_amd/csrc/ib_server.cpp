@@ -154,7 +154,7 @@ struct ib_server_s {
             if (opts.use_graph) {
                 st = graph_launch(slot, bl);
             } else {
-                const size_t nb = align_up(sizeof(BatchTable)) + (size_t)k * sizeof(BatchJob);
+                const size_t nb = batch_jobs_offset() + (size_t)k * sizeof(BatchJob);
                 hipError_t e = hipMemcpyAsync(header, stage, nb, hipMemcpyHostToDevice, stream);
                 if (e == hipSuccess) e = launch_batch_plan(bl, stream);
                 if (e == hipSuccess) e = launch_batch_ops(bl, stream);
@@ -194,8 +194,7 @@ struct ib_server_s {
             BatchLaunch bl = exact;
             for (int s = 0; s < BS_COUNT; ++s) bl.grid[s] = GRAPH_GRID;
             bl.keys_lds = (size_t)BATCH_MAX_PASSES * ((size_t)1 << BATCH_RBITS) * sizeof(uint32_t);
-            const size_t nb = align_up(sizeof(BatchTable)) +
-                              (size_t)opts.max_jobs_per_batch * sizeof(BatchJob);
+            const size_t nb = batch_jobs_offset() + (size_t)opts.max_jobs_per_batch * sizeof(BatchJob);
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return IB_ERR_HIP;

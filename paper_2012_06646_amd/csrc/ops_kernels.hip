@@ -393,7 +393,7 @@ struct SpreadTile {
 };
 
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__device__ void spread_body(const OpArgs& a, int bid)
+__device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
     // Tile rows padded in x (3 before, 3 after).  The tile accumulates in FP64 for both
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
 
 // Forces into the sorted order of staggering 0 (one gather of whole rows).
 template <typename T>
-__device__ void gather_rows_body(int64_t n, int ncols, const int32_t* __restrict__ perm,
+__device__ __forceinline__ void gather_rows_body(int64_t n, int ncols, const int32_t* __restrict__ perm,
                                  const T* __restrict__ src, T* __restrict__ dst, int bid, int nblk)
 {
     const int64_t total = n * ncols;
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int ncols,
 // neighbouring cells, so the 4^d gathers of a wave share cache lines.  All components of a
 // point are accumulated in registers and written together.
 template <typename T, int DIM, int KERN>
-__device__ void interp_body(const OpArgs& a, int bid, int nblk)
+__device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
 {
     const GeomArgs& g = a.g;
     const int64_t n = g.npts;
@@ -803,7 +803,8 @@ __device__ __forceinline__ int batch_job_of(const int32_t* starts, int njobs, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* jobs, const BatchTable* bt)
+__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_GATHER];
     const int nj = bt->njobs, total = st[nj];
@@ -816,7 +817,8 @@ __global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* jobs,
 }
 
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void batch_spread_kernel(const BatchJob* jobs, const BatchTable* bt)
+__global__ __launch_bounds__(256) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_SPREAD];
     const int nj = bt->njobs, total = st[nj];
@@ -828,7 +830,8 @@ __global__ __launch_bounds__(256) void batch_spread_kernel(const BatchJob* jobs,
 }
 
 template <typename T, int DIM, int KERN>
-__global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* jobs, const BatchTable* bt)
+__global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_INTERP];
     const int nj = bt->njobs, total = st[nj];

@@ -17,7 +17,7 @@
 namespace ibk {
 
 // ---- reset: clear histograms, look-back words, tickets and the error flag -------------
-__device__ void plan_reset_body(uint32_t* __restrict__ p, size_t nwords, int bid, int nblk)
+__device__ __forceinline__ void plan_reset_body(uint32_t* __restrict__ p, size_t nwords, int bid, int nblk)
 {
     for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < nwords; i += (size_t)nblk * blockDim.x)
         p[i] = 0u;
@@ -31,7 +31,7 @@ __global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
 // ---- keys: one per point and distinct staggering, plus all pass histograms ----------
 // Keys of staggerings [s0, s1) and their digit histograms for every pass.
 template <typename T>
-__device__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk, int s0,
+__device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk, int s0,
                           int s1)
 {
     extern __shared__ uint32_t lhist[];  // [s1 - s0][npass][R]
@@ -116,7 +116,7 @@ __device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t st
 
 // ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
 template <int RBITS>
-__device__ void radix_pass_body(const SortArgs& a, int s, int pass)
+__device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pass)
 {
     constexpr int R = 1 << RBITS;
     constexpr int NW = SORT_BLOCK / 64;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
 
 // ---- segments: run heads, q, seg_off and the cell-block start table -------------------
 template <typename T>
-__device__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
+__device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
 {
     // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
     const bool in_a = (a.g.npts == 0) || (a.npass & 1);
@@ -346,7 +346,8 @@ __device__ __forceinline__ int batch_job(const int32_t* starts, int njobs, int v
     return lo;
 }
 
-__global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* jobs, const BatchTable* bt)
+__global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_RESET];
     const int nj = bt->njobs, total = st[nj];
@@ -358,7 +359,8 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* jobs, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* jobs, const BatchTable* bt)
+__global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_KEYS];
     const int nj = bt->njobs, total = st[nj];
@@ -371,8 +373,9 @@ __global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* jobs, c
 
 // Radix pass p of every job with more than p passes.  Blocks take tiles by ticket inside
 // the body, so only the number of virtual blocks per job (its tile count) matters.
-__global__ __launch_bounds__(SORT_BLOCK) void batch_sort_kernel(const BatchJob* jobs,
-                                                                const BatchTable* bt, int pass)
+__global__ __launch_bounds__(SORT_BLOCK) void batch_sort_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt,
+                                                                int pass)
 {
     const int32_t* st = bt->starts[BS_SORT0 + pass];
     const int nj = bt->njobs, total = st[nj];
@@ -384,8 +387,8 @@ __global__ __launch_bounds__(SORT_BLOCK) void batch_sort_kernel(const BatchJob* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(SORT_BLOCK) void batch_segments_kernel(const BatchJob* jobs,
-                                                                    const BatchTable* bt)
+__global__ __launch_bounds__(SORT_BLOCK) void batch_segments_kernel(
+    const BatchJob* __restrict__ jobs, const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_SEG];
     const int nj = bt->njobs, total = st[nj];

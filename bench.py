@@ -87,6 +87,47 @@ def cpu_baseline(g, X, F, u, sample):
                       f"staggering, spread, interpolate), single thread, {dt:.1f} s"}
 
 
+def rbc_bench(torch, ibops, wl, K):
+    """Red-blood-cell surfaces: 64 um periodic box on a 256^3 MAC grid (h = 0.25 um), 1111
+    biconcave cells of 2562 vertices (2,846,382 points, FP32), smooth forces.  A step is plan
+    update + spread + interpolate (the points do not move); K steps between two events."""
+    dt = torch.float32
+    dev = torch.device("cuda:0")
+    g, X, F, u, placed = wl.config3(np.float32)
+    n = X.shape[0]
+    Xd, Fd, ud = (torch.from_numpy(a).to(dev) for a in (X, F, u))
+    p = ibops.Plan(g, n, dt, dev)
+    f = torch.empty(p.grid_shape, dtype=dt, device=dev)
+    U = torch.empty((n, 3), dtype=dt, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    for _ in range(3):
+        p.update(Xd)
+        p.spread(Fd, f)
+        p.interpolate(ud, U)
+    torch.cuda.synchronize()
+    for k in range(K):
+        e = ev[k]
+        e[0].record(stream)
+        p.update(Xd)
+        e[1].record(stream)
+        p.spread(Fd, f)
+        e[2].record(stream)
+        p.interpolate(ud, U)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0][0].elapsed_time(ev[K - 1][3]) / K
+    stage = {name: round(float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])), 5)
+             for i, name in enumerate(["plan", "spread", "interp"])}
+    b = 4
+    algo = algorithmic_bytes(n, 3, 3, 256 ** 3, b)
+    spread_gbs = algo["spread"] / (stage["spread"] / 1e3) / 1e9
+    return {"workload": "RBC surfaces, 256^3 MAC grid, 64 um box, 1111 cells x 2562 vertices "
+                        f"({placed} placed without overlap), FP32, step = plan + spread + interpolate",
+            "npts": n, "ms_per_step": round(ms, 5), "points_per_s": round(n / (ms / 1e3), 1),
+            "stage_ms": stage, "spread_hbm_frac": round(spread_gbs / HBM_PEAK_GBS, 4)}
+
+
 def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
                   rhos=(0.5, 0.8, 0.95, 1.2)):
     """The serving mix: independent FP32 jobs on {32,64,96,128}^3 MAC grids with
@@ -212,6 +253,8 @@ def main():
     ap.add_argument("--tune", choices=["auto", "none"], default="auto",
                     help="pick the plan tuning (spreading tile, tile sharing, radix digits) with "
                          "the autotuner on the initial positions, or use the built-in choices")
+    ap.add_argument("--no-rbc", action="store_true",
+                    help="skip the red-blood-cell workload (256^3, 2.8 million clustered points)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the batched-serving measurement (Poisson job stream)")
     ap.add_argument("--serving-only", action="store_true")
@@ -368,8 +411,11 @@ def main():
         "host_wall_s": round(t_host, 4),
         "roofline": roofline,
         "cpu_baseline": None,
+        "rbc_256": None,
         "serving": None,
     }
+    if not args.no_rbc:
+        out["rbc_256"] = rbc_bench(torch, ibops, wl, args.steps)
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:

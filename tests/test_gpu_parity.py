@@ -302,3 +302,25 @@ def test_config2_after_advection(ib, orc):
     Xk = to_host(Xd)
     check_plan(ib, orc, g, Xk, dtype, "config2 step 50")
     check_ops(ib, orc, g, Xk, F, u, dtype, "config2 step 50")
+
+
+def test_config3_rbc_full_size(ib, orc):
+    """Red-blood-cell surfaces on the 256^3 grid (2,846,382 clustered points, FP32): the
+    plan bit for bit and both operators against the oracle at full size."""
+    g, X, F, u, placed = wl.config3(np.float32)
+    say(f"RBC 256^3: {X.shape[0]} points, {placed} cells placed without overlap")
+    check_plan_stagger0(ib, orc, g, X, torch.float32, "RBC 256^3")
+    check_ops(ib, orc, g, X, F, u, torch.float32, "RBC 256^3")
+
+
+def check_plan_stagger0(ib, orc, g, X, dtype, label):
+    p = ib.Plan(g, X.shape[0], dtype)
+    p.update(to_dev(X, dtype))
+    assert p.status() == 0
+    got = p.export(0)
+    k_ref, bad = orc.keys(g, np.asarray(X, np.float64), g["stagger"][0], _prec(dtype))
+    assert bad == 0
+    sk_ref, perm_ref, seg_ref, q_ref = orc.plan(k_ref)
+    assert np.array_equal(to_host(got["keys"]), k_ref), label
+    assert np.array_equal(to_host(got["perm"]), perm_ref), label
+    assert got["q"] == q_ref and np.array_equal(to_host(got["seg_off"]), seg_ref), label

@@ -334,12 +334,17 @@ struct SpreadTile {
                 gbase = goff;
             }
             // The first P members of a group (sub-leaders) each sum every P-th member, then
-            // a tree over the sub-leaders folds their sums into the leader.  P grows with
-            // the largest group of the wave, so a crowded cell costs O(k / P + log P)
-            // rounds instead of O(k); a tree step moves all 4^d sums between lanes and costs
-            // about five member rounds, which sets the thresholds.  P is uniform across the
-            // wave and depends only on the data, so the order of every sum is fixed.
-            const int P = maxk > 40 ? 8 : maxk > 20 ? 4 : maxk > 10 ? 2 : 1;
+            // add their sums into the tile in P rounds, one rank per round, so the active
+            // lanes of each round still hold distinct cells.  P ~ sqrt(largest group * m / a)
+            // balances the member rounds (cost m each) against the add rounds (cost a each,
+            // measured ~1.3 m in FP64 and ~2 m in FP32, where member rounds move half the
+            // bytes); it is uniform across the wave and depends only on the data, so the
+            // order in which every tile value receives its contributions is fixed.
+            constexpr int K1 = sizeof(T) == 8 ? 3 : 4, K2 = sizeof(T) == 8 ? 8 : 10;
+            constexpr int K3 = sizeof(T) == 8 ? 15 : 20, K4 = sizeof(T) == 8 ? 24 : 32;
+            constexpr int K5 = sizeof(T) == 8 ? 35 : 46, K6 = sizeof(T) == 8 ? 48 : 62;
+            const int P = maxk <= K1 ? 1 : maxk <= K2 ? 2 : maxk <= K3 ? 3 : maxk <= K4 ? 4
+                        : maxk <= K5 ? 5 : maxk <= K6 ? 6 : 7;
             const bool sub = has && rank < P;
             T acc[NZ][4][4];
 #pragma unroll
@@ -371,22 +376,13 @@ struct SpreadTile {
                 for (int i = 0; i < 4; ++i) wk[DIM - 1][i] *= on;
                 accumulate(acc, wk);
             }
-            for (int st = 1; st < P; st <<= 1) {
-                const int pr = rank + st;
-                const bool ok = sub && (rank & (2 * st - 1)) == 0 && pr < gk && pr < P;
-                const int src = ok ? ltab[(gbase + pr) & 63] : lane;
-#pragma unroll
-                for (int iz = 0; iz < NZ; ++iz)
-#pragma unroll
-                    for (int iy = 0; iy < 4; ++iy)
-#pragma unroll
-                        for (int ix = 0; ix < 4; ++ix) {
-                            const T v = __shfl(acc[iz][iy][ix], src, 64);
-                            acc[iz][iy][ix] += ok ? v : T(0);
-                        }
-            }
             wave_sync();
-            add_to_tile(acc, leader, cx, cy, cz, ey, ez, tile);
+            if (P == 1) {
+                add_to_tile(acc, sub, cx, cy, cz, ey, ez, tile);
+            } else {
+                for (int rr = 0; rr < P; ++rr)
+                    add_to_tile(acc, sub && rank == rr, cx, cy, cz, ey, ez, tile);
+            }
             wave_sync();
         }
     }

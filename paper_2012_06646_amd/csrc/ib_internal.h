@@ -10,7 +10,10 @@ namespace ibk {
 
 // Sort configuration: 256-thread blocks, SORT_IPT keys per thread.
 constexpr int SORT_BLOCK = 256;
-constexpr int SORT_IPT = 8;
+#ifndef IBK_SORT_IPT
+#define IBK_SORT_IPT 8
+#endif
+constexpr int SORT_IPT = IBK_SORT_IPT;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
 constexpr int MAX_RADIX_BITS = 8;
 

@@ -499,6 +499,8 @@ template <typename T>
 __device__ __forceinline__ void gather_rows_body(int64_t n, int ncols, const int32_t* __restrict__ perm,
                                  const T* __restrict__ src, T* __restrict__ dst, int bid, int nblk)
 {
+    // One element per thread and step: the threads of a row read its contiguous values, and
+    // the writes are fully coalesced.
     const int64_t total = n * ncols;
     for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
         const int64_t i = e / ncols;

@@ -232,6 +232,40 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int 
 }
 
 // ---- segments: run heads, q, seg_off and the cell-block start table -------------------
+// Rows base + t + k * SORT_BLOCK (k < SORT_IPT) of a tile: dst[i] = src[perm[i]] for rows
+// of D values, all permutation entries first, then all rows.
+template <typename T, int D>
+__device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ perm,
+                                                 const T* __restrict__ src, T* __restrict__ dst,
+                                                 int64_t base, int64_t n)
+{
+    // Rows past n are neither read nor written (with n == 0, src may be null).
+    int64_t p[SORT_IPT];
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
+        const int32_t v = i < n ? perm[i] : 0;
+        p[k] = (uint32_t)v < (uint64_t)n ? v : 0;
+    }
+    T row[SORT_IPT][D];
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
+        if (i < n) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) row[k][d] = src[p[k] * D + d];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
+        if (i < n) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) dst[i * D + d] = row[k][d];
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
 {
@@ -308,18 +342,12 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
         const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
         if (head[k]) seg[off + rank[k]] = (int32_t)i;
     }
-    // Positions in this sorted order (staggering 0 only): coalesced writes, one gather.
+    // Positions in this sorted order (staggering 0 only): one row per sorted position, the
+    // tile's SORT_IPT rows of a thread loaded together so their random reads overlap.
     if (Xs != nullptr) {
         const int32_t* perm = perm_all + (int64_t)s * n;
-        const int dim = g.dim;
-        for (int e = tid; e < SORT_TILE * dim; e += SORT_BLOCK) {
-            const int64_t i = base + e / dim;
-            if (i < n) {
-                const int k = e - (e / dim) * dim;
-                const int64_t p = (uint32_t)perm[i] < (uint64_t)n ? perm[i] : 0;
-                Xs[i * dim + k] = X[p * dim + k];
-            }
-        }
+        if (g.dim == 3) gather_tile_rows<T, 3>(perm, X, Xs, base, n);
+        else gather_tile_rows<T, 2>(perm, X, Xs, base, n);
     }
 }
 

@@ -144,6 +144,16 @@ int32_t ib_spread(ib_plan plan, const void *F, void *f, int32_t accumulate, void
  * device; U (npts x ncomp) device, overwritten. */
 int32_t ib_interpolate(ib_plan plan, const void *u, void *U, void *stream);
 
+/* Interpolation followed by the position update of the IB step, in one pass:
+ * U = J(X) u as ib_interpolate, then X <- X + dt U with each coordinate wrapped into
+ * [0, length_k) exactly as ib_advect does (bitwise the same results as the two calls).
+ * Needs ncomp == dim.  X (npts x dim, device) is the array of the last update (or any
+ * array with the same values): it is overwritten in place, after which the plan still
+ * serves spreading and interpolation at the update's positions, but ib_plan_export can no
+ * longer key a staggering it had not sorted yet (IB_ERR_ARG). */
+int32_t ib_interpolate_advect(ib_plan plan, const void *u, void *U, void *X, double dt,
+                              void *stream);
+
 /* Position gradient of interpolation, for differentiating through J(X):
  * dX_{j,k} (+)= sum_c W_{j,c} dU_{j,c}/dX_{j,k}, U = J(X) u as in ib_interpolate, where
  * dW/dX_k = (1/h_k) phi'-term: the derivative of the tensor-product weight along axis k.

@@ -254,6 +254,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     p->X = nullptr;
     p->last_stream = nullptr;
     p->updated = 0;
+    p->x_moved = 0;
     p->sorted_mask = 0;
 }
 
@@ -326,6 +327,7 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     p->X = X;
     p->last_stream = st;
     p->updated = 1;
+    p->x_moved = 0;
     p->sorted_mask = 1u;
     return IB_OK;
 }
@@ -336,6 +338,7 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
     if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (!(p->sorted_mask & (1u << sid))) {
+        if (p->x_moved) return IB_ERR_ARG;  // X was advanced in place since the update
         hipError_t e0 = launch_keys(p->sa, p->dtype, p->X, sid, st);
         if (e0 == hipSuccess) e0 = launch_sort_stagger(p->sa, sid, p->dtype, nullptr, false, st);
         int32_t r = hip_status(e0);
@@ -414,6 +417,26 @@ int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
     a.U = U;
     hipStream_t st = (hipStream_t)stream;
     p->last_stream = st;
+    return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
+}
+
+int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double dt, void* stream)
+{
+    if (!p || !u || !p->updated) return IB_ERR_ARG;
+    if ((!U || !X) && p->npts > 0) return IB_ERR_ARG;
+    if (p->grid.ncomp != p->grid.dim || !std::isfinite(dt)) return IB_ERR_ARG;
+    if (p->npts == 0) return IB_OK;
+    OpArgs a;
+    fill_op_args(p, &a);
+    a.u = u;
+    a.U = U;
+    a.Xadv = X;
+    a.adv_dt = dt;
+    for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
+    hipStream_t st = (hipStream_t)stream;
+    p->last_stream = st;
+    // Positions of staggerings not yet sorted can no longer be derived from this update.
+    if (X == p->X) p->x_moved = 1;
     return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
 }
 

@@ -18,6 +18,7 @@ struct ib_plan_s {
     const void* X;         // positions of the last update
     hipStream_t last_stream;
     int updated;
+    int x_moved;           // X advanced in place (ib_interpolate_advect) since the update
     uint32_t sorted_mask;  // staggerings sorted since the last update
 };
 

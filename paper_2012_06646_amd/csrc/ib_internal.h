@@ -114,6 +114,9 @@ struct OpArgs {
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
     double* partial;             // split spreading: partial tile sums
     uint32_t* tile_count;        // split spreading: arrivals per tile
+    void* Xadv;                  // interpolation: also advance these positions (or null)
+    double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len
+    double adv_len[3];
 };
 
 // ---- batches: many independent jobs, one launch per stage ------------------------------

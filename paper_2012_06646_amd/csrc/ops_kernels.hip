@@ -40,6 +40,16 @@ __device__ __forceinline__ int64_t clamp_index(int32_t p, int64_t n)
     return (uint32_t)p < (uint64_t)n ? (int64_t)p : 0;
 }
 
+// Position update of the IB step for one coordinate: x + dt u wrapped into [0, L).
+template <typename T>
+__device__ __forceinline__ T advect_coord(T x, T u, T dt, T L)
+{
+    T y = fma(dt, u, x);
+    y -= L * floor(y / L);
+    if (y >= L || y < T(0)) y = T(0);
+    return y;
+}
+
 // Weights of a point at coordinates x for component c, and the offset of its component-c
 // cell from its staggering-0 cell per dimension.  The cells follow the key rule exactly
 // (t = x * inv_h rounded once, minus the staggering, floored).
@@ -587,17 +597,22 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
         const int64_t p = clamp_index(a.perm[j], n);
+        T res[3] = {T(0), T(0), T(0)};
         if (sizeof(T) == 4 && unrolled) {
-            T res[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) U[p * DIM + c] = res[c];
         } else {
-            T res[3] = {T(0), T(0), T(0)};
 #pragma unroll 1
             for (int c = 0; c < ncomp; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
             for (int c = 0; c < ncomp; ++c) U[p * ncomp + c] = res[c];
+        }
+        if (a.Xadv) {  // fused position update (ncomp == DIM): the same arithmetic as advect
+            T* __restrict__ Xa = (T*)a.Xadv;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+                Xa[p * DIM + k] = advect_coord(x[k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
         }
     }
 }
@@ -736,10 +751,7 @@ __global__ __launch_bounds__(256) void advect_kernel(int dim, int ncomp, int64_t
         const int64_t j = i / dim;
         const int k = (int)(i - j * dim);
         const T L = k == 0 ? L0 : (k == 1 ? L1 : L2);
-        T y = fma(dt, U[j * ncomp + k], X[i]);
-        y -= L * floor(y / L);
-        if (y >= L || y < T(0)) y = T(0);
-        X[i] = y;
+        X[i] = advect_coord(X[i], U[j * ncomp + k], dt, L);
     }
 }
 

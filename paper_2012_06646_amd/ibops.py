@@ -74,6 +74,8 @@ _lib.ib_spread.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.ib_interpolate.restype = _i32
 _lib.ib_interpolate.argtypes = [_vp, _vp, _vp, _vp]
 
+_lib.ib_interpolate_advect.restype = _i32
+_lib.ib_interpolate_advect.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]
 _lib.ib_interpolate_grad.restype = _i32
 _lib.ib_interpolate_grad.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp]
 class JobDesc(ctypes.Structure):
@@ -117,7 +119,7 @@ _lib.ib_server_destroy.argtypes = [_vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
 
-EXPORTED = ["ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
+EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
             "ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
@@ -268,6 +270,18 @@ class Plan:
         _check(_lib.ib_spread(self._h, _ptr(F), _ptr(f), int(bool(accumulate)), _stream(stream)),
                "ib_spread")
         return f
+
+    def interpolate_advect(self, u, X, dt, U=None, stream=None):
+        """U = J(X) u, then X <- wrap(X + dt U) in place (one pass; same results as
+        interpolate followed by advect)."""
+        u = self._grid(u, "u")
+        if X.dtype != self.dtype or not X.is_contiguous() or tuple(X.shape) != (self.npts, self.dim):
+            raise ValueError(f"X must be a contiguous ({self.npts}, {self.dim}) {self.dtype} tensor")
+        if U is None:
+            U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
+        _check(_lib.ib_interpolate_advect(self._h, _ptr(u), _ptr(U), _ptr(X), float(dt), _stream(stream)),
+               "ib_interpolate_advect")
+        return U
 
     def interpolate(self, u, U=None, stream=None):
         u = self._grid(u, "u")

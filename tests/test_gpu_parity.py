@@ -324,3 +324,27 @@ def check_plan_stagger0(ib, orc, g, X, dtype, label):
     assert np.array_equal(to_host(got["keys"]), k_ref), label
     assert np.array_equal(to_host(got["perm"]), perm_ref), label
     assert got["q"] == q_ref and np.array_equal(to_host(got["seg_off"]), seg_ref), label
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_interpolate_advect_equals_two_calls(ib, dtype):
+    """The fused interpolation + position update gives bitwise the results of
+    ib_interpolate followed by ib_advect, including the periodic wrap."""
+    g = wl.grid(3, [40, 36, 44], 1.0)
+    X, F, u = wl.uniform_case(g, 70000, 61)
+    X[:50] = 1.0 - 1e-9   # right at the box edge: the wrap is exercised
+    ud = to_dev(u, dtype)
+    dt = 3.0 / 40
+    X1, X2 = to_dev(X, dtype), to_dev(X, dtype)
+    p1 = ib.Plan(g, X.shape[0], dtype).update(X1)
+    U1 = p1.interpolate(ud)
+    ib.advect(g, X1, U1, dt)
+    p2 = ib.Plan(g, X.shape[0], dtype).update(X2)
+    U2 = p2.interpolate_advect(ud, X2, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2) and torch.equal(X1, X2)
+    assert bool(((X2 >= 0) & (X2 < 1.0)).all())
+    # the update's sorted staggering is still there; unsorted ones can no longer be keyed
+    assert p2.export(0)["q"] > 0
+    with pytest.raises(ib.IBError):
+        p2.export(1)

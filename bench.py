@@ -71,6 +71,17 @@ def measured_traffic(op, dtype):
     return None
 
 
+def device_facts(torch):
+    """What the runtime reports about the device (not assumed)."""
+    p = torch.cuda.get_device_properties(0)
+    facts = {"name": p.name, "compute_units": p.multi_processor_count,
+             "memory_GiB": round(p.total_memory / 2 ** 30, 1)}
+    for attr in ("gcnArchName", "L2_cache_size", "warp_size", "max_threads_per_multi_processor"):
+        if hasattr(p, attr):
+            facts[attr] = getattr(p, attr)
+    return facts
+
+
 def cpu_baseline(g, X, F, u, sample):
     """The CPU oracle as it stands (single thread) on the first `sample` points of the same
     workload: keys + stable sort for each staggering, spreading, interpolation."""
@@ -356,6 +367,27 @@ def main():
     stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
                 for i, name in enumerate(["plan", "spread", "interp_advect"])}
 
+    per_step = np.array([ev[k][0].elapsed_time(ev[k][3]) for k in range(K)])
+    step_pct = {f"p{q}": round(float(np.percentile(per_step, q)), 5) for q in (10, 50, 90)}
+
+    # Cold caches: the same steps with 1 GiB streamed through the memory system between them
+    # (outside the timed events), so no step finds its data in L2 or the MALL.
+    restart()
+    flush_src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    flush_dst = torch.empty_like(flush_src)
+    cold = []
+    for k in range(K):
+        flush_dst.copy_(flush_src)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        step()
+        c1.record(stream)
+        cold.append((c0, c1))
+    torch.cuda.synchronize()
+    cold_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in cold]))  # same K steps
+    del flush_src, flush_dst
+
     graph_ms = None
     if args.graph:
         gr = torch.cuda.CUDAGraph()
@@ -394,6 +426,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "ms_per_step_graph": graph_ms,
+        "step_ms_percentiles": step_pct,
+        "cold_cache_ms_per_step": round(cold_ms, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -405,6 +439,7 @@ def main():
                    "grid": [128, 128, 128], "npts": npts, "seed": 1002},
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "tuning": tune_info,
+        "device": device_facts(torch),
         "step_algorithmic_bytes": sum(algo.values()),
         "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "host_wall_s": round(t_host, 4),

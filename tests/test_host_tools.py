@@ -1,0 +1,48 @@
+"""Host-side helpers of the measurement and tuning code (no device): the tuning cache, the
+algorithmic byte counts, and how the benchmark reads committed traffic counts."""
+import importlib
+import json
+import os
+import sys
+
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_tune_cache_roundtrip(tmp_path, monkeypatch):
+    from paper_2012_06646_amd import tune, workloads as wl
+    monkeypatch.setenv("IB_TUNE_CACHE", str(tmp_path / "sub" / "t.json"))
+    g = wl.grid(3, 64, 1.0)
+    assert tune.cached(g, torch.float32, 100000) is None
+    k = tune.key(g, torch.float32, 100000)
+    assert k == tune.key(g, torch.float32, 120000)          # same power-of-two bucket
+    assert k != tune.key(g, torch.float64, 100000)
+    assert k != tune.key(wl.grid(3, 32, 1.0), torch.float32, 100000)
+    tune._store(k, {"tuning": {"spread_tile": 2, "split_points": 0, "radix_bits": 8}, "ms": 1.0})
+    assert tune.cached(g, torch.float32, 100000) == {"spread_tile": 2, "split_points": 0, "radix_bits": 8}
+    data = json.load(open(tmp_path / "sub" / "t.json"))
+    assert list(data) == [k]
+
+
+def test_algorithmic_bytes_of_the_benchmark_workload():
+    bench = importlib.import_module("bench")
+    a = bench.algorithmic_bytes(10 ** 6, 3, 3, 128 ** 3, 8)
+    # plan: X + sorted keys and permutation; spread: plan + X + F + f; interp: perm + X + u + U
+    assert a["plan"] == 24_000_000 + 24_000_000
+    assert a["spread"] == 24_000_000 + 24_000_000 + 24_000_000 + 3 * 8 * 128 ** 3
+    assert a["interp"] == 12_000_000 + 24_000_000 + 3 * 8 * 128 ** 3 + 24_000_000
+
+
+def test_traffic_is_read_only_for_matching_kernel_sources(tmp_path, monkeypatch):
+    bench = importlib.import_module("bench")
+    f = tmp_path / "traffic.md"
+    f.write_text(f"kernel sources sha256: {bench.kernel_source_hash()}\n"
+                 "traffic f64 spread: 123456 bytes\ntraffic f32 interp: 789 bytes\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("spread", "f64") == 123456
+    assert bench.measured_traffic("interp", "f32") == 789
+    assert bench.measured_traffic("interp", "f64") is None
+    f.write_text("kernel sources sha256: 0000000000000000\ntraffic f64 spread: 123456 bytes\n")
+    assert bench.measured_traffic("spread", "f64") is None

@@ -105,7 +105,7 @@ def rbc_bench(torch, ibops, wl, K):
     update + spread + interpolate (the points do not move); K steps between two events."""
     dt = torch.float32
     dev = torch.device("cuda:0")
-    g, X, F, u, placed = wl.config3(np.float32)
+    g, X, F, u, placed = wl.rbc256(np.float32)
     n = X.shape[0]
     Xd, Fd, ud = (torch.from_numpy(a).to(dev) for a in (X, F, u))
     p = ibops.Plan(g, n, dt, dev)
@@ -306,7 +306,7 @@ def main():
 
     dtype = torch.float64 if args.dtype == "f64" else torch.float32
     b = 8 if args.dtype == "f64" else 4
-    g, X0, F, u = wl.config2(np.float64, args.npts)
+    g, X0, F, u = wl.cube128_1m(np.float64, args.npts)
     npts, dim, ncomp = X0.shape[0], 3, 3
     G = 128 ** 3
     h = 1.0 / 128

@@ -52,7 +52,7 @@ def uniform_case(g, npts, seed, dtype=np.float64):
 
 # ---- the named workloads ----------------------------------------------------------
 
-def config1():
+def square32_1k():
     """2-D periodic unit square, 32 x 32 collocated (cell-centred) grid with two components,
     1000 uniform points, FP64; seed 1001."""
     g = grid(2, 32, 1.0, stagger=[[0.5, 0.5], [0.5, 0.5]])
@@ -60,7 +60,7 @@ def config1():
     return g, X, F, u
 
 
-def config2(dtype=np.float64, npts=1_000_000):
+def cube128_1m(dtype=np.float64, npts=1_000_000):
     """3-D periodic unit cube, 128^3 MAC grid, 10^6 uniform points; seed 1002."""
     g = grid(3, 128, 1.0)
     X, F, u = uniform_case(g, npts, 1002, dtype)
@@ -248,14 +248,14 @@ def rbc_case(box, n, count, seeds, dtype, max_trials):
     return g, z["X"].astype(dtype), z["F"].astype(dtype), z["u"].astype(dtype), int(z["placed"])
 
 
-def config3(dtype=np.float32):
+def rbc256(dtype=np.float32):
     """256^3 MAC grid in a 64 um periodic box (h = 0.25 um), 1111 RBCs of 2562 vertices
     (40% volume fraction), seeds 3001-3004.  Random sequential addition jams below 40%; the
     cells that do not fit without overlap are placed at random (count returned)."""
     return rbc_case(64.0, 256, 1111, (3001, 3002, 3003, 3004), dtype, 40000)
 
 
-def config5(dtype=np.float64):
+def rbc128(dtype=np.float64):
     """128^3 MAC grid in a 32 um periodic box (h = 0.25 um), 78 RBCs (about 2 x 10^5 points),
     seeds 5001-5004; the loss's grid field g is drawn with seed 5005."""
     g, X, F, u, placed = rbc_case(32.0, 128, 78, (5001, 5002, 5003, 5004), dtype, 200000)

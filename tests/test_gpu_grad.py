@@ -93,13 +93,13 @@ def test_position_gradient_matches_central_differences(mods):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_config5_gradients(mods, orc, dtype):
+def test_rbc128_gradients(mods, orc, dtype):
     """128^3 MAC grid, 78 RBCs (about 2 x 10^5 surface points), loss of the
     differentiation workload; GPU gradients against the oracle's."""
     ib, ag = mods
     nd = np.float32 if dtype == torch.float32 else np.float64
-    g, X, F, u, gfield, _ = wl.config5(nd)
-    say(f"grad config5 {dtype} n={X.shape[0]}")
+    g, X, F, u, gfield, _ = wl.rbc128(nd)
+    say(f"grad rbc128 {dtype} n={X.shape[0]}")
     dX, dF, du = gpu_loss_grads(ag, g, X, F, u, gfield, dtype)
     rX, rF, ru = oracle_loss_grads(orc, g, X, F, u, gfield)
     tol = TOL[dtype]

@@ -71,9 +71,9 @@ def check_ops(ib, orc, g, X, F, u, dtype, label, tier=1):
 
 # ---- plans ----------------------------------------------------------------------------
 
-def test_plan_config1(ib, orc):
-    g, X, F, u = wl.config1()
-    check_plan(ib, orc, g, X, torch.float64, "config1")
+def test_plan_square32_1k(ib, orc):
+    g, X, F, u = wl.square32_1k()
+    check_plan(ib, orc, g, X, torch.float64, "32^2 collocated, 1000 points")
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -112,9 +112,9 @@ def test_plan_2d_and_collocated(ib, orc):
 
 # ---- operators -------------------------------------------------------------------------
 
-def test_ops_config1(ib, orc):
-    g, X, F, u = wl.config1()
-    check_ops(ib, orc, g, X, F, u, torch.float64, "config1", tier=0)
+def test_ops_square32_1k(ib, orc):
+    g, X, F, u = wl.square32_1k()
+    check_ops(ib, orc, g, X, F, u, torch.float64, "32^2 collocated, 1000 points", tier=0)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -278,18 +278,18 @@ def test_bitwise_run_to_run(ib, dtype):
 # ---- the 128^3 / 10^6-point workload at full size ----------------------------------------
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_config2_full_size(ib, orc, dtype):
-    g, X, F, u = wl.config2()
+def test_cube128_1m_full_size(ib, orc, dtype):
+    g, X, F, u = wl.cube128_1m()
     nd = _np_dtype(dtype)
     Xc = X.astype(nd)
-    check_plan(ib, orc, g, Xc, dtype, "config2")
-    check_ops(ib, orc, g, X, F, u, dtype, "config2")
+    check_plan(ib, orc, g, Xc, dtype, "cube128_1m")
+    check_ops(ib, orc, g, X, F, u, dtype, "cube128_1m")
 
 
-def test_config2_after_advection(ib, orc):
+def test_cube128_1m_after_advection(ib, orc):
     """The 128^3 / 10^6 workload after 50 steps of its own advection (points have gathered
     into crowded cells): plan and operators against the oracle on the GPU's positions."""
-    g, X, F, u = wl.config2()
+    g, X, F, u = wl.cube128_1m()
     dtype = torch.float64
     h = 1.0 / 128
     Xd, Fd, ud = to_dev(X, dtype), to_dev(F, dtype), to_dev(u, dtype)
@@ -300,14 +300,14 @@ def test_config2_after_advection(ib, orc):
         ib.advect(g, Xd, U, 0.1 * h)
     assert p.status() == 0
     Xk = to_host(Xd)
-    check_plan(ib, orc, g, Xk, dtype, "config2 step 50")
-    check_ops(ib, orc, g, Xk, F, u, dtype, "config2 step 50")
+    check_plan(ib, orc, g, Xk, dtype, "cube128_1m step 50")
+    check_ops(ib, orc, g, Xk, F, u, dtype, "cube128_1m step 50")
 
 
-def test_config3_rbc_full_size(ib, orc):
+def test_rbc256_full_size(ib, orc):
     """Red-blood-cell surfaces on the 256^3 grid (2,846,382 clustered points, FP32): the
     plan bit for bit and both operators against the oracle at full size."""
-    g, X, F, u, placed = wl.config3(np.float32)
+    g, X, F, u, placed = wl.rbc256(np.float32)
     say(f"RBC 256^3: {X.shape[0]} points, {placed} cells placed without overlap")
     check_plan_stagger0(ib, orc, g, X, torch.float32, "RBC 256^3")
     check_ops(ib, orc, g, X, F, u, torch.float32, "RBC 256^3")

@@ -24,20 +24,57 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
-__device__ __forceinline__ int wave_max_i32(int v)
+// ---- cross-lane steps on DPP lane moves ------------------------------------------------
+// A wave64 is four rows of 16 lanes.  DPP (data-parallel primitives) moves a VGPR between
+// lanes inside the VALU instruction, with no LDS round trip.  Encodings (GFX9 DPP_CTRL):
+// row_shr:n = 0x110 + n (lane l reads l - n within its row), wave_shr:1 = 0x138 (lane l
+// reads l - 1 across the wave), row_bcast:15 = 0x142 (lane 15 of a row to every lane of the
+// next row) and row_bcast:31 = 0x143 (lane 31 to rows 2 and 3).  ROWS masks the rows that
+// are written; lanes that are not written, or whose source lane does not exist, get 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// v of lane l - 1 (0 in lane 0).
+__device__ __forceinline__ uint32_t wave_shr1_u32(uint32_t v) { return dpp_move<0x138>(v); }
+
+// Inclusive prefix sum over the lanes of a wave (a Hillis-Steele scan within rows, then
+// the row totals carried across rows).
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    v += dpp_move<0x111>(v);
+    v += dpp_move<0x112>(v);
+    v += dpp_move<0x114>(v);
+    v += dpp_move<0x118>(v);
+    v += dpp_move<0x142, 0xa>(v);
+    v += dpp_move<0x143, 0xc>(v);
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v)
+// Inclusive prefix maximum of non-negative values over the lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v)
 {
-    const int lane = lane_id();
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, (unsigned)o, 64);
-        if (lane >= o) v += t;
-    }
+    v = max(v, dpp_move<0x111>(v));
+    v = max(v, dpp_move<0x112>(v));
+    v = max(v, dpp_move<0x114>(v));
+    v = max(v, dpp_move<0x118>(v));
+    v = max(v, dpp_move<0x142, 0xa>(v));
+    v = max(v, dpp_move<0x143, 0xc>(v));
     return v;
+}
+
+// Value of lane 63, uniform across the wave.
+__device__ __forceinline__ uint32_t wave_last_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Maximum of non-negative values over the wave, uniform across the wave.
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+    return (int)wave_last_u32(wave_incl_max_u32((uint32_t)v));
 }
 
 // Exclusive scan of one value per thread over a block of NT threads (NT a multiple of

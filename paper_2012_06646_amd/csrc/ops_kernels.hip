@@ -62,8 +62,12 @@ __device__ __forceinline__ void comp_weights(const GeomArgs& g, int c, const T x
         const T ih = Prec<T>::inv_h(g, k);
         const T yc = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
         const T fc = floor(yc);
-        const T y0 = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
-        delta[k] = min(max((int)(fc - floor(y0)), g.dlo[c][k]), g.dhi[c][k]);
+        if (g.dlo[c][k] == g.dhi[c][k]) {
+            delta[k] = g.dlo[c][k];  // the same staggering as staggering 0 along this axis
+        } else {
+            const T y0 = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
+            delta[k] = min(max((int)(fc - floor(y0)), g.dlo[c][k]), g.dhi[c][k]);
+        }
         T r = yc - fc;
         r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
         weights4<T, KERN>(r, w[k]);
@@ -89,6 +93,7 @@ template <int MAXR>
 struct SliceTable {
     int32_t lo[MAXR];
     int32_t hi[MAXR];
+    int32_t base[MAXR];   // sorted index of slice position v in range r: base[r] + v
     int32_t xo[MAXR];     // source-frame x of a key: key + xo
     int32_t uy[MAXR];     // source-frame y of the row
     int32_t pref[MAXR + 1];
@@ -102,12 +107,20 @@ struct SpreadTile {
     static constexpr int NZ = (DIM == 3) ? 4 : 1;            // stencil extent in z
     static constexpr int MAXROWS = (DIM == 3) ? TY + 5 : 1;   // x-rows per slice
     static constexpr int MAXR = 3 * MAXROWS;
+    static_assert(MAXR <= 64, "one lane per range of a slice");
     using Table = SliceTable<MAXR>;
 
+    // Per-wave LDS scratch of the chunk loop.
+    struct WaveScratch {
+        int32_t ltab[64];  // lanes of each group in rank order (cells matched by code)
+        int32_t mark[64];  // range starts inside a chunk
+    };
+
     // Range table of source slice q (frame origin ox, oy, oz; lenx cells per row, nrows
-    // rows); returns the slice's point count.
+    // rows); returns the slice's point count.  Afterwards lane r < 3 * nrows holds range r's
+    // first slice position (*rp) and whether the range is non-empty (*rn).
     __device__ static int build(const GeomArgs& g, const int32_t* __restrict__ cb, int q, int ox,
-                                int oy, int oz, int lenx, int nrows, Table& tb)
+                                int oy, int oz, int lenx, int nrows, Table& tb, int* rp, bool* rn)
     {
         const int lane = lane_id();
         const int n0 = g.n[0];
@@ -149,13 +162,36 @@ struct SpreadTile {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 tb.pref[lane * 3 + k] = run;
+                tb.base[lane * 3 + k] = tb.lo[lane * 3 + k] - run;
                 run += tb.hi[lane * 3 + k] - tb.lo[lane * 3 + k];
             }
         }
-        const int total_pts = __shfl((int)incl, 63, 64);
+        const int total_pts = (int)wave_last_u32(incl);
         if (lane == 0) tb.pref[nrows * 3] = total_pts;
         wave_sync();
+        const int nranges = 3 * nrows;
+        *rp = lane < nranges ? tb.pref[lane] : total_pts;
+        *rn = lane < nranges && tb.hi[lane] > tb.lo[lane];
+        wave_sync();
         return total_pts;
+    }
+
+    // Range of slice position v0 + lane, for v0 < total.  The range holding v0 is the last
+    // one whose first position is <= v0 (it is non-empty); the non-empty ranges starting
+    // inside the chunk are marked at their offsets, and a prefix maximum over the lanes
+    // carries each mark up to the next one.  Called by the whole wave.
+    __device__ static int locate(int32_t* mark, int rp, bool rn, int nranges, int v0)
+    {
+        const int lane = lane_id();
+        const int carry = (int)__popcll(__ballot(lane < nranges && rp <= v0)) - 1;
+        mark[lane] = 0;
+        wave_sync();
+        const int s = rp - v0;
+        if (rn && s > 0 && s < 64) mark[s] = lane + 1;  // distinct offsets: non-empty ranges
+        wave_sync();
+        const int m = (int)wave_incl_max_u32((uint32_t)mark[lane]);
+        wave_sync();
+        return max(m - 1, carry);
     }
 
     __device__ static void accumulate(T acc[NZ][4][4], const T w[DIM][4])
@@ -167,6 +203,19 @@ struct SpreadTile {
                 const T cyz = (DIM == 3) ? w[1][iy] * w[2][iz] : w[1][iy];
 #pragma unroll
                 for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = fma(w[0][ix], cyz, acc[iz][iy][ix]);
+            }
+    }
+
+    // acc = the 4^d weight products of one point (a first term needs no addition).
+    __device__ static void products(T acc[NZ][4][4], const T w[DIM][4])
+    {
+#pragma unroll
+        for (int iz = 0; iz < NZ; ++iz)
+#pragma unroll
+            for (int iy = 0; iy < 4; ++iy) {
+                const T cyz = (DIM == 3) ? w[1][iy] * w[2][iz] : w[1][iy];
+#pragma unroll
+                for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = w[0][ix] * cyz;
             }
     }
 
@@ -229,26 +278,21 @@ struct SpreadTile {
             }
     }
 
-    // Sorted position v of the slice: its range, key, coordinates and force (zeros past
-    // the end).
+    // Slice positions v0 + lane: range, key, coordinates and force (zeros past the end).
+    // The sorted index is kept inside [0, n) whatever the tables hold.  Called by the whole
+    // wave.
     __device__ static void load(const OpArgs& a, int c, const int32_t* __restrict__ sk,
-                                const Table& tb, int nranges, int total, int v, int& rr,
-                                int32_t& key, T x[DIM], T& F)
+                                const Table& tb, int32_t* mark, int rp, bool rn, int nranges,
+                                int total, int v0, int& rr, int32_t& key, T x[DIM], T& F)
     {
-        rr = 0;
+        rr = locate(mark, rp, rn, nranges, v0);
         key = 0;
         F = T(0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = T(0);
+        const int v = v0 + lane_id();
         if (v < total) {
-            int lo = 0, hi = nranges;  // last range whose prefix is <= v (it is non-empty)
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (tb.pref[mid] <= v) lo = mid;
-                else hi = mid;
-            }
-            rr = lo;
-            const int64_t j = (int64_t)tb.lo[rr] + (v - tb.pref[rr]);
+            const int64_t j = clamp_index(tb.base[rr] + v, a.g.npts);
             const T* __restrict__ Xs = (const T*)a.Xs;
             key = sk[j];
 #pragma unroll
@@ -260,12 +304,12 @@ struct SpreadTile {
     // Reduce the slice in chunks of 64 points and add the sums into the tile.
     // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
     // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
-    // group; its lowest lane (the leader) sums the group's contributions to all 4^d shifts
-    // in registers, pulling each member's offsets and force from the member's lane.
+    // group; its lowest lanes (sub-leaders) sum the group's contributions to all 4^d shifts
+    // in registers, pulling the other members' weights from their lanes.
     __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
-                                  const Table& tb, int nranges, int total, int q, const int off[3],
-                                  int ex, int ey, int ez, bool same0, double* tile,
-                                  int32_t* ltab, int k0, int kstride)
+                                  const Table& tb, int rp, bool rn, int nranges, int total, int q,
+                                  const int off[3], int ex, int ey, int ez, bool same0,
+                                  double* tile, WaveScratch& ws, int k0, int kstride)
     {
         const GeomArgs& g = a.g;
         const int lane = lane_id();
@@ -277,7 +321,8 @@ struct SpreadTile {
         // This block's chunks of the slice: k0, k0 + kstride, ... (all of them unless the
         // tile is split over several blocks).
         const int step = 64 * kstride;
-        load(a, c, sk, tb, nranges, total, 64 * k0 + lane, nrr, nkey, nx, nF);
+        if (64 * k0 < total)
+            load(a, c, sk, tb, ws.mark, rp, rn, nranges, total, 64 * k0, nrr, nkey, nx, nF);
         for (int v0 = 64 * k0; v0 < total; v0 += step) {
             const int v = v0 + lane;
             const bool valid = v < total;
@@ -287,7 +332,8 @@ struct SpreadTile {
 #pragma unroll
             for (int k = 0; k < DIM; ++k) x[k] = nx[k];
             const T Fc = nF;
-            if (v0 + step < total) load(a, c, sk, tb, nranges, total, v + step, nrr, nkey, nx, nF);
+            if (v0 + step < total)
+                load(a, c, sk, tb, ws.mark, rp, rn, nranges, total, v0 + step, nrr, nkey, nx, nF);
             T w[DIM][4];
             int cx = 0, cy = 0, cz = 0;
             bool has = false;
@@ -307,18 +353,19 @@ struct SpreadTile {
                                   ((uint32_t)(cz + 4) << (XB + YB));
             unsigned long long grp;
             bool leader;
+            int head = lane;
             if (same0) {
                 // Cells of staggering 0 itself: a cell's points are adjacent in sorted order,
                 // so a group runs from its first lane to the next change of cell.
-                const uint32_t prev = (uint32_t)__shfl_up((int)code, 1u, 64);
-                const int hprev = __shfl_up((int)has, 1u, 64);
+                const uint32_t prev = wave_shr1_u32(code);
+                const uint32_t hprev = wave_shr1_u32((uint32_t)has);
                 leader = has && (lane == 0 || !hprev || prev != code);
                 const unsigned long long heads = __ballot(leader);
                 const unsigned long long holes = ~__ballot(has);
                 // This lane's run starts at the highest head at or below it and ends at the
                 // next head or hole above that.
                 const unsigned long long hb = heads & ((2ull << lane) - 1ull);
-                const int head = hb ? 63 - __clzll((long long)hb) : lane;
+                head = hb ? 63 - __clzll((long long)hb) : lane;
                 const unsigned long long stop = (heads | holes) & ~((2ull << head) - 1ull);
                 const int end = stop ? __ffsll((long long)stop) - 1 : 64;
                 const unsigned long long upto = (end == 64) ? ~0ull : ((1ull << end) - 1ull);
@@ -327,21 +374,20 @@ struct SpreadTile {
                 grp = match_code(code, has);
                 leader = has && (grp & below) == 0ull;
             }
-            // Group layout: each group gets a contiguous range of the wave's lane table, in
-            // rank order (the rank of a lane is the number of group lanes below it), so any
-            // member's lane is found from (group offset, rank).
+            // The rank of a lane is the number of group lanes below it.  Adjacent groups hold
+            // their members in lanes head + rank; matched groups list them in the wave's lane
+            // table, one contiguous piece per group in rank order.
             const int rank = __popcll(grp & below);
             const int gk = __popcll(grp);
             const int maxk = wave_max_i32(gk);
-            int gbase;
-            {
+            int gbase = 0;
+            if (!same0 && maxk > 1) {
                 const uint32_t kl = leader ? (uint32_t)gk : 0u;
                 const int goff_l = (int)(wave_incl_scan_u32(kl) - kl);
                 const int lead_lane = has ? __ffsll((long long)grp) - 1 : lane;
-                const int goff = __shfl(goff_l, lead_lane, 64);
-                if (has) ltab[goff + rank] = lane;
+                gbase = __shfl(goff_l, lead_lane, 64);
+                if (has) ws.ltab[(gbase + rank) & 63] = lane;
                 wave_sync();
-                gbase = goff;
             }
             // The first P members of a group (sub-leaders) each sum every P-th member, then
             // add their sums into the tile in P rounds, one rank per round, so the active
@@ -356,26 +402,14 @@ struct SpreadTile {
             const int P = maxk <= K1 ? 1 : maxk <= K2 ? 2 : maxk <= K3 ? 3 : maxk <= K4 ? 4
                         : maxk <= K5 ? 5 : maxk <= K6 ? 6 : 7;
             const bool sub = has && rank < P;
+            // Lanes other than sub-leaders compute sums that are never added.
             T acc[NZ][4][4];
-#pragma unroll
-            for (int iz = 0; iz < NZ; ++iz)
-#pragma unroll
-                for (int iy = 0; iy < 4; ++iy)
-#pragma unroll
-                    for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = T(0);
-            {
-                T wl[DIM][4];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) wl[d][i] = sub ? w[d][i] : T(0);
-                accumulate(acc, wl);
-            }
+            products(acc, w);
             const int iters = (maxk + P - 1) / P - 1;
             for (int j = 1; j <= iters; ++j) {
                 const int mr = rank + j * P;
                 const bool ok = sub && mr < gk;
-                const int src = ok ? ltab[(gbase + mr) & 63] : lane;
+                const int src = !ok ? lane : same0 ? head + mr : ws.ltab[(gbase + mr) & 63];
                 T wk[DIM][4];
 #pragma unroll
                 for (int d = 0; d < DIM; ++d)
@@ -406,7 +440,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     // precisions: FP64 LDS atomic adds run at full LDS rate on gfx950, FP32 ones do not.
     __shared__ double tile[ST::PXS * TY * TZ];
     __shared__ typename ST::Table tables[4];
-    __shared__ int32_t ltabs[4][64];  // per wave: lanes of each group in rank order
+    __shared__ typename ST::WaveScratch scratch[4];
     const GeomArgs& g = a.g;
     // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
     // chunk of its points and add their partial tiles at the end.
@@ -444,10 +478,12 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
         for (int m = w;; m += 4) {
             const int q = phase + nphase * m;
             if (q >= nslices) break;
-            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb);
+            int rp;
+            bool rn;
+            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
             if (total > 0)
-                ST::reduce(a, c, a.sorted_keys, tb, nranges, total, q, off, ex, ey, ez, same0,
-                           tile, ltabs[w], ksub, split);
+                ST::reduce(a, c, a.sorted_keys, tb, rp, rn, nranges, total, q, off, ex, ey, ez,
+                           same0, tile, scratch[w], ksub, split);
             wave_sync();
         }
         __syncthreads();

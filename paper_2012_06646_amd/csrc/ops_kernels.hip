@@ -16,11 +16,12 @@
 // component-c cell form a group (adjacent lanes for staggering 0, found by matching cell
 // codes with ballots otherwise).  The group's sum over its points of the 4^d weight
 // products -- the segmented reduce of Alg. 4, for all shifts at once -- is formed in
-// registers (by one lane, or for a crowded cell by several lanes combined in a tree), and
-// its first lane adds it into an FP64 LDS copy of the tile with LDS atomic adds.  Those
-// lanes hold distinct cells, so for one shift the active lanes of an instruction hit
-// distinct addresses; the waves of a block take source planes far enough apart that their
-// targets are disjoint, in phases separated by barriers.  The order in which every grid
+// registers (by one lane, or for a crowded cell by a few sub-leader lanes that add in
+// separate rounds), and added into an FP64 LDS copy of the tile with LDS atomic adds.  The
+// lanes adding in one round hold distinct cells, so for one shift the active lanes of an
+// instruction hit distinct addresses; waves of a block work at the same time only on source
+// planes far enough apart that their targets are disjoint, and overlapping planes follow one
+// fixed order.  The order in which every grid
 // value receives its contributions is therefore fixed by the data alone, and the result is
 // bitwise reproducible; no global atomics are used.
 //
@@ -455,7 +456,10 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
 
+    constexpr int MAXSLICES = ((DIM == 3) ? TZ : TY) + 4;
+    __shared__ int s_done[MAXSLICES];
     for (int i = threadIdx.x; i < ST::PXS * TY * TZ; i += blockDim.x) tile[i] = 0.0;
+    if (threadIdx.x < MAXSLICES) s_done[threadIdx.x] = 0;
     __syncthreads();
 
     // Source frame: staggering-0 cells that can reach the tile for this component.
@@ -472,22 +476,46 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int w = wave_id();
     typename ST::Table& tb = tables[w];
 
-    // Slices q and q + nphase feed disjoint target slices, so the four waves take slices
-    // of one residue class concurrently and the phases are separated by barriers.
-    for (int phase = 0; phase < nphase; ++phase) {
-        for (int m = w;; m += 4) {
-            const int q = phase + nphase * m;
-            if (q >= nslices) break;
-            int rp;
-            bool rn;
-            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
-            if (total > 0)
-                ST::reduce(a, c, a.sorted_keys, tb, rp, rn, nranges, total, q, off, ex, ey, ez,
-                           same0, tile, scratch[w], ksub, split);
-            wave_sync();
+    // Slices less than nphase apart have overlapping targets; slices nphase apart do not.
+    // The slices are worked in one fixed order: by phase (q mod nphase), then by q; wave w
+    // takes positions w, w + 4, ... of that order.  A slice starts once the overlapping
+    // slices before it in the order are done (those after it wait for it in turn).  So slices
+    // that run at the same time have disjoint targets, and every tile value receives its
+    // contributions in an order fixed by the data alone.  Unlike barriers between phases,
+    // this lets a wave go on as soon as its own dependences are met.  No wave waits forever:
+    // the first unfinished position of the order has all its dependences done, and its wave
+    // has finished everything before it.
+    const int lane = lane_id();
+    for (int t = __builtin_amdgcn_readfirstlane(w); t < nslices; t += 4) {
+        int p = 0, first = 0;  // phase of position t and the first position of that phase
+        for (;;) {
+            const int cnt = (nslices - p + nphase - 1) / nphase;
+            if (t < first + cnt) break;
+            first += cnt;
+            ++p;
         }
-        __syncthreads();
+        const int q = p + nphase * (t - first);
+        // Overlapping slices of earlier phases: q - p .. q - 1 and q + nphase - p .. q + nphase - 1.
+        const int dep = lane < p ? q - p + lane : q + nphase - 2 * p + lane;
+        const bool need = lane < 2 * p && dep >= 0 && dep < nslices;
+        for (;;) {
+            const bool ok = !need || __hip_atomic_load(&s_done[need ? dep : 0], __ATOMIC_ACQUIRE,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+            if (__ballot(!ok) == 0ull) break;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        int rp;
+        bool rn;
+        const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
+        if (total > 0)
+            ST::reduce(a, c, a.sorted_keys, tb, rp, rn, nranges, total, q, off, ex, ey, ez,
+                       same0, tile, scratch[w], ksub, split);
+        wave_sync();
+        // Every lane writes the same flag (no lane-dependent branch around the loop's back
+        // edge); the release orders it after all of this wave's additions into the tile.
+        __hip_atomic_store(&s_done[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    __syncthreads();
 
     T* f = (T*)a.f;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);

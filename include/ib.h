@@ -68,8 +68,9 @@ typedef struct {
 typedef struct ib_plan_s *ib_plan;
 
 /* Tuning of a plan; all-zero fields select the built-in choices.
- *   spread_tile   3-D spreading tile (x*y*z cells owned by one block): 0 = 32x16x13,
- *                 1 = 32x8x13, 2 = 64x8x8 (2-D grids always use 64x32)
+ *   spread_tile   3-D spreading tile (x*y*z cells owned by one block): 1 = 32x16x13,
+ *                 2 = 32x8x13, 3 = 64x8x8; 0 = 32x16x13 for IB_F64 and 32x8x13 for
+ *                 IB_F32 (2-D grids always use 64x32)
  *   split_points  points per block before a spreading tile is shared by several blocks
  *                 (at most 16): 0 = 2048, < 0 = never share
  *   radix_bits    radix digit width of the key sort, 4..8: 0 = the key bits spread evenly

@@ -66,7 +66,7 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
 int32_t check_tuning(const ib_tuning* t)
 {
     if (!t) return IB_OK;
-    if (t->spread_tile < 0 || t->spread_tile >= SPREAD_TILE_SHAPES) return IB_ERR_ARG;
+    if (t->spread_tile < 0 || t->spread_tile > SPREAD_TILE_SHAPES) return IB_ERR_ARG;
     if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > MAX_RADIX_BITS)) return IB_ERR_ARG;
     return IB_OK;
 }
@@ -111,7 +111,10 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->Xs = take((size_t)n * g->dim * b);
     L->Fs = take((size_t)n * g->ncomp * b);
     int tiles[3];
-    L->sp_tile = (tuning && g->dim == 3) ? tuning->spread_tile : 0;
+    // ib_tuning.spread_tile: 0 = the built-in shape of the precision, k = shape k - 1.
+    L->sp_tile = g->dim != 3 ? 0
+                 : (tuning && tuning->spread_tile > 0) ? tuning->spread_tile - 1
+                                                       : builtin_spread_shape(dtype);
     spread_tiles(g->dim, L->sp_tile, g->n, tiles);
     L->sp_tiles = tiles[0] * tiles[1] * tiles[2] * g->ncomp;
     L->split = spread_split(n, L->sp_tiles, tuning ? tuning->split_points : 0);

@@ -167,7 +167,12 @@ int keys_blocks(const SortArgs& a);
 size_t keys_lds_bytes(const SortArgs& a);
 int gather_blocks(int64_t npts, int ncomp);
 int interp_blocks(int64_t npts);
+// 3-D spreading tile shapes (index into the shape table of the spreading kernels):
+// 0 = 32x16x13, 1 = 32x8x13, 2 = 64x8x8.  FP32 plans and batches use 32x8x13 by default:
+// its kernel fits four waves per SIMD (FP32 sums need half the registers), and its LDS tile
+// lets four blocks share a CU.  FP64 plans use 32x16x13 (two waves per SIMD either way).
 constexpr int SPREAD_TILE_SHAPES = 3;
+constexpr int builtin_spread_shape(int32_t dtype) { return dtype == IB_F32 ? 1 : 0; }
 void spread_tiles(int dim, int shape, const int n[3], int tiles[3]);
 // Cells of one spreading tile, and the number of blocks that share a tile (1 .. 16) for
 // npts points over ntiles (tiles x components) tiles: a dense point set on a small grid

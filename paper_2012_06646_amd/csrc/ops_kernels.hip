@@ -562,8 +562,18 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     }
 }
 
+// Waves per SIMD a spreading kernel is compiled for.  FP32 with the 32x8x13 tile fits four
+// (its sums take half the registers of FP64, and four of its LDS tiles fit in a CU); the
+// others keep two, with the registers they need.
+template <typename T, int TX, int TY, int TZ>
+constexpr int spread_waves_per_eu()
+{
+    return (sizeof(T) == 4 && TX == 32 && TY == 8 && TZ == 13) ? 4 : 1;
+}
+
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void spread_kernel(OpArgs a)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(spread_waves_per_eu<T, TX, TY, TZ>()))) void spread_kernel(OpArgs a)
 {
     spread_body<T, DIM, KERN, TX, TY, TZ>(a, blockIdx.x);
 }
@@ -839,9 +849,8 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // Launchers
 // ---------------------------------------------------------------------------------------
 namespace {
-// Spreading tiles (3-D) selectable per plan; shape 0 is the default (960 blocks at 128^3).
+// Spreading tiles (3-D) selectable per plan (960 blocks of 32x16x13 at 128^3).
 constexpr int SP_SHAPE[SPREAD_TILE_SHAPES][3] = {{32, 16, 13}, {32, 8, 13}, {64, 8, 8}};
-constexpr int SP_TX = SP_SHAPE[0][0], SP_TY = SP_SHAPE[0][1], SP_TZ = SP_SHAPE[0][2];
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -913,8 +922,9 @@ __global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* __res
 }
 
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
-                                                                const BatchTable* __restrict__ bt)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    spread_waves_per_eu<T, TX, TY, TZ>()))) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
+                                                                     const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_SPREAD];
     const int nj = bt->njobs, total = st[nj];
@@ -940,8 +950,10 @@ __global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* __res
 template <typename T, int DIM, int KERN>
 void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
 {
-    constexpr int TX = DIM == 3 ? SP_TX : SP2_TX, TY = DIM == 3 ? SP_TY : SP2_TY;
-    constexpr int TZ = DIM == 3 ? SP_TZ : 1;
+    // the built-in tile of the precision (batches are never tuned)
+    constexpr int S = builtin_spread_shape(sizeof(T) == 4 ? IB_F32 : IB_F64);
+    constexpr int TX = DIM == 3 ? SP_SHAPE[S][0] : SP2_TX, TY = DIM == 3 ? SP_SHAPE[S][1] : SP2_TY;
+    constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
     if (b.grid[BS_GATHER] > 0)
         hipLaunchKernelGGL(batch_gather_kernel<T>, dim3(b.grid[BS_GATHER]), dim3(256), 0, st, b.jobs,
                            b.table);

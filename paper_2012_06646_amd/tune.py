@@ -18,7 +18,7 @@ import torch
 
 from . import ibops
 
-TILE_SHAPES = {0: "32x16x13", 1: "32x8x13", 2: "64x8x8"}
+TILE_SHAPES = {1: "32x16x13", 2: "32x8x13", 3: "64x8x8"}  # 0: built-in (FP64 1, FP32 2)
 SPLIT_CHOICES = (0, 1024, 4096, -1)    # 0: built-in (2048 points per block); -1: never split
 RADIX_CHOICES = (0, 8, 6)              # 0: built-in (even digits of at most 8 bits)
 MARGIN = 0.02                          # a candidate must be this much faster to be taken
@@ -102,7 +102,8 @@ def autotune(grid, X, F, u, reps=10, store=True, verbose=False):
     cur = measure(best)
     axes = [("split_points", SPLIT_CHOICES), ("radix_bits", RADIX_CHOICES)]
     if int(grid["dim"]) == 3:
-        axes.insert(0, ("spread_tile", tuple(TILE_SHAPES)))
+        builtin = 2 if X.dtype == torch.float32 else 1
+        axes.insert(0, ("spread_tile", tuple(k for k in TILE_SHAPES if k != builtin)))
     for name, choices in axes:
         for c in choices:
             cand = dict(best, **{name: c})

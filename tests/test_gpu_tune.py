@@ -20,9 +20,9 @@ def ib():
     return ibops
 
 
-TUNINGS = [None, {"spread_tile": 1}, {"spread_tile": 2}, {"split_points": 256},
+TUNINGS = [None, {"spread_tile": 1}, {"spread_tile": 2}, {"spread_tile": 3}, {"split_points": 256},
            {"split_points": -1}, {"radix_bits": 8}, {"radix_bits": 4},
-           {"spread_tile": 2, "split_points": 512, "radix_bits": 6}]
+           {"spread_tile": 3, "split_points": 512, "radix_bits": 6}]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

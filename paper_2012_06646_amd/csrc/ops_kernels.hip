@@ -697,6 +697,151 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
     interp_body<T, DIM, KERN>(a, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// Interpolation through LDS (3-D plans).  A block owns a TX x TY x TZ tile of staggering-0
+// cells, i.e. the sorted points whose cells lie in it (one contiguous sorted range per
+// x-row of the tile).  For each component in turn it stages the grid values that the
+// stencils of those points can touch -- the tile widened by the stencil and by the offset
+// between the component's cells and staggering-0 cells -- in LDS with coalesced loads, and
+// every point then reads its 4^3 values from LDS instead of gathering them from L2.  The
+// weights and the order of the multiply-adds are those of interp_component, so the values
+// are bitwise equal to the gather kernel's.  Each point's components are written by the
+// same thread, pass by pass; the fused position update reads them back in the last pass.
+template <typename T, int KERN, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
+{
+    constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region
+    constexpr int ROWS = TY * TZ;
+    __shared__ T su[RX * RY * RZ];
+    __shared__ int32_t s_lo[ROWS];
+    __shared__ int32_t s_pref[ROWS + 1];
+    __shared__ uint32_t s_scan[256 / 64 + 1];
+    const GeomArgs& g = a.g;
+    const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+    const int64_t G = (int64_t)n0 * n1 * n2;
+    const int64_t n = g.npts;
+    const int tid = threadIdx.x;
+    const int ntx = (n0 + TX - 1) / TX, nty = (n1 + TY - 1) / TY;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = bid % ntx, by = (bid / ntx) % nty, bz = bid / (ntx * nty);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int ex = min(TX, n0 - x0), ey = min(TY, n1 - y0), ez = min(TZ, n2 - z0);
+    const int nrt = ey * ez;
+
+    // Sorted range of each x-row of the tile (exact: tiles start at multiples of the
+    // 4-cell blocks of the cell-block table), and their prefix counts.
+    uint32_t cnt = 0;
+    int32_t lo = 0;
+    if (tid < nrt) {
+        const int row = (z0 + tid / ey) * n1 + (y0 + tid % ey);
+        const int64_t rb = (int64_t)row * (g.nbx + 1);
+        lo = a.cblk[rb + (x0 >> CBLK_SHIFT)];
+        const int32_t hi = a.cblk[rb + ((x0 + ex + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT)];
+        cnt = hi > lo ? (uint32_t)(hi - lo) : 0u;
+    }
+    uint32_t total_u;
+    const uint32_t pref = block_excl_scan_u32<256>(cnt, s_scan, &total_u);
+    if (tid < nrt) {
+        s_lo[tid] = lo;
+        s_pref[tid] = (int32_t)pref;
+    }
+    if (tid == 0) s_pref[nrt] = (int32_t)total_u;
+    const int total = (int)total_u;
+
+    const T* __restrict__ Xs = (const T*)a.Xs;
+    const T* __restrict__ u = (const T*)a.u;
+    T* __restrict__ U = (T*)a.U;
+    const int ncomp = g.ncomp;
+    for (int c = 0; c < ncomp; ++c) {
+        // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + 2) per axis, wrapped.
+        const int hx = g.dhi[c][0] - g.dlo[c][0], hy = g.dhi[c][1] - g.dlo[c][1];
+        const int hz = g.dhi[c][2] - g.dlo[c][2];
+        const int lx = ex + 3 + hx, ly = ey + 3 + hy, lz = ez + 3 + hz;
+        const int rx = x0 + g.dlo[c][0] - 1, ry = y0 + g.dlo[c][1] - 1, rz = z0 + g.dlo[c][2] - 1;
+        __syncthreads();  // the previous component's points are done with su
+        {
+            const int rstep = 256 / lx;
+            const int xi = tid % lx;
+            int r = tid / lx;
+            if (r < rstep) {
+                const int gx = wrap_small(rx + xi, n0);
+                const T* __restrict__ uc = u + (int64_t)c * G;
+                int iy = r % ly, iz = r / ly;
+                for (; iz < lz; r += rstep) {
+                    const int gy = wrap_small(ry + iy, n1), gz = wrap_small(rz + iz, n2);
+                    su[(iz * ly + iy) * lx + xi] = uc[((int64_t)gz * n1 + gy) * n0 + gx];
+                    iy += rstep;
+                    while (iy >= ly) {
+                        iy -= ly;
+                        ++iz;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const bool last = c == ncomp - 1;
+        for (int v = tid; v < total; v += 256) {
+            int lo_r = 0, hi_r = nrt;  // row of position v: last row whose prefix is <= v
+            while (hi_r - lo_r > 1) {
+                const int mid = (lo_r + hi_r) >> 1;
+                if (s_pref[mid] <= v) lo_r = mid;
+                else hi_r = mid;
+            }
+            const int ry_t = lo_r % ey, rz_t = lo_r / ey;
+            const int64_t j = clamp_index(s_lo[lo_r] + (v - s_pref[lo_r]), n);
+            const int rowkey = ((z0 + rz_t) * n1 + (y0 + ry_t)) * n0;
+            const int sx = min(max(a.sorted_keys[j] - rowkey, x0), x0 + ex - 1);
+            T x[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x[k] = Xs[j * 3 + k];
+            const int64_t p = clamp_index(a.perm[j], n);
+            // weights as in interp_component; the component's cell from the staggering-0 cell
+            T w[3][4];
+            int base[3];
+            const int s0[3] = {sx - x0, ry_t, rz_t};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const T ih = Prec<T>::inv_h(g, k);
+                const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
+                const T fy = floor(y);
+                T r = y - fy;
+                r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
+                weights4<T, KERN>(r, w[k]);
+                int d = g.dlo[c][k];
+                if (g.dhi[c][k] != d) {
+                    const T y0s = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
+                    d = min(max((int)(fy - floor(y0s)), g.dlo[c][k]), g.dhi[c][k]);
+                }
+                base[k] = s0[k] + d - g.dlo[c][k];  // first stencil cell, region-relative
+            }
+            T sum = T(0);
+#pragma unroll
+            for (int iz = 0; iz < 4; ++iz) {
+                T sy = T(0);
+#pragma unroll
+                for (int iy = 0; iy < 4; ++iy) {
+                    const T* line = su + ((base[2] + iz) * ly + (base[1] + iy)) * lx + base[0];
+                    T sx_ = T(0);
+#pragma unroll
+                    for (int ix = 0; ix < 4; ++ix) sx_ = fma(w[0][ix], line[ix], sx_);
+                    sy = fma(w[1][iy], sx_, sy);
+                }
+                sum = fma(w[2][iz], sy, sum);
+            }
+            U[p * ncomp + c] = sum;
+            if (last && a.Xadv) {  // fused position update (ncomp == 3)
+                T* __restrict__ Xa = (T*)a.Xadv;
+                T res[3];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) res[k] = U[p * 3 + k];  // this thread's earlier passes
+                res[2] = sum;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    Xa[p * 3 + k] = advect_coord(x[k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Position gradient of interpolation: dX_j += sum_c W_{j,c} dU_{j,c} / dX_j, U = J(X) u.
 // dW/dX_k = (1/h_k) dw_k(r_k) prod_{l != k} w_l(r_l); one thread per sorted point.
@@ -852,6 +997,7 @@ namespace {
 // Spreading tiles (3-D) selectable per plan (960 blocks of 32x16x13 at 128^3).
 constexpr int SP_SHAPE[SPREAD_TILE_SHAPES][3] = {{32, 16, 13}, {32, 8, 13}, {64, 8, 8}};
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
+constexpr int IT_TX = 16, IT_TY = 16, IT_TZ = 8;    // interpolation tile (3-D plans)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -887,7 +1033,11 @@ template <typename T, int KERN>
 hipError_t interp_dispatch(OpArgs a, hipStream_t st)
 {
     const unsigned nb = (unsigned)interp_blocks(a.g.npts);
-    if (a.g.dim == 3)
+    if (a.g.dim == 3 && a.g.npts > 0) {
+        const unsigned nt = (unsigned)(cdiv(a.g.n[0], IT_TX) * cdiv(a.g.n[1], IT_TY) * cdiv(a.g.n[2], IT_TZ));
+        hipLaunchKernelGGL((interp_tile_kernel<T, KERN, IT_TX, IT_TY, IT_TZ>), dim3(nt), dim3(256), 0,
+                           st, a);
+    } else if (a.g.dim == 3)
         hipLaunchKernelGGL((interp_kernel<T, 3, KERN>), dim3(nb), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((interp_kernel<T, 2, KERN>), dim3(nb), dim3(256), 0, st, a);

@@ -91,6 +91,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.Xs = p.sa.d.Xs;
         a.F = J.F;
         a.Fs = p.sa.d.Fs;
+        a.Us = p.sa.d.Us;
         a.partial = p.sa.d.partial;
         a.tile_count = p.sa.d.tile_count;
         a.f = J.f;

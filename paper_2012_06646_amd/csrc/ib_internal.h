@@ -43,6 +43,7 @@ struct PlanDev {
     uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
     void* Fs;              // [n][ncomp] forces in that order (filled by each spread call)
+    void* Us;              // [n][2] interpolation: the first components in that order
     double* partial;       // [tiles][split][tile cells] partial tile sums (split > 1 only)
     uint32_t* tile_count;  // [tiles] blocks of a split tile done (in the cleared region)
     uint32_t* zero_begin;  // region cleared at each update
@@ -107,6 +108,7 @@ struct OpArgs {
     const void* Xs;              // staggering-0 order
     const void* F;
     void* Fs;
+    void* Us;
     void* f;
     const void* u;
     void* U;

@@ -704,11 +704,13 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 // between the component's cells and staggering-0 cells -- in LDS with coalesced loads, and
 // every point then reads its 4^3 values from LDS instead of gathering them from L2.  The
 // weights and the order of the multiply-adds are those of interp_component, so the values
-// are bitwise equal to the gather kernel's.  Each point's components are written by the
-// same thread, pass by pass; the fused position update reads them back in the last pass.
+// are bitwise equal to the gather kernel's.  A point is handled by the same thread in every
+// pass: the first components wait in a sorted-order scratch (written and read coalesced),
+// and the last pass writes the point's row of U, and the position update if fused, once.
 template <typename T, int KERN, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
 {
+    constexpr int KP = 4;
     constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region
     constexpr int ROWS = TY * TZ;
     __shared__ T su[RX * RY * RZ];
@@ -750,6 +752,7 @@ __global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
     const T* __restrict__ Xs = (const T*)a.Xs;
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
+    T* __restrict__ Us = (T*)a.Us;
     const int ncomp = g.ncomp;
     for (int c = 0; c < ncomp; ++c) {
         // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + 2) per axis, wrapped.
@@ -759,84 +762,121 @@ __global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
         const int rx = x0 + g.dlo[c][0] - 1, ry = y0 + g.dlo[c][1] - 1, rz = z0 + g.dlo[c][2] - 1;
         __syncthreads();  // the previous component's points are done with su
         {
+            // Thread tid stages x-column tid % lx of rows tid / lx, tid / lx + rstep, ...; SU
+            // rows per round are loaded before any is stored, so their loads overlap.
+            constexpr int SU = 8;
             const int rstep = 256 / lx;
             const int xi = tid % lx;
-            int r = tid / lx;
+            const int r = tid / lx;
+            const int nr = ly * lz;
+            const float inv_ly = 1.0f / (float)ly;
             if (r < rstep) {
                 const int gx = wrap_small(rx + xi, n0);
                 const T* __restrict__ uc = u + (int64_t)c * G;
-                int iy = r % ly, iz = r / ly;
-                for (; iz < lz; r += rstep) {
-                    const int gy = wrap_small(ry + iy, n1), gz = wrap_small(rz + iz, n2);
-                    su[(iz * ly + iy) * lx + xi] = uc[((int64_t)gz * n1 + gy) * n0 + gx];
-                    iy += rstep;
-                    while (iy >= ly) {
-                        iy -= ly;
-                        ++iz;
+                for (int r0 = r; r0 < nr; r0 += SU * rstep) {
+                    T val[SU];
+#pragma unroll
+                    for (int q = 0; q < SU; ++q) {
+                        const int rr = r0 + q * rstep;
+                        val[q] = T(0);
+                        if (rr < nr) {
+                            int iz = (int)((float)rr * inv_ly);  // rr / ly, corrected below
+                            iz += (rr - iz * ly >= ly) - (rr - iz * ly < 0);
+                            const int iy = rr - iz * ly;
+                            const int gy = wrap_small(ry + iy, n1), gz = wrap_small(rz + iz, n2);
+                            val[q] = uc[((int64_t)gz * n1 + gy) * n0 + gx];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < SU; ++q) {
+                        const int rr = r0 + q * rstep;
+                        if (rr < nr) su[rr * lx + xi] = val[q];
                     }
                 }
             }
         }
         __syncthreads();
+        // The first components of a point wait in sorted order (coalesced) until the last
+        // pass writes its whole row of U, and the fused position update (ncomp == 3).
         const bool last = c == ncomp - 1;
-        for (int v = tid; v < total; v += 256) {
-            int lo_r = 0, hi_r = nrt;  // row of position v: last row whose prefix is <= v
-            while (hi_r - lo_r > 1) {
-                const int mid = (lo_r + hi_r) >> 1;
-                if (s_pref[mid] <= v) lo_r = mid;
-                else hi_r = mid;
-            }
-            const int ry_t = lo_r % ey, rz_t = lo_r / ey;
-            const int64_t j = clamp_index(s_lo[lo_r] + (v - s_pref[lo_r]), n);
-            const int rowkey = ((z0 + rz_t) * n1 + (y0 + ry_t)) * n0;
-            const int sx = min(max(a.sorted_keys[j] - rowkey, x0), x0 + ex - 1);
-            T x[3];
+        const bool adv = last && a.Xadv != nullptr;
+        // KP points per thread and round: their lookups and loads are issued together, so a
+        // round waits for one memory latency rather than one per point.
+        for (int v0 = tid; v0 < total; v0 += 256 * KP) {
+            int64_t pj[KP], jj[KP];
+            int s0[KP][3];
+            T x[KP][3], done[KP][2];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) x[k] = Xs[j * 3 + k];
-            const int64_t p = clamp_index(a.perm[j], n);
-            // weights as in interp_component; the component's cell from the staggering-0 cell
-            T w[3][4];
-            int base[3];
-            const int s0[3] = {sx - x0, ry_t, rz_t};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const T ih = Prec<T>::inv_h(g, k);
-                const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
-                const T fy = floor(y);
-                T r = y - fy;
-                r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
-                weights4<T, KERN>(r, w[k]);
-                int d = g.dlo[c][k];
-                if (g.dhi[c][k] != d) {
-                    const T y0s = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
-                    d = min(max((int)(fy - floor(y0s)), g.dlo[c][k]), g.dhi[c][k]);
+            for (int q = 0; q < KP; ++q) {
+                const int v = v0 + 256 * q;
+                int lo_r = 0, hi_r = nrt;  // row of position v: last row whose prefix is <= v
+                while (hi_r - lo_r > 1) {
+                    const int mid = (lo_r + hi_r) >> 1;
+                    if (s_pref[mid] <= v) lo_r = mid;
+                    else hi_r = mid;
                 }
-                base[k] = s0[k] + d - g.dlo[c][k];  // first stencil cell, region-relative
+                const int ry_t = lo_r % ey, rz_t = lo_r / ey;
+                const int64_t j = clamp_index(v < total ? s_lo[lo_r] + (v - s_pref[lo_r]) : 0, n);
+                const int rowkey = ((z0 + rz_t) * n1 + (y0 + ry_t)) * n0;
+                s0[q][0] = min(max(a.sorted_keys[j] - rowkey, x0), x0 + ex - 1) - x0;
+                s0[q][1] = ry_t;
+                s0[q][2] = rz_t;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) x[q][k] = Xs[j * 3 + k];
+                pj[q] = clamp_index(a.perm[j], n);
+                jj[q] = j;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) done[q][k] = (last && k < c) ? Us[j * 2 + k] : T(0);
             }
-            T sum = T(0);
 #pragma unroll
-            for (int iz = 0; iz < 4; ++iz) {
-                T sy = T(0);
+            for (int q = 0; q < KP; ++q) {
+                if (v0 + 256 * q >= total) break;
+                // weights as in interp_component; the component's cell from the
+                // staggering-0 cell
+                T w[3][4];
+                int base[3];
 #pragma unroll
-                for (int iy = 0; iy < 4; ++iy) {
-                    const T* line = su + ((base[2] + iz) * ly + (base[1] + iy)) * lx + base[0];
-                    T sx_ = T(0);
-#pragma unroll
-                    for (int ix = 0; ix < 4; ++ix) sx_ = fma(w[0][ix], line[ix], sx_);
-                    sy = fma(w[1][iy], sx_, sy);
+                for (int k = 0; k < 3; ++k) {
+                    const T ih = Prec<T>::inv_h(g, k);
+                    const T y = shifted_scaled<T>(x[q][k], ih, (T)g.comp_xi[c][k]);
+                    const T fy = floor(y);
+                    T r = y - fy;
+                    r += product_residual<T>(x[q][k], ih, Prec<T>::inv_lo(g, k));
+                    weights4<T, KERN>(r, w[k]);
+                    int d = g.dlo[c][k];
+                    if (g.dhi[c][k] != d) {
+                        const T y0s = shifted_scaled<T>(x[q][k], ih, (T)g.stag_xi[0][k]);
+                        d = min(max((int)(fy - floor(y0s)), g.dlo[c][k]), g.dhi[c][k]);
+                    }
+                    base[k] = s0[q][k] + d - g.dlo[c][k];  // first stencil cell, region-relative
                 }
-                sum = fma(w[2][iz], sy, sum);
-            }
-            U[p * ncomp + c] = sum;
-            if (last && a.Xadv) {  // fused position update (ncomp == 3)
-                T* __restrict__ Xa = (T*)a.Xadv;
-                T res[3];
+                T sum = T(0);
 #pragma unroll
-                for (int k = 0; k < 2; ++k) res[k] = U[p * 3 + k];  // this thread's earlier passes
-                res[2] = sum;
+                for (int iz = 0; iz < 4; ++iz) {
+                    T sy = T(0);
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-                    Xa[p * 3 + k] = advect_coord(x[k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                    for (int iy = 0; iy < 4; ++iy) {
+                        const T* line = su + ((base[2] + iz) * ly + (base[1] + iy)) * lx + base[0];
+                        T sx_ = T(0);
+#pragma unroll
+                        for (int ix = 0; ix < 4; ++ix) sx_ = fma(w[0][ix], line[ix], sx_);
+                        sy = fma(w[1][iy], sx_, sy);
+                    }
+                    sum = fma(w[2][iz], sy, sum);
+                }
+                if (!last) {
+                    Us[jj[q] * 2 + c] = sum;
+                    continue;
+                }
+                const int64_t p = pj[q];
+                const T res[3] = {c == 0 ? sum : done[q][0], c == 1 ? sum : done[q][1], sum};
+                for (int k = 0; k < ncomp; ++k) U[p * ncomp + k] = res[k];
+                if (adv) {
+                    T* __restrict__ Xa = (T*)a.Xadv;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        Xa[p * 3 + k] = advect_coord(x[q][k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                }
             }
         }
     }

@@ -43,25 +43,40 @@ __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict
 
     const int64_t n = g.npts;
     bool any_bad = false;
-    for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)nblk * blockDim.x) {
-        T x[3];
-        for (int k = 0; k < g.dim; ++k) x[k] = X[j * g.dim + k];
-        bool bad = false;
-        for (int s = s0; s < s1; ++s) {
-            int key = 0, stride = 1;
-            for (int k = 0; k < g.dim; ++k) {
-                const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
-                int c = 0;
-                if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
-                else bad = true;
-                key += c * stride;
-                stride *= g.n[k];
-            }
-            a.d.keys0[(int64_t)s * n + j] = key;
-            for (int p = 0; p < a.npass; ++p)
-                atomicAdd(&lhist[((s - s0) * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
+    // Each thread takes KU points per round, all positions loaded before any is keyed, so
+    // the loads of a round are in flight together.
+    constexpr int KU = 4;
+    const int64_t step = (int64_t)nblk * blockDim.x;
+    for (int64_t j0 = (int64_t)bid * blockDim.x + threadIdx.x; j0 < n; j0 += KU * step) {
+        T xs[KU][3];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int64_t j = j0 + u * step;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xs[u][k] = (j < n && k < g.dim) ? X[j * g.dim + k] : T(0);
         }
-        any_bad |= bad;
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int64_t j = j0 + u * step;
+            if (j >= n) break;
+            const T* x = xs[u];
+            bool bad = false;
+            for (int s = s0; s < s1; ++s) {
+                int key = 0, stride = 1;
+                for (int k = 0; k < g.dim; ++k) {
+                    const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
+                    int c = 0;
+                    if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
+                    else bad = true;
+                    key += c * stride;
+                    stride *= g.n[k];
+                }
+                a.d.keys0[(int64_t)s * n + j] = key;
+                for (int p = 0; p < a.npass; ++p)
+                    atomicAdd(&lhist[((s - s0) * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
+            }
+            any_bad |= bad;
+        }
     }
     if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
     __syncthreads();
@@ -138,6 +153,8 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
     const int64_t t = s_ticket;
     const int64_t base = t * SORT_TILE;
     const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
+    // The digit's global count, loaded now so its latency overlaps the ranking.
+    const uint32_t gcount = tid < R ? a.d.hist[((int64_t)s * a.npass + pass) * R + tid] : 0u;
 
     // Source and destination: pass 0 reads the unsorted keys and generates the indices.
     const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
@@ -179,14 +196,13 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
 
     // Per digit: wave offsets within the tile, the tile count, its exclusive prefix over
     // earlier tiles (look-back), the digit's global base and its start inside the tile.
-    uint32_t cnt = 0, gcount = 0;
+    uint32_t cnt = 0;
     if (tid < R) {
         for (int v = 0; v < NW; ++v) {
             const uint32_t c = s_wcnt[v][tid];
             s_wcnt[v][tid] = cnt;
             cnt += c;
         }
-        gcount = a.d.hist[((int64_t)s * a.npass + pass) * R + tid];
     }
     uint32_t tot;
     const uint32_t tstart = block_excl_scan_u32<SORT_BLOCK>(tid < R ? cnt : 0u, s_scan, &tot);

@@ -109,7 +109,9 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         counts[BS_SEG] = (int)sa.nseg_tiles;
         counts[BS_GATHER] = J.f ? gather_blocks(n, a.g.ncomp) : 0;
         counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;
-        counts[BS_INTERP] = J.u ? interp_blocks(n) : 0;
+        const int itiles = J.u ? interp_tiles(a.g.dim, a.g.n, n) : 0;
+        a.interp_tiled = itiles > 0;
+        counts[BS_INTERP] = J.u ? (itiles > 0 ? itiles : interp_blocks(n)) : 0;
         for (int s = 0; s < BS_COUNT; ++s) ht->starts[s][j + 1] = ht->starts[s][j] + counts[s];
         if (counts[BS_KEYS] > 0 && keys_lds_bytes(sa) > keys_lds) keys_lds = keys_lds_bytes(sa);
     }

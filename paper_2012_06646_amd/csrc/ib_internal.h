@@ -116,6 +116,7 @@ struct OpArgs {
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
     double* partial;             // split spreading: partial tile sums
     uint32_t* tile_count;        // split spreading: arrivals per tile
+    int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     void* Xadv;                  // interpolation: also advance these positions (or null)
     double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len
     double adv_len[3];
@@ -169,6 +170,11 @@ int keys_blocks(const SortArgs& a);
 size_t keys_lds_bytes(const SortArgs& a);
 int gather_blocks(int64_t npts, int ncomp);
 int interp_blocks(int64_t npts);
+// Tiles of the LDS-staged interpolation of a 3-D plan, or 0 when its points should gather
+// directly: staging pays off with at least 256 tiles (one block each) and 200 points per tile
+// on average (measured crossover on 32^3..192^3 grids with 10^4..10^6 points).  Both paths
+// give bitwise-equal results.
+int interp_tiles(int dim, const int n[3], int64_t npts);
 // 3-D spreading tile shapes (index into the shape table of the spreading kernels):
 // 0 = 32x16x13, 1 = 32x8x13, 2 = 64x8x8.  FP32 plans and batches use 32x8x13 by default:
 // its kernel fits four waves per SIMD (FP32 sums need half the registers), and its LDS tile

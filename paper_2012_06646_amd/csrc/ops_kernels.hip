@@ -707,8 +707,11 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 // are bitwise equal to the gather kernel's.  A point is handled by the same thread in every
 // pass: the first components wait in a sorted-order scratch (written and read coalesced),
 // and the last pass writes the point's row of U, and the position update if fused, once.
+constexpr int IT_TX = 16, IT_TY = 16, IT_TZ = 8;  // interpolation tile (3-D plans)
+
+// Tile `bid` of the plan (blocks of 256 threads).
 template <typename T, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
+__device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
 {
     constexpr int KP = 4;
     constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region
@@ -723,7 +726,6 @@ __global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
     const int64_t n = g.npts;
     const int tid = threadIdx.x;
     const int ntx = (n0 + TX - 1) / TX, nty = (n1 + TY - 1) / TY;
-    const int bid = xcd_block(blockIdx.x, gridDim.x);
     const int bx = bid % ntx, by = (bid / ntx) % nty, bz = bid / (ntx * nty);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int ex = min(TX, n0 - x0), ey = min(TY, n1 - y0), ez = min(TZ, n2 - z0);
@@ -883,6 +885,12 @@ __global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
     }
 }
 
+template <typename T, int KERN, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
+{
+    interp_tile_body<T, KERN, TX, TY, TZ>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------------------
 // Position gradient of interpolation: dX_j += sum_c W_{j,c} dU_{j,c} / dX_j, U = J(X) u.
 // dW/dX_k = (1/h_k) dw_k(r_k) prod_{l != k} w_l(r_l); one thread per sorted point.
@@ -1038,7 +1046,6 @@ namespace {
 // Spreading tiles (3-D) selectable per plan (960 blocks of 32x16x13 at 128^3).
 constexpr int SP_SHAPE[SPREAD_TILE_SHAPES][3] = {{32, 16, 13}, {32, 8, 13}, {64, 8, 8}};
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
-constexpr int IT_TX = 16, IT_TY = 16, IT_TZ = 8;    // interpolation tile (3-D plans)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -1074,14 +1081,8 @@ template <typename T, int KERN>
 hipError_t interp_dispatch(OpArgs a, hipStream_t st)
 {
     const unsigned nb = (unsigned)interp_blocks(a.g.npts);
-    // Staging pays off when there are enough tiles to fill the GPU (one block per tile) and
-    // each holds many points; otherwise the points gather directly.  Measured crossover at
-    // 10^4..10^6 points on 32^3..192^3 grids: at least 256 tiles and 200 points per tile on
-    // average.  Both kernels give bitwise-equal results.
-    const int64_t nt = a.g.dim == 3 ? (int64_t)cdiv(a.g.n[0], IT_TX) * cdiv(a.g.n[1], IT_TY) *
-                                          cdiv(a.g.n[2], IT_TZ)
-                                    : 0;
-    if (a.g.dim == 3 && nt >= 256 && a.g.npts >= 200 * nt) {
+    const int nt = interp_tiles(a.g.dim, a.g.n, a.g.npts);
+    if (nt > 0) {
         hipLaunchKernelGGL((interp_tile_kernel<T, KERN, IT_TX, IT_TY, IT_TZ>), dim3((unsigned)nt),
                            dim3(256), 0, st, a);
     } else if (a.g.dim == 3)
@@ -1140,7 +1141,16 @@ __global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* __res
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job_of(st, nj, vb);
-        interp_body<T, DIM, KERN>(jobs[j].op, vb - st[j], st[j + 1] - st[j]);
+        const OpArgs& a = jobs[j].op;
+        const int nb = st[j + 1] - st[j];
+        if constexpr (DIM == 3) {
+            if (a.interp_tiled) {  // a block per tile, as for a single plan (uniform per block)
+                interp_tile_body<T, KERN, IT_TX, IT_TY, IT_TZ>(a, xcd_block(vb - st[j], nb));
+                __syncthreads();  // the next virtual block reuses the LDS
+                continue;
+            }
+        }
+        interp_body<T, DIM, KERN>(a, vb - st[j], nb);
     }
 }
 
@@ -1182,6 +1192,13 @@ int gather_blocks(int64_t npts, int ncomp)
 int interp_blocks(int64_t npts)
 {
     return npts > 0 ? (int)min((int64_t)65536, (npts + 255) / 256) : 0;
+}
+
+int interp_tiles(int dim, const int n[3], int64_t npts)
+{
+    if (dim != 3) return 0;
+    const int64_t nt = (int64_t)cdiv(n[0], IT_TX) * cdiv(n[1], IT_TY) * cdiv(n[2], IT_TZ);
+    return (nt >= 256 && nt <= (1 << 30) && npts >= 200 * nt) ? (int)nt : 0;
 }
 
 void spread_tiles(int dim, int shape, const int n[3], int tiles[3])

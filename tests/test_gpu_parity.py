@@ -355,7 +355,7 @@ def test_interpolate_advect_equals_two_calls(ib, dtype):
 def test_interp_tiles_ragged_grid(ib, orc, dtype, kernel):
     """Interpolation of a dense point set on a grid whose sizes are not multiples of the
     interpolation tile (16 x 16 x 8 cells): the LDS-staged path, against the oracle, against
-    the gather path of a batch (bit for bit), and with the fused position update."""
+    the gather path (bit for bit), through a batch, and with the fused position update."""
     g = wl.grid(3, [100, 90, 70], [1.0, 0.9, 0.7], kernel=kernel)
     n = 120000   # 378 tiles, ~317 points per tile
     X, F, u = wl.uniform_case(g, n, 77)
@@ -371,7 +371,12 @@ def test_interp_tiles_ragged_grid(ib, orc, dtype, kernel):
     assert p.status() == 0
     U_ref = orc.interp(g, Xc.astype(np.float64), uc.astype(np.float64))
     assert normwise(to_host(U), U_ref) <= TOL[dtype]
-    # the same job through a batch, whose interpolation gathers directly
+    # a point's value depends on that point alone: a plan of the first 5000 points, too
+    # sparse for tiles, gathers directly and must agree bit for bit
+    m = 5000
+    p_small = ib.Plan(g, m, dtype).update(to_dev(Xc[:m], dtype))
+    assert torch.equal(p_small.interpolate(ud), U[:m])
+    # the same job through a batch (tiled as well)
     b = ib.Batch([{"grid": g, "X": to_dev(Xc, dtype), "u": ud}], dtype).run()
     assert b.status() == [0]
     assert torch.equal(b.results()[0][1], U)

@@ -92,6 +92,7 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
     L->nseg_tiles = L->ntiles > 0 ? L->ntiles : 1;
     const int64_t R = int64_t(1) << L->rbits;
+    L->nscan_tiles = L->ntiles > 0 ? (R * L->ntiles + SCAN_TILE - 1) / SCAN_TILE : 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -127,6 +128,7 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
     L->sort_status = take((size_t)L->npass * nstag * L->ntiles * R * sizeof(uint32_t));
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
+    L->scan_status = take((size_t)nstag * L->npass * L->nscan_tiles * sizeof(uint32_t));
     L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
     L->tile_count = take((size_t)L->sp_tiles * sizeof(uint32_t));
@@ -245,6 +247,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     d.hist = (uint32_t*)(base + L.hist);
     d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
+    d.scan_status = (uint32_t*)(base + L.scan_status);
     d.counters = (uint32_t*)(base + L.counters);
     d.flag = (uint32_t*)(base + L.flag);
     d.zero_begin = (uint32_t*)(base + L.zero_begin);
@@ -253,6 +256,8 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     p->sa.rbits = L.rbits;
     p->sa.ntiles = L.ntiles;
     p->sa.nseg_tiles = L.nseg_tiles;
+    p->sa.nscan_tiles = L.nscan_tiles;
+    p->sa.scanned = 1;
     const bool in_a = (npts == 0) || (L.npass & 1);
     p->sorted_keys = in_a ? d.kA : d.kB;
     p->perm = in_a ? d.vA : d.vB;

@@ -80,6 +80,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         BatchJob& b = hj[j];
         std::memset(&b, 0, sizeof b);
         b.sa = p.sa;
+        b.sa.scanned = 0;  // batched passes sort by one-sweep look-back (digit histograms)
         // All error flags of the batch sit in the table, so one copy reads them back.
         b.sa.d.flag = flags_dev + j;
         OpArgs& a = b.op;

@@ -31,10 +31,10 @@ size_t align_up(size_t v);
 // Byte layout of one plan's workspace.
 struct Layout {
     int nstag, npass, rbits, rows, nbx;
-    int64_t ntiles, nseg_tiles, G;
+    int64_t ntiles, nseg_tiles, nscan_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Fs, Us, partial, zero_begin, hist,
-        sort_status, seg_status, counters, flag, tile_count, zero_end, total;
+        sort_status, seg_status, scan_status, counters, flag, tile_count, zero_end, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

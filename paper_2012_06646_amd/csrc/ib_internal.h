@@ -15,6 +15,8 @@ constexpr int SORT_BLOCK = 256;
 #endif
 constexpr int SORT_IPT = IBK_SORT_IPT;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
+constexpr int SCAN_VPT = 16;                      // counts per thread of the count scan
+constexpr int SCAN_TILE = SORT_BLOCK * SCAN_VPT;  // counts per scan block
 constexpr int MAX_RADIX_BITS = 8;
 
 // Look-back status words: 2 flag bits over a 30-bit count.
@@ -41,6 +43,7 @@ struct PlanDev {
     int32_t* seg_off;      // [nstag][n + 1]
     int32_t* q;            // [nstag]
     uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
+    uint32_t* scan_status; // [nstag][npass][nscan_tiles] look-back words of the count scans
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
     void* Fs;              // [n][ncomp] forces in that order (filled by each spread call)
     void* Us;              // [n][2] interpolation: the first components in that order
@@ -97,6 +100,8 @@ struct SortArgs {
     int rbits;
     int64_t ntiles;        // sort tiles per stagger
     int64_t nseg_tiles;    // segment tiles per stagger
+    int64_t nscan_tiles;   // scan tiles of one pass's digit-major tile counts
+    int scanned;           // radix passes: count, scan, scatter (else one-sweep look-back)
 };
 
 struct OpArgs {

@@ -72,7 +72,8 @@ __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict
                     stride *= g.n[k];
                 }
                 a.d.keys0[(int64_t)s * n + j] = key;
-                for (int p = 0; p < a.npass; ++p)
+                if (!a.scanned)  // one-sweep passes take digit histograms from here
+                    for (int p = 0; p < a.npass; ++p)
                     atomicAdd(&lhist[((s - s0) * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
             }
             any_bad |= bad;
@@ -81,8 +82,9 @@ __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict
     if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
     __syncthreads();
     uint32_t* gh = a.d.hist + (size_t)s0 * a.npass * R;
-    for (int i = threadIdx.x; i < nh; i += blockDim.x)
-        if (lhist[i]) atomicAdd(&gh[i], lhist[i]);
+    if (!a.scanned)
+        for (int i = threadIdx.x; i < nh; i += blockDim.x)
+            if (lhist[i]) atomicAdd(&gh[i], lhist[i]);
 }
 
 template <typename T>
@@ -130,7 +132,10 @@ __device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t st
 }
 
 // ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
-template <int RBITS>
+// SCANNED: tile = block, and each digit's destination base for this tile comes from the
+// scanned digit-major tile counts (radix_count_kernel + radix_scan_kernel) instead of the
+// digit histogram plus a look-back over earlier tiles.  Both give the same stable order.
+template <int RBITS, bool SCANNED = false>
 __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pass)
 {
     constexpr int R = 1 << RBITS;
@@ -145,16 +150,20 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
     __shared__ uint32_t s_ticket;
 
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
+    if (!SCANNED && tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
     for (int i = tid; i < NW * R; i += SORT_BLOCK) (&s_wcnt[0][0])[i] = 0u;
     __syncthreads();
 
     const int64_t n = a.g.npts;
-    const int64_t t = s_ticket;
+    const int64_t t = SCANNED ? (int64_t)blockIdx.x : (int64_t)s_ticket;
     const int64_t base = t * SORT_TILE;
     const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
-    // The digit's global count, loaded now so its latency overlaps the ranking.
-    const uint32_t gcount = tid < R ? a.d.hist[((int64_t)s * a.npass + pass) * R + tid] : 0u;
+    // The digit's global count (one-sweep) or this tile's destination base for the digit
+    // (scanned), loaded now so its latency overlaps the ranking.
+    const uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
+    const uint32_t gcount = tid >= R ? 0u
+                            : SCANNED ? counts[(int64_t)tid * a.ntiles + t]
+                                      : a.d.hist[((int64_t)s * a.npass + pass) * R + tid];
 
     // Source and destination: pass 0 reads the unsorted keys and generates the indices.
     const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
@@ -206,15 +215,23 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
     }
     uint32_t tot;
     const uint32_t tstart = block_excl_scan_u32<SORT_BLOCK>(tid < R ? cnt : 0u, s_scan, &tot);
-    const uint32_t gbase = block_excl_scan_u32<SORT_BLOCK>(tid < R ? gcount : 0u, s_scan, &tot);
-    if (tid < R) {
-        s_tstart[tid] = tstart;
-        s_gbase[tid] = gbase;
-        // Look-back column of this digit: tile-major, digit-minor words.
-        uint32_t* col = a.d.sort_status +
-                        (((int64_t)s * a.npass + pass) * a.ntiles) * R + tid;
-        const uint32_t excl = lookback_strided(col, R, t, cnt, a.d.flag);
-        s_excl[tid] = excl;
+    if (SCANNED) {
+        if (tid < R) {
+            s_tstart[tid] = tstart;
+            s_gbase[tid] = gcount;
+            s_excl[tid] = 0u;
+        }
+    } else {
+        const uint32_t gbase = block_excl_scan_u32<SORT_BLOCK>(tid < R ? gcount : 0u, s_scan, &tot);
+        if (tid < R) {
+            s_tstart[tid] = tstart;
+            s_gbase[tid] = gbase;
+            // Look-back column of this digit: tile-major, digit-minor words.
+            uint32_t* col = a.d.sort_status +
+                            (((int64_t)s * a.npass + pass) * a.ntiles) * R + tid;
+            const uint32_t excl = lookback_strided(col, R, t, cnt, a.d.flag);
+            s_excl[tid] = excl;
+        }
     }
     __syncthreads();
 
@@ -245,6 +262,82 @@ template <int RBITS>
 __global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int s, int pass)
 {
     radix_pass_body<RBITS>(a, s, pass);
+}
+
+template <int RBITS>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_scatter_kernel(SortArgs a, int s, int pass)
+{
+    radix_pass_body<RBITS, true>(a, s, pass);
+}
+
+// ---- scanned passes: per-tile digit counts, then one exclusive scan over them ---------
+// Counts are stored digit-major, counts[digit][tile], so the exclusive scan of the whole
+// array is, for each (digit, tile), the position of the tile's first key of that digit in
+// the pass's output: all keys of smaller digits, then those of the digit in earlier tiles.
+template <int RBITS>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_count_kernel(SortArgs a, int s, int pass)
+{
+    constexpr int R = 1 << RBITS;
+    __shared__ uint32_t s_cnt[R];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < R; i += SORT_BLOCK) s_cnt[i] = 0u;
+    __syncthreads();
+    const int64_t n = a.g.npts;
+    const int64_t t = blockIdx.x;
+    const int64_t base = t * SORT_TILE;
+    const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
+    const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
+    srck += (int64_t)s * n;
+    const int shift = pass * RBITS;
+    int32_t key[SORT_IPT];
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int li = k * SORT_BLOCK + tid;
+        key[k] = li < nvalid ? srck[base + li] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k)
+        if (k * SORT_BLOCK + tid < nvalid) atomicAdd(&s_cnt[((uint32_t)key[k] >> shift) & (R - 1)], 1u);
+    __syncthreads();
+    uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
+    for (int d = tid; d < R; d += SORT_BLOCK) counts[(int64_t)d * a.ntiles + t] = s_cnt[d];
+}
+
+// In-place exclusive scan of the R * ntiles counts of one pass: SCAN_TILE counts per block,
+// blocks in ticket order, the prefix over earlier blocks by look-back.
+__global__ __launch_bounds__(SORT_BLOCK) void radix_scan_kernel(SortArgs a, int s, int pass)
+{
+    __shared__ uint32_t s_scan[SORT_BLOCK / 64 + 1];
+    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_excl;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
+    __syncthreads();
+    const int64_t t = s_ticket;
+    const int64_t R = int64_t(1) << a.rbits;
+    const int64_t V = R * a.ntiles;
+    uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
+    const int64_t first = t * SCAN_TILE + (int64_t)tid * SCAN_VPT;
+    uint32_t v[SCAN_VPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_VPT; ++k) {
+        v[k] = first + k < V ? counts[first + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t btot;
+    const uint32_t excl = block_excl_scan_u32<SORT_BLOCK>(sum, s_scan, &btot);
+    if (tid == 0) {
+        uint32_t* chain = a.d.scan_status + ((int64_t)s * a.npass + pass) * a.nscan_tiles;
+        s_excl = lookback_strided(chain, 1, t, btot, a.d.flag);
+    }
+    __syncthreads();
+    uint32_t run = s_excl + excl;
+#pragma unroll
+    for (int k = 0; k < SCAN_VPT; ++k) {
+        if (first + k < V) counts[first + k] = run;
+        run += v[k];
+    }
 }
 
 // ---- segments: run heads, q, seg_off and the cell-block start table -------------------
@@ -514,7 +607,26 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
                                hipStream_t st)
 {
     const GeomArgs& g = a.g;
-    if (g.npts > 0) {
+    if (g.npts > 0 && a.scanned) {
+        const unsigned tiles = (unsigned)a.ntiles, sblocks = (unsigned)a.nscan_tiles;
+        for (int p = 0; p < a.npass; ++p) {
+            switch (a.rbits) {
+#define IBK_SCANNED_PASS(B)                                                                        \
+    case B:                                                                                        \
+        hipLaunchKernelGGL(radix_count_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p);   \
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(sblocks), dim3(SORT_BLOCK), 0, st, a, s, p);     \
+        hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); \
+        break;
+            IBK_SCANNED_PASS(4)
+            IBK_SCANNED_PASS(5)
+            IBK_SCANNED_PASS(6)
+            IBK_SCANNED_PASS(7)
+            IBK_SCANNED_PASS(8)
+#undef IBK_SCANNED_PASS
+            default: return hipErrorInvalidValue;
+            }
+        }
+    } else if (g.npts > 0) {
         const unsigned tiles = (unsigned)a.ntiles;
         for (int p = 0; p < a.npass; ++p) {
             switch (a.rbits) {

@@ -131,6 +131,53 @@ __device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t st
     return excl;
 }
 
+// The same over a chain of stride 1, walked by a whole wave: each round reads the words of
+// up to 64 earlier tiles at once and stops at the nearest one that holds an inclusive
+// prefix, so a chain of k tiles takes about k / 64 rounds instead of k reads one after
+// another.  Called by all 64 lanes of one wave; returns the exclusive prefix in every lane.
+__device__ __forceinline__ uint32_t lookback_wave(uint32_t* chain, int64_t t, uint32_t mine,
+                                                  uint32_t* flag)
+{
+    const int lane = lane_id();
+    if (t == 0) {
+        if (lane == 0)
+            __hip_atomic_store(&chain[0], LB_INC | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0u;
+    }
+    if (lane == 0)
+        __hip_atomic_store(&chain[t], LB_AGG | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    int64_t j = t - 1;  // newest tile of the window; lane l reads tile j - l
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t idx = j - lane;
+        // before tile 0: an inclusive prefix of 0, which ends the walk
+        const uint32_t v = idx >= 0 ? __hip_atomic_load(&chain[idx], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                    : LB_INC;
+        const uint32_t f = v & ~LB_MASK;
+        const unsigned long long inc = __ballot(f == LB_INC);
+        const unsigned long long pending = __ballot(f == 0u);
+        const int stop = inc ? __ffsll((long long)inc) - 1 : 63;  // nearest inclusive prefix
+        const unsigned long long upto = stop == 63 ? ~0ull : ((2ull << stop) - 1ull);
+        if (pending & upto) {  // a tile in the window has not published yet
+            if (++spins > (1u << 22)) {  // never expected; keep the kernel finite
+                if (lane == 0) atomicOr(flag, FLAG_LOOKBACK_STALL);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_last_u32(wave_incl_scan_u32(lane <= stop ? (v & LB_MASK) : 0u));
+        if (inc) break;
+        j -= 64;
+    }
+    if (lane == 0)
+        __hip_atomic_store(&chain[t], LB_INC | (excl + mine), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
 // ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
 // SCANNED: tile = block, and each digit's destination base for this tile comes from the
 // scanned digit-major tile counts (radix_count_kernel + radix_scan_kernel) instead of the
@@ -327,9 +374,10 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_scan_kernel(SortArgs a, int 
     }
     uint32_t btot;
     const uint32_t excl = block_excl_scan_u32<SORT_BLOCK>(sum, s_scan, &btot);
-    if (tid == 0) {
+    if (wave_id() == 0) {
         uint32_t* chain = a.d.scan_status + ((int64_t)s * a.npass + pass) * a.nscan_tiles;
-        s_excl = lookback_strided(chain, 1, t, btot, a.d.flag);
+        const uint32_t e = lookback_wave(chain, t, btot, a.d.flag);
+        if (lane_id() == 0) s_excl = e;
     }
     __syncthreads();
     uint32_t run = s_excl + excl;
@@ -423,20 +471,27 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
     }
     if (lane == 0) s_wtot[w] = wrun;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
+    if (w == 0) {  // the whole first wave walks the look-back chain
+        uint32_t wt[NW], run = 0;
+#pragma unroll
         for (int v = 0; v < NW; ++v) {
-            const uint32_t c = s_wtot[v];
-            s_wtot[v] = run;
-            run += c;
+            wt[v] = s_wtot[v];
+            run += wt[v];
         }
         uint32_t* chain = a.d.seg_status + (int64_t)s * a.nseg_tiles;
-        const uint32_t excl = lookback_strided(chain, 1, t, run, a.d.flag);
-        s_excl = excl;
-        if (t == a.nseg_tiles - 1) {
-            const uint32_t q = excl + run;
-            a.d.q[s] = (int32_t)q;
-            seg[q] = (int32_t)n;
+        const uint32_t excl = lookback_wave(chain, t, run, a.d.flag);
+        if (lane == 0) {
+            uint32_t r = 0;
+            for (int v = 0; v < NW; ++v) {
+                s_wtot[v] = r;
+                r += wt[v];
+            }
+            s_excl = excl;
+            if (t == a.nseg_tiles - 1) {
+                const uint32_t q = excl + run;
+                a.d.q[s] = (int32_t)q;
+                seg[q] = (int32_t)n;
+            }
         }
     }
     // The last tile fills the table entries after the last key with n.

@@ -5,13 +5,16 @@
 // that groups equal keys, the count of distinct keys and where each run starts (Fig. 2).
 // The sort is stable, so the permutation is unique: ties keep input order.
 //
-// gfx950 design: every distinct staggering of the grid is sorted in the same launches
-// (one tile queue across staggerings).  Each radix pass is a single kernel: tiles of 4096
-// keys take a ticket from an atomic counter, rank their keys stably within the tile with
-// wave64 ballots, publish per-digit tile counts, and obtain the exclusive prefix over all
-// earlier tiles by decoupled look-back; keys are then staged in LDS in digit order so the
-// global writes are contiguous runs.  Digit histograms for every pass are accumulated by
-// the key kernel in the same sweep over X.  Only ceil(log2(#cells)) key bits are sorted.
+// gfx950 design.  Only ceil(log2(#cells)) key bits are sorted, in passes of at most 8 bits,
+// over tiles of SORT_TILE (2048) keys.  Within a tile, keys are ranked stably with wave64
+// ballots and staged in LDS in digit order, so the global writes are contiguous runs per
+// digit.  Where a tile's run of a digit goes comes from one of two schemes:
+//   plans    three launches per pass: per-tile digit counts stored digit-major, one
+//            exclusive scan over them (its blocks chained by a wave-parallel look-back),
+//            and the ranked scatter;
+//   batches  one launch per pass ("one-sweep"): digit histograms of every pass from the
+//            keys kernel, and per digit a decoupled look-back over the earlier tiles.
+// Both give the same permutation.
 #include "device_common.h"
 
 namespace ibk {
@@ -303,12 +306,6 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
             dstv[dst] = s_val[i];
         }
     }
-}
-
-template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_pass_kernel(SortArgs a, int s, int pass)
-{
-    radix_pass_body<RBITS>(a, s, pass);
 }
 
 template <int RBITS>
@@ -662,7 +659,7 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
                                hipStream_t st)
 {
     const GeomArgs& g = a.g;
-    if (g.npts > 0 && a.scanned) {
+    if (g.npts > 0) {  // plans sort with scanned passes
         const unsigned tiles = (unsigned)a.ntiles, sblocks = (unsigned)a.nscan_tiles;
         for (int p = 0; p < a.npass; ++p) {
             switch (a.rbits) {
@@ -678,18 +675,6 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
             IBK_SCANNED_PASS(7)
             IBK_SCANNED_PASS(8)
 #undef IBK_SCANNED_PASS
-            default: return hipErrorInvalidValue;
-            }
-        }
-    } else if (g.npts > 0) {
-        const unsigned tiles = (unsigned)a.ntiles;
-        for (int p = 0; p < a.npass; ++p) {
-            switch (a.rbits) {
-            case 4: hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
-            case 5: hipLaunchKernelGGL(radix_pass_kernel<5>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
-            case 6: hipLaunchKernelGGL(radix_pass_kernel<6>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
-            case 7: hipLaunchKernelGGL(radix_pass_kernel<7>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
-            case 8: hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); break;
             default: return hipErrorInvalidValue;
             }
         }

@@ -387,3 +387,29 @@ def test_interp_tiles_ragged_grid(ib, orc, dtype, kernel):
     U2 = p.interpolate_advect(ud, X2, dt)
     torch.cuda.synchronize()
     assert torch.equal(U2, U) and torch.equal(X1, X2)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_thin_slab_grid(ib, orc, dtype):
+    """A 256 x 256 x 4 slab: four cells in z, fewer than an interpolation tile (8) or a
+    spreading tile (13) spans, so staged regions and stencils wrap around z more than once.
+    Dense enough for the tiled interpolation (256 tiles); both operators against the oracle,
+    and interpolation bit for bit against the gather path of a sparse subset."""
+    g = wl.grid(3, [256, 256, 4], [1.0, 1.0, 4.0 / 256])
+    n = 300000
+    X, F, u = wl.uniform_case(g, n, 91)
+    nd = _np_dtype(dtype)
+    Xc, Fc, uc = X.astype(nd), F.astype(nd), u.astype(nd)
+    say(f"thin slab grid={g['n']} n={n} dtype={dtype}")
+    ud = to_dev(uc, dtype)
+    p = ib.Plan(g, n, dtype).update(to_dev(Xc, dtype))
+    f = p.spread(to_dev(Fc, dtype))
+    U = p.interpolate(ud)
+    torch.cuda.synchronize()
+    assert p.status() == 0
+    X64 = Xc.astype(np.float64)
+    assert normwise(to_host(f), orc.spread(g, X64, Fc.astype(np.float64))) <= TOL[dtype]
+    assert normwise(to_host(U), orc.interp(g, X64, uc.astype(np.float64))) <= TOL[dtype]
+    m = 3000
+    p_small = ib.Plan(g, m, dtype).update(to_dev(Xc[:m], dtype))
+    assert torch.equal(p_small.interpolate(ud), U[:m])

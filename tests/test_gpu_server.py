@@ -82,6 +82,28 @@ def test_server_small_arena_wraps(ib, graph):
         assert torch.equal(jobs[j]["f"], f1) and torch.equal(jobs[j]["U"], U1)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_server_dense_jobs_tiled(ib, graph):
+    """Dense jobs interpolate through LDS tiles inside batches (also in the slot graphs),
+    mixed with sparse jobs that gather: bit for bit against the jobs run alone."""
+    dtype = torch.float32
+    jobs = []
+    for i, (N, n) in enumerate([(96, 120000), (32, 2000), (96, 100000), (48, 5000), (96, 150000)]):
+        g = wl.grid(3, N, 1.0)
+        X, F, u = wl.uniform_case(g, n, 6400 + i)
+        jobs.append({"grid": g, "X": to_dev(X, dtype), "F": to_dev(F, dtype), "u": to_dev(u, dtype),
+                     "f": torch.empty(wl.grid_shape(g), dtype=dtype, device="cuda"),
+                     "U": torch.empty((n, 3), dtype=dtype, device="cuda")})
+    say(f"server dense jobs graph={graph}")
+    srv = ib.Server(dtype, arena_bytes=512 << 20, max_jobs_per_batch=8, use_graph=graph)
+    out = run_all(srv, jobs)
+    srv.close()
+    assert all(s == 0 for s, _ in out)
+    for j, job in enumerate(jobs):
+        f1, U1 = alone(ib, job, dtype)
+        assert torch.equal(job["f"], f1) and torch.equal(job["U"], U1), f"job {j}"
+
+
 def test_server_rejects_and_flags(ib):
     dtype = torch.float32
     jobs = serving_jobs(3, dtype, 6200, sizes=(16,), nmax=500)

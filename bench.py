@@ -38,8 +38,8 @@ def algorithmic_bytes(npts, dim, ncomp, G, b):
 
 
 # Kernels behind each operator call (the roofline's unit is one operator call).
-OP_KERNELS = {"spread": "ib_spread = gather_rows_kernel (F into sorted order) + spread_kernel",
-              "interp_advect": "ib_interpolate_advect = interp_kernel with the position update"}
+OP_KERNELS = {"spread": "ib_spread = spread_kernel (forces read through the permutation)",
+              "interp_advect": "ib_interpolate_advect = interp_tile_kernel with the position update"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_128cube_1e6pts.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2012_06646_amd", "csrc", f)
                   for f in ("ops_kernels.hip", "device_common.h", "ib_internal.h")]

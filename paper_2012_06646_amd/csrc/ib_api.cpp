@@ -110,7 +110,6 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->q = take((size_t)nstag * sizeof(int32_t));
     const size_t b = dtype == IB_F64 ? 8 : 4;
     L->Xs = take((size_t)n * g->dim * b);
-    L->Fs = take((size_t)n * g->ncomp * b);
     L->Us = take(g->dim == 3 ? (size_t)n * 2 * b : 0);
     int tiles[3];
     // ib_tuning.spread_tile: 0 = the built-in shape of the precision, k = shape k - 1.
@@ -240,7 +239,6 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     d.seg_off = (int32_t*)(base + L.seg_off);
     d.q = (int32_t*)(base + L.q);
     d.Xs = base + L.Xs;
-    d.Fs = base + L.Fs;
     d.Us = base + L.Us;
     d.partial = (double*)(base + L.partial);
     d.tile_count = (uint32_t*)(base + L.tile_count);
@@ -397,7 +395,6 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->cblk = p->sa.d.cblk;
     a->X = p->X;
     a->Xs = p->sa.d.Xs;
-    a->Fs = p->sa.d.Fs;
     a->Us = p->sa.d.Us;
     a->partial = p->sa.d.partial;
     a->tile_count = p->sa.d.tile_count;

@@ -91,7 +91,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.X = J.X;
         a.Xs = p.sa.d.Xs;
         a.F = J.F;
-        a.Fs = p.sa.d.Fs;
         a.Us = p.sa.d.Us;
         a.partial = p.sa.d.partial;
         a.tile_count = p.sa.d.tile_count;
@@ -108,7 +107,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         for (int q = 0; q < BATCH_MAX_PASSES; ++q)
             counts[BS_SORT0 + q] = (n > 0 && q < sa.npass) ? (int)sa.ntiles : 0;
         counts[BS_SEG] = (int)sa.nseg_tiles;
-        counts[BS_GATHER] = J.f ? gather_blocks(n, a.g.ncomp) : 0;
         counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;
         const int itiles = J.u ? interp_tiles(a.g.dim, a.g.n, n) : 0;
         a.interp_tiled = itiles > 0;

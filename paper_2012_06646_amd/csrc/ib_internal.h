@@ -45,7 +45,6 @@ struct PlanDev {
     uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
     uint32_t* scan_status; // [nstag][npass][nscan_tiles] look-back words of the count scans
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
-    void* Fs;              // [n][ncomp] forces in that order (filled by each spread call)
     void* Us;              // [n][2] interpolation: the first components in that order
     double* partial;       // [tiles][split][tile cells] partial tile sums (split > 1 only)
     uint32_t* tile_count;  // [tiles] blocks of a split tile done (in the cleared region)
@@ -112,7 +111,6 @@ struct OpArgs {
     const void* X;               // input order
     const void* Xs;              // staggering-0 order
     const void* F;
-    void* Fs;
     void* Us;
     void* f;
     const void* u;
@@ -142,7 +140,6 @@ enum BatchStage {
     BS_KEYS,
     BS_SORT0,  // BS_SORT0 + p: radix pass p
     BS_SEG = BS_SORT0 + BATCH_MAX_PASSES,
-    BS_GATHER,
     BS_SPREAD,
     BS_INTERP,
     BS_COUNT
@@ -173,7 +170,6 @@ struct BatchLaunch {
 int reset_blocks(const SortArgs& a);
 int keys_blocks(const SortArgs& a);
 size_t keys_lds_bytes(const SortArgs& a);
-int gather_blocks(int64_t npts, int ncomp);
 int interp_blocks(int64_t npts);
 // Tiles of the LDS-staged interpolation of a 3-D plan, or 0 when its points should gather
 // directly: staging pays off with at least 256 tiles (one block each) and 200 points per tile

@@ -1,10 +1,10 @@
 // Spreading and interpolation kernels.
 //
 // Both operators visit the points in the sorted order of staggering 0 (the staggering of
-// component 0): the plan stores the positions in that order, each spread call first
-// gathers the forces into it, and interpolation writes each point's values once.  So the
-// only scattered memory accesses per call are one gather of F (spreading) and one scatter
-// of U (interpolation); everything else streams.  A point's cell for component c differs
+// component 0): the plan stores the positions in that order, spreading reads each point's
+// force through the permutation as it loads the point, and interpolation writes each
+// point's values once.  So the only scattered memory accesses per call are the force reads
+// (spreading) and one scatter of U (interpolation); everything else streams.  A point's cell for component c differs
 // from its staggering-0 cell by at most one per dimension, so the tiles below widen their
 // halos by that offset.
 //
@@ -298,7 +298,8 @@ struct SpreadTile {
             key = sk[j];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
-            F = ((const T*)a.Fs)[j * a.g.ncomp + c];
+            // the force of the point, read through the permutation (its input-order row)
+            F = ((const T*)a.F)[clamp_index(a.perm[j], a.g.npts) * a.g.ncomp + c];
         }
     }
 
@@ -576,30 +577,6 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(spread_waves_per_eu<T, TX, TY, TZ>()))) void spread_kernel(OpArgs a)
 {
     spread_body<T, DIM, KERN, TX, TY, TZ>(a, blockIdx.x);
-}
-
-// Forces into the sorted order of staggering 0 (one gather of whole rows).
-template <typename T>
-__device__ __forceinline__ void gather_rows_body(int64_t n, int ncols, const int32_t* __restrict__ perm,
-                                 const T* __restrict__ src, T* __restrict__ dst, int bid, int nblk)
-{
-    // One element per thread and step: the threads of a row read its contiguous values, and
-    // the writes are fully coalesced.
-    const int64_t total = n * ncols;
-    for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total; e += (int64_t)nblk * blockDim.x) {
-        const int64_t i = e / ncols;
-        const int k = (int)(e - i * ncols);
-        dst[e] = src[clamp_index(perm[i], n) * ncols + k];
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int ncols,
-                                                          const int32_t* __restrict__ perm,
-                                                          const T* __restrict__ src,
-                                                          T* __restrict__ dst)
-{
-    gather_rows_body<T>(n, ncols, perm, src, dst, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1052,10 +1029,6 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 {
-    const int gb = gather_blocks(a.g.npts, a.g.ncomp);
-    if (gb > 0)
-        hipLaunchKernelGGL(gather_rows_kernel<T>, dim3(gb), dim3(256), 0, st, a.g.npts, a.g.ncomp,
-                           a.perm, (const T*)a.F, (T*)a.Fs);
     spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles);
     const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split);
     if (a.g.dim == 3) {
@@ -1105,20 +1078,6 @@ __device__ __forceinline__ int batch_job_of(const int32_t* starts, int njobs, in
     return lo;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void batch_gather_kernel(const BatchJob* __restrict__ jobs,
-                                                                const BatchTable* __restrict__ bt)
-{
-    const int32_t* st = bt->starts[BS_GATHER];
-    const int nj = bt->njobs, total = st[nj];
-    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        const int j = batch_job_of(st, nj, vb);
-        const OpArgs& a = jobs[j].op;
-        gather_rows_body<T>(a.g.npts, a.g.ncomp, a.perm, (const T*)a.F, (T*)a.Fs, vb - st[j],
-                            st[j + 1] - st[j]);
-    }
-}
-
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     spread_waves_per_eu<T, TX, TY, TZ>()))) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
@@ -1161,9 +1120,6 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
     constexpr int S = builtin_spread_shape(sizeof(T) == 4 ? IB_F32 : IB_F64);
     constexpr int TX = DIM == 3 ? SP_SHAPE[S][0] : SP2_TX, TY = DIM == 3 ? SP_SHAPE[S][1] : SP2_TY;
     constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
-    if (b.grid[BS_GATHER] > 0)
-        hipLaunchKernelGGL(batch_gather_kernel<T>, dim3(b.grid[BS_GATHER]), dim3(256), 0, st, b.jobs,
-                           b.table);
     if (b.grid[BS_SPREAD] > 0)
         hipLaunchKernelGGL((batch_spread_kernel<T, DIM, KERN, TX, TY, TZ>), dim3(b.grid[BS_SPREAD]),
                            dim3(256), 0, st, b.jobs, b.table);
@@ -1182,12 +1138,6 @@ void batch_ops_by_shape(const BatchLaunch& b, hipStream_t st)
              : batch_ops_dispatch<T, 2, IB_KERNEL_PESKIN4>(b, st);
 }
 }  // namespace
-
-int gather_blocks(int64_t npts, int ncomp)
-{
-    const int64_t nel = npts * ncomp;
-    return nel > 0 ? (int)min((int64_t)8192, (nel + 255) / 256) : 0;
-}
 
 int interp_blocks(int64_t npts)
 {

@@ -445,14 +445,17 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     __shared__ typename ST::WaveScratch scratch[4];
     const GeomArgs& g = a.g;
     // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
-    // chunk of its points and add their partial tiles at the end.
+    // chunk of its points and add their partial tiles at the end.  Tiles are numbered with
+    // the component fastest, then x, y, z: the components of one region, and neighbouring
+    // regions, run close together and (through xcd_block) on one XCD, so the points and
+    // forces that their source frames share are read from HBM once and then from that L2.
     const int split = g.split;
     const int tile_id = bid / split, ksub = bid - tile_id * split;
     int b = tile_id;
+    const int c = b % g.ncomp; b /= g.ncomp;
     const int bx = b % a.tiles[0]; b /= a.tiles[0];
     const int by = b % a.tiles[1]; b /= a.tiles[1];
-    const int bz = b % a.tiles[2]; b /= a.tiles[2];
-    const int c = b;
+    const int bz = b;
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
@@ -576,7 +579,7 @@ template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(spread_waves_per_eu<T, TX, TY, TZ>()))) void spread_kernel(OpArgs a)
 {
-    spread_body<T, DIM, KERN, TX, TY, TZ>(a, blockIdx.x);
+    spread_body<T, DIM, KERN, TX, TY, TZ>(a, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------------------

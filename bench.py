@@ -140,6 +140,75 @@ def rbc_bench(torch, ibops, wl, K):
             "stage_ms": stage, "spread_hbm_frac": round(spread_gbs / HBM_PEAK_GBS, 4)}
 
 
+# The paper's own per-call GPU times for this test (one K80 die, FP64, 2^16 points, seconds),
+# from the grid-refinement table of Sec. 4.1.1: interpolation (Alg. 3) and spreading by
+# sort + segmented reduce (Alg. 4) and with pre-allocated buffers (Alg. 5, its fastest).
+PAPER_K80_S = {16: (0.01253, 0.03930, 0.01715), 32: (0.01317, 0.04020, 0.02049),
+               64: (0.01722, 0.04215, 0.02370), 128: (0.01816, 0.04755, 0.03656)}
+
+
+def unstructured_bench(torch, ibops, wl, K):
+    """The paper's unstructured-point test (Sec. 4.1), FP64: random points tethered to their
+    initial positions in a 16 um periodic box with a shear-like flow; per step, the velocity
+    is interpolated twice and the tether force spread once (two plan updates).  Times per
+    call, from events around every call of K steps: the grid-refinement series at 2^16
+    points and the weak-scaling series on the 64^3 grid."""
+    from paper_2012_06646_amd.unstructured import TetheredPoints
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cases = [(N, 1 << 16) for N in wl.UNSTRUCTURED_GRIDS]
+    cases += [(wl.UNSTRUCTURED_WEAK_GRID, n) for n in wl.UNSTRUCTURED_WEAK if n != 1 << 16]
+    out = []
+    for N, n in cases:
+        g, X0, u = wl.unstructured_case(N, n)
+        t = TetheredPoints(g, torch.from_numpy(X0).to(dev), torch.from_numpy(u).to(dev), device=dev)
+        for _ in range(5):
+            t.step()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(8)] for _ in range(K)]
+        for k in range(K):
+            e = ev[k]
+            e[0].record(stream)
+            t.plan.update(t.X)
+            e[1].record(stream)
+            t.Xstar.copy_(t.X)
+            e[2].record(stream)
+            t.plan.interpolate_advect(t.u, t.Xstar, t.dt, t.U)
+            e[3].record(stream)
+            ibops.tether_force(g, t.X0, t.Xstar, t.k, t.F)
+            e[4].record(stream)
+            t.plan_star.update(t.Xstar)
+            e[5].record(stream)
+            t.plan_star.spread(t.F, t.f)
+            e[6].record(stream)
+            t.correct()
+            e[7].record(stream)
+        torch.cuda.synchronize()
+
+        def avg(i, j):
+            return float(np.mean([ev[k][i].elapsed_time(ev[k][j]) for k in range(K)])) * 1e3
+
+        row = {"grid": N, "npts": n, "h_um": 16.0 / N,
+               "step_us": round(ev[0][0].elapsed_time(ev[K - 1][7]) / K * 1e3, 2),
+               "plan_us": round(0.5 * (avg(0, 1) + avg(4, 5)), 2),
+               "interp_us": round(0.5 * (avg(2, 3) + avg(6, 7)), 2),
+               "spread_us": round(avg(5, 6), 2),
+               "plan_and_spread_us": round(avg(4, 6), 2),
+               "tether_us": round(avg(3, 4), 2),
+               "copy_us": round(avg(1, 2), 2)}
+        if n == 1 << 16 and N in PAPER_K80_S:
+            ki, ks4, ks5 = PAPER_K80_S[N]
+            row["paper_k80_us"] = {"interp_alg3": ki * 1e6, "spread_alg4": ks4 * 1e6,
+                                   "spread_alg5": ks5 * 1e6}
+        out.append(row)
+        del t
+    return {"workload": "unstructured-point test of Sec. 4.1: 16 um periodic box, MAC grid, "
+                        "u = (0, 0, 1000/s (y - 8 um)), uniform random points tied by 0.01 dyn/cm "
+                        "springs, dt = 0.1 us, FP64; per step 2 plan updates, 2 interpolations "
+                        "(with the position update), 1 tether force, 1 spread",
+            "steps": K, "cases": out}
+
+
 def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
                   rhos=(0.5, 0.8, 0.95, 1.2)):
     """The serving mix: independent FP32 jobs on {32,64,96,128}^3 MAC grids with
@@ -269,6 +338,8 @@ def main():
                     help="skip the red-blood-cell workload (256^3, 2.8 million clustered points)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the batched-serving measurement (Poisson job stream)")
+    ap.add_argument("--no-unstructured", action="store_true",
+                    help="skip the paper's unstructured-point test (Sec. 4.1 grid and weak series)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once in a HIP graph and replayed")
@@ -446,10 +517,13 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
         "rbc_256": None,
+        "paper_unstructured": None,
         "serving": None,
     }
     if not args.no_rbc:
         out["rbc_256"] = rbc_bench(torch, ibops, wl, args.steps)
+    if not args.no_unstructured:
+        out["paper_unstructured"] = unstructured_bench(torch, ibops, wl, args.steps)
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:

@@ -71,8 +71,10 @@ typedef struct ib_plan_s *ib_plan;
  *   spread_tile   3-D spreading tile (x*y*z cells owned by one block): 1 = 32x16x13,
  *                 2 = 32x8x13, 3 = 64x8x8; 0 = 32x16x13 for IB_F64 and 32x8x13 for
  *                 IB_F32 (2-D grids always use 64x32)
- *   split_points  points per block before a spreading tile is shared by several blocks
- *                 (at most 16): 0 = 2048, < 0 = never share
+ *   split_points  sharing of a spreading tile by several blocks (at most 256 per tile),
+ *                 whose partial tiles a second kernel adds in block order: > 0 = at least
+ *                 that many points per block; 0 = about 512 blocks in all, with at least
+ *                 128 points per block (batches use this rule too); < 0 = never share
  *   radix_bits    radix digit width of the key sort, 4..8: 0 = the key bits spread evenly
  *                 over the fewest passes of at most 8 bits
  * Results do not depend on the tuning beyond rounding: keys, permutations and offsets are
@@ -171,6 +173,16 @@ int32_t ib_interpolate_grad(ib_plan plan, const void *u, const void *W, void *dX
  * the box.  Errors: IB_ERR_ARG. */
 int32_t ib_advect(const ib_grid_desc *grid, int32_t dtype, int64_t npts, void *X, const void *U,
                   double dt, void *stream);
+
+/* Tether force of the unstructured-point test of Sec. 4.1 (each point tied by a Hookean
+ * spring of constant k to its initial position): F_{j,c} = k d_{j,c}, where d = X0 - X per
+ * coordinate, moved by one box length into [-length_c / 2, length_c / 2) when it lies
+ * outside (the nearest periodic image; exact for displacements below half a box).
+ * X0, X (npts x dim) and F (npts x ncomp, overwritten) are device arrays of the dtype, with
+ * ncomp == dim; grid supplies dim and the box.  Errors: IB_ERR_ARG (k not finite, ncomp !=
+ * dim, null pointers with npts > 0), and the descriptor checks of ib_advect. */
+int32_t ib_tether_force(const ib_grid_desc *grid, int32_t dtype, int64_t npts, const void *X0,
+                        const void *X, double k, void *F, void *stream);
 
 /* ---- batches of independent jobs ---------------------------------------------------- */
 

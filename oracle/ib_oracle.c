@@ -18,7 +18,9 @@
  *     Sec. 2: U_j = sum_i delta_h(x_i - X_j) u_i h^d and f_i = sum_j delta_h(x_i - X_j) F_j,
  *     where F_j already carries the Lagrangian weight dtheta_j;
  *   - sort keys and the stable key/index sort of Alg. 4 (Sec. 3.3), keys numbered
- *     x-fastest as in Fig. 2, counted from 0.
+ *     x-fastest as in Fig. 2, counted from 0;
+ *   - the position update X + dt U of the IB time step (Sec. 2), rounded once and wrapped
+ *     into the periodic box.
  *
  * phi is evaluated from its piecewise closed form (Peskin 2002, the kernel reference of
  * Sec. 2): the 4-point kernel, or the cosine kernel the paper itself uses.
@@ -410,4 +412,23 @@ int or_interp_grad(int dim, const int *n, const double *length, int ncomp,
         for (int k = 0; k < dim; ++k) dX[j * dim + k] = (double)grad[k];
     }
     return 0;
+}
+
+/* ---- position update ------------------------------------------------------------ */
+
+/* Position update of the IB time step (Sec. 2, steps (b) and (g)): y = X + dt U per
+ * coordinate, the exact value rounded once (C99 fma), then wrapped into [0, L_k):
+ * y - L_k floor(y / L_k); a result that rounds to L_k or falls below 0 is set to 0.
+ * out: np x dim (may alias X). */
+void or_advect(int dim, const double *length, long np, const double *X, const double *U,
+               double dt, double *out)
+{
+    for (long j = 0; j < np; ++j)
+        for (int k = 0; k < dim; ++k) {
+            const double L = length[k];
+            double y = fma(dt, U[j * dim + k], X[j * dim + k]);
+            y = y - L * floor(y / L);
+            if (y >= L || y < 0.0) y = 0.0;
+            out[j * dim + k] = y;
+        }
 }

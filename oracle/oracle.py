@@ -54,6 +54,8 @@ def lib():
                                             _i64p, _dp]
         L.or_interp_grad.restype = ctypes.c_int
         L.or_interp_grad.argtypes = common + [ctypes.c_long, _dp, _dp, _dp, _dp]
+        L.or_advect.restype = None
+        L.or_advect.argtypes = [ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, ctypes.c_double, _dp]
         _lib = L
     return _lib
 
@@ -170,3 +172,39 @@ def interp_grad(grid, X, u, W):
 def mac_stagger(dim):
     """MAC staggering: component c sits at the cell centre shifted by -h e_c / 2 (Sec. 2)."""
     return [[0.0 if k == c else 0.5 for k in range(dim)] for c in range(dim)]
+
+
+def advect(grid, X, U, dt):
+    """Position update of the IB step (Sec. 2, steps (b) and (g)): X + dt U per coordinate,
+    rounded once, wrapped into [0, L_k) (a result that rounds to L_k or below 0 is set to 0).
+    U has dim columns."""
+    dim = int(grid["dim"])
+    L = np.array(grid["length"][:dim], dtype=np.float64)
+    X = _f64(X).reshape(-1, dim)
+    U = _f64(U).reshape(-1, dim)
+    out = np.empty_like(X)
+    lib().or_advect(dim, _ptr(L, _dp), X.shape[0], _ptr(X, _dp), _ptr(U, _dp), float(dt),
+                    _ptr(out, _dp))
+    return out
+
+
+def tether_force(grid, X0, X, k):
+    """Hookean tether of the unstructured-point test (Sec. 4.1): F = k (X0 - X), each
+    coordinate difference taken to its nearest periodic image, in [-L_k / 2, L_k / 2)."""
+    dim = int(grid["dim"])
+    L = np.array(grid["length"][:dim], dtype=np.float64)
+    d = _f64(X0).reshape(-1, dim) - _f64(X).reshape(-1, dim)
+    d = np.where(d >= 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+    return float(k) * d
+
+
+def unstructured_step(grid, X, X0, u, k, dt):
+    """One step of the unstructured-point test (Sec. 4.1), in the paper's order: U = J(X)u
+    and the predicted X* = X + dt U; F = k (X0 - X*) spread from X*; then the velocity at X
+    again and X + dt U.  Returns (X_next, X_star, F, f, U)."""
+    U = interp(grid, X, u)
+    Xs = advect(grid, X, U, dt)
+    F = tether_force(grid, X0, Xs, k)
+    f = spread(grid, Xs, F)
+    U2 = interp(grid, X, u)
+    return advect(grid, X, U2, dt), Xs, F, f, U2

@@ -130,7 +130,6 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->scan_status = take((size_t)nstag * L->npass * L->nscan_tiles * sizeof(uint32_t));
     L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
-    L->tile_count = take((size_t)L->sp_tiles * sizeof(uint32_t));
     L->zero_end = off;
     L->total = off;
 }
@@ -241,7 +240,6 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     d.Xs = base + L.Xs;
     d.Us = base + L.Us;
     d.partial = (double*)(base + L.partial);
-    d.tile_count = (uint32_t*)(base + L.tile_count);
     d.hist = (uint32_t*)(base + L.hist);
     d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
@@ -397,7 +395,6 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->Xs = p->sa.d.Xs;
     a->Us = p->sa.d.Us;
     a->partial = p->sa.d.partial;
-    a->tile_count = p->sa.d.tile_count;
 }
 
 int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
@@ -472,6 +469,19 @@ int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X
     if (grid->ncomp != grid->dim || !std::isfinite(dt)) return IB_ERR_ARG;
     if (npts > 0 && (!X || !U)) return IB_ERR_ARG;
     return hip_status(launch_advect(grid->dim, grid->ncomp, npts, grid->length, dtype, X, U, dt,
+                                    (hipStream_t)stream));
+}
+
+int32_t ib_tether_force(const ib_grid_desc* grid, int32_t dtype, int64_t npts, const void* X0,
+                        const void* X, double k, void* F, void* stream)
+{
+    int nstag, cs[3];
+    double sx[3][3];
+    int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
+    if (st != IB_OK) return st;
+    if (grid->ncomp != grid->dim || !std::isfinite(k)) return IB_ERR_ARG;
+    if (npts > 0 && (!X0 || !X || !F)) return IB_ERR_ARG;
+    return hip_status(launch_tether(grid->dim, npts, grid->length, dtype, X0, X, k, F,
                                     (hipStream_t)stream));
 }
 

@@ -93,7 +93,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.F = J.F;
         a.Us = p.sa.d.Us;
         a.partial = p.sa.d.partial;
-        a.tile_count = p.sa.d.tile_count;
         a.f = J.f;
         a.u = J.u;
         a.U = J.U;
@@ -108,6 +107,11 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
             counts[BS_SORT0 + q] = (n > 0 && q < sa.npass) ? (int)sa.ntiles : 0;
         counts[BS_SEG] = (int)sa.nseg_tiles;
         counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;
+        counts[BS_SPLITSUM] =
+            (J.f && a.g.split > 1)
+                ? (int)((a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp *
+                             (int64_t)spread_tile_cells(a.g.dim, a.g.sp_tile) + 255) / 256)
+                : 0;
         const int itiles = J.u ? interp_tiles(a.g.dim, a.g.n, n) : 0;
         a.interp_tiled = itiles > 0;
         counts[BS_INTERP] = J.u ? (itiles > 0 ? itiles : interp_blocks(n)) : 0;

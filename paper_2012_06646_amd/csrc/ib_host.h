@@ -34,7 +34,7 @@ struct Layout {
     int64_t ntiles, nseg_tiles, nscan_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, zero_begin, hist,
-        sort_status, seg_status, scan_status, counters, flag, tile_count, zero_end, total;
+        sort_status, seg_status, scan_status, counters, flag, zero_end, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

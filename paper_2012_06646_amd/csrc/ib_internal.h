@@ -47,7 +47,6 @@ struct PlanDev {
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
     void* Us;              // [n][2] interpolation: the first components in that order
     double* partial;       // [tiles][split][tile cells] partial tile sums (split > 1 only)
-    uint32_t* tile_count;  // [tiles] blocks of a split tile done (in the cleared region)
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
@@ -118,7 +117,6 @@ struct OpArgs {
     int accumulate;
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
     double* partial;             // split spreading: partial tile sums
-    uint32_t* tile_count;        // split spreading: arrivals per tile
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     void* Xadv;                  // interpolation: also advance these positions (or null)
     double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len
@@ -141,6 +139,7 @@ enum BatchStage {
     BS_SORT0,  // BS_SORT0 + p: radix pass p
     BS_SEG = BS_SORT0 + BATCH_MAX_PASSES,
     BS_SPREAD,
+    BS_SPLITSUM,  // partial tiles of split spreading tiles added
     BS_INTERP,
     BS_COUNT
 };
@@ -183,9 +182,13 @@ int interp_tiles(int dim, const int n[3], int64_t npts);
 constexpr int SPREAD_TILE_SHAPES = 3;
 constexpr int builtin_spread_shape(int32_t dtype) { return dtype == IB_F32 ? 1 : 0; }
 void spread_tiles(int dim, int shape, const int n[3], int tiles[3]);
-// Cells of one spreading tile, and the number of blocks that share a tile (1 .. 16) for
-// npts points over ntiles (tiles x components) tiles: a dense point set on a small grid
-// would otherwise leave most of the GPU idle.  split_points as in ib_tuning.
+// Cells of one spreading tile, and the number of blocks that share a tile (1 .. SPLIT_MAX)
+// for npts points over ntiles (tiles x components) tiles: a dense point set on a small grid
+// would otherwise leave most of the GPU idle.  split_points as in ib_tuning.  The partial
+// tiles of shared tiles are added by a second kernel, one thread per tile cell.
+constexpr int SPLIT_MAX = 256;
+constexpr int SPLIT_BLOCKS = 512;      // built-in target of blocks per spreading launch
+constexpr int SPLIT_MIN_POINTS = 128;  // built-in floor of points per block
 size_t spread_tile_cells(int dim, int shape);
 int spread_split(int64_t npts, int ntiles, int split_points);
 
@@ -206,5 +209,7 @@ hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void
                               int accumulate, hipStream_t st);
 hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
                          void* X, const void* U, double dt, hipStream_t st);
+hipError_t launch_tether(int dim, int64_t npts, const double length[3], int dtype,
+                         const void* X0, const void* X, double k, void* F, hipStream_t st);
 
 }  // namespace ibk

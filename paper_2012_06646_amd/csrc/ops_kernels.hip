@@ -30,6 +30,8 @@
 // (neighbouring lanes hold neighbouring cells, so a wave's gathers share cache lines);
 // the point's components are accumulated in registers in tensor-product order and
 // written together.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace ibk {
@@ -434,6 +436,21 @@ struct SpreadTile {
     }
 };
 
+// Component and first cell of spreading tile `tile_id`: tiles are numbered with the
+// component fastest, then x, y, z.
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ void spread_tile_at(const OpArgs& a, int tile_id, int& c, int& x0,
+                                               int& y0, int& z0)
+{
+    int b = tile_id;
+    c = b % a.g.ncomp;
+    b /= a.g.ncomp;
+    x0 = (b % a.tiles[0]) * TX;
+    b /= a.tiles[0];
+    y0 = (b % a.tiles[1]) * TY;
+    z0 = (b / a.tiles[1]) * TZ;
+}
+
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
 {
@@ -451,12 +468,8 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     // forces that their source frames share are read from HBM once and then from that L2.
     const int split = g.split;
     const int tile_id = bid / split, ksub = bid - tile_id * split;
-    int b = tile_id;
-    const int c = b % g.ncomp; b /= g.ncomp;
-    const int bx = b % a.tiles[0]; b /= a.tiles[0];
-    const int by = b % a.tiles[1]; b /= a.tiles[1];
-    const int bz = b;
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    int c, x0, y0, z0;
+    spread_tile_at<TX, TY, TZ>(a, tile_id, c, x0, y0, z0);
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
 
@@ -525,35 +538,15 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
     constexpr int CELLS = TX * TY * TZ;
     if (split > 1) {
-        // Publish this block's partial tile; the last of the tile's blocks to arrive adds
-        // the partials in block order (a fixed order) and writes the grid values.
-        __shared__ int s_last;
-        double* part = a.partial + (int64_t)tile_id * split * CELLS;
+        // Publish this block's partial tile; split_sum_kernel adds a tile's partials in
+        // block order (a fixed order) and writes the grid values.  (A last block to arrive
+        // could add them here, but its agent-scope release and acquire write back and
+        // invalidate the XCD's L2 for every block, which cost far more on this GPU.)
+        double* part = a.partial + ((int64_t)tile_id * split + ksub) * CELLS;
         for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
             const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
-            part[(int64_t)ksub * CELLS + i] = tile[(zr * TY + yr) * ST::PXS + xr + 3];
+            part[i] = tile[(zr * TY + yr) * ST::PXS + xr + 3];
         }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t prev = __hip_atomic_fetch_add(&a.tile_count[tile_id], 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            s_last = prev == (uint32_t)(split - 1);
-        }
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
-            const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
-            if (xr >= ex || yr >= ey || zr >= ez) continue;
-            double sum = 0.0;
-            for (int kk = 0; kk < split; ++kk) sum += part[(int64_t)kk * CELLS + i];
-            const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
-            const T v = (T)(sum * g.scale);
-            T* dst = f + (int64_t)c * G + gi;
-            *dst = a.accumulate ? *dst + v : v;
-        }
-        if (threadIdx.x == 0) a.tile_count[tile_id] = 0u;  // ready for the next call
         return;
     }
     for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
@@ -564,6 +557,39 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
         T* dst = f + (int64_t)c * G + gi;
         *dst = a.accumulate ? *dst + v : v;
     }
+}
+
+// Grid values of split tiles, after the spreading kernel has published every block's
+// partial tile: one thread per tile cell (i < ncells, the tiles' cells) adds the partials
+// in block order and writes the cell's value.
+template <typename T, int DIM, int TX, int TY, int TZ>
+__device__ __forceinline__ void split_sum_body(const OpArgs& a, int64_t i, int64_t ncells)
+{
+    constexpr int CELLS = TX * TY * TZ;
+    if (i >= ncells) return;
+    const GeomArgs& g = a.g;
+    const int tile_id = (int)(i / CELLS), cell = (int)(i - (int64_t)tile_id * CELLS);
+    int c, x0, y0, z0;
+    spread_tile_at<TX, TY, TZ>(a, tile_id, c, x0, y0, z0);
+    const int xr = cell % TX, yr = (cell / TX) % TY, zr = cell / (TX * TY);
+    const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
+    const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
+    if (xr >= ex || yr >= ey || zr >= ez) return;
+    const int split = g.split;
+    const double* part = a.partial + (int64_t)tile_id * split * CELLS + cell;
+    double sum = 0.0;
+    for (int kk = 0; kk < split; ++kk) sum += part[(int64_t)kk * CELLS];
+    const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
+    const T v = (T)(sum * g.scale);
+    T* dst = (T*)a.f + (int64_t)c * G + gi;
+    *dst = a.accumulate ? *dst + v : v;
+}
+
+template <typename T, int DIM, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void split_sum_kernel(OpArgs a, int64_t ncells)
+{
+    split_sum_body<T, DIM, TX, TY, TZ>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncells);
 }
 
 // Waves per SIMD a spreading kernel is compiled for.  FP32 with the 32x8x13 tile fits four
@@ -1020,6 +1046,52 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 }
 
 // ---------------------------------------------------------------------------------------
+// Tether force of the unstructured-point test (Sec. 4.1): every point hangs on a Hookean
+// spring from its initial position, F = k (X0 - X), with the difference taken to the
+// nearest periodic image of X0 (the displacement is far below half a box).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T tether_coord(T x0, T x, T k, T L)
+{
+    T d = x0 - x;
+    if (d >= T(0.5) * L) d -= L;
+    else if (d < T(-0.5) * L) d += L;
+    return k * d;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void tether_kernel(int dim, int64_t npts, T L0, T L1, T L2,
+                                                     const T* __restrict__ X0,
+                                                     const T* __restrict__ X, T k,
+                                                     T* __restrict__ F)
+{
+    const int64_t total = npts * dim;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % dim);
+        const T L = c == 0 ? L0 : (c == 1 ? L1 : L2);
+        F[i] = tether_coord(X0[i], X[i], k, L);
+    }
+}
+
+hipError_t launch_tether(int dim, int64_t npts, const double length[3], int dtype,
+                         const void* X0, const void* X, double k, void* F, hipStream_t st)
+{
+    if (npts == 0) return hipSuccess;
+    const int64_t total = npts * dim;
+    const unsigned blocks = (unsigned)min((int64_t)4096, (total + 255) / 256);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(tether_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, npts,
+                           length[0], length[1], length[2], (const double*)X0, (const double*)X,
+                           k, (double*)F);
+    else
+        hipLaunchKernelGGL(tether_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, npts,
+                           (float)length[0], (float)length[1], (float)length[2],
+                           (const float*)X0, (const float*)X, (float)k, (float*)F);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
 namespace {
@@ -1028,6 +1100,15 @@ constexpr int SP_SHAPE[SPREAD_TILE_SHAPES][3] = {{32, 16, 13}, {32, 8, 13}, {64,
 constexpr int SP2_TX = 64, SP2_TY = 32;             // spreading tile (2-D)
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T, int DIM, int TX, int TY, int TZ>
+void launch_split_sum(const OpArgs& a, hipStream_t st)
+{
+    const int64_t ncells =
+        (int64_t)a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * (TX * TY * TZ);
+    hipLaunchKernelGGL((split_sum_kernel<T, DIM, TX, TY, TZ>), dim3((unsigned)((ncells + 255) / 256)),
+                       dim3(256), 0, st, a, ncells);
+}
 
 template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
@@ -1040,6 +1121,8 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
     case i:                                                                                       \
         hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_SHAPE[i][0], SP_SHAPE[i][1], SP_SHAPE[i][2]>), \
                            dim3(nb), dim3(256), 0, st, a);                                        \
+        if (a.g.split > 1)                                                                        \
+            launch_split_sum<T, 3, SP_SHAPE[i][0], SP_SHAPE[i][1], SP_SHAPE[i][2]>(a, st);         \
         break;
             IBK_SPREAD_SHAPE(0)
             IBK_SPREAD_SHAPE(1)
@@ -1047,9 +1130,11 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 #undef IBK_SPREAD_SHAPE
         default: return hipErrorInvalidValue;
         }
-    } else
+    } else {
         hipLaunchKernelGGL((spread_kernel<T, 2, KERN, SP2_TX, SP2_TY, 1>), dim3(nb), dim3(256),
                            0, st, a);
+        if (a.g.split > 1) launch_split_sum<T, 2, SP2_TX, SP2_TY, 1>(a, st);
+    }
     return hipGetLastError();
 }
 
@@ -1116,6 +1201,23 @@ __global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* __res
     }
 }
 
+// Split-tile sums of the jobs of a batch: virtual block vb of job j covers that job's tile
+// cells 256 (vb - start) .. 256 (vb - start) + 255.
+template <typename T, int DIM, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void batch_split_sum_kernel(const BatchJob* __restrict__ jobs,
+                                                              const BatchTable* __restrict__ bt)
+{
+    const int32_t* st = bt->starts[BS_SPLITSUM];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job_of(st, nj, vb);
+        const OpArgs& a = jobs[j].op;
+        const int64_t ncells =
+            (int64_t)a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * (TX * TY * TZ);
+        split_sum_body<T, DIM, TX, TY, TZ>(a, (int64_t)(vb - st[j]) * 256 + threadIdx.x, ncells);
+    }
+}
+
 template <typename T, int DIM, int KERN>
 void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
 {
@@ -1125,6 +1227,9 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
     constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
     if (b.grid[BS_SPREAD] > 0)
         hipLaunchKernelGGL((batch_spread_kernel<T, DIM, KERN, TX, TY, TZ>), dim3(b.grid[BS_SPREAD]),
+                           dim3(256), 0, st, b.jobs, b.table);
+    if (b.grid[BS_SPLITSUM] > 0)
+        hipLaunchKernelGGL((batch_split_sum_kernel<T, DIM, TX, TY, TZ>), dim3(b.grid[BS_SPLITSUM]),
                            dim3(256), 0, st, b.jobs, b.table);
     if (b.grid[BS_INTERP] > 0)
         hipLaunchKernelGGL((batch_interp_kernel<T, DIM, KERN>), dim3(b.grid[BS_INTERP]), dim3(256), 0,
@@ -1175,14 +1280,21 @@ size_t spread_tile_cells(int dim, int shape)
     return (size_t)t[0] * t[1] * t[2];
 }
 
-// By default about 2048 points per block at least: the 128^3 grid with 10^6 points keeps
-// one block per tile, a 32^3 grid with 10^6 points gets 16.
+// With split_points > 0, at least that many points per block.  Built in: about
+// SPLIT_BLOCKS blocks in all, the most that run at once at two blocks per CU (measured best
+// from 16^3 to 64^3 grids with 2^16 to 2^19 points), but no fewer than SPLIT_MIN_POINTS
+// points per block.  The 128^3 grid keeps one block per tile up to about 10^8 points.
 int spread_split(int64_t npts, int ntiles, int split_points)
 {
     if (ntiles <= 0 || split_points < 0) return 1;
-    const int64_t per = split_points > 0 ? split_points : 2048;
-    const int64_t s = npts / ((int64_t)ntiles * per);
-    return (int)(s < 1 ? 1 : (s > 16 ? 16 : s));
+    int64_t s;
+    if (split_points > 0) {
+        s = npts / ((int64_t)ntiles * split_points);
+    } else {
+        s = (SPLIT_BLOCKS + ntiles - 1) / ntiles;
+        s = std::min(s, npts / ((int64_t)ntiles * SPLIT_MIN_POINTS));
+    }
+    return (int)(s < 1 ? 1 : (s > SPLIT_MAX ? SPLIT_MAX : s));
 }
 
 hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st)

@@ -118,10 +118,12 @@ _lib.ib_server_destroy.restype = None
 _lib.ib_server_destroy.argtypes = [_vp]
 _lib.ib_advect.restype = _i32
 _lib.ib_advect.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp]
+_lib.ib_tether_force.restype = _i32
+_lib.ib_tether_force.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64, _vp, _vp, ctypes.c_double, _vp, _vp]
 
 EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
-            "ib_advect", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
+            "ib_advect", "ib_tether_force", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
 
@@ -312,6 +314,21 @@ def advect(grid, X, U, dt, stream=None):
     _check(_lib.ib_advect(ctypes.byref(make_desc(grid)), _dtype_code(X.dtype), X.shape[0], _ptr(X),
                           _ptr(U), float(dt), _stream(stream)), "ib_advect")
     return X
+
+
+def tether_force(grid, X0, X, k, F=None, stream=None):
+    """F = k (X0 - X), per coordinate to the nearest periodic image: the Hookean tether of the
+    unstructured-point test (Sec. 4.1)."""
+    if X0.shape != X.shape or X0.dtype != X.dtype or not X0.is_contiguous() or not X.is_contiguous():
+        raise ValueError("X0 and X must be contiguous with matching shape and dtype")
+    if F is None:
+        F = torch.empty_like(X)
+    if F.shape != X.shape or F.dtype != X.dtype or not F.is_contiguous():
+        raise ValueError("F must be contiguous, with the shape and dtype of X")
+    _check(_lib.ib_tether_force(ctypes.byref(make_desc(grid)), _dtype_code(X.dtype), X.shape[0],
+                                _ptr(X0), _ptr(X), float(k), _ptr(F), _stream(stream)),
+           "ib_tether_force")
+    return F
 
 
 def spread(grid, X, F):

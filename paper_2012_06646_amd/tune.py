@@ -19,7 +19,7 @@ import torch
 from . import ibops
 
 TILE_SHAPES = {1: "32x16x13", 2: "32x8x13", 3: "64x8x8"}  # 0: built-in (FP64 1, FP32 2)
-SPLIT_CHOICES = (0, 1024, 4096, -1)    # 0: built-in (2048 points per block); -1: never split
+SPLIT_CHOICES = (0, 256, 2048, -1)     # 0: built-in (~512 blocks, >= 128 points each); -1: never split
 RADIX_CHOICES = (0, 8, 6)              # 0: built-in (even digits of at most 8 bits)
 MARGIN = 0.02                          # a candidate must be this much faster to be taken
 

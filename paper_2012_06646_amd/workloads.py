@@ -299,3 +299,41 @@ def poisson_arrivals(count, rate_per_s, seed=4001):
     """Open-loop arrival times (seconds from the start) of a Poisson stream."""
     r = rng(seed + 7)
     return np.cumsum(r.exponential(1.0 / rate_per_s, count))
+
+
+# ---- the paper's unstructured-point test (Sec. 4.1) ------------------------------------
+# Units: micrometres and microseconds; forces in dyn.  The test runs in a 16 um triply
+# periodic box with the shear-like flow u = (0, 0, rate (y - 8 um)), rate 1000 / s, and
+# points tied to their initial positions by springs of 0.01 dyn/cm.  The paper states no
+# time step for this test; 0.1 us, the step of its red-blood-cell tests, is used.
+
+UNSTRUCTURED_BOX = 16.0           # um
+UNSTRUCTURED_SHEAR = 1.0e-3       # 1000 / s in 1 / us
+UNSTRUCTURED_TETHER = 1.0e-6      # 0.01 dyn/cm in dyn / um
+UNSTRUCTURED_DT = 0.1             # us
+UNSTRUCTURED_GRIDS = (16, 32, 64, 128)  # grid points per 16 um, at 2^16 points (Sec. 4.1.1)
+# Weak scaling (Sec. 4.1.3): 2^16 .. 2^19 points on the 64^3 grid (h = 0.25 um).  The table's
+# caption says h = 0.5 um, but the text's densities (one point per 4 cells at 2^16 points, 2
+# per cell at 2^19) and the grid the paper keeps from Sec. 4.1.1 on are those of 64^3.
+UNSTRUCTURED_WEAK_GRID = 64
+UNSTRUCTURED_WEAK = (1 << 16, 1 << 17, 1 << 18, 1 << 19)
+
+
+def shear_field(g, rate=UNSTRUCTURED_SHEAR):
+    """The shear-like grid velocity on the MAC grid g: u_x = u_y = 0 and
+    u_z = rate (y - L_y / 2) at the y-coordinate (j + xi_{z,y}) h_y of every u_z node (a
+    jump at the periodic boundary y = 0)."""
+    n = [int(v) for v in g["n"]]
+    h = g["length"][1] / n[1]
+    u = np.zeros(grid_shape(g))
+    y = (np.arange(n[1]) + g["stagger"][2][1]) * h
+    u[2] = (rate * (y - 0.5 * g["length"][1]))[None, :, None]
+    return u
+
+
+def unstructured_case(N, npts, seed=6001, dtype=np.float64):
+    """npts points uniform in the 16 um box (seed 6001 unless given), the N^3 MAC grid and
+    its shear field: the initial (tether) positions X0 and the grid velocity u."""
+    g = grid(3, N, UNSTRUCTURED_BOX)
+    X0 = rng(seed).random((npts, 3)) * UNSTRUCTURED_BOX
+    return g, X0.astype(dtype), shear_field(g).astype(dtype)

@@ -179,6 +179,25 @@ def test_ops_dense_2d_split_tiles(ib, orc):
     check_ops(ib, orc, g, X, F, u, torch.float64, "dense 2-D (split tiles)")
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_split_settings_agree(ib, orc, dtype):
+    """A 16^3 grid with 16 points per cell: one block per tile, the built-in sharing (85
+    blocks per tile, summed by the second kernel) and 2048 points per block (5 blocks per
+    tile) all match the oracle; each setting is bitwise reproducible."""
+    g = wl.grid(3, 16, 1.0)
+    X, F, u = wl.uniform_case(g, 65536, 49)
+    nd = _np_dtype(dtype)
+    Xd, Fd = to_dev(X.astype(nd), dtype), to_dev(F.astype(nd), dtype)
+    ref = orc.spread(g, X.astype(nd).astype(np.float64), F.astype(nd).astype(np.float64))
+    for tuning in ({"split_points": -1}, None, {"split_points": 2048}):
+        say(f"16^3 dense, tuning {tuning} dtype={dtype}")
+        p = ib.Plan(g, X.shape[0], dtype, tuning=tuning).update(Xd)
+        f = to_host(p.spread(Fd))
+        assert p.status() == 0
+        assert normwise(f, ref) <= TOL[dtype], tuning
+        assert np.array_equal(to_host(p.spread(Fd)), f)
+
+
 def test_split_tiles_bitwise_run_to_run(ib):
     g = wl.grid(3, 32, 1.0)
     r = wl.rng(47)
@@ -190,7 +209,7 @@ def test_split_tiles_bitwise_run_to_run(ib):
     for _ in range(3):
         p.update(Xd)
         outs.append(to_host(p.spread(Fd)))
-        outs.append(to_host(p.spread(Fd)))  # a second call reuses the per-tile counters
+        outs.append(to_host(p.spread(Fd)))  # a second call rewrites the partial tiles
     for f in outs[1:]:
         assert np.array_equal(f, outs[0])
 

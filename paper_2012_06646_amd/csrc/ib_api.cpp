@@ -253,7 +253,10 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
     p->sa.ntiles = L.ntiles;
     p->sa.nseg_tiles = L.nseg_tiles;
     p->sa.nscan_tiles = L.nscan_tiles;
-    p->sa.scanned = 1;
+    // Scanned passes pay three launches per pass for a short chained step; one-sweep passes
+    // one launch, but a look-back across all tiles per digit.  Scanned from
+    // SCANNED_MIN_POINTS points up.
+    p->sa.scanned = npts >= SCANNED_MIN_POINTS ? 1 : 0;
     const bool in_a = (npts == 0) || (L.npass & 1);
     p->sorted_keys = in_a ? d.kA : d.kB;
     p->perm = in_a ? d.vA : d.vB;

@@ -15,6 +15,10 @@ constexpr int SORT_BLOCK = 256;
 #endif
 constexpr int SORT_IPT = IBK_SORT_IPT;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
+#ifndef IBK_SCANNED_MIN_POINTS
+#define IBK_SCANNED_MIN_POINTS (1 << 18)
+#endif
+constexpr int64_t SCANNED_MIN_POINTS = IBK_SCANNED_MIN_POINTS;  // plans: scanned passes from here
 constexpr int SCAN_VPT = 16;                      // counts per thread of the count scan
 constexpr int SCAN_TILE = SORT_BLOCK * SCAN_VPT;  // counts per scan block
 constexpr int MAX_RADIX_BITS = 8;

@@ -314,6 +314,14 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_scatter_kernel(SortArgs a, i
     radix_pass_body<RBITS, true>(a, s, pass);
 }
 
+// A whole pass in one launch (plans with few points): digit bases from the keys kernel's
+// histograms and a decoupled look-back over earlier tiles.
+template <int RBITS>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_onesweep_kernel(SortArgs a, int s, int pass)
+{
+    radix_pass_body<RBITS, false>(a, s, pass);
+}
+
 // ---- scanned passes: per-tile digit counts, then one exclusive scan over them ---------
 // Counts are stored digit-major, counts[digit][tile], so the exclusive scan of the whole
 // array is, for each (digit, tile), the position of the tile's first key of that digit in
@@ -659,12 +667,17 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
                                hipStream_t st)
 {
     const GeomArgs& g = a.g;
-    if (g.npts > 0) {  // plans sort with scanned passes
+    if (g.npts > 0) {  // scanned passes (three launches each) or one-sweep passes
         const unsigned tiles = (unsigned)a.ntiles, sblocks = (unsigned)a.nscan_tiles;
         for (int p = 0; p < a.npass; ++p) {
             switch (a.rbits) {
 #define IBK_SCANNED_PASS(B)                                                                        \
     case B:                                                                                        \
+        if (!a.scanned) {                                                                          \
+            hipLaunchKernelGGL(radix_onesweep_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, \
+                               p);                                                                 \
+            break;                                                                                 \
+        }                                                                                          \
         hipLaunchKernelGGL(radix_count_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p);   \
         hipLaunchKernelGGL(radix_scan_kernel, dim3(sblocks), dim3(SORT_BLOCK), 0, st, a, s, p);     \
         hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); \

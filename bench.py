@@ -209,6 +209,43 @@ def unstructured_bench(torch, ibops, wl, K):
             "steps": K, "cases": out}
 
 
+def walls_bench(torch, ibops, wl, K, dtype):
+    """The 128^3 / 10^6 workload with walls along z (a non-periodic dimension): plan update,
+    spread and interpolation per call, from events around K calls each.  The walled plan
+    runs on a grid padded by 4 ghost planes, with the caller's field copied in (zero ghost
+    values) before interpolation and out (ghost values dropped) after spreading."""
+    dev = torch.device("cuda:0")
+    g, X, F, u = wl.cube128_1m(np.float64)
+    g = dict(g, walls=4)
+    Xd, Fd, ud = (torch.from_numpy(a).to(dev, dtype) for a in (X, F, u))
+    n = X.shape[0]
+    p = ibops.Plan(g, n, dtype, dev)
+    f = torch.empty(p.grid_shape, dtype=dtype, device=dev)
+    U = torch.empty((n, 3), dtype=dtype, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        p.update(Xd)
+        p.spread(Fd, f)
+        p.interpolate(ud, U)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    for k in range(K):
+        e = ev[k]
+        e[0].record(stream)
+        p.update(Xd)
+        e[1].record(stream)
+        p.spread(Fd, f)
+        e[2].record(stream)
+        p.interpolate(ud, U)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    stage = {name: round(float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])), 5)
+             for i, name in enumerate(["plan", "spread", "interp"])}
+    return {"workload": "128^3 MAC grid, unit box walled along z (periodic x, y), 10^6 uniform "
+                        "points at their initial positions, N(0,1) forces and grid velocities",
+            "dtype": "f64" if dtype == torch.float64 else "f32", "stage_ms": stage}
+
+
 def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
                   rhos=(0.5, 0.8, 0.95, 1.2)):
     """The serving mix: independent FP32 jobs on {32,64,96,128}^3 MAC grids with
@@ -340,6 +377,8 @@ def main():
                     help="skip the batched-serving measurement (Poisson job stream)")
     ap.add_argument("--no-unstructured", action="store_true",
                     help="skip the paper's unstructured-point test (Sec. 4.1 grid and weak series)")
+    ap.add_argument("--no-walls", action="store_true",
+                    help="skip the walled-grid measurement (128^3 with walls along z)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once in a HIP graph and replayed")
@@ -518,12 +557,15 @@ def main():
         "cpu_baseline": None,
         "rbc_256": None,
         "paper_unstructured": None,
+        "walls_128": None,
         "serving": None,
     }
     if not args.no_rbc:
         out["rbc_256"] = rbc_bench(torch, ibops, wl, args.steps)
     if not args.no_unstructured:
         out["paper_unstructured"] = unstructured_bench(torch, ibops, wl, args.steps)
+    if not args.no_walls:
+        out["walls_128"] = walls_bench(torch, ibops, wl, args.steps, dtype)
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:

@@ -12,7 +12,8 @@
  *   plan           cell keys, stable key/index sort, unique-key count and segment offsets,
  *                  the preparatory steps of Alg. 4 (Sec. 3.3).
  * Grid points of component c are x = h (i + xi_c), i taken modulo n (periodic box,
- * Sec. 3.1); phi is Peskin's 4-point kernel or the cosine kernel (Sec. 2).
+ * Sec. 3.1), except along walled dimensions (ib_grid_desc.walls); phi is Peskin's 4-point
+ * kernel or the cosine kernel (Sec. 2).
  *
  * Layouts:
  *   points X, forces F, velocities U : row-major (npts x dim) and (npts x ncomp)
@@ -63,7 +64,21 @@ typedef struct {
     int32_t ncomp;            /* grid components, 1..3 (a MAC velocity grid has ncomp = dim) */
     double  stagger[3][3];    /* xi_c in [0,1)^dim per component; MAC: 0.5 - 0.5 e_c */
     int32_t kernel;           /* ib_kernel */
+    int32_t walls;            /* non-periodic dimensions: bit k set = dimension k is walled */
 } ib_grid_desc;
+
+/* Walled dimensions (the non-periodic boundaries of Sec. 3.1).  Along a walled dimension
+ * the grid points are x = h (i + xi) for i = 0 .. n_k - 1 only, with no wrap: a stencil
+ * point outside that range is no grid point (the grid indexing function # gives no index),
+ * so spreading drops its contribution and interpolation reads nothing there.  Points
+ * belong in [0, length_k); a point up to two cells outside still reaches the grid points
+ * near the wall; results for points further out are unspecified (no fault).  Positions are
+ * advanced without wrap along walled dimensions (ib_advect, ib_interpolate_advect).
+ * A walled plan runs on a periodic grid with 4 ghost indices added per walled dimension
+ * (n_k + 4; the stencil indices -2 and -1 wrap to n_k + 2 and n_k + 3), whose ghost values
+ * are dropped after spreading and zero for interpolation; ib_plan_export's keys index that
+ * padded grid.  Batches and the server take periodic jobs only (IB_ERR_UNSUPPORTED). */
+#define IB_WALL_GHOSTS 4
 
 typedef struct ib_plan_s *ib_plan;
 
@@ -168,7 +183,8 @@ int32_t ib_interpolate_grad(ib_plan plan, const void *u, const void *W, void *dX
                             int32_t accumulate, void *stream);
 
 /* Position update of the IB time step, steps (b)/(g) of Sec. 2 with the interpolated
- * velocity: X <- X + dt * U, each coordinate wrapped back into [0, length_k).  X (npts x dim)
+ * velocity: X <- X + dt * U, each coordinate of a periodic dimension wrapped back into
+ * [0, length_k) (walled dimensions: no wrap).  X (npts x dim)
  * device, updated in place; U (npts x ncomp) device with ncomp == dim; grid supplies dim and
  * the box.  Errors: IB_ERR_ARG. */
 int32_t ib_advect(const ib_grid_desc *grid, int32_t dtype, int64_t npts, void *X, const void *U,
@@ -177,7 +193,8 @@ int32_t ib_advect(const ib_grid_desc *grid, int32_t dtype, int64_t npts, void *X
 /* Tether force of the unstructured-point test of Sec. 4.1 (each point tied by a Hookean
  * spring of constant k to its initial position): F_{j,c} = k d_{j,c}, where d = X0 - X per
  * coordinate, moved by one box length into [-length_c / 2, length_c / 2) when it lies
- * outside (the nearest periodic image; exact for displacements below half a box).
+ * outside (the nearest periodic image; exact for displacements below half a box); along
+ * walled dimensions d is the plain difference.
  * X0, X (npts x dim) and F (npts x ncomp, overwritten) are device arrays of the dtype, with
  * ncomp == dim; grid supplies dim and the box.  Errors: IB_ERR_ARG (k not finite, ncomp !=
  * dim, null pointers with npts > 0), and the descriptor checks of ib_advect. */

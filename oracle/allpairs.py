@@ -34,7 +34,9 @@ def grid_points(grid, c):
 
 
 def matrix(grid, X, c):
-    """Dense S for component c: S[i, j] = prod_k h_k^-1 phi(minimum-image (x_ik - X_jk)/h_k)."""
+    """Dense S for component c: S[i, j] = prod_k h_k^-1 phi((x_ik - X_jk)/h_k), the
+    difference taken to its minimum image along periodic dimensions; along a walled
+    dimension (bit k of grid["walls"]) only the grid points 0..n_k-1 exist, unfolded."""
     dim = grid["dim"]
     kern = PHI[grid.get("kernel", "peskin4")]
     X = np.asarray(X, dtype=np.float64).reshape(-1, dim)
@@ -44,7 +46,8 @@ def matrix(grid, X, c):
         L = grid["length"][k]
         h = L / grid["n"][k]
         d = xg[:, k][:, None] - X[:, k][None, :]
-        d = d - L * np.round(d / L)
+        if not (int(grid.get("walls", 0)) >> k) & 1:
+            d = d - L * np.round(d / L)
         S *= kern(d / h) / h
     return S
 

@@ -20,7 +20,11 @@
  *   - sort keys and the stable key/index sort of Alg. 4 (Sec. 3.3), keys numbered
  *     x-fastest as in Fig. 2, counted from 0;
  *   - the position update X + dt U of the IB time step (Sec. 2), rounded once and wrapped
- *     into the periodic box.
+ *     into the periodic box;
+ *   - non-periodic ("walled") dimensions (Sec. 3.1, the grid indexing function #): a grid
+ *     index outside 0..n_k-1 of such a dimension is no grid point, so it takes no part in
+ *     spreading or interpolation, and distances along it are not folded to a periodic
+ *     image.  walls is a bit mask over dimensions (bit k set: dimension k is walled).
  *
  * phi is evaluated from its piecewise closed form (Peskin 2002, the kernel reference of
  * Sec. 2): the 4-point kernel, or the cosine kernel the paper itself uses.
@@ -163,18 +167,18 @@ long or_plan(long np, const int32_t *keys, int32_t *sorted_keys, int32_t *perm,
 /* ---- operators ------------------------------------------------------------------- */
 
 typedef struct {
-    int dim, ncomp, kernel;
+    int dim, ncomp, kernel, walls;
     int n[3];
     double length[3];
     double xi[3][3];
 } grid_t;
 
 static grid_t make_grid(int dim, const int *n, const double *length, int ncomp,
-                        const double *stagger, int kernel)
+                        const double *stagger, int kernel, int walls)
 {
     grid_t g;
     memset(&g, 0, sizeof g);
-    g.dim = dim; g.ncomp = ncomp; g.kernel = kernel;
+    g.dim = dim; g.ncomp = ncomp; g.kernel = kernel; g.walls = walls;
     for (int k = 0; k < 3; ++k) { g.n[k] = 1; g.length[k] = 1.0; }
     for (int k = 0; k < dim; ++k) { g.n[k] = n[k]; g.length[k] = length[k]; }
     for (int c = 0; c < ncomp; ++c)
@@ -195,14 +199,17 @@ static long double scaled(const grid_t *g, int k, double Xk)
     return (long double)Xk * (long double)g->n[k] / (long double)g->length[k];
 }
 
-/* Tier A weight: rho_k = (i_k + xi_k) - X_k / h_k folded to the nearest periodic image. */
+static int walled(const grid_t *g, int k) { return (g->walls >> k) & 1; }
+
+/* Tier A weight: rho_k = (i_k + xi_k) - X_k / h_k, folded to the nearest periodic image
+ * along periodic dimensions. */
 static double weight_allpairs(const grid_t *g, int c, const long *idx, const double *Xj)
 {
     double w = 1.0;
     for (int k = 0; k < g->dim; ++k) {
         long double rho = ((long double)idx[k] + g->xi[c][k]) - scaled(g, k, Xj[k]);
         long double N = g->n[k];
-        rho -= N * roundl(rho / N);
+        if (!walled(g, k)) rho -= N * roundl(rho / N);
         if (fabsl(rho) >= 2.0L) return 0.0;
         w *= or_phi(g->kernel, (double)rho);
     }
@@ -223,7 +230,8 @@ static long flatten(const grid_t *g, const long *idx)
 }
 
 /* Tier B: enumerate the 6^d candidate indices i_k = floor(X_k/h_k - xi_k) + {-2..3}
- * around point Xj, calling back with the (wrapped) flat grid index and the weight. */
+ * around point Xj, calling back with the (wrapped) flat grid index and the weight; along a
+ * walled dimension an index outside 0..n_k-1 is skipped. */
 typedef void (*visit_fn)(void *ctx, long m, double w);
 
 static void visit_stencil(const grid_t *g, int c, const double *Xj, visit_fn fn, void *ctx)
@@ -246,6 +254,7 @@ static void visit_stencil(const grid_t *g, int c, const double *Xj, visit_fn fn,
                     long i = base[k] - 2 + a[k];
                     long double rho = ((long double)i + g->xi[c][k]) - s[k];
                     if (fabsl(rho) >= 2.0L) { w = 0.0; break; }
+                    if (walled(g, k) && (i < 0 || i >= g->n[k])) { w = 0.0; break; }
                     w *= or_phi(g->kernel, (double)rho);
                     long im = i % g->n[k];
                     if (im < 0) im += g->n[k];
@@ -273,9 +282,10 @@ static void interp_visit(void *vctx, long m, double w)
  * X: np x dim row-major; F: np x ncomp row-major; f: ncomp x G (x fastest), overwritten.
  * tier 0 = all pairs, 1 = candidate stencil.  Returns 0, or -1 on allocation failure. */
 int or_spread(int dim, const int *n, const double *length, int ncomp, const double *stagger,
-              int kernel, int tier, long np, const double *X, const double *F, double *f)
+              int kernel, int walls, int tier, long np, const double *X, const double *F,
+              double *f)
 {
-    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel);
+    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel, walls);
     long G = grid_size(&g);
     long double hd = 1.0L;
     for (int k = 0; k < dim; ++k) hd *= (long double)length[k] / (long double)n[k];
@@ -307,9 +317,10 @@ int or_spread(int dim, const int *n, const double *length, int ncomp, const doub
 /* Interpolation, eq. (disc-interp) with delta_h h^d = prod phi:
  * U_{j,c} = sum_i W_{c,i,j} u_{c,i}.  u: ncomp x G; U: np x ncomp, overwritten. */
 int or_interp(int dim, const int *n, const double *length, int ncomp, const double *stagger,
-              int kernel, int tier, long np, const double *X, const double *u, double *U)
+              int kernel, int walls, int tier, long np, const double *X, const double *u,
+              double *U)
 {
-    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel);
+    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel, walls);
     long G = grid_size(&g);
     for (long j = 0; j < np; ++j) {
         const double *Xj = X + j * dim;
@@ -337,11 +348,11 @@ int or_interp(int dim, const int *n, const double *length, int ncomp, const doub
 /* Spreading evaluated only at the listed targets: out[t] = f_{comp[t], idx[t]}, each by a
  * plain loop over all points (used to check large problems at sampled grid points). */
 int or_spread_at(int dim, const int *n, const double *length, int ncomp,
-                 const double *stagger, int kernel, long np, const double *X,
+                 const double *stagger, int kernel, int walls, long np, const double *X,
                  const double *F, long nt, const int32_t *comp, const int64_t *target,
                  double *out)
 {
-    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel);
+    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel, walls);
     long double hd = 1.0L;
     for (int k = 0; k < dim; ++k) hd *= (long double)length[k] / (long double)n[k];
     for (long t = 0; t < nt; ++t) {
@@ -364,10 +375,10 @@ int or_spread_at(int dim, const int *n, const double *length, int ncomp,
  * The same routine gives the position gradient of <S(X)F, g>_h with u = g and W = F.
  * dX: np x dim, overwritten.  Candidate-stencil order. */
 int or_interp_grad(int dim, const int *n, const double *length, int ncomp,
-                   const double *stagger, int kernel, long np, const double *X,
+                   const double *stagger, int kernel, int walls, long np, const double *X,
                    const double *u, const double *W, double *dX)
 {
-    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel);
+    grid_t g = make_grid(dim, n, length, ncomp, stagger, kernel, walls);
     long G = grid_size(&g);
     for (long j = 0; j < np; ++j) {
         const double *Xj = X + j * dim;
@@ -393,6 +404,7 @@ int or_interp_grad(int dim, const int *n, const double *length, int ncomp,
                             long i = base[k] - 2 + a[k];
                             long double rho = ((long double)i + g.xi[c][k]) - s[k];
                             if (fabsl(rho) >= 2.0L) { inside = 0; break; }
+                            if (walled(&g, k) && (i < 0 || i >= g.n[k])) { inside = 0; break; }
                             ph[k] = or_phi(kernel, (double)rho);
                             dph[k] = or_dphi(kernel, (double)rho);
                             long im = i % g.n[k];
@@ -417,16 +429,20 @@ int or_interp_grad(int dim, const int *n, const double *length, int ncomp,
 /* ---- position update ------------------------------------------------------------ */
 
 /* Position update of the IB time step (Sec. 2, steps (b) and (g)): y = X + dt U per
- * coordinate, the exact value rounded once (C99 fma), then wrapped into [0, L_k):
- * y - L_k floor(y / L_k); a result that rounds to L_k or falls below 0 is set to 0.
- * out: np x dim (may alias X). */
-void or_advect(int dim, const double *length, long np, const double *X, const double *U,
-               double dt, double *out)
+ * coordinate, the exact value rounded once (C99 fma), then wrapped into [0, L_k) along
+ * periodic dimensions: y - L_k floor(y / L_k); a result that rounds to L_k or falls below
+ * 0 is set to 0.  Along walled dimensions y is left as it is.  out: np x dim (may alias X). */
+void or_advect(int dim, const double *length, int walls, long np, const double *X,
+               const double *U, double dt, double *out)
 {
     for (long j = 0; j < np; ++j)
         for (int k = 0; k < dim; ++k) {
             const double L = length[k];
             double y = fma(dt, U[j * dim + k], X[j * dim + k]);
+            if ((walls >> k) & 1) {
+                out[j * dim + k] = y;
+                continue;
+            }
             y = y - L * floor(y / L);
             if (y >= L || y < 0.0) y = 0.0;
             out[j * dim + k] = y;

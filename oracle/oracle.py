@@ -10,6 +10,7 @@ Grid description used throughout (a plain dict, independent of the product's str
     length   periodic box edge per dimension (list of dim floats); h_k = length_k / n_k
     stagger  list of ncomp staggerings xi_c (each a list of dim floats in [0, 1))
     kernel   "peskin4" or "cosine4"
+    walls    optional bit mask of non-periodic dimensions (bit k: dimension k has walls)
 """
 import ctypes
 import os
@@ -44,7 +45,7 @@ def lib():
                               _i32p]
         L.or_plan.restype = ctypes.c_long
         L.or_plan.argtypes = [ctypes.c_long, _i32p, _i32p, _i32p, _i32p]
-        common = [ctypes.c_int, _ip, _dp, ctypes.c_int, _dp, ctypes.c_int]
+        common = [ctypes.c_int, _ip, _dp, ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int]
         L.or_spread.restype = ctypes.c_int
         L.or_spread.argtypes = common + [ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
         L.or_interp.restype = ctypes.c_int
@@ -55,7 +56,8 @@ def lib():
         L.or_interp_grad.restype = ctypes.c_int
         L.or_interp_grad.argtypes = common + [ctypes.c_long, _dp, _dp, _dp, _dp]
         L.or_advect.restype = None
-        L.or_advect.argtypes = [ctypes.c_int, _dp, ctypes.c_long, _dp, _dp, ctypes.c_double, _dp]
+        L.or_advect.argtypes = [ctypes.c_int, _dp, ctypes.c_int, ctypes.c_long, _dp, _dp,
+                                ctypes.c_double, _dp]
         _lib = L
     return _lib
 
@@ -77,7 +79,7 @@ def _grid_args(grid):
         st[c, :dim] = xi
     ncomp = st.shape[0]
     kernel = KERNELS[grid.get("kernel", "peskin4")]
-    return dim, n, length, ncomp, st, kernel
+    return dim, n, length, ncomp, st, kernel, int(grid.get("walls", 0))
 
 
 def phi(r, kernel="peskin4"):
@@ -96,7 +98,7 @@ def dphi(r, kernel="peskin4"):
 
 def keys(grid, X, xi, prec="f64"):
     """Cell keys of the points X (np x dim) on the staggering xi; -1 marks invalid points."""
-    dim, n, length, _, _, _ = _grid_args(grid)
+    dim, n, length, _, _, _, _ = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     xi_a = np.zeros(3)
     xi_a[:dim] = xi
@@ -120,13 +122,13 @@ def plan(k):
 
 def spread(grid, X, F, tier=1):
     """f (ncomp x n_{d-1} x ... x n_0) from points X (np x dim) and forces F (np x ncomp)."""
-    dim, n, length, ncomp, st, kernel = _grid_args(grid)
+    dim, n, length, ncomp, st, kernel, walls = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     F = _f64(F).reshape(-1, ncomp)
     G = int(np.prod(n[:dim]))
     f = np.empty(ncomp * G, dtype=np.float64)
     rc = lib().or_spread(dim, _ptr(n, _ip), _ptr(length, _dp), ncomp, _ptr(st, _dp), kernel,
-                         tier, X.shape[0], _ptr(X, _dp), _ptr(F, _dp), _ptr(f, _dp))
+                         walls, tier, X.shape[0], _ptr(X, _dp), _ptr(F, _dp), _ptr(f, _dp))
     if rc != 0:
         raise MemoryError("oracle spread: allocation failed")
     return f.reshape([ncomp] + [int(v) for v in n[:dim][::-1]])
@@ -134,38 +136,39 @@ def spread(grid, X, F, tier=1):
 
 def interp(grid, X, u, tier=1):
     """U (np x ncomp) from grid values u (ncomp x ...)."""
-    dim, n, length, ncomp, st, kernel = _grid_args(grid)
+    dim, n, length, ncomp, st, kernel, walls = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     u = _f64(u).reshape(ncomp, -1)
     U = np.empty((X.shape[0], ncomp), dtype=np.float64)
-    lib().or_interp(dim, _ptr(n, _ip), _ptr(length, _dp), ncomp, _ptr(st, _dp), kernel, tier,
+    lib().or_interp(dim, _ptr(n, _ip), _ptr(length, _dp), ncomp, _ptr(st, _dp), kernel, walls,
+                    tier,
                     X.shape[0], _ptr(X, _dp), _ptr(u, _dp), _ptr(U, _dp))
     return U
 
 
 def spread_at(grid, X, F, comp, target):
     """Spread values at sampled (component, flat grid index) pairs, by plain loops."""
-    dim, n, length, ncomp, st, kernel = _grid_args(grid)
+    dim, n, length, ncomp, st, kernel, walls = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     F = _f64(F).reshape(-1, ncomp)
     comp = np.ascontiguousarray(np.asarray(comp, dtype=np.int32))
     target = np.ascontiguousarray(np.asarray(target, dtype=np.int64))
     out = np.empty(comp.shape[0], dtype=np.float64)
     lib().or_spread_at(dim, _ptr(n, _ip), _ptr(length, _dp), ncomp, _ptr(st, _dp), kernel,
-                       X.shape[0], _ptr(X, _dp), _ptr(F, _dp), comp.shape[0],
+                       walls, X.shape[0], _ptr(X, _dp), _ptr(F, _dp), comp.shape[0],
                        _ptr(comp, _i32p), _ptr(target, _i64p), _ptr(out, _dp))
     return out
 
 
 def interp_grad(grid, X, u, W):
     """dX (np x dim): sum_c W_{j,c} dU_{j,c}/dX_j for U = J(X)u."""
-    dim, n, length, ncomp, st, kernel = _grid_args(grid)
+    dim, n, length, ncomp, st, kernel, walls = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     u = _f64(u).reshape(ncomp, -1)
     W = _f64(W).reshape(-1, ncomp)
     dX = np.empty_like(X)
     lib().or_interp_grad(dim, _ptr(n, _ip), _ptr(length, _dp), ncomp, _ptr(st, _dp), kernel,
-                         X.shape[0], _ptr(X, _dp), _ptr(u, _dp), _ptr(W, _dp), _ptr(dX, _dp))
+                         walls, X.shape[0], _ptr(X, _dp), _ptr(u, _dp), _ptr(W, _dp), _ptr(dX, _dp))
     return dX
 
 
@@ -183,19 +186,21 @@ def advect(grid, X, U, dt):
     X = _f64(X).reshape(-1, dim)
     U = _f64(U).reshape(-1, dim)
     out = np.empty_like(X)
-    lib().or_advect(dim, _ptr(L, _dp), X.shape[0], _ptr(X, _dp), _ptr(U, _dp), float(dt),
-                    _ptr(out, _dp))
+    lib().or_advect(dim, _ptr(L, _dp), int(grid.get("walls", 0)), X.shape[0], _ptr(X, _dp),
+                    _ptr(U, _dp), float(dt), _ptr(out, _dp))
     return out
 
 
 def tether_force(grid, X0, X, k):
     """Hookean tether of the unstructured-point test (Sec. 4.1): F = k (X0 - X), each
-    coordinate difference taken to its nearest periodic image, in [-L_k / 2, L_k / 2)."""
+    coordinate difference of a periodic dimension taken to its nearest periodic image, in
+    [-L_k / 2, L_k / 2); along walled dimensions the plain difference."""
     dim = int(grid["dim"])
     L = np.array(grid["length"][:dim], dtype=np.float64)
+    periodic = np.array([not (int(grid.get("walls", 0)) >> k) & 1 for k in range(dim)])
     d = _f64(X0).reshape(-1, dim) - _f64(X).reshape(-1, dim)
-    d = np.where(d >= 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
-    return float(k) * d
+    folded = np.where(d >= 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+    return float(k) * np.where(periodic, folded, d)
 
 
 def unstructured_step(grid, X, X0, u, k, dt):

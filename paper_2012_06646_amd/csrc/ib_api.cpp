@@ -34,11 +34,12 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     if (g->ncomp < 1 || g->ncomp > 3) return IB_ERR_ARG;
     if (npts < 0) return IB_ERR_ARG;
     if (npts > MAX_POINTS) return IB_ERR_UNSUPPORTED;
+    if (g->walls < 0 || g->walls >= (1 << g->dim)) return IB_ERR_ARG;
     int64_t G = 1;
     for (int k = 0; k < g->dim; ++k) {
         if (g->n[k] < 4) return IB_ERR_UNSUPPORTED;
         if (!(g->length[k] > 0.0) || !std::isfinite(g->length[k])) return IB_ERR_ARG;
-        G *= g->n[k];
+        G *= (int64_t)g->n[k] + (((g->walls >> k) & 1) ? IB_WALL_GHOSTS : 0);
         if (G > 2147483647LL) return IB_ERR_UNSUPPORTED;
     }
     int ns = 0;
@@ -71,9 +72,23 @@ int32_t check_tuning(const ib_tuning* t)
     return IB_OK;
 }
 
-void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
+ib_grid_desc kernel_grid(const ib_grid_desc& g)
+{
+    ib_grid_desc k = g;
+    k.walls = 0;
+    for (int d = 0; d < g.dim; ++d)
+        if ((g.walls >> d) & 1) {
+            k.n[d] = g.n[d] + IB_WALL_GHOSTS;
+            k.length[d] = g.length[d] / g.n[d] * k.n[d];  // only the index range matters
+        }
+    return k;
+}
+
+void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, Layout* L,
                  int rbits_fixed, const ib_tuning* tuning)
 {
+    const ib_grid_desc kg = kernel_grid(*user);
+    const ib_grid_desc* g = &kg;
     if (rbits_fixed == 0 && tuning && tuning->radix_bits) rbits_fixed = tuning->radix_bits;
     L->nstag = nstag;
     L->G = 1;
@@ -131,6 +146,7 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
     L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
     L->zero_end = off;
+    L->gpad = take(user->walls ? (size_t)g->ncomp * (size_t)L->G * b : 0);
     L->total = off;
 }
 
@@ -180,10 +196,12 @@ size_t ib_plan_workspace_bytes(const ib_grid_desc* grid, int32_t dtype, int64_t 
 
 namespace ibk {
 
-void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t npts, int nstag,
+void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t npts, int nstag,
                 const int cs[3], const double sx[3][3], const Layout& L, void* workspace)
 {
-    p->grid = *grid;
+    p->user = *user;
+    p->grid = kernel_grid(*user);
+    const ib_grid_desc* grid = &p->grid;
     p->dtype = dtype;
     p->npts = npts;
     GeomArgs& g = p->sa.g;
@@ -203,11 +221,12 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
             g.inv_h_f[k] = 1.0f;
             continue;
         }
-        const double N = grid->n[k], Lk = grid->length[k];
-        g.inv_n[k] = 1.0 / N;
+        // spacing from the caller's grid (a walled dimension keeps it; only indices differ)
+        const double N = user->n[k], Lk = user->length[k];
+        g.inv_n[k] = 1.0 / grid->n[k];
         g.inv_h_d[k] = N / Lk;
         g.inv_lo_d[k] = (double)((long double)N / (long double)Lk - (long double)g.inv_h_d[k]);
-        g.inv_h_f[k] = (float)grid->n[k] / (float)grid->length[k];
+        g.inv_h_f[k] = (float)user->n[k] / (float)user->length[k];
         g.inv_lo_f[k] = (float)((long double)N / (long double)Lk - (long double)g.inv_h_f[k]);
         hd *= Lk / N;
     }
@@ -228,6 +247,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t n
         for (int k = 0; k < 3; ++k) g.stag_xi[s][k] = sx[s][k];
 
     char* base = (char*)workspace;
+    p->gpad = user->walls ? (void*)(base + L.gpad) : nullptr;
     PlanDev& d = p->sa.d;
     d.keys0 = (int32_t*)(base + L.keys0);
     d.kA = (int32_t*)(base + L.kA);
@@ -400,6 +420,14 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->partial = p->sa.d.partial;
 }
 
+// The caller's grid field u, or (walled plans) its copy padded with zero ghost values.
+static const void* kernel_field(ib_plan p, const void* u, hipStream_t st, hipError_t* e)
+{
+    if (!p->user.walls) return u;
+    *e = launch_pad(p->user, p->grid, p->dtype, u, p->gpad, st);
+    return p->gpad;
+}
+
 int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
 {
     if (!p || !f || !p->updated) return IB_ERR_ARG;
@@ -407,11 +435,14 @@ int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* s
     OpArgs a;
     fill_op_args(p, &a);
     a.F = F;
-    a.f = f;
-    a.accumulate = accumulate != 0;
+    a.f = p->user.walls ? p->gpad : f;  // walled: spread onto the padded grid, then drop ghosts
+    a.accumulate = !p->user.walls && accumulate != 0;
     hipStream_t st = (hipStream_t)stream;
     p->last_stream = st;
-    return hip_status(launch_spread(a, p->dtype, p->grid.kernel, st));
+    hipError_t e = launch_spread(a, p->dtype, p->grid.kernel, st);
+    if (e == hipSuccess && p->user.walls)
+        e = launch_unpad(p->user, p->grid, p->dtype, p->gpad, f, accumulate != 0, st);
+    return hip_status(e);
 }
 
 int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
@@ -421,11 +452,13 @@ int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
     if (p->npts == 0) return IB_OK;
     OpArgs a;
     fill_op_args(p, &a);
-    a.u = u;
-    a.U = U;
     hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    a.u = kernel_field(p, u, st, &e);
+    a.U = U;
     p->last_stream = st;
-    return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
+    if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
+    return hip_status(e);
 }
 
 int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double dt, void* stream)
@@ -436,16 +469,23 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     if (p->npts == 0) return IB_OK;
     OpArgs a;
     fill_op_args(p, &a);
-    a.u = u;
-    a.U = U;
-    a.Xadv = X;
-    a.adv_dt = dt;
-    for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
     hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    a.u = kernel_field(p, u, st, &e);
+    a.U = U;
+    if (!p->user.walls) {  // walled: interpolation, then the update without wrap along walls
+        a.Xadv = X;
+        a.adv_dt = dt;
+        for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
+    }
     p->last_stream = st;
     // Positions of staggerings not yet sorted can no longer be derived from this update.
     if (X == p->X) p->x_moved = 1;
-    return hip_status(launch_interp(a, p->dtype, p->grid.kernel, st));
+    if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
+    if (e == hipSuccess && p->user.walls)
+        e = launch_advect(p->user.dim, p->user.ncomp, p->npts, p->user.length, p->user.walls,
+                          p->dtype, X, U, dt, st);
+    return hip_status(e);
 }
 
 int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, int32_t accumulate,
@@ -456,10 +496,13 @@ int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, i
     if (p->npts == 0) return IB_OK;
     OpArgs a;
     fill_op_args(p, &a);
-    a.u = u;
     hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    a.u = kernel_field(p, u, st, &e);
     p->last_stream = st;
-    return hip_status(launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st));
+    if (e == hipSuccess)
+        e = launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st);
+    return hip_status(e);
 }
 
 int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X, const void* U,
@@ -471,8 +514,8 @@ int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X
     if (st != IB_OK) return st;
     if (grid->ncomp != grid->dim || !std::isfinite(dt)) return IB_ERR_ARG;
     if (npts > 0 && (!X || !U)) return IB_ERR_ARG;
-    return hip_status(launch_advect(grid->dim, grid->ncomp, npts, grid->length, dtype, X, U, dt,
-                                    (hipStream_t)stream));
+    return hip_status(launch_advect(grid->dim, grid->ncomp, npts, grid->length, grid->walls, dtype,
+                                    X, U, dt, (hipStream_t)stream));
 }
 
 int32_t ib_tether_force(const ib_grid_desc* grid, int32_t dtype, int64_t npts, const void* X0,
@@ -484,8 +527,8 @@ int32_t ib_tether_force(const ib_grid_desc* grid, int32_t dtype, int64_t npts, c
     if (st != IB_OK) return st;
     if (grid->ncomp != grid->dim || !std::isfinite(k)) return IB_ERR_ARG;
     if (npts > 0 && (!X0 || !X || !F)) return IB_ERR_ARG;
-    return hip_status(launch_tether(grid->dim, npts, grid->length, dtype, X0, X, k, F,
-                                    (hipStream_t)stream));
+    return hip_status(launch_tether(grid->dim, grid->walls, npts, grid->length, dtype, X0, X, k,
+                                    F, (hipStream_t)stream));
 }
 
 }  // extern "C"

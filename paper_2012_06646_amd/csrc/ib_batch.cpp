@@ -45,6 +45,7 @@ int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayo
         std::memset(G.sx, 0, sizeof G.sx);
         int32_t st = check_grid(&J.grid, dtype, J.npts, &G.nstag, G.cs, G.sx);
         if (st != IB_OK) return st;
+        if (J.grid.walls) return IB_ERR_UNSUPPORTED;  // batches run periodic jobs only
         if (J.grid.dim != jobs[0].grid.dim || J.grid.kernel != jobs[0].grid.kernel)
             return IB_ERR_UNSUPPORTED;
         if (J.npts > 0 && !J.X) return IB_ERR_ARG;
@@ -145,6 +146,7 @@ size_t batch_job_bytes(const ib_job* job, int32_t dtype)
     int nstag, cs[3];
     double sx[3][3];
     if (!job || check_grid(&job->grid, dtype, job->npts, &nstag, cs, sx) != IB_OK) return 0;
+    if (job->grid.walls) return 0;
     Layout L;
     make_layout(&job->grid, dtype, nstag, job->npts, &L, BATCH_RBITS);
     return L.total;

@@ -9,7 +9,9 @@
 #include "ib_internal.h"
 
 struct ib_plan_s {
-    ib_grid_desc grid;
+    ib_grid_desc grid;     // the grid the kernels run on (padded if the caller's has walls)
+    ib_grid_desc user;     // the caller's grid
+    void* gpad;            // walled plans: one padded grid field (ncomp x padded cells)
     int32_t dtype;
     int64_t npts;
     ibk::SortArgs sa;      // geometry, device pointers, radix configuration
@@ -34,7 +36,7 @@ struct Layout {
     int64_t ntiles, nseg_tiles, nscan_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, zero_begin, hist,
-        sort_status, seg_status, scan_status, counters, flag, zero_end, total;
+        sort_status, seg_status, scan_status, counters, flag, zero_end, gpad, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,
@@ -42,14 +44,20 @@ struct Layout {
 int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nstag,
                    int comp_stag[3], double stag_xi[3][3]);
 
-// Workspace layout of a plan; rbits_fixed > 0 forces that radix digit width (batched plans
-// share one sort kernel), else the digit width spreads the key bits evenly over passes.
+// Workspace layout of a plan on the caller's descriptor g (sized for kernel_grid(*g), plus
+// one padded grid field when g has walls); rbits_fixed > 0 forces that radix digit width
+// (batched plans share one sort kernel), else the digit width spreads the key bits evenly
+// over passes.
 void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
                  int rbits_fixed = 0, const ib_tuning* tuning = nullptr);
+// The periodic grid a plan runs on: the caller's grid with IB_WALL_GHOSTS ghost indices
+// added along every walled dimension (same spacing), walls cleared.
+ib_grid_desc kernel_grid(const ib_grid_desc& g);
 // IB_OK if every field of a (possibly null) tuning is in range.
 int32_t check_tuning(const ib_tuning* t);
 
-// Fill a plan object for a validated descriptor over a workspace of layout L.
+// Fill a plan object for a validated (caller's) descriptor over a workspace of layout L.
+// The kernels run on kernel_grid(*grid); keys and weights use the caller's spacing.
 void plan_setup(ib_plan_s* p, const ib_grid_desc* grid, int32_t dtype, int64_t npts, int nstag,
                 const int cs[3], const double sx[3][3], const Layout& L, void* workspace);
 

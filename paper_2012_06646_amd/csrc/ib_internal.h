@@ -211,9 +211,15 @@ hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st)
 hipError_t launch_interp(const OpArgs& a, int dtype, int kernel, hipStream_t st);
 hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
                               int accumulate, hipStream_t st);
-hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
+hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int walls, int dtype,
                          void* X, const void* U, double dt, hipStream_t st);
-hipError_t launch_tether(int dim, int64_t npts, const double length[3], int dtype,
+// Walled plans: the caller's grid field (user grid) to the kernels' padded grid (zero ghost
+// values), and back (ghost values dropped; accumulate adds into dst).
+hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype, const void* src,
+                      void* dst, hipStream_t st);
+hipError_t launch_unpad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype,
+                        const void* src, void* dst, bool accumulate, hipStream_t st);
+hipError_t launch_tether(int dim, int walls, int64_t npts, const double length[3], int dtype,
                          const void* X0, const void* X, double k, void* F, hipStream_t st);
 
 }  // namespace ibk

@@ -1012,11 +1012,12 @@ hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void
 }
 
 // ---------------------------------------------------------------------------------------
-// Position update: X <- wrap(X + dt U) into [0, L) per coordinate.
+// Position update: X <- wrap(X + dt U) into [0, L) per coordinate; along walled dimensions
+// (bit k of walls) X + dt U without wrap.
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void advect_kernel(int dim, int ncomp, int64_t npts, T L0, T L1,
-                                                     T L2, T* __restrict__ X,
+__global__ __launch_bounds__(256) void advect_kernel(int dim, int ncomp, int walls, int64_t npts,
+                                                     T L0, T L1, T L2, T* __restrict__ X,
                                                      const T* __restrict__ U, T dt)
 {
     const int64_t total = npts * dim;
@@ -1025,30 +1026,128 @@ __global__ __launch_bounds__(256) void advect_kernel(int dim, int ncomp, int64_t
         const int64_t j = i / dim;
         const int k = (int)(i - j * dim);
         const T L = k == 0 ? L0 : (k == 1 ? L1 : L2);
-        X[i] = advect_coord(X[i], U[j * ncomp + k], dt, L);
+        const T u = U[j * ncomp + k];
+        X[i] = ((walls >> k) & 1) ? fma(dt, u, X[i]) : advect_coord(X[i], u, dt, L);
     }
 }
 
-hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int dtype,
-                         void* X, const void* U, double dt, hipStream_t st)
+hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int walls,
+                         int dtype, void* X, const void* U, double dt, hipStream_t st)
 {
     if (npts == 0) return hipSuccess;
     const int64_t total = npts * dim;
     const unsigned blocks = (unsigned)min((int64_t)4096, (total + 255) / 256);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(advect_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, ncomp, npts,
-                           length[0], length[1], length[2], (double*)X, (const double*)U, dt);
+        hipLaunchKernelGGL(advect_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, ncomp, walls,
+                           npts, length[0], length[1], length[2], (double*)X, (const double*)U, dt);
     else
-        hipLaunchKernelGGL(advect_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, ncomp, npts,
-                           (float)length[0], (float)length[1], (float)length[2], (float*)X,
+        hipLaunchKernelGGL(advect_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, ncomp, walls,
+                           npts, (float)length[0], (float)length[1], (float)length[2], (float*)X,
                            (const float*)U, (float)dt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Walled plans run on a periodic grid with ghost indices n_k .. m_k - 1 added along walled
+// dimensions (m_k = n_k elsewhere).  The caller's field (n) sits at the same indices of the
+// padded field (m): pad copies it in with zero ghost values (ghost points are no grid
+// points, so interpolation reads nothing there), unpad copies the interior back out and
+// drops the ghost values that spreading wrote.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void pad_kernel(int64_t total, int n0, int n1, int n2, int m0,
+                                                  int m1, int m2, const T* __restrict__ src,
+                                                  T* __restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int x = (int)(r % m0);
+        r /= m0;
+        const int y = (int)(r % m1);
+        r /= m1;
+        const int z = (int)(r % m2);
+        const int64_t c = r / m2;
+        dst[i] = (x < n0 && y < n1 && z < n2) ? src[((c * n2 + z) * n1 + y) * n0 + x] : T(0);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void unpad_kernel(int64_t total, int n0, int n1, int n2, int m0,
+                                                    int m1, int m2, const T* __restrict__ src,
+                                                    T* __restrict__ dst, int accumulate)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = i;
+        const int x = (int)(r % n0);
+        r /= n0;
+        const int y = (int)(r % n1);
+        r /= n1;
+        const int z = (int)(r % n2);
+        const int64_t c = r / n2;
+        const T v = src[((c * m2 + z) * m1 + y) * m0 + x];
+        dst[i] = accumulate ? dst[i] + v : v;
+    }
+}
+
+namespace {
+struct PadDims {
+    int n[3], m[3];
+    int64_t user_cells, kernel_cells;  // both times ncomp
+};
+
+PadDims pad_dims(const ib_grid_desc& user, const ib_grid_desc& kg)
+{
+    PadDims d;
+    d.user_cells = d.kernel_cells = user.ncomp;
+    for (int k = 0; k < 3; ++k) {
+        d.n[k] = k < user.dim ? user.n[k] : 1;
+        d.m[k] = k < kg.dim ? kg.n[k] : 1;
+        d.user_cells *= d.n[k];
+        d.kernel_cells *= d.m[k];
+    }
+    return d;
+}
+}  // namespace
+
+hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype, const void* src,
+                      void* dst, hipStream_t st)
+{
+    const PadDims d = pad_dims(user, kg);
+    const unsigned blocks = (unsigned)min((int64_t)8192, (d.kernel_cells + 255) / 256);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.kernel_cells,
+                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
+                           (double*)dst);
+    else
+        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.kernel_cells,
+                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
+                           (float*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype,
+                        const void* src, void* dst, bool accumulate, hipStream_t st)
+{
+    const PadDims d = pad_dims(user, kg);
+    const unsigned blocks = (unsigned)min((int64_t)8192, (d.user_cells + 255) / 256);
+    if (dtype == IB_F64)
+        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.user_cells,
+                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
+                           (double*)dst, (int)accumulate);
+    else
+        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.user_cells,
+                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
+                           (float*)dst, (int)accumulate);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // Tether force of the unstructured-point test (Sec. 4.1): every point hangs on a Hookean
 // spring from its initial position, F = k (X0 - X), with the difference taken to the
-// nearest periodic image of X0 (the displacement is far below half a box).
+// nearest periodic image of X0 (the displacement is far below half a box); along walled
+// dimensions the plain difference.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T tether_coord(T x0, T x, T k, T L)
@@ -1060,8 +1159,8 @@ __device__ __forceinline__ T tether_coord(T x0, T x, T k, T L)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void tether_kernel(int dim, int64_t npts, T L0, T L1, T L2,
-                                                     const T* __restrict__ X0,
+__global__ __launch_bounds__(256) void tether_kernel(int dim, int walls, int64_t npts, T L0, T L1,
+                                                     T L2, const T* __restrict__ X0,
                                                      const T* __restrict__ X, T k,
                                                      T* __restrict__ F)
 {
@@ -1070,22 +1169,22 @@ __global__ __launch_bounds__(256) void tether_kernel(int dim, int64_t npts, T L0
          i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % dim);
         const T L = c == 0 ? L0 : (c == 1 ? L1 : L2);
-        F[i] = tether_coord(X0[i], X[i], k, L);
+        F[i] = ((walls >> c) & 1) ? k * (X0[i] - X[i]) : tether_coord(X0[i], X[i], k, L);
     }
 }
 
-hipError_t launch_tether(int dim, int64_t npts, const double length[3], int dtype,
+hipError_t launch_tether(int dim, int walls, int64_t npts, const double length[3], int dtype,
                          const void* X0, const void* X, double k, void* F, hipStream_t st)
 {
     if (npts == 0) return hipSuccess;
     const int64_t total = npts * dim;
     const unsigned blocks = (unsigned)min((int64_t)4096, (total + 255) / 256);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(tether_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, npts,
+        hipLaunchKernelGGL(tether_kernel<double>, dim3(blocks), dim3(256), 0, st, dim, walls, npts,
                            length[0], length[1], length[2], (const double*)X0, (const double*)X,
                            k, (double*)F);
     else
-        hipLaunchKernelGGL(tether_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, npts,
+        hipLaunchKernelGGL(tether_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, walls, npts,
                            (float)length[0], (float)length[1], (float)length[2],
                            (const float*)X0, (const float*)X, (float)k, (float*)F);
     return hipGetLastError();

@@ -428,6 +428,8 @@ __device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ per
     }
 }
 
+constexpr int CB_LANE_RUN = 16;  // table runs up to this long are written by their own lane
+
 template <typename T>
 __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
 {
@@ -460,14 +462,26 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
     for (int k = 0; k < SORT_IPT; ++k) {
         const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
         bool hd = false;
+        // Table entries (block(i-1), block(i)] start at sorted position i.  A lane writes a
+        // short run itself; longer runs (empty stretches of the grid, e.g. ghost planes or
+        // the space between clustered points) are written by the whole wave, one at a time.
+        int32_t bp = 0, bc = 0;
         if (i < n) {
             const int32_t kc = sk[i];
             const int32_t kp = i > 0 ? sk[i - 1] : -1;
             hd = (i == 0) || (kc != kp);
-            // Table entries (block(i-1), block(i)] start at sorted position i.
-            const int64_t bp = i > 0 ? min(cblk_index(kp, g), nent - 1) : -1;
-            const int64_t bc = min(cblk_index(kc, g), nent - 1);
-            for (int64_t e = bp + 1; e <= bc; ++e) cb[e] = (int32_t)i;
+            bp = i > 0 ? (int32_t)min(cblk_index(kp, g), nent - 1) : -1;
+            bc = (int32_t)min(cblk_index(kc, g), nent - 1);
+            if (bc - bp <= CB_LANE_RUN)
+                for (int32_t e = bp + 1; e <= bc; ++e) cb[e] = (int32_t)i;
+        }
+        unsigned long long longs = __ballot(bc - bp > CB_LANE_RUN);
+        while (longs) {
+            const int src = __ffsll((long long)longs) - 1;
+            longs &= longs - 1ull;
+            const int32_t b0 = __shfl(bp, src, 64) + 1, b1 = __shfl(bc, src, 64);
+            const int32_t v = (int32_t)(base + w * (64 * SORT_IPT) + k * 64 + src);
+            for (int32_t e = b0 + lane; e <= b1; e += 64) cb[e] = v;
         }
         const unsigned long long m = __ballot(hd);
         head[k] = hd;

@@ -27,7 +27,7 @@ STATUS = {0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_OOM", -3: "IB_ERR_HIP",
 class GridDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("length", ctypes.c_double * 3),
                 ("ncomp", ctypes.c_int32), ("stagger", (ctypes.c_double * 3) * 3),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("walls", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -150,7 +150,8 @@ def _ptr(t):
 
 
 def make_desc(grid):
-    """ib_grid_desc from a grid dict (dim, n, length, stagger, kernel)."""
+    """ib_grid_desc from a grid dict (dim, n, length, stagger, kernel; optional walls: bit k
+    set for a non-periodic dimension k)."""
     d = GridDesc()
     d.dim = int(grid["dim"])
     for k in range(3):
@@ -161,6 +162,7 @@ def make_desc(grid):
         for k in range(3):
             d.stagger[c][k] = float(xi[k]) if k < d.dim else 0.0
     d.kernel = KERNELS[grid.get("kernel", "peskin4")]
+    d.walls = int(grid.get("walls", 0))
     return d
 
 

@@ -458,6 +458,15 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
     bool head[SORT_IPT];
     uint32_t wrun = 0;
     const unsigned long long below = (1ull << lane) - 1ull;
+    // All keys of this thread (and their predecessors) first, so their loads overlap rather
+    // than wait behind the table stores below.
+    int32_t kcs[SORT_IPT], kps[SORT_IPT];
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+        kcs[k] = i < n ? sk[i] : 0;
+        kps[k] = (i < n && i > 0) ? sk[i - 1] : -1;
+    }
 #pragma unroll
     for (int k = 0; k < SORT_IPT; ++k) {
         const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
@@ -467,8 +476,8 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
         // the space between clustered points) are written by the whole wave, one at a time.
         int32_t bp = 0, bc = 0;
         if (i < n) {
-            const int32_t kc = sk[i];
-            const int32_t kp = i > 0 ? sk[i - 1] : -1;
+            const int32_t kc = kcs[k];
+            const int32_t kp = kps[k];
             hd = (i == 0) || (kc != kp);
             bp = i > 0 ? (int32_t)min(cblk_index(kp, g), nent - 1) : -1;
             bc = (int32_t)min(cblk_index(kc, g), nent - 1);

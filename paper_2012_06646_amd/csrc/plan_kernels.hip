@@ -233,11 +233,16 @@ __device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pa
     uint32_t rank[SORT_IPT];
     const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
+    for (int k = 0; k < SORT_IPT; ++k) {  // all loads first, so that they overlap
         const int li = w * (64 * SORT_IPT) + k * 64 + lane;
         const bool valid = li < nvalid;
         key[k] = valid ? srck[base + li] : 0;
         val[k] = valid ? (pass == 0 ? (int32_t)(base + li) : srcv[base + li]) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k) {
+        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
+        const bool valid = li < nvalid;
         const uint32_t digit = ((uint32_t)key[k] >> shift) & (R - 1);
         unsigned long long m = __ballot(valid);
 #pragma unroll

@@ -723,6 +723,8 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region
     constexpr int ROWS = TY * TZ;
     __shared__ T su[RX * RY * RZ];
+    __shared__ int32_t s_rowoff[RY * RZ];  // grid offset of each staged row (wrapped y, z)
+    static_assert(RY * RZ <= 256, "one thread per staged row");
     __shared__ int32_t s_lo[ROWS];
     __shared__ int32_t s_pref[ROWS + 1];
     __shared__ uint32_t s_scan[256 / 64 + 1];
@@ -769,6 +771,11 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
         const int hz = g.dhi[c][2] - g.dlo[c][2];
         const int lx = ex + 3 + hx, ly = ey + 3 + hy, lz = ez + 3 + hz;
         const int rx = x0 + g.dlo[c][0] - 1, ry = y0 + g.dlo[c][1] - 1, rz = z0 + g.dlo[c][2] - 1;
+        const int nr = ly * lz;
+        if (tid < nr) {  // one thread per staged row (nr <= RY * RZ <= 256)
+            const int iz = tid / ly, iy = tid - iz * ly;
+            s_rowoff[tid] = (wrap_small(rz + iz, n2) * n1 + wrap_small(ry + iy, n1)) * n0;
+        }
         __syncthreads();  // the previous component's points are done with su
         {
             // Thread tid stages x-column tid % lx of rows tid / lx, tid / lx + rstep, ...; SU
@@ -777,8 +784,6 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
             const int rstep = 256 / lx;
             const int xi = tid % lx;
             const int r = tid / lx;
-            const int nr = ly * lz;
-            const float inv_ly = 1.0f / (float)ly;
             if (r < rstep) {
                 const int gx = wrap_small(rx + xi, n0);
                 const T* __restrict__ uc = u + (int64_t)c * G;
@@ -788,13 +793,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                     for (int q = 0; q < SU; ++q) {
                         const int rr = r0 + q * rstep;
                         val[q] = T(0);
-                        if (rr < nr) {
-                            int iz = (int)((float)rr * inv_ly);  // rr / ly, corrected below
-                            iz += (rr - iz * ly >= ly) - (rr - iz * ly < 0);
-                            const int iy = rr - iz * ly;
-                            const int gy = wrap_small(ry + iy, n1), gz = wrap_small(rz + iz, n2);
-                            val[q] = uc[((int64_t)gz * n1 + gy) * n0 + gx];
-                        }
+                        if (rr < nr) val[q] = uc[(int64_t)s_rowoff[rr] + gx];
                     }
 #pragma unroll
                     for (int q = 0; q < SU; ++q) {

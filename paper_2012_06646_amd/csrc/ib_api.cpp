@@ -85,7 +85,7 @@ ib_grid_desc kernel_grid(const ib_grid_desc& g)
 }
 
 void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed, const ib_tuning* tuning)
+                 int rbits_fixed, const ib_tuning* tuning, bool batch)
 {
     const ib_grid_desc kg = kernel_grid(*user);
     const ib_grid_desc* g = &kg;
@@ -105,7 +105,10 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
         if (L->npass < 1) L->npass = 1;
     }
     L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
-    L->nseg_tiles = L->ntiles > 0 ? L->ntiles : 1;
+    // Batches keep the one segments tile size their shared kernel is built for.
+    L->seg_ipt = (!batch && n < SEG_SMALL_POINTS) ? SEG_IPT_SMALL : SEG_IPT;
+    const int64_t seg_tile = (int64_t)SORT_BLOCK * L->seg_ipt;
+    L->nseg_tiles = n > 0 ? (n + seg_tile - 1) / seg_tile : 1;
     const int64_t R = int64_t(1) << L->rbits;
     L->nscan_tiles = L->ntiles > 0 ? (R * L->ntiles + SCAN_TILE - 1) / SCAN_TILE : 1;
     size_t off = 0;
@@ -272,6 +275,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     p->sa.rbits = L.rbits;
     p->sa.ntiles = L.ntiles;
     p->sa.nseg_tiles = L.nseg_tiles;
+    p->sa.seg_ipt = L.seg_ipt;
     p->sa.nscan_tiles = L.nscan_tiles;
     // Scanned passes pay three launches per pass for a short chained step; one-sweep passes
     // one launch, but a look-back across all tiles per digit.  Scanned from

@@ -51,7 +51,7 @@ int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayo
         if (J.npts > 0 && !J.X) return IB_ERR_ARG;
         if (J.f && J.npts > 0 && !J.F) return IB_ERR_ARG;
         if (J.u && J.npts > 0 && !J.U) return IB_ERR_ARG;
-        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, BATCH_RBITS);
+        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, BATCH_RBITS, nullptr, true);
         G.off = off;
         off += G.L.total;
     }
@@ -148,7 +148,7 @@ size_t batch_job_bytes(const ib_job* job, int32_t dtype)
     if (!job || check_grid(&job->grid, dtype, job->npts, &nstag, cs, sx) != IB_OK) return 0;
     if (job->grid.walls) return 0;
     Layout L;
-    make_layout(&job->grid, dtype, nstag, job->npts, &L, BATCH_RBITS);
+    make_layout(&job->grid, dtype, nstag, job->npts, &L, BATCH_RBITS, nullptr, true);
     return L.total;
 }
 

@@ -32,7 +32,7 @@ size_t align_up(size_t v);
 
 // Byte layout of one plan's workspace.
 struct Layout {
-    int nstag, npass, rbits, rows, nbx;
+    int nstag, npass, rbits, rows, nbx, seg_ipt;
     int64_t ntiles, nseg_tiles, nscan_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, zero_begin, hist,
@@ -49,7 +49,7 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
 // (batched plans share one sort kernel), else the digit width spreads the key bits evenly
 // over passes.
 void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed = 0, const ib_tuning* tuning = nullptr);
+                 int rbits_fixed = 0, const ib_tuning* tuning = nullptr, bool batch = false);
 // The periodic grid a plan runs on: the caller's grid with IB_WALL_GHOSTS ghost indices
 // added along every walled dimension (same spacing), walls cleared.
 ib_grid_desc kernel_grid(const ib_grid_desc& g);

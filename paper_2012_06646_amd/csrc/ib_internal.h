@@ -15,6 +15,11 @@ constexpr int SORT_BLOCK = 256;
 #endif
 constexpr int SORT_IPT = IBK_SORT_IPT;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
+// Sorted positions per thread of the segments kernel: 8, or 2 for plans below
+// SEG_SMALL_POINTS points (four times the blocks, where few tiles would leave most CUs idle).
+constexpr int SEG_IPT = 8;
+constexpr int SEG_IPT_SMALL = 2;
+constexpr int64_t SEG_SMALL_POINTS = int64_t(1) << 18;
 #ifndef IBK_SCANNED_MIN_POINTS
 #define IBK_SCANNED_MIN_POINTS (1 << 18)
 #endif
@@ -104,6 +109,7 @@ struct SortArgs {
     int64_t nseg_tiles;    // segment tiles per stagger
     int64_t nscan_tiles;   // scan tiles of one pass's digit-major tile counts
     int scanned;           // radix passes: count, scan, scatter (else one-sweep look-back)
+    int seg_ipt;           // sorted positions per thread of the segments kernel
 };
 
 struct OpArgs {

@@ -399,24 +399,24 @@ __global__ __launch_bounds__(SORT_BLOCK) void radix_scan_kernel(SortArgs a, int 
 }
 
 // ---- segments: run heads, q, seg_off and the cell-block start table -------------------
-// Rows base + t + k * SORT_BLOCK (k < SORT_IPT) of a tile: dst[i] = src[perm[i]] for rows
+// Rows base + t + k * SORT_BLOCK (k < SEG_IPT) of a tile: dst[i] = src[perm[i]] for rows
 // of D values, all permutation entries first, then all rows.
-template <typename T, int D>
+template <typename T, int D, int SEG_IPT>
 __device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ perm,
                                                  const T* __restrict__ src, T* __restrict__ dst,
                                                  int64_t base, int64_t n)
 {
     // Rows past n are neither read nor written (with n == 0, src may be null).
-    int64_t p[SORT_IPT];
+    int64_t p[SEG_IPT];
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
+    for (int k = 0; k < SEG_IPT; ++k) {
         const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
         const int32_t v = i < n ? perm[i] : 0;
         p[k] = (uint32_t)v < (uint64_t)n ? v : 0;
     }
-    T row[SORT_IPT][D];
+    T row[SEG_IPT][D];
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
+    for (int k = 0; k < SEG_IPT; ++k) {
         const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
         if (i < n) {
 #pragma unroll
@@ -424,7 +424,7 @@ __device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ per
         }
     }
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
+    for (int k = 0; k < SEG_IPT; ++k) {
         const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
         if (i < n) {
 #pragma unroll
@@ -435,7 +435,7 @@ __device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ per
 
 constexpr int CB_LANE_RUN = 16;  // table runs up to this long are written by their own lane
 
-template <typename T>
+template <typename T, int SEG_IPT>
 __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
 {
     // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
@@ -453,28 +453,29 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
     const GeomArgs& g = a.g;
     const int64_t n = g.npts;
     const int64_t t = s_ticket;
-    const int64_t base = t * SORT_TILE;
+    constexpr int SEG_TILE = SORT_BLOCK * SEG_IPT;
+    const int64_t base = t * SEG_TILE;
     const int32_t* sk = sk_all + (int64_t)s * n;
     int32_t* seg = a.d.seg_off + (int64_t)s * (n + 1);
     const int64_t nent = (int64_t)g.rows * (g.nbx + 1);
     int32_t* cb = a.d.cblk + (int64_t)s * nent;
 
-    uint32_t rank[SORT_IPT];
-    bool head[SORT_IPT];
+    uint32_t rank[SEG_IPT];
+    bool head[SEG_IPT];
     uint32_t wrun = 0;
     const unsigned long long below = (1ull << lane) - 1ull;
     // All keys of this thread (and their predecessors) first, so their loads overlap rather
     // than wait behind the table stores below.
-    int32_t kcs[SORT_IPT], kps[SORT_IPT];
+    int32_t kcs[SEG_IPT], kps[SEG_IPT];
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
-        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+    for (int k = 0; k < SEG_IPT; ++k) {
+        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
         kcs[k] = i < n ? sk[i] : 0;
         kps[k] = (i < n && i > 0) ? sk[i - 1] : -1;
     }
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
-        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+    for (int k = 0; k < SEG_IPT; ++k) {
+        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
         bool hd = false;
         // Table entries (block(i-1), block(i)] start at sorted position i.  A lane writes a
         // short run itself; longer runs (empty stretches of the grid, e.g. ghost planes or
@@ -494,7 +495,7 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
             const int src = __ffsll((long long)longs) - 1;
             longs &= longs - 1ull;
             const int32_t b0 = __shfl(bp, src, 64) + 1, b1 = __shfl(bc, src, 64);
-            const int32_t v = (int32_t)(base + w * (64 * SORT_IPT) + k * 64 + src);
+            const int32_t v = (int32_t)(base + w * (64 * SEG_IPT) + k * 64 + src);
             for (int32_t e = b0 + lane; e <= b1; e += 64) cb[e] = v;
         }
         const unsigned long long m = __ballot(hd);
@@ -535,24 +536,24 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
     __syncthreads();
     const uint32_t off = s_excl + s_wtot[w];
 #pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
-        const int64_t i = base + w * (64 * SORT_IPT) + k * 64 + lane;
+    for (int k = 0; k < SEG_IPT; ++k) {
+        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
         if (head[k]) seg[off + rank[k]] = (int32_t)i;
     }
     // Positions in this sorted order (staggering 0 only): one row per sorted position, the
-    // tile's SORT_IPT rows of a thread loaded together so their random reads overlap.
+    // tile's SEG_IPT rows of a thread loaded together so their random reads overlap.
     if (Xs != nullptr) {
         const int32_t* perm = perm_all + (int64_t)s * n;
-        if (g.dim == 3) gather_tile_rows<T, 3>(perm, X, Xs, base, n);
-        else gather_tile_rows<T, 2>(perm, X, Xs, base, n);
+        if (g.dim == 3) gather_tile_rows<T, 3, SEG_IPT>(perm, X, Xs, base, n);
+        else gather_tile_rows<T, 2, SEG_IPT>(perm, X, Xs, base, n);
     }
 }
 
-template <typename T>
+template <typename T, int SEG_IPT>
 __global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s, const T* __restrict__ X,
                                                               T* __restrict__ Xs)
 {
-    segments_body<T>(a, s, X, Xs);
+    segments_body<T, SEG_IPT>(a, s, X, Xs);
 }
 
 // ---- host launchers ---------------------------------------------------------------------
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void batch_segments_kernel(
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
         const BatchJob& J = jobs[j];
-        segments_body<T>(J.sa, 0, (const T*)J.op.X, (T*)J.sa.d.Xs);
+        segments_body<T, SEG_IPT>(J.sa, 0, (const T*)J.op.X, (T*)J.sa.d.Xs);
         __syncthreads();
     }
 }
@@ -721,12 +722,24 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
         }
     }
     const dim3 grid((unsigned)a.nseg_tiles);
-    if (dtype == IB_F64)
-        hipLaunchKernelGGL(segments_kernel<double>, grid, dim3(SORT_BLOCK), 0, st, a, s,
-                           (const double*)X, gather_x ? (double*)a.d.Xs : nullptr);
-    else
-        hipLaunchKernelGGL(segments_kernel<float>, grid, dim3(SORT_BLOCK), 0, st, a, s,
-                           (const float*)X, gather_x ? (float*)a.d.Xs : nullptr);
+    const bool small = a.seg_ipt == SEG_IPT_SMALL;
+    if (dtype == IB_F64) {
+        double* Xs = gather_x ? (double*)a.d.Xs : nullptr;
+        if (small)
+            hipLaunchKernelGGL((segments_kernel<double, SEG_IPT_SMALL>), grid, dim3(SORT_BLOCK), 0, st,
+                               a, s, (const double*)X, Xs);
+        else
+            hipLaunchKernelGGL((segments_kernel<double, SEG_IPT>), grid, dim3(SORT_BLOCK), 0, st, a,
+                               s, (const double*)X, Xs);
+    } else {
+        float* Xs = gather_x ? (float*)a.d.Xs : nullptr;
+        if (small)
+            hipLaunchKernelGGL((segments_kernel<float, SEG_IPT_SMALL>), grid, dim3(SORT_BLOCK), 0, st,
+                               a, s, (const float*)X, Xs);
+        else
+            hipLaunchKernelGGL((segments_kernel<float, SEG_IPT>), grid, dim3(SORT_BLOCK), 0, st, a, s,
+                               (const float*)X, Xs);
+    }
     return hipGetLastError();
 }
 

@@ -213,7 +213,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:  # the module may be gone at exit
             _lib.ib_plan_destroy(h)
             self._h = None
 
@@ -491,7 +491,7 @@ class Server:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:  # the module may be gone at exit
             _lib.ib_server_destroy(h)
             self._h = None
         self._live.clear()

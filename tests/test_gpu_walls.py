@@ -111,3 +111,15 @@ def test_batches_refuse_walls(ib):
 def test_bad_walls_rejected(ib):
     with pytest.raises(ib.IBError):
         ib.Plan(walled(wl.grid(2, 16, 1.0), 4), 10, torch.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_walled_plan_without_points(ib, dtype):
+    g = walled(wl.grid(3, 16, 1.0), 3)
+    p = ib.Plan(g, 0, dtype).update(torch.empty((0, 3), dtype=dtype, device="cuda"))
+    f = torch.full(p.grid_shape, 7.0, dtype=dtype, device="cuda")
+    p.spread(torch.empty((0, 3), dtype=dtype, device="cuda"), f)
+    assert p.status() == 0
+    assert torch.count_nonzero(f).item() == 0  # overwritten with the empty sum
+    U = p.interpolate(torch.ones(p.grid_shape, dtype=dtype, device="cuda"))
+    assert U.shape == (0, 3)

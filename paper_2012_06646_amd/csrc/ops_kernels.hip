@@ -1053,59 +1053,57 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // points, so interpolation reads nothing there), unpad copies the interior back out and
 // drops the ghost values that spreading wrote.
 // ---------------------------------------------------------------------------------------
+// One block per grid row (component, z, y), its threads along x: the row's indices are
+// worked out once, not per value.
 template <typename T>
-__global__ __launch_bounds__(256) void pad_kernel(int64_t total, int n0, int n1, int n2, int m0,
+__global__ __launch_bounds__(128) void pad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
                                                   int m1, int m2, const T* __restrict__ src,
                                                   T* __restrict__ dst)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = i;
-        const int x = (int)(r % m0);
-        r /= m0;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {  // rows of the padded field
         const int y = (int)(r % m1);
-        r /= m1;
-        const int z = (int)(r % m2);
-        const int64_t c = r / m2;
-        dst[i] = (x < n0 && y < n1 && z < n2) ? src[((c * n2 + z) * n1 + y) * n0 + x] : T(0);
+        const int64_t cz = r / m1;
+        const int z = (int)(cz % m2);
+        const int64_t c = cz / m2;
+        const bool inside = y < n1 && z < n2;
+        const int64_t srow = inside ? ((c * n2 + z) * n1 + y) * n0 : 0;
+        T* __restrict__ d = dst + r * m0;
+        for (int x = threadIdx.x; x < m0; x += blockDim.x)
+            d[x] = (inside && x < n0) ? src[srow + x] : T(0);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void unpad_kernel(int64_t total, int n0, int n1, int n2, int m0,
+__global__ __launch_bounds__(128) void unpad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
                                                     int m1, int m2, const T* __restrict__ src,
                                                     T* __restrict__ dst, int accumulate)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = i;
-        const int x = (int)(r % n0);
-        r /= n0;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {  // rows of the caller's field
         const int y = (int)(r % n1);
-        r /= n1;
-        const int z = (int)(r % n2);
-        const int64_t c = r / n2;
-        const T v = src[((c * m2 + z) * m1 + y) * m0 + x];
-        dst[i] = accumulate ? dst[i] + v : v;
+        const int64_t cz = r / n1;
+        const int z = (int)(cz % n2);
+        const int64_t c = cz / n2;
+        const T* __restrict__ s = src + ((c * m2 + z) * m1 + y) * m0;
+        T* __restrict__ d = dst + r * n0;
+        for (int x = threadIdx.x; x < n0; x += blockDim.x) d[x] = accumulate ? d[x] + s[x] : s[x];
     }
 }
 
 namespace {
 struct PadDims {
     int n[3], m[3];
-    int64_t user_cells, kernel_cells;  // both times ncomp
+    int64_t user_rows, kernel_rows;  // x-rows of the caller's and the padded field (x ncomp)
 };
 
 PadDims pad_dims(const ib_grid_desc& user, const ib_grid_desc& kg)
 {
     PadDims d;
-    d.user_cells = d.kernel_cells = user.ncomp;
     for (int k = 0; k < 3; ++k) {
         d.n[k] = k < user.dim ? user.n[k] : 1;
         d.m[k] = k < kg.dim ? kg.n[k] : 1;
-        d.user_cells *= d.n[k];
-        d.kernel_cells *= d.m[k];
     }
+    d.user_rows = (int64_t)user.ncomp * d.n[1] * d.n[2];
+    d.kernel_rows = (int64_t)user.ncomp * d.m[1] * d.m[2];
     return d;
 }
 }  // namespace
@@ -1114,13 +1112,13 @@ hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtyp
                       void* dst, hipStream_t st)
 {
     const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)8192, (d.kernel_cells + 255) / 256);
+    const unsigned blocks = (unsigned)min((int64_t)65536, d.kernel_rows);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.kernel_cells,
+        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(128), 0, st, d.kernel_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
                            (double*)dst);
     else
-        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.kernel_cells,
+        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(128), 0, st, d.kernel_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
                            (float*)dst);
     return hipGetLastError();
@@ -1130,13 +1128,13 @@ hipError_t launch_unpad(const ib_grid_desc& user, const ib_grid_desc& kg, int dt
                         const void* src, void* dst, bool accumulate, hipStream_t st)
 {
     const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)8192, (d.user_cells + 255) / 256);
+    const unsigned blocks = (unsigned)min((int64_t)65536, d.user_rows);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.user_cells,
+        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(128), 0, st, d.user_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
                            (double*)dst, (int)accumulate);
     else
-        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.user_cells,
+        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(128), 0, st, d.user_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
                            (float*)dst, (int)accumulate);
     return hipGetLastError();

@@ -661,7 +661,7 @@ int reset_blocks(const SortArgs& a)
 // Few blocks: each adds its LDS histograms to the global ones with atomics.
 int keys_blocks(const SortArgs& a)
 {
-    return a.g.npts > 0 ? (int)min((int64_t)512, (a.g.npts + 255) / 256) : 0;
+    return a.g.npts > 0 ? (int)min((int64_t)1024, (a.g.npts + 255) / 256) : 0;
 }
 
 size_t keys_lds_bytes(const SortArgs& a)  // one staggering at a time

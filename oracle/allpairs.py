@@ -20,7 +20,16 @@ def phi_cosine4(r):
     return np.where(a <= 2.0, 0.25 * (1.0 + np.cos(np.pi * a / 2.0)), 0.0)
 
 
-PHI = {"peskin4": phi_peskin4, "cosine4": phi_cosine4}
+def phi_roma3(r):
+    """3-point kernel (Roma, Peskin & Berger 1999), support |r| < 3/2."""
+    a = np.abs(np.asarray(r, dtype=np.float64))
+    inner = (1.0 + np.sqrt(np.clip(1.0 - 3.0 * a * a, 0.0, None))) / 3.0
+    b = 1.0 - a
+    outer = (5.0 - 3.0 * a - np.sqrt(np.clip(1.0 - 3.0 * b * b, 0.0, None))) / 6.0
+    return np.where(a <= 0.5, inner, np.where(a <= 1.5, outer, 0.0))
+
+
+PHI = {"peskin4": phi_peskin4, "cosine4": phi_cosine4, "roma3": phi_roma3}
 
 
 def grid_points(grid, c):

@@ -27,7 +27,9 @@
  *     image.  walls is a bit mask over dimensions (bit k set: dimension k is walled).
  *
  * phi is evaluated from its piecewise closed form (Peskin 2002, the kernel reference of
- * Sec. 2): the 4-point kernel, or the cosine kernel the paper itself uses.
+ * Sec. 2): the 4-point kernel, or the cosine kernel the paper itself uses, or the 3-point
+ * kernel of Roma, Peskin & Berger (J. Comput. Phys. 153, 1999), the odd-support (s = 3)
+ * case of Fig. 1(b).
  *
  * Two independent evaluation orders are provided for the operators:
  *   tier A ("all pairs")  loops every (point, grid point) pair with the nearest periodic image;
@@ -44,6 +46,7 @@
 
 #define OR_PESKIN4 0
 #define OR_COSINE4 1
+#define OR_ROMA3 2
 
 /* ---- the one-dimensional kernel phi and its derivative ------------------------- */
 
@@ -87,13 +90,40 @@ static double dphi_cosine4(double r)
     return 0.0;
 }
 
+/* The 3-point kernel of Roma, Peskin & Berger 1999, piecewise closed form at |r|:
+ * (1 + sqrt(1 - 3 r^2)) / 3 on |r| <= 1/2, (5 - 3|r| - sqrt(1 - 3 (1 - |r|)^2)) / 6 on
+ * 1/2 <= |r| <= 3/2, zero beyond. */
+static double phi_roma3(double r)
+{
+    double a = fabs(r);
+    if (a <= 0.5)
+        return (1.0 + sqrt(1.0 - 3.0 * a * a)) / 3.0;
+    if (a <= 1.5)
+        return (5.0 - 3.0 * a - sqrt(1.0 - 3.0 * (1.0 - a) * (1.0 - a))) / 6.0;
+    return 0.0;
+}
+
+static double dphi_roma3(double r)
+{
+    double a = fabs(r), g;
+    if (a <= 0.5)
+        g = -a / sqrt(1.0 - 3.0 * a * a);
+    else if (a < 1.5)
+        g = -0.5 - (1.0 - a) / (2.0 * sqrt(1.0 - 3.0 * (1.0 - a) * (1.0 - a)));
+    else
+        g = 0.0;
+    return r < 0.0 ? -g : g;
+}
+
 double or_phi(int kernel, double r)
 {
+    if (kernel == OR_ROMA3) return phi_roma3(r);
     return kernel == OR_COSINE4 ? phi_cosine4(r) : phi_peskin4(r);
 }
 
 double or_dphi(int kernel, double r)
 {
+    if (kernel == OR_ROMA3) return dphi_roma3(r);
     return kernel == OR_COSINE4 ? dphi_cosine4(r) : dphi_peskin4(r);
 }
 

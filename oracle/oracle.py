@@ -9,7 +9,7 @@ Grid description used throughout (a plain dict, independent of the product's str
     n        cells per dimension (list of dim ints)
     length   periodic box edge per dimension (list of dim floats); h_k = length_k / n_k
     stagger  list of ncomp staggerings xi_c (each a list of dim floats in [0, 1))
-    kernel   "peskin4" or "cosine4"
+    kernel   "peskin4", "cosine4" or "roma3" (the 3-point kernel of Roma, Peskin & Berger)
     walls    optional bit mask of non-periodic dimensions (bit k: dimension k has walls)
 """
 import ctypes
@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "liboracle.so")
 _lib = None
 
-KERNELS = {"peskin4": 0, "cosine4": 1}
+KERNELS = {"peskin4": 0, "cosine4": 1, "roma3": 2}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)

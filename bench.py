@@ -209,14 +209,15 @@ def unstructured_bench(torch, ibops, wl, K):
             "steps": K, "cases": out}
 
 
-def walls_bench(torch, ibops, wl, K, dtype):
-    """The 128^3 / 10^6 workload with walls along z (a non-periodic dimension): plan update,
-    spread and interpolation per call, from events around K calls each.  The walled plan
-    runs on a grid padded by 4 ghost planes, with the caller's field copied in (zero ghost
-    values) before interpolation and out (ghost values dropped) after spreading."""
+def variant_bench(torch, ibops, wl, K, dtype, walls=0, kernel="peskin4"):
+    """The 128^3 / 10^6 workload with walls (a bit mask of non-periodic dimensions) or with
+    another one-dimensional kernel: plan update, spread and interpolation per call, from
+    events around K calls each.  A walled plan runs on a grid padded by 4 ghost planes per
+    walled dimension, with the caller's field copied in (zero ghost values) before
+    interpolation and out (ghost values dropped) after spreading."""
     dev = torch.device("cuda:0")
     g, X, F, u = wl.cube128_1m(np.float64)
-    g = dict(g, walls=4)
+    g = dict(g, walls=walls, kernel=kernel)
     Xd, Fd, ud = (torch.from_numpy(a).to(dev, dtype) for a in (X, F, u))
     n = X.shape[0]
     p = ibops.Plan(g, n, dtype, dev)
@@ -241,8 +242,11 @@ def walls_bench(torch, ibops, wl, K, dtype):
     torch.cuda.synchronize()
     stage = {name: round(float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)])), 5)
              for i, name in enumerate(["plan", "spread", "interp"])}
-    return {"workload": "128^3 MAC grid, unit box walled along z (periodic x, y), 10^6 uniform "
-                        "points at their initial positions, N(0,1) forces and grid velocities",
+    walled = "".join("xyz"[k] for k in range(3) if (walls >> k) & 1)
+    return {"workload": f"128^3 MAC grid, unit box, {kernel} kernel, "
+                        + (f"walled along {walled}" if walled else "periodic")
+                        + ", 10^6 uniform points at their initial positions, N(0,1) forces "
+                          "and grid velocities",
             "dtype": "f64" if dtype == torch.float64 else "f32", "stage_ms": stage}
 
 
@@ -379,6 +383,8 @@ def main():
                     help="skip the paper's unstructured-point test (Sec. 4.1 grid and weak series)")
     ap.add_argument("--no-walls", action="store_true",
                     help="skip the walled-grid measurement (128^3 with walls along z)")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the per-kernel measurements (4-point, cosine, 3-point; 128^3, periodic)")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="also time the step captured once in a HIP graph and replayed")
@@ -558,6 +564,7 @@ def main():
         "rbc_256": None,
         "paper_unstructured": None,
         "walls_128": None,
+        "kernels_128": None,
         "serving": None,
     }
     if not args.no_rbc:
@@ -565,7 +572,10 @@ def main():
     if not args.no_unstructured:
         out["paper_unstructured"] = unstructured_bench(torch, ibops, wl, args.steps)
     if not args.no_walls:
-        out["walls_128"] = walls_bench(torch, ibops, wl, args.steps, dtype)
+        out["walls_128"] = variant_bench(torch, ibops, wl, args.steps, dtype, walls=4)
+    if not args.no_kernels:
+        out["kernels_128"] = {k: variant_bench(torch, ibops, wl, args.steps, dtype, kernel=k)
+                              for k in ("peskin4", "cosine4", "roma3")}
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:

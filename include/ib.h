@@ -54,8 +54,14 @@ typedef enum { IB_F64 = 0, IB_F32 = 1 } ib_dtype;
 
 typedef enum {
     IB_KERNEL_PESKIN4 = 0,    /* Peskin's 4-point kernel */
-    IB_KERNEL_COSINE4 = 1     /* phi(r) = (1 + cos(pi r / 2)) / 4 on |r| <= 2 (the paper's choice) */
+    IB_KERNEL_COSINE4 = 1,    /* phi(r) = (1 + cos(pi r / 2)) / 4 on |r| <= 2 (the paper's choice) */
+    IB_KERNEL_ROMA3 = 2       /* the 3-point kernel of Roma, Peskin & Berger (1999): odd support
+                                 s = 3, Fig. 1(b).  It runs on the same plan (cells and 4x4(x4)
+                                 shift window) as the 4-point kernels: the window's fourth weight
+                                 per dimension is zero, on the side away from the nearest node. */
 } ib_kernel;
+
+#define IB_KERNEL_COUNT 3
 
 typedef struct {
     int32_t dim;              /* 2 or 3 */

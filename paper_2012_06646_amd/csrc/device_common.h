@@ -139,11 +139,12 @@ __device__ __forceinline__ T product_residual(T x, T inv_h, T inv_lo)
     return fma(x, inv_h, -t) + x * inv_lo;
 }
 
-// Square root of x in [1, 2] (the argument of the Peskin weights): the hardware reciprocal
-// square root refined by one Goldschmidt step and one Newton correction, accurate to one
-// ulp on that interval without the range handling of the general routine.  FP32 uses the
+// Square root of x in [1/4, 2] (the arguments of the 4-point and 3-point weights): the
+// hardware reciprocal square root refined by one Goldschmidt step and one Newton
+// correction, accurate to one ulp on that interval without the range handling of the
+// general routine.  FP32 uses the
 // hardware square root (one ulp).
-__device__ __forceinline__ double sqrt_1to2(double x)
+__device__ __forceinline__ double weight_sqrt(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y, h = 0.5 * y;
@@ -154,7 +155,7 @@ __device__ __forceinline__ double sqrt_1to2(double x)
     return fma(d, h, g);
 }
 
-__device__ __forceinline__ float sqrt_1to2(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float weight_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ---- one-dimensional kernel weights for the four shifts sigma = -1, 0, 1, 2 --------------
 // w[k] = phi(sigma_k - r) for a point at fractional offset r in [0, 1) of its cell.
@@ -171,22 +172,37 @@ __device__ __forceinline__ void weights4(T r, T w[4])
         w[1] = q + q * c;
         w[2] = q + q * s;
         w[3] = q - q * c;
-    } else {
+    } else if constexpr (KERN == IB_KERNEL_PESKIN4) {
         // Peskin 4-point, with s = sqrt(1 + 4r - 4r^2): phi(-1-r) = (3 - 2r - s)/8,
         // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = (1 + 2r - s)/8.
         // The two differences lose relative (not absolute) accuracy when a weight is
         // tiny, which leaves every weighted sum accurate to working precision.
-        const T s = sqrt_1to2(T(1) + T(4) * r * (T(1) - r));
+        const T s = weight_sqrt(T(1) + T(4) * r * (T(1) - r));
         const T a = T(3) - T(2) * r;
         const T b = T(1) + T(2) * r;
         w[0] = (a - s) * T(0.125);
         w[1] = (a + s) * T(0.125);
         w[2] = (b + s) * T(0.125);
         w[3] = (b - s) * T(0.125);
+    } else {
+        // 3-point kernel.  With m the signed offset of the point from its nearest node
+        // (m = r or r - 1, |m| <= 1/2) and s = sqrt(1 - 3 m^2): the nearest node weighs
+        // (1 + s)/3, its lower neighbour (2 - 3m - s)/6, its upper neighbour (2 + 3m - s)/6.
+        // The nearest node is sigma = 0 for r < 1/2 and sigma = 1 otherwise; the remaining
+        // window entry (at distance >= 3/2) is zero.
+        const bool lo = r < T(0.5);
+        const T m = lo ? r : r - T(1);
+        const T s = weight_sqrt(T(1) - T(3) * m * m);
+        const T c = (T(1) + s) * T(1.0 / 3.0);
+        const T a = (T(2) - s - T(3) * m) * T(1.0 / 6.0);
+        const T b = (T(2) - s + T(3) * m) * T(1.0 / 6.0);
+        w[0] = lo ? a : T(0);
+        w[1] = lo ? c : a;
+        w[2] = lo ? b : c;
+        w[3] = lo ? T(0) : b;
     }
 }
 
-// a mod n for a in [-n, 2n) (unwrapped tile and halo coordinates), without division.
 // Derivatives d w[k] / d r of the four weights of weights4 (r increases with X).
 template <typename T, int KERN>
 __device__ __forceinline__ void dweights4(T r, T dw[4])
@@ -200,7 +216,7 @@ __device__ __forceinline__ void dweights4(T r, T dw[4])
         dw[1] = -q * s;
         dw[2] = q * c;
         dw[3] = q * s;
-    } else {
+    } else if constexpr (KERN == IB_KERNEL_PESKIN4) {
         // with s = sqrt(1 + 4r - 4r^2), ds/dr = (2 - 4r) / s
         const T s = sqrt(T(1) + T(4) * r * (T(1) - r));
         const T ds = (T(2) - T(4) * r) / s;
@@ -208,9 +224,22 @@ __device__ __forceinline__ void dweights4(T r, T dw[4])
         dw[1] = (T(-2) + ds) * T(0.125);
         dw[2] = (T(2) + ds) * T(0.125);
         dw[3] = (T(2) - ds) * T(0.125);
+    } else {
+        // 3-point kernel (see weights4): dm/dr = 1 and ds/dm = -3m / s.
+        const bool lo = r < T(0.5);
+        const T m = lo ? r : r - T(1);
+        const T ds = T(-3) * m / sqrt(T(1) - T(3) * m * m);
+        const T dc = ds * T(1.0 / 3.0);
+        const T da = (T(-3) - ds) * T(1.0 / 6.0);
+        const T db = (T(3) - ds) * T(1.0 / 6.0);
+        dw[0] = lo ? da : T(0);
+        dw[1] = lo ? dc : da;
+        dw[2] = lo ? db : dc;
+        dw[3] = lo ? T(0) : db;
     }
 }
 
+// a mod n for a in [-n, 2n) (unwrapped tile and halo coordinates), without division.
 __device__ __forceinline__ int wrap_small(int a, int n)
 {
     a = a < 0 ? a + n : a;

@@ -30,7 +30,7 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     if (!g) return IB_ERR_ARG;
     if (g->dim != 2 && g->dim != 3) return IB_ERR_UNSUPPORTED;
     if (dtype != IB_F64 && dtype != IB_F32) return IB_ERR_UNSUPPORTED;
-    if (g->kernel != IB_KERNEL_PESKIN4 && g->kernel != IB_KERNEL_COSINE4) return IB_ERR_UNSUPPORTED;
+    if (g->kernel < 0 || g->kernel >= IB_KERNEL_COUNT) return IB_ERR_UNSUPPORTED;
     if (g->ncomp < 1 || g->ncomp > 3) return IB_ERR_ARG;
     if (npts < 0) return IB_ERR_ARG;
     if (npts > MAX_POINTS) return IB_ERR_UNSUPPORTED;

@@ -64,7 +64,7 @@ struct ib_server_s {
     bool slot_busy[MAX_INFLIGHT];
     // With use_graph: one graph per slot and (dimension, kernel), captured on first use; its
     // grids are fixed and its kernels loop over the batch's virtual blocks.
-    hipGraphExec_t graphs[MAX_INFLIGHT][2][2];
+    hipGraphExec_t graphs[MAX_INFLIGHT][2][IB_KERNEL_COUNT];
     std::chrono::steady_clock::time_point t0;
 
     std::mutex mu;
@@ -187,7 +187,7 @@ struct ib_server_s {
     // the flags.  The header's host copy is already in the slot's staging buffer.
     int32_t graph_launch(int slot, const BatchLaunch& exact)
     {
-        const int di = exact.dim == 3 ? 1 : 0, ki = exact.kernel == IB_KERNEL_COSINE4 ? 1 : 0;
+        const int di = exact.dim == 3 ? 1 : 0, ki = exact.kernel;
         hipGraphExec_t& ge = graphs[slot][di][ki];
         if (!ge) {
             char* header = arena + (size_t)slot * header_bytes;
@@ -356,7 +356,7 @@ void ib_server_destroy(ib_server s)
     for (int i = 0; i < MAX_INFLIGHT; ++i) {
         (void)hipEventDestroy(s->events[i]);
         for (int d = 0; d < 2; ++d)
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < IB_KERNEL_COUNT; ++k)
                 if (s->graphs[i][d][k]) (void)hipGraphExecDestroy(s->graphs[i][d][k]);
     }
     (void)hipStreamDestroy(s->stream);

@@ -31,10 +31,23 @@
 // the point's components are accumulated in registers in tensor-product order and
 // written together.
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
 namespace ibk {
+
+// Calls f with the kernel id as a compile-time constant (std::integral_constant), so each
+// launch site instantiates its kernels once per supported one-dimensional kernel.
+template <typename F>
+hipError_t with_kernel(int kernel, F&& f)
+{
+    switch (kernel) {
+    case IB_KERNEL_COSINE4: return f(std::integral_constant<int, IB_KERNEL_COSINE4>{});
+    case IB_KERNEL_ROMA3: return f(std::integral_constant<int, IB_KERNEL_ROMA3>{});
+    default: return f(std::integral_constant<int, IB_KERNEL_PESKIN4>{});
+    }
+}
 
 // Point index from a permutation entry, kept inside [0, n) so that no data can steer a
 // load or store out of bounds (a valid permutation is never changed by this).
@@ -981,33 +994,30 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
     }
 }
 
+template <typename T, int D, int K>
+void grad_launch(const OpArgs& a, const void* W, void* dX, int accumulate, unsigned nb,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL((interp_grad_kernel<T, D, K>), dim3(nb), dim3(256), 0, st, a,
+                       (const T*)W, (T*)dX, accumulate);
+}
+
 hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
                               int accumulate, hipStream_t st)
 {
     if (a.g.npts == 0) return hipSuccess;
     const unsigned nb = (unsigned)min((int64_t)65536, (a.g.npts + 255) / 256);
-#define IBK_GRAD_LAUNCH(T, D, K)                                                              \
-    hipLaunchKernelGGL((interp_grad_kernel<T, D, K>), dim3(nb), dim3(256), 0, st, a,           \
-                       (const T*)W, (T*)dX, accumulate)
-    if (dtype == IB_F64) {
-        if (a.g.dim == 3) {
-            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(double, 3, IB_KERNEL_COSINE4);
-            else IBK_GRAD_LAUNCH(double, 3, IB_KERNEL_PESKIN4);
+    return with_kernel(kernel, [&](auto K) {
+        constexpr int KN = decltype(K)::value;
+        if (dtype == IB_F64) {
+            if (a.g.dim == 3) grad_launch<double, 3, KN>(a, W, dX, accumulate, nb, st);
+            else grad_launch<double, 2, KN>(a, W, dX, accumulate, nb, st);
         } else {
-            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(double, 2, IB_KERNEL_COSINE4);
-            else IBK_GRAD_LAUNCH(double, 2, IB_KERNEL_PESKIN4);
+            if (a.g.dim == 3) grad_launch<float, 3, KN>(a, W, dX, accumulate, nb, st);
+            else grad_launch<float, 2, KN>(a, W, dX, accumulate, nb, st);
         }
-    } else {
-        if (a.g.dim == 3) {
-            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(float, 3, IB_KERNEL_COSINE4);
-            else IBK_GRAD_LAUNCH(float, 3, IB_KERNEL_PESKIN4);
-        } else {
-            if (kernel == IB_KERNEL_COSINE4) IBK_GRAD_LAUNCH(float, 2, IB_KERNEL_COSINE4);
-            else IBK_GRAD_LAUNCH(float, 2, IB_KERNEL_PESKIN4);
-        }
-    }
-#undef IBK_GRAD_LAUNCH
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1335,11 +1345,11 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
 template <typename T>
 void batch_ops_by_shape(const BatchLaunch& b, hipStream_t st)
 {
-    const bool cos = b.kernel == IB_KERNEL_COSINE4;
-    if (b.dim == 3) cos ? batch_ops_dispatch<T, 3, IB_KERNEL_COSINE4>(b, st)
-                        : batch_ops_dispatch<T, 3, IB_KERNEL_PESKIN4>(b, st);
-    else cos ? batch_ops_dispatch<T, 2, IB_KERNEL_COSINE4>(b, st)
-             : batch_ops_dispatch<T, 2, IB_KERNEL_PESKIN4>(b, st);
+    with_kernel(b.kernel, [&](auto K) {
+        if (b.dim == 3) batch_ops_dispatch<T, 3, decltype(K)::value>(b, st);
+        else batch_ops_dispatch<T, 2, decltype(K)::value>(b, st);
+        return hipSuccess;
+    });
 }
 }  // namespace
 
@@ -1402,20 +1412,18 @@ hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st)
 
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st)
 {
-    if (dtype == IB_F64)
-        return kernel == IB_KERNEL_COSINE4 ? spread_dispatch<double, IB_KERNEL_COSINE4>(a, st)
-                                           : spread_dispatch<double, IB_KERNEL_PESKIN4>(a, st);
-    return kernel == IB_KERNEL_COSINE4 ? spread_dispatch<float, IB_KERNEL_COSINE4>(a, st)
-                                       : spread_dispatch<float, IB_KERNEL_PESKIN4>(a, st);
+    return with_kernel(kernel, [&](auto K) {
+        return dtype == IB_F64 ? spread_dispatch<double, decltype(K)::value>(a, st)
+                               : spread_dispatch<float, decltype(K)::value>(a, st);
+    });
 }
 
 hipError_t launch_interp(const OpArgs& a, int dtype, int kernel, hipStream_t st)
 {
-    if (dtype == IB_F64)
-        return kernel == IB_KERNEL_COSINE4 ? interp_dispatch<double, IB_KERNEL_COSINE4>(a, st)
-                                           : interp_dispatch<double, IB_KERNEL_PESKIN4>(a, st);
-    return kernel == IB_KERNEL_COSINE4 ? interp_dispatch<float, IB_KERNEL_COSINE4>(a, st)
-                                       : interp_dispatch<float, IB_KERNEL_PESKIN4>(a, st);
+    return with_kernel(kernel, [&](auto K) {
+        return dtype == IB_F64 ? interp_dispatch<double, decltype(K)::value>(a, st)
+                               : interp_dispatch<float, decltype(K)::value>(a, st);
+    });
 }
 
 }  // namespace ibk

@@ -19,7 +19,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 IB_F64, IB_F32 = 0, 1
-KERNELS = {"peskin4": 0, "cosine4": 1}
+KERNELS = {"peskin4": 0, "cosine4": 1, "roma3": 2}
 STATUS = {0: "IB_OK", -1: "IB_ERR_ARG", -2: "IB_ERR_OOM", -3: "IB_ERR_HIP",
           -4: "IB_ERR_UNSUPPORTED", -5: "IB_ERR_BUSY", -6: "IB_ERR_DEVICE_FLAG", 1: "IB_PENDING"}
 

@@ -42,7 +42,7 @@ def gpu_loss_grads(ag, g, X, F, u, gfield, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("kernel", ["peskin4", "cosine4"])
+@pytest.mark.parametrize("kernel", ["peskin4", "cosine4", "roma3"])
 def test_loss_gradients_match_oracle(mods, orc, dtype, kernel):
     ib, ag = mods
     g = wl.grid(3, [24, 20, 16], [1.2, 1.0, 0.8], kernel=kernel)

@@ -370,7 +370,7 @@ def test_interpolate_advect_equals_two_calls(ib, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("kernel", ["peskin4", "cosine4"])
+@pytest.mark.parametrize("kernel", ["peskin4", "cosine4", "roma3"])
 def test_interp_tiles_ragged_grid(ib, orc, dtype, kernel):
     """Interpolation of a dense point set on a grid whose sizes are not multiples of the
     interpolation tile (16 x 16 x 8 cells): the LDS-staged path, against the oracle, against

@@ -134,7 +134,8 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->sp_tile = g->dim != 3 ? 0
                  : (tuning && tuning->spread_tile > 0) ? tuning->spread_tile - 1
                                                        : builtin_spread_shape(dtype);
-    spread_tiles(g->dim, L->sp_tile, g->n, tiles);
+    int slow;
+    spread_tiles(g->dim, L->sp_tile, g->n, tiles, &slow);
     L->sp_tiles = tiles[0] * tiles[1] * tiles[2] * g->ncomp;
     L->split = spread_split(n, L->sp_tiles, tuning ? tuning->split_points : 0);
     L->partial = take(L->split > 1 ? (size_t)L->split * L->sp_tiles *

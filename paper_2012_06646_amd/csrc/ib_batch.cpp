@@ -98,7 +98,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.u = J.u;
         a.U = J.U;
         a.accumulate = 0;
-        spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles);
+        spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles, &a.tile_slow);
 
         const SortArgs& sa = b.sa;
         const int64_t n = J.npts;

@@ -126,6 +126,7 @@ struct OpArgs {
     void* U;
     int accumulate;
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
+    int tile_slow;               // dimension whose tile index varies slowest (spread_tiles)
     double* partial;             // split spreading: partial tile sums
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     void* Xadv;                  // interpolation: also advance these positions (or null)
@@ -191,7 +192,7 @@ int interp_tiles(int dim, const int n[3], int64_t npts);
 // lets four blocks share a CU.  FP64 plans use 32x16x13 (two waves per SIMD either way).
 constexpr int SPREAD_TILE_SHAPES = 3;
 constexpr int builtin_spread_shape(int32_t dtype) { return dtype == IB_F32 ? 1 : 0; }
-void spread_tiles(int dim, int shape, const int n[3], int tiles[3]);
+void spread_tiles(int dim, int shape, const int n[3], int tiles[3], int* slow);
 // Cells of one spreading tile, and the number of blocks that share a tile (1 .. SPLIT_MAX)
 // for npts points over ntiles (tiles x components) tiles: a dense point set on a small grid
 // would otherwise leave most of the GPU idle.  split_points as in ib_tuning.  The partial

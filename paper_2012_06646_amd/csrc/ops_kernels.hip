@@ -1094,14 +1094,18 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // points, so interpolation reads nothing there), unpad copies the interior back out and
 // drops the ghost values that spreading wrote.
 // ---------------------------------------------------------------------------------------
-// One block per grid row (component, z, y), its threads along x: the row's indices are
-// worked out once, not per value.
+// One wave per grid row (component, z, y), four rows per block, lanes along x with two
+// values in flight per lane: the row's indices are worked out once, not per value.
+constexpr int PAD_ROWS_PER_BLOCK = 4;
+
 template <typename T>
-__global__ __launch_bounds__(128) void pad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
+__global__ __launch_bounds__(256) void pad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
                                                   int m1, int m2, const T* __restrict__ src,
                                                   T* __restrict__ dst)
 {
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {  // rows of the padded field
+    const int lane = lane_id();
+    for (int64_t r = (int64_t)blockIdx.x * PAD_ROWS_PER_BLOCK + wave_id(); r < rows;
+         r += (int64_t)gridDim.x * PAD_ROWS_PER_BLOCK) {  // rows of the padded field
         const int y = (int)(r % m1);
         const int64_t cz = r / m1;
         const int z = (int)(cz % m2);
@@ -1109,24 +1113,41 @@ __global__ __launch_bounds__(128) void pad_kernel(int64_t rows, int n0, int n1, 
         const bool inside = y < n1 && z < n2;
         const int64_t srow = inside ? ((c * n2 + z) * n1 + y) * n0 : 0;
         T* __restrict__ d = dst + r * m0;
-        for (int x = threadIdx.x; x < m0; x += blockDim.x)
-            d[x] = (inside && x < n0) ? src[srow + x] : T(0);
+        for (int x = lane; x < m0; x += 128) {
+            const int x2 = x + 64;
+            const T v0 = (inside && x < n0) ? src[srow + x] : T(0);
+            const T v1 = (inside && x2 < n0) ? src[srow + x2] : T(0);
+            d[x] = v0;
+            if (x2 < m0) d[x2] = v1;
+        }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(128) void unpad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
+__global__ __launch_bounds__(256) void unpad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
                                                     int m1, int m2, const T* __restrict__ src,
                                                     T* __restrict__ dst, int accumulate)
 {
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {  // rows of the caller's field
+    const int lane = lane_id();
+    for (int64_t r = (int64_t)blockIdx.x * PAD_ROWS_PER_BLOCK + wave_id(); r < rows;
+         r += (int64_t)gridDim.x * PAD_ROWS_PER_BLOCK) {  // rows of the caller's field
         const int y = (int)(r % n1);
         const int64_t cz = r / n1;
         const int z = (int)(cz % n2);
         const int64_t c = cz / n2;
         const T* __restrict__ s = src + ((c * m2 + z) * m1 + y) * m0;
         T* __restrict__ d = dst + r * n0;
-        for (int x = threadIdx.x; x < n0; x += blockDim.x) d[x] = accumulate ? d[x] + s[x] : s[x];
+        for (int x = lane; x < n0; x += 128) {
+            const int x2 = x + 64;
+            const bool two = x2 < n0;
+            T v0 = s[x], v1 = two ? s[x2] : T(0);
+            if (accumulate) {
+                v0 += d[x];
+                if (two) v1 += d[x2];
+            }
+            d[x] = v0;
+            if (two) d[x2] = v1;
+        }
     }
 }
 
@@ -1153,13 +1174,14 @@ hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtyp
                       void* dst, hipStream_t st)
 {
     const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)65536, d.kernel_rows);
+    const unsigned blocks = (unsigned)min((int64_t)65536,
+                                          (d.kernel_rows + PAD_ROWS_PER_BLOCK - 1) / PAD_ROWS_PER_BLOCK);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(128), 0, st, d.kernel_rows,
+        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.kernel_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
                            (double*)dst);
     else
-        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(128), 0, st, d.kernel_rows,
+        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.kernel_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
                            (float*)dst);
     return hipGetLastError();
@@ -1169,13 +1191,14 @@ hipError_t launch_unpad(const ib_grid_desc& user, const ib_grid_desc& kg, int dt
                         const void* src, void* dst, bool accumulate, hipStream_t st)
 {
     const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)65536, d.user_rows);
+    const unsigned blocks = (unsigned)min((int64_t)65536,
+                                          (d.user_rows + PAD_ROWS_PER_BLOCK - 1) / PAD_ROWS_PER_BLOCK);
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(128), 0, st, d.user_rows,
+        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.user_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
                            (double*)dst, (int)accumulate);
     else
-        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(128), 0, st, d.user_rows,
+        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.user_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
                            (float*)dst, (int)accumulate);
     return hipGetLastError();

@@ -432,3 +432,21 @@ def test_thin_slab_grid(ib, orc, dtype):
     m = 3000
     p_small = ib.Plan(g, m, dtype).update(to_dev(Xc[:m], dtype))
     assert torch.equal(p_small.interpolate(ud), U[:m])
+
+
+# Grids whose tiles vary in each of the three orders (the slowest tile dimension is z unless
+# its last row of tiles is at most half full): 64 x 40 x 16 spreads with x slowest in FP64
+# (y in FP32), 48 x 48 x 16 with y slowest, and 160 x 88 x 36 interpolates through LDS tiles
+# (300 of them) with x slowest.
+TILE_ORDER_CASES = [([64, 40, 16], [1.0, 0.625, 0.25], 20000),
+                    ([48, 48, 16], [1.0, 1.0, 1 / 3], 20000),
+                    ([160, 88, 36], [1.0, 0.55, 0.225], 80000)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("ci", range(len(TILE_ORDER_CASES)))
+def test_tile_orders(ib, orc, ci, dtype):
+    n, L, npts = TILE_ORDER_CASES[ci]
+    g = wl.grid(3, n, L)
+    X, F, u = wl.uniform_case(g, npts, 600 + ci)
+    check_ops(ib, orc, g, X, F, u, dtype, f"tile order {n}")

@@ -99,6 +99,36 @@ def cpu_baseline(g, X, F, u, sample):
                       f"staggering, spread, interpolate), single thread, {dt:.1f} s"}
 
 
+def cpu_baseline_threads(g, X, F, u, sample, threads):
+    """The same oracle calls on the host's cores: the points split into `threads` contiguous
+    chunks, one thread each (the oracle's C functions release the GIL).  Keys and
+    interpolation per chunk; one stable sort per staggering of all the keys; spreading per
+    chunk into a grid of its own, the chunk grids then added in chunk order."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import oracle as orc
+    orc.lib()
+    Xs, Fs = np.asarray(X[:sample], np.float64), np.asarray(F[:sample], np.float64)
+    uu = np.asarray(u, np.float64)
+    cuts = np.linspace(0, sample, threads + 1).astype(np.int64)
+    chunks = list(zip(cuts[:-1], cuts[1:]))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        for xi in g["stagger"]:
+            parts = list(ex.map(lambda ab, xi=xi: orc.keys(g, Xs[ab[0]:ab[1]], xi)[0], chunks))
+            orc.plan(np.concatenate(parts))
+        grids = list(ex.map(lambda ab: orc.spread(g, Xs[ab[0]:ab[1]], Fs[ab[0]:ab[1]]), chunks))
+        f = grids[0]
+        for part in grids[1:]:
+            f = f + part
+        U = np.concatenate(list(ex.map(lambda ab: orc.interp(g, Xs[ab[0]:ab[1]], uu), chunks)))
+    dt = time.perf_counter() - t0
+    assert f.shape[0] == len(g["stagger"]) and U.shape[0] == sample
+    return {"value": sample / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {sample} points of the same workload (one step: keys+sort per "
+                      f"staggering, spread, interpolate), points split over {threads} threads, "
+                      f"{dt:.1f} s"}
+
+
 def rbc_bench(torch, ibops, wl, K):
     """Red-blood-cell surfaces: 64 um periodic box on a 256^3 MAC grid (h = 0.25 um), 1111
     biconcave cells of 2562 vertices (2,846,382 points, FP32), smooth forces.  A step is plan
@@ -561,6 +591,7 @@ def main():
         "host_wall_s": round(t_host, 4),
         "roofline": roofline,
         "cpu_baseline": None,
+        "cpu_baseline_threads": None,
         "rbc_256": None,
         "paper_unstructured": None,
         "walls_128": None,
@@ -579,8 +610,10 @@ def main():
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, X0.astype(np.float32 if b == 4 else np.float64)
-                                           .astype(np.float64), F, u, min(args.cpu_sample, npts))
+        Xh = X0.astype(np.float32 if b == 4 else np.float64).astype(np.float64)
+        out["cpu_baseline"] = cpu_baseline(g, Xh, F, u, min(args.cpu_sample, npts))
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        out["cpu_baseline_threads"] = cpu_baseline_threads(g, Xh, F, u, npts, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -46,3 +46,12 @@ def test_traffic_is_read_only_for_matching_kernel_sources(tmp_path, monkeypatch)
     assert bench.measured_traffic("interp", "f64") is None
     f.write_text("kernel sources sha256: 0000000000000000\ntraffic f64 spread: 123456 bytes\n")
     assert bench.measured_traffic("spread", "f64") is None
+
+
+def test_threaded_cpu_baseline_runs_the_oracle_on_chunks():
+    import bench
+    from paper_2012_06646_amd import workloads as wl
+    g = wl.grid(3, 16, 1.0)
+    X, F, u = wl.uniform_case(g, 3000, 77)
+    r = bench.cpu_baseline_threads(g, X, F, u, 3000, 3)
+    assert r["cores"] == 3 and r["kind"] == "oracle" and r["value"] > 0

@@ -160,8 +160,13 @@ int32_t ib_plan_create_tuned(const ib_grid_desc *grid, int32_t dtype, int64_t np
  * W = prod_k phi((x_{i,k} - X_{j,k}) / h_k) taken at the nearest periodic image.  F is
  * (npts x ncomp) device, already multiplied by the Lagrangian weights dtheta_j.  f is
  * (ncomp x grid) device; overwritten, or added to when accumulate != 0.  Every grid value
- * is written exactly once; no floating-point atomics are used and the result is bitwise
- * reproducible run to run. */
+ * is written exactly once.  The sum at each grid value is exact integer arithmetic on its
+ * contributions F_{j,c} W, each rounded once to a multiple of 2^-S, where S depends only on
+ * max_j |F_{j,c}| and the point counts of the value's tile: so no floating-point atomics
+ * are used and the result is bitwise reproducible run to run, whatever the order of work.
+ * The rounding adds at most 2^-(S+1) per contribution, below 2^-52 max_j |F_{j,c}| times the
+ * bound on contributions per grid value.  A non-finite force makes its component's values
+ * NaN. */
 int32_t ib_spread(ib_plan plan, const void *F, void *f, int32_t accumulate, void *stream);
 
 /* Interpolation, eq. (disc-interp): U_{j,c} = sum_i W_{c,i,j} u_c(x_i).  u (ncomp x grid)

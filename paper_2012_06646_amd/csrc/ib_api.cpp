@@ -129,6 +129,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     const size_t b = dtype == IB_F64 ? 8 : 4;
     L->Xs = take((size_t)n * g->dim * b);
     L->Us = take(g->dim == 3 ? (size_t)n * 2 * b : 0);
+
     int tiles[3];
     // ib_tuning.spread_tile: 0 = the built-in shape of the precision, k = shape k - 1.
     L->sp_tile = g->dim != 3 ? 0
@@ -139,8 +140,10 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->sp_tiles = tiles[0] * tiles[1] * tiles[2] * g->ncomp;
     L->split = spread_split(n, L->sp_tiles, tuning ? tuning->split_points : 0);
     L->partial = take(L->split > 1 ? (size_t)L->split * L->sp_tiles *
-                                         spread_tile_cells(g->dim, L->sp_tile) * sizeof(double)
+                                         spread_tile_cells(g->dim, L->sp_tile) * sizeof(long long)
                                    : 0);
+    L->tile_shift = take(L->split > 1 ? (size_t)L->sp_tiles * sizeof(int32_t) : 0);
+    L->fmax = take((size_t)3 * FMAX_PARTS * sizeof(unsigned long long));
     // Everything from here to zero_end is cleared at every update.
     L->zero_begin = off;
     L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
@@ -263,7 +266,10 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     d.q = (int32_t*)(base + L.q);
     d.Xs = base + L.Xs;
     d.Us = base + L.Us;
-    d.partial = (double*)(base + L.partial);
+
+    d.partial = (long long*)(base + L.partial);
+    d.tile_shift = (int32_t*)(base + L.tile_shift);
+    d.fmax = (unsigned long long*)(base + L.fmax);
     d.hist = (uint32_t*)(base + L.hist);
     d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
@@ -422,7 +428,10 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->X = p->X;
     a->Xs = p->sa.d.Xs;
     a->Us = p->sa.d.Us;
+
     a->partial = p->sa.d.partial;
+    a->tile_shift = p->sa.d.tile_shift;
+    a->fmax = p->sa.d.fmax;
 }
 
 // The caller's grid field u, or (walled plans) its copy padded with zero ghost values.

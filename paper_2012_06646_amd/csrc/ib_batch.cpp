@@ -93,7 +93,10 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.Xs = p.sa.d.Xs;
         a.F = J.F;
         a.Us = p.sa.d.Us;
+
         a.partial = p.sa.d.partial;
+        a.tile_shift = p.sa.d.tile_shift;
+        a.fmax = p.sa.d.fmax;
         a.f = J.f;
         a.u = J.u;
         a.U = J.U;
@@ -103,6 +106,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         const SortArgs& sa = b.sa;
         const int64_t n = J.npts;
         counts[BS_RESET] = reset_blocks(sa);
+        counts[BS_FMAX] = J.f ? FMAX_PARTS : 0;
         counts[BS_KEYS] = keys_blocks(sa);
         for (int q = 0; q < BATCH_MAX_PASSES; ++q)
             counts[BS_SORT0 + q] = (n > 0 && q < sa.npass) ? (int)sa.ntiles : 0;

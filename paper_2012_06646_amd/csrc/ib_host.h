@@ -35,7 +35,7 @@ struct Layout {
     int nstag, npass, rbits, rows, nbx, seg_ipt;
     int64_t ntiles, nseg_tiles, nscan_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
-    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, zero_begin, hist,
+    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, tile_shift, fmax, zero_begin, hist,
         sort_status, seg_status, scan_status, counters, flag, zero_end, gpad, total;
 };
 

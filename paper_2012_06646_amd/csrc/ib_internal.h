@@ -55,7 +55,9 @@ struct PlanDev {
     uint32_t* scan_status; // [nstag][npass][nscan_tiles] look-back words of the count scans
     void* Xs;              // [n][dim] positions in the sorted order of staggering 0
     void* Us;              // [n][2] interpolation: the first components in that order
-    double* partial;       // [tiles][split][tile cells] partial tile sums (split > 1 only)
+    long long* partial;    // [tiles][split][tile cells] partial fixed-point tile sums (split > 1 only)
+    int32_t* tile_shift;   // [tiles] fixed-point scale exponent of each split tile
+    unsigned long long* fmax;  // [3][FMAX_BLOCKS] partial maxima of |F| per component
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
@@ -127,7 +129,9 @@ struct OpArgs {
     int accumulate;
     int tiles[3];                // tiles per dimension (tiles[2] = 1 in 2-D)
     int tile_slow;               // dimension whose tile index varies slowest (spread_tiles)
-    double* partial;             // split spreading: partial tile sums
+    long long* partial;          // split spreading: partial fixed-point tile sums
+    int32_t* tile_shift;         //   and each split tile's scale exponent
+    const unsigned long long* fmax;  // partial maxima of |F| per component (fmax_kernel)
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     void* Xadv;                  // interpolation: also advance these positions (or null)
     double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len
@@ -146,6 +150,7 @@ constexpr int BATCH_RBITS = 8;       // one radix digit width for every job of a
 constexpr int BATCH_MAX_PASSES = 4;  // ceil(31 / 8)
 enum BatchStage {
     BS_RESET = 0,
+    BS_FMAX,   // force maxima of every spreading job
     BS_KEYS,
     BS_SORT0,  // BS_SORT0 + p: radix pass p
     BS_SEG = BS_SORT0 + BATCH_MAX_PASSES,
@@ -214,7 +219,9 @@ hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, int s, hipSt
 // the positions in that order (used for staggering 0 only).
 hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,
                                hipStream_t st);
+// Spreading, preceded by the pass that finds the force maxima (fmax_kernel).
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st);
+constexpr int FMAX_PARTS = 1024;  // partial maxima per component (blocks of fmax_kernel)
 hipError_t launch_interp(const OpArgs& a, int dtype, int kernel, hipStream_t st);
 hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
                               int accumulate, hipStream_t st);

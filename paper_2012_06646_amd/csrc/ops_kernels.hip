@@ -8,24 +8,16 @@
 // from its staggering-0 cell by at most one per dimension, so the tiles below widen their
 // halos by that offset.
 //
-// Spreading (eq. disc-spread, Sec. 2; parallel algorithm Alg. 4, Sec. 3.3).  Each block
+// Spreading (eq. disc-spread, Sec. 2; parallel algorithm Alg. 4, Sec. 3.4).  Each block
 // owns a tile of one component's grid and produces every value of it exactly once.  It
 // reads the sorted points whose cells can reach the tile (contiguous sorted ranges per
-// x-row, since keys are x-fastest), one source plane at a time.  A wave takes 64
-// consecutive points of a plane and computes their weights; lanes holding the same
-// component-c cell form a group (adjacent lanes for staggering 0, found by matching cell
-// codes with ballots otherwise).  The group's sum over its points of the 4^d weight
-// products -- the segmented reduce of Alg. 4, for all shifts at once -- is formed in
-// registers (by one lane, or for a crowded cell by a few sub-leader lanes that add in
-// separate rounds), and added into an FP64 LDS copy of the tile with LDS atomic adds.  The
-// lanes adding in one round hold distinct cells, so for one shift the active lanes of an
-// instruction hit distinct addresses; waves of a block work at the same time only on source
-// planes far enough apart that their targets are disjoint, and overlapping planes follow one
-// fixed order.  The order in which every grid
-// value receives its contributions is therefore fixed by the data alone, and the result is
-// bitwise reproducible; no global atomics are used.
+// x-row, since keys are x-fastest), one source plane at a time; a wave takes 64 of them,
+// one per lane, computes their separable weights and adds the 4^d products into the tile
+// held in LDS.  The sums are exact integer (fixed-point) sums, so their value does not
+// depend on the order of the additions: waves and blocks need no ordering among
+// themselves, no floating-point atomics are used, and the result is bitwise reproducible.
 //
-// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.2).  One thread per point in the sorted
+// Interpolation (eq. disc-interp; Alg. 3, Sec. 3.3).  One thread per point in the sorted
 // order of staggering 0, gathering the 4^d grid values of each component directly
 // (neighbouring lanes hold neighbouring cells, so a wave's gathers share cache lines);
 // the point's components are accumulated in registers in tensor-product order and
@@ -130,6 +122,114 @@ __device__ __forceinline__ void wave_sync()
 // ---------------------------------------------------------------------------------------
 // Spreading
 // ---------------------------------------------------------------------------------------
+//
+// Exact fixed-point accumulation.  Every contribution F_j W to a grid value of a tile is
+// rounded once to an integer multiple of 2^-S (S chosen per tile, below) and added to a
+// 64-bit integer in LDS.  Integer addition is exact and associative, so the tile's sums do
+// not depend on the order in which its points arrive: no wave waits for another, any number
+// of blocks may share a tile, and the result is the same bits on every run.  The rounding
+// of a contribution is the only error beyond those of the weights.
+//
+// The scale.  With vmax = max_j |F_{j,c}| < 2^e (all points) and M an upper bound on the
+// contributions any one grid value of the tile receives (from the cell-block counts of its
+// source frame, see spread_body), S = min(51 - e, 62 - ceil(log2 M) - e).  Then every
+// contribution, scaled by 2^S, has magnitude below 2^51 (so one fused multiply-add with
+// 1.5 * 2^52 rounds it to an integer held in the low bits of its result), and no partial
+// sum reaches 2^62.  The rounding error of one contribution is at most
+// 2^-(S+1) <= M vmax 2^-62 (or vmax 2^-52 when M is small).  Weights are at most 1 for
+// every kernel, so |F W| <= vmax.
+
+constexpr double FX_MAGIC = 6755399441055744.0;          // 1.5 * 2^52
+constexpr long long FX_MAGIC_BITS = 0x4338000000000000LL; // its bit pattern
+constexpr unsigned long long FX_NONFINITE = 0x7FF0000000000000ull;
+
+// Nearest integer to a * b + 0 (|a b| < 2^51), as a two's-complement 64-bit word.
+__device__ __forceinline__ unsigned long long fx_round(double a, double b)
+{
+    const double t = fma(a, b, FX_MAGIC);
+    return (unsigned long long)(__double_as_longlong(t) - FX_MAGIC_BITS);
+}
+
+// Scale exponent of a tile from the bit pattern of vmax (non-negative, finite, not zero)
+// and its bound on contributions per grid value.
+__device__ __forceinline__ int fx_shift(unsigned long long vmax_bits, uint32_t nt)
+{
+    const int E = (int)((vmax_bits >> 52) & 0x7FFu);
+    const int e = (E == 0 ? 1 : E) - 1022;  // vmax < 2^e
+    const int m = nt <= 1u ? 0 : 32 - __clz((int)(nt - 1u));
+    return min(51 - e, 62 - m - e);
+}
+
+// Largest |F_{j,c}| per component, as non-negative bit patterns (a NaN or infinity compares
+// above every finite value): FMAX_PARTS blocks each write the maxima of their share of the
+// rows (read in input order, coalesced), and a spreading block takes the maximum of those
+// partial maxima.
+constexpr int SPREAD_THREADS = 512;
+
+template <typename T>
+__device__ __forceinline__ void fmax_body(const T* __restrict__ F, int64_t n, int ncomp,
+                                          unsigned long long* __restrict__ out, int bid)
+{
+    __shared__ unsigned long long s_m[3][256 / 64];
+    unsigned long long m[3] = {0ull, 0ull, 0ull};
+    const int64_t total = n * ncomp;
+    // element e of F belongs to component e mod ncomp; each thread keeps its elements'
+    // components apart with a rotating index (ncomp <= 3)
+    for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)FMAX_PARTS * blockDim.x) {
+        const int c = (int)(e % ncomp);
+        const double v = fabs((double)F[e]);  // exact for FP32
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        m[0] = (c == 0 && b > m[0]) ? b : m[0];
+        m[1] = (c == 1 && b > m[1]) ? b : m[1];
+        m[2] = (c == 2 && b > m[2]) ? b : m[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            const unsigned long long o = __shfl_xor(m[c], s, 64);
+            m[c] = o > m[c] ? o : m[c];
+        }
+        if (lane_id() == 0) s_m[c][wave_id()] = m[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long r = 0ull;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) r = s_m[threadIdx.x][w] > r ? s_m[threadIdx.x][w] : r;
+        out[threadIdx.x * FMAX_PARTS + bid] = r;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fmax_kernel(const T* __restrict__ F, int64_t n, int ncomp,
+                                                   unsigned long long* __restrict__ out)
+{
+    fmax_body<T>(F, n, ncomp, out, blockIdx.x);
+}
+
+// Maximum of the FMAX_PARTS partial maxima of component c, uniform over the block.
+template <int NT>
+__device__ __forceinline__ unsigned long long fmax_of(const unsigned long long* __restrict__ part,
+                                                      int c, unsigned long long* s_red)
+{
+    unsigned long long m = 0ull;
+    for (int i = threadIdx.x; i < FMAX_PARTS; i += NT) {
+        const unsigned long long v = part[c * FMAX_PARTS + i];
+        m = v > m ? v : m;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        const unsigned long long o = __shfl_xor(m, s, 64);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) s_red[wave_id()] = m;
+    __syncthreads();
+    unsigned long long r = 0ull;
+    for (int w = 0; w < NT / 64; ++w) r = s_red[w] > r ? s_red[w] : r;
+    __syncthreads();
+    return r;
+}
 
 // A source slice (an x-y plane of staggering-0 cells in 3-D, one x-row in 2-D) as a list
 // of sorted ranges, one per x-row piece (at most 3 pieces per row, since a tile is never
@@ -146,22 +246,17 @@ struct SliceTable {
     int32_t pref[MAXR + 1];
 };
 
-constexpr uint32_t NO_CELL = 0xFFFFFFu;
-
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 struct SpreadTile {
     static constexpr int PXS = TX + 6;  // padded row pitch of the LDS tile (x from -3 to TX + 2)
     static constexpr int NZ = (DIM == 3) ? 4 : 1;            // stencil extent in z
     static constexpr int MAXROWS = (DIM == 3) ? TY + 5 : 1;   // x-rows per slice
     static constexpr int MAXR = 3 * MAXROWS;
+    static constexpr int CELLS = PXS * TY * TZ;               // LDS tile words
     static_assert(MAXR <= 64, "one lane per range of a slice");
+    static_assert(3 * ((DIM == 3 ? TY * PXS * 8 : 0) + PXS * 8) + 24 < 65536,
+                  "stencil offsets fit the LDS instruction offset field");
     using Table = SliceTable<MAXR>;
-
-    // Per-wave LDS scratch of the chunk loop.
-    struct WaveScratch {
-        int32_t ltab[64];  // lanes of each group in rank order (cells matched by code)
-        int32_t mark[64];  // range starts inside a chunk
-    };
 
     // Range table of source slice q (frame origin ox, oy, oz; lenx cells per row, nrows
     // rows); returns the slice's point count.  Afterwards lane r < 3 * nrows holds range r's
@@ -223,6 +318,44 @@ struct SpreadTile {
         return total_pts;
     }
 
+    // Visits of source slice q without building its table (the sum over its row pieces),
+    // and the most visits of any 4-cell block of those pieces.  Called by the whole wave;
+    // both results are uniform.
+    __device__ static void count(const GeomArgs& g, const int32_t* __restrict__ cb, int q, int ox,
+                                 int oy, int oz, int lenx, int nrows, int* total, int* maxblk)
+    {
+        const int lane = lane_id();
+        const int n0 = g.n[0];
+        int cnt = 0, mb = 0;
+        if (lane < nrows) {
+            int r;
+            if (DIM == 3) r = wrap_small(oz + q, g.n[2]) * g.n[1] + wrap_small(oy + lane, g.n[1]);
+            else r = wrap_small(oy + q, g.n[1]);
+            const int64_t rb = (int64_t)r * (g.nbx + 1);
+            int done = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (done < lenx) {
+                    const int xa = wrap_small(ox + done, n0);
+                    const int len = min(lenx - done, n0 - xa);
+                    const int b0 = xa >> CBLK_SHIFT;
+                    const int b1 = (xa + len + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT;
+                    int prev = cb[rb + b0];
+                    const int first = prev;
+                    for (int b = b0 + 1; b <= b1; ++b) {
+                        const int cur = cb[rb + b];
+                        mb = max(mb, cur - prev);
+                        prev = cur;
+                    }
+                    cnt += prev - first;
+                    done += len;
+                }
+            }
+        }
+        *total = (int)wave_last_u32(wave_incl_scan_u32((uint32_t)cnt));
+        *maxblk = wave_max_i32(mb);
+    }
+
     // Range of slice position v0 + lane, for v0 < total.  The range holding v0 is the last
     // one whose first position is <= v0 (it is non-empty); the non-empty ranges starting
     // inside the chunk are marked at their offsets, and a prefix maximum over the lanes
@@ -241,90 +374,6 @@ struct SpreadTile {
         return max(m - 1, carry);
     }
 
-    __device__ static void accumulate(T acc[NZ][4][4], const T w[DIM][4])
-    {
-#pragma unroll
-        for (int iz = 0; iz < NZ; ++iz)
-#pragma unroll
-            for (int iy = 0; iy < 4; ++iy) {
-                const T cyz = (DIM == 3) ? w[1][iy] * w[2][iz] : w[1][iy];
-#pragma unroll
-                for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = fma(w[0][ix], cyz, acc[iz][iy][ix]);
-            }
-    }
-
-    // acc = the 4^d weight products of one point (a first term needs no addition).
-    __device__ static void products(T acc[NZ][4][4], const T w[DIM][4])
-    {
-#pragma unroll
-        for (int iz = 0; iz < NZ; ++iz)
-#pragma unroll
-            for (int iy = 0; iy < 4; ++iy) {
-                const T cyz = (DIM == 3) ? w[1][iy] * w[2][iz] : w[1][iy];
-#pragma unroll
-                for (int ix = 0; ix < 4; ++ix) acc[iz][iy][ix] = w[0][ix] * cyz;
-            }
-    }
-
-    static constexpr int bits_for(int v) { return v <= 1 ? 1 : 1 + bits_for((v + 1) / 2); }
-    static constexpr int XB = bits_for(TX + 6);
-    static constexpr int YB = bits_for(TY + 6);
-    static constexpr int ZB = (DIM == 3) ? bits_for(TZ + 6) : 0;
-    static constexpr int CB = XB + YB + ZB;
-    static_assert(CB <= 24, "cell code too wide");
-
-    // Lanes holding the same (tile-relative) cell as this lane, by matching the cell code
-    // bit by bit with ballots; lanes without a cell match nothing.
-    __device__ static unsigned long long match_code(uint32_t code, bool has)
-    {
-        unsigned long long m = __ballot(has);
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-            const bool bit = (code >> b) & 1u;
-            const unsigned long long bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        return has ? m : 0ull;
-    }
-
-    // Add a leader's 4^d sums into the tile with LDS atomic adds (ds_add), which apply the
-    // read-add-write inside the LDS unit, so no lane waits for a value.  The order of the
-    // additions into any tile value is still fixed: the leaders of one wave hold distinct
-    // cells, so for one shift the active lanes of an instruction hit distinct addresses;
-    // a wave's LDS instructions execute in program order; and waves working at the same
-    // time own disjoint target regions.  Tile rows are padded in x (PXS = TX + 6, target
-    // x from -3 to TX + 2), so only whole rows can fall outside the tile; those are skipped.
-    __device__ static void add_to_tile(const T acc[NZ][4][4], bool leader, int cx, int cy,
-                                       int cz, int ey, int ez, double* tile)
-    {
-        // Rows of the stencil: slice-axis offset ia (z in 3-D, y in 2-D), in-plane offset ib
-        // (y in 3-D); row (ia, ib) starts `base + (ia * TY + ib) * PXS` (3-D) or
-        // `base + ia * PXS` (2-D) elements into the tile.
-        const int zb = (DIM == 3) ? cz - 1 : 0, yb = cy - 1;
-        const int base = (zb * TY + yb) * PXS + (cx + 2);
-        bool oka[4], okb[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            oka[i] = leader && ((DIM == 3) ? (unsigned)(zb + i) < (unsigned)ez
-                                           : (unsigned)(yb + i) < (unsigned)ey);
-            okb[i] = (DIM == 3) ? (unsigned)(yb + i) < (unsigned)ey : i == 0;
-        }
-#pragma unroll
-        for (int ia = 0; ia < 4; ++ia)
-#pragma unroll
-            for (int ib = 0; ib < ((DIM == 3) ? 4 : 1); ++ib) {
-                if (oka[ia] && okb[ib]) {
-                    double* row = tile + base + ((DIM == 3) ? (ia * TY + ib) * PXS : ia * PXS);
-#pragma unroll
-                    for (int ix = 0; ix < 4; ++ix) {
-                        const double v = (DIM == 3) ? acc[ia][ib][ix] : acc[0][ia][ix];
-                        __hip_atomic_fetch_add(row + ix, v, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                }
-            }
-    }
-
     // Slice positions v0 + lane: range, key, coordinates and force (zeros past the end).
     // The sorted index is kept inside [0, n) whatever the tables hold.  Called by the whole
     // wave.
@@ -332,12 +381,16 @@ struct SpreadTile {
                                 const Table& tb, int32_t* mark, int rp, bool rn, int nranges,
                                 int total, int v0, int& rr, int32_t& key, T x[DIM], T& F)
     {
-        rr = locate(mark, rp, rn, nranges, v0);
+        // Lane l takes chunk position 4 (l mod 16) + l / 16: the LDS unit serves a wave's
+        // 64-bit additions 16 lanes at a time, and consecutive sorted points (which often
+        // share a cell, i.e. all 4^d target addresses) then fall into different groups.
+        const int pos = chunk_pos(lane_id());
+        rr = __shfl(locate(mark, rp, rn, nranges, v0), pos, 64);
         key = 0;
         F = T(0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x[k] = T(0);
-        const int v = v0 + lane_id();
+        const int v = v0 + pos;
         if (v < total) {
             const int64_t j = clamp_index(tb.base[rr] + v, a.g.npts);
             const T* __restrict__ Xs = (const T*)a.Xs;
@@ -349,31 +402,61 @@ struct SpreadTile {
         }
     }
 
-    // Reduce the slice in chunks of 64 points and add the sums into the tile.
+    __device__ static int chunk_pos(int lane) { return ((lane & 15) << 2) | (lane >> 4); }
+
+    // Add the 4^d contributions of every lane's point (lanes with has) into the tile, as
+    // fixed-point integers.  Tile rows are padded in x (PXS = TX + 6, target x from -3 to
+    // TX + 2), so only whole rows can fall outside the tile; those are skipped.
+    __device__ static void add_point(const T w[DIM][4], double Fs, bool has, int cx, int cy, int cz,
+                                     int ey, int ez, unsigned long long* tile)
+    {
+        const int zb = (DIM == 3) ? cz - 1 : 0, yb = cy - 1;
+        const int base = (zb * TY + yb) * PXS + (cx + 2);
+        double wz[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wz[i] = (DIM == 3) ? (double)w[DIM - 1][i] * Fs : 0.0;
+        bool oka[4], okb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            oka[i] = has && ((DIM == 3) ? (unsigned)(zb + i) < (unsigned)ez
+                                        : (unsigned)(yb + i) < (unsigned)ey);
+            okb[i] = (DIM == 3) ? (unsigned)(yb + i) < (unsigned)ey : i == 0;
+        }
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < ((DIM == 3) ? 4 : 1); ++ib) {
+                if (oka[ia] && okb[ib]) {
+                    const double cyz = (DIM == 3) ? (double)w[1][ib] * wz[ia] : (double)w[1][ia] * Fs;
+                    unsigned long long* row =
+                        tile + base + ((DIM == 3) ? (ia * TY + ib) * PXS : ia * PXS);
+#pragma unroll
+                    for (int ix = 0; ix < 4; ++ix)
+                        __hip_atomic_fetch_add(row + ix, fx_round((double)w[0][ix], cyz),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+    }
+
+    // Add the slice's points, in chunks of 64 (one point per lane), into the tile.
     // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
-    // staggering-0 cell + delta - off.  Within a chunk, the points of one cell form a
-    // group; its lowest lanes (sub-leaders) sum the group's contributions to all 4^d shifts
-    // in registers, pulling the other members' weights from their lanes.
-    __device__ static void reduce(const OpArgs& a, int c, const int32_t* __restrict__ sk,
-                                  const Table& tb, int rp, bool rn, int nranges, int total, int q,
-                                  const int off[3], int ex, int ey, int ez, bool same0,
-                                  double* tile, WaveScratch& ws, int k0, int kstride)
+    // staggering-0 cell + delta - off.
+    __device__ static void spread_slice(const OpArgs& a, int c, const Table& tb, int32_t* mark,
+                                        int rp, bool rn, int nranges, int total, int q,
+                                        const int off[3], int ex, int ey, int ez, int fshift,
+                                        unsigned long long* tile, int k0, int kstride)
     {
         const GeomArgs& g = a.g;
         const int lane = lane_id();
-        const unsigned long long below = (1ull << lane) - 1ull;
+        const int32_t* __restrict__ sk = a.sorted_keys;
         // Chunk data is loaded one chunk ahead, so its latency overlaps the current chunk.
         int nrr = 0;
         int32_t nkey = 0;
         T nx[DIM], nF = T(0);
-        // This block's chunks of the slice: k0, k0 + kstride, ... (all of them unless the
-        // tile is split over several blocks).
         const int step = 64 * kstride;
-        if (64 * k0 < total)
-            load(a, c, sk, tb, ws.mark, rp, rn, nranges, total, 64 * k0, nrr, nkey, nx, nF);
+        if (64 * k0 < total) load(a, c, sk, tb, mark, rp, rn, nranges, total, 64 * k0, nrr, nkey, nx, nF);
         for (int v0 = 64 * k0; v0 < total; v0 += step) {
-            const int v = v0 + lane;
-            const bool valid = v < total;
+            const bool valid = v0 + chunk_pos(lane) < total;
             const int rr = nrr;
             const int32_t key = nkey;
             T x[DIM];
@@ -381,101 +464,16 @@ struct SpreadTile {
             for (int k = 0; k < DIM; ++k) x[k] = nx[k];
             const T Fc = nF;
             if (v0 + step < total)
-                load(a, c, sk, tb, ws.mark, rp, rn, nranges, total, v0 + step, nrr, nkey, nx, nF);
+                load(a, c, sk, tb, mark, rp, rn, nranges, total, v0 + step, nrr, nkey, nx, nF);
             T w[DIM][4];
-            int cx = 0, cy = 0, cz = 0;
-            bool has = false;
-            {
-                int delta[DIM];
-                comp_weights<T, DIM, KERN>(g, c, x, w, delta);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) w[DIM - 1][i] *= Fc;
-                cx = key + tb.xo[rr] + delta[0] - off[0];
-                cy = tb.uy[rr] + delta[1] - off[1];
-                cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
-                has = valid && cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
-                      (DIM == 2 || (cz >= -2 && cz <= ez));
-            }
-            // Tile-relative cell code: x + 4, y + 4 and z + 4 in fields of XB, YB, ZB bits.
-            const uint32_t code = (uint32_t)(cx + 4) | ((uint32_t)(cy + 4) << XB) |
-                                  ((uint32_t)(cz + 4) << (XB + YB));
-            unsigned long long grp;
-            bool leader;
-            int head = lane;
-            if (same0) {
-                // Cells of staggering 0 itself: a cell's points are adjacent in sorted order,
-                // so a group runs from its first lane to the next change of cell.
-                const uint32_t prev = wave_shr1_u32(code);
-                const uint32_t hprev = wave_shr1_u32((uint32_t)has);
-                leader = has && (lane == 0 || !hprev || prev != code);
-                const unsigned long long heads = __ballot(leader);
-                const unsigned long long holes = ~__ballot(has);
-                // This lane's run starts at the highest head at or below it and ends at the
-                // next head or hole above that.
-                const unsigned long long hb = heads & ((2ull << lane) - 1ull);
-                head = hb ? 63 - __clzll((long long)hb) : lane;
-                const unsigned long long stop = (heads | holes) & ~((2ull << head) - 1ull);
-                const int end = stop ? __ffsll((long long)stop) - 1 : 64;
-                const unsigned long long upto = (end == 64) ? ~0ull : ((1ull << end) - 1ull);
-                grp = has ? (upto & ~((1ull << head) - 1ull)) : 0ull;
-            } else {
-                grp = match_code(code, has);
-                leader = has && (grp & below) == 0ull;
-            }
-            // The rank of a lane is the number of group lanes below it.  Adjacent groups hold
-            // their members in lanes head + rank; matched groups list them in the wave's lane
-            // table, one contiguous piece per group in rank order.
-            const int rank = __popcll(grp & below);
-            const int gk = __popcll(grp);
-            const int maxk = wave_max_i32(gk);
-            int gbase = 0;
-            if (!same0 && maxk > 1) {
-                const uint32_t kl = leader ? (uint32_t)gk : 0u;
-                const int goff_l = (int)(wave_incl_scan_u32(kl) - kl);
-                const int lead_lane = has ? __ffsll((long long)grp) - 1 : lane;
-                gbase = __shfl(goff_l, lead_lane, 64);
-                if (has) ws.ltab[(gbase + rank) & 63] = lane;
-                wave_sync();
-            }
-            // The first P members of a group (sub-leaders) each sum every P-th member, then
-            // add their sums into the tile in P rounds, one rank per round, so the active
-            // lanes of each round still hold distinct cells.  P ~ sqrt(largest group * m / a)
-            // balances the member rounds (cost m each) against the add rounds (cost a each,
-            // measured ~1.3 m in FP64 and ~2 m in FP32, where member rounds move half the
-            // bytes); it is uniform across the wave and depends only on the data, so the
-            // order in which every tile value receives its contributions is fixed.
-            constexpr int K1 = sizeof(T) == 8 ? 3 : 4, K2 = sizeof(T) == 8 ? 8 : 10;
-            constexpr int K3 = sizeof(T) == 8 ? 15 : 20, K4 = sizeof(T) == 8 ? 24 : 32;
-            constexpr int K5 = sizeof(T) == 8 ? 35 : 46, K6 = sizeof(T) == 8 ? 48 : 62;
-            const int P = maxk <= K1 ? 1 : maxk <= K2 ? 2 : maxk <= K3 ? 3 : maxk <= K4 ? 4
-                        : maxk <= K5 ? 5 : maxk <= K6 ? 6 : 7;
-            const bool sub = has && rank < P;
-            // Lanes other than sub-leaders compute sums that are never added.
-            T acc[NZ][4][4];
-            products(acc, w);
-            const int iters = (maxk + P - 1) / P - 1;
-            for (int j = 1; j <= iters; ++j) {
-                const int mr = rank + j * P;
-                const bool ok = sub && mr < gk;
-                const int src = !ok ? lane : same0 ? head + mr : ws.ltab[(gbase + mr) & 63];
-                T wk[DIM][4];
-#pragma unroll
-                for (int d = 0; d < DIM; ++d)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) wk[d][i] = __shfl(w[d][i], src, 64);
-                const T on = ok ? T(1) : T(0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) wk[DIM - 1][i] *= on;
-                accumulate(acc, wk);
-            }
-            wave_sync();
-            if (P == 1) {
-                add_to_tile(acc, sub, cx, cy, cz, ey, ez, tile);
-            } else {
-                for (int rr = 0; rr < P; ++rr)
-                    add_to_tile(acc, sub && rank == rr, cx, cy, cz, ey, ez, tile);
-            }
-            wave_sync();
+            int delta[DIM];
+            comp_weights<T, DIM, KERN>(g, c, x, w, delta);
+            const int cx = key + tb.xo[rr] + delta[0] - off[0];
+            const int cy = tb.uy[rr] + delta[1] - off[1];
+            const int cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
+            const bool has = valid && cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
+                             (DIM == 2 || (cz >= -2 && cz <= ez));
+            add_point(w, ldexp((double)Fc, fshift), has, cx, cy, cz, ey, ez, tile);
         }
     }
 };
@@ -496,21 +494,33 @@ __device__ __forceinline__ void spread_tile_at(const OpArgs& a, int tile_id, int
     z0 = iz * TZ;
 }
 
+// The grid value of one tile cell from its fixed-point sum: sum 2^-S h^-d, or NaN when a
+// force was not finite.
+template <typename T>
+__device__ __forceinline__ T fx_value(unsigned long long acc, int fshift, bool finite, double scale)
+{
+    if (!finite) return T(__builtin_nan(""));
+    return (T)(ldexp((double)(long long)acc, -fshift) * scale);
+}
+
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
-    // Tile rows padded in x (3 before, 3 after).  The tile accumulates in FP64 for both
-    // precisions: FP64 LDS atomic adds run at full LDS rate on gfx950, FP32 ones do not.
-    __shared__ double tile[ST::PXS * TY * TZ];
-    __shared__ typename ST::Table tables[4];
-    __shared__ typename ST::WaveScratch scratch[4];
+    constexpr int NW = SPREAD_THREADS / 64;  // waves per block
+    __shared__ unsigned long long tile[ST::CELLS];
+    __shared__ typename ST::Table tables[NW];
+    __shared__ int32_t marks[NW][64];
+    __shared__ unsigned long long s_red[NW];
+    __shared__ int s_cnt[NW];
+    __shared__ int s_mb[NW];
     const GeomArgs& g = a.g;
     // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
-    // chunk of its points and add their partial tiles at the end.  Tiles are numbered with
+    // chunk of its points and publish their partial integer sums.  Tiles are numbered with
     // the component fastest, then the three dimensions (spread_tile_at): the components of
-    // one region, and neighbouring regions, run close together and (through xcd_block) on one XCD, so the points and
-    // forces that their source frames share are read from HBM once and then from that L2.
+    // one region, and neighbouring regions, run close together and (through xcd_block) on
+    // one XCD, so the points and forces that their source frames share are read from HBM
+    // once and then from that L2.
     const int split = g.split;
     const int tile_id = bid / split, ksub = bid - tile_id * split;
     int c, x0, y0, z0;
@@ -518,11 +528,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int ex = min(TX, g.n[0] - x0), ey = min(TY, g.n[1] - y0);
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
 
-    constexpr int MAXSLICES = ((DIM == 3) ? TZ : TY) + 4;
-    __shared__ int s_done[MAXSLICES];
-    for (int i = threadIdx.x; i < ST::PXS * TY * TZ; i += blockDim.x) tile[i] = 0.0;
-    if (threadIdx.x < MAXSLICES) s_done[threadIdx.x] = 0;
-    __syncthreads();
+    for (int i = threadIdx.x; i < ST::CELLS; i += blockDim.x) tile[i] = 0ull;
 
     // Source frame: staggering-0 cells that can reach the tile for this component.
     const int hx = g.dhi[c][0] - g.dlo[c][0], hy = g.dhi[c][1] - g.dlo[c][1];
@@ -532,81 +538,79 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int lenx = ex + 3 + hx;
     const int nrows = (DIM == 3) ? ey + 3 + hy : 1;
     const int nslices = (DIM == 3) ? ez + 3 + hz : ey + 3 + hy;
-    const int nphase = 4 + ((DIM == 3) ? hz : hy);
     const int nranges = 3 * nrows;
-    const bool same0 = hx == 0 && hy == 0 && hz == 0;
     const int w = wave_id();
-    typename ST::Table& tb = tables[w];
 
-    // Slices less than nphase apart have overlapping targets; slices nphase apart do not.
-    // The slices are worked in one fixed order: by phase (q mod nphase), then by q; wave w
-    // takes positions w, w + 4, ... of that order.  A slice starts once the overlapping
-    // slices before it in the order are done (those after it wait for it in turn).  So slices
-    // that run at the same time have disjoint targets, and every tile value receives its
-    // contributions in an order fixed by the data alone.  Unlike barriers between phases,
-    // this lets a wave go on as soon as its own dependences are met.  No wave waits forever:
-    // the first unfinished position of the order has all its dependences done, and its wave
-    // has finished everything before it.
-    const int lane = lane_id();
-    for (int t = __builtin_amdgcn_readfirstlane(w); t < nslices; t += 4) {
-        int p = 0, first = 0;  // phase of position t and the first position of that phase
-        for (;;) {
-            const int cnt = (nslices - p + nphase - 1) / nphase;
-            if (t < first + cnt) break;
-            first += cnt;
-            ++p;
+    // The most contributions any grid value of the tile can receive (every split block of
+    // the tile finds the same), and the maximum force of component c: the scale of the
+    // tile.  A grid value's stencil window holds (4 + hy)(4 + hz) source rows (3-D) of at
+    // most 5 cells each, which lie in at most two 4-cell blocks of the cell-block table, so
+    // it receives at most 2 (4 + hy)(4 + hz) maxblock contributions, and never more than the
+    // tile's visit count n_t.
+    int cnt = 0, mb = 0;
+    for (int q = w; q < nslices; q += NW) {
+        int t, m;
+        ST::count(g, a.cblk, q, ox, oy, oz, lenx, nrows, &t, &m);
+        cnt += t;
+        mb = max(mb, m);
+    }
+    if (lane_id() == 0) {
+        s_cnt[w] = cnt;
+        s_mb[w] = mb;
+    }
+    const unsigned long long vmax = fmax_of<SPREAD_THREADS>(a.fmax, c, s_red);  // has barriers
+    uint32_t nt = 0, mbt = 0;
+    for (int i = 0; i < NW; ++i) {
+        nt += (uint32_t)s_cnt[i];
+        mbt = max(mbt, (uint32_t)s_mb[i]);
+    }
+    const uint32_t rows_win = (DIM == 3) ? (uint32_t)((4 + hy) * (4 + hz)) : (uint32_t)(4 + hy);
+    const uint32_t mbound = (uint32_t)min((uint64_t)nt, (uint64_t)2u * rows_win * mbt);
+    const bool finite = vmax < FX_NONFINITE;
+    const int fshift = (vmax == 0ull || !finite) ? 0 : fx_shift(vmax, mbound);
+
+    typename ST::Table& tb = tables[w];
+    if (finite) {
+        // Slices in any order: the integer sums do not depend on it.
+        for (int q = w; q < nslices; q += NW) {
+            int rp;
+            bool rn;
+            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
+            if (total > 0)
+                ST::spread_slice(a, c, tb, marks[w], rp, rn, nranges, total, q, off, ex, ey, ez,
+                                 fshift, tile, ksub, split);
+            wave_sync();
         }
-        const int q = p + nphase * (t - first);
-        // Overlapping slices of earlier phases: q - p .. q - 1 and q + nphase - p .. q + nphase - 1.
-        const int dep = lane < p ? q - p + lane : q + nphase - 2 * p + lane;
-        const bool need = lane < 2 * p && dep >= 0 && dep < nslices;
-        for (;;) {
-            const bool ok = !need || __hip_atomic_load(&s_done[need ? dep : 0], __ATOMIC_ACQUIRE,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
-            if (__ballot(!ok) == 0ull) break;
-            __builtin_amdgcn_s_sleep(1);
-        }
-        int rp;
-        bool rn;
-        const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
-        if (total > 0)
-            ST::reduce(a, c, a.sorted_keys, tb, rp, rn, nranges, total, q, off, ex, ey, ez,
-                       same0, tile, scratch[w], ksub, split);
-        wave_sync();
-        // Every lane writes the same flag (no lane-dependent branch around the loop's back
-        // edge); the release orders it after all of this wave's additions into the tile.
-        __hip_atomic_store(&s_done[q], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
 
-    T* f = (T*)a.f;
-    const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
     constexpr int CELLS = TX * TY * TZ;
     if (split > 1) {
-        // Publish this block's partial tile; split_sum_kernel adds a tile's partials in
-        // block order (a fixed order) and writes the grid values.  (A last block to arrive
-        // could add them here, but its agent-scope release and acquire write back and
-        // invalidate the XCD's L2 for every block, which cost far more on this GPU.)
-        double* part = a.partial + ((int64_t)tile_id * split + ksub) * CELLS;
+        // Publish this block's partial sums; split_sum_kernel adds a tile's partials (exact
+        // integer sums, in any order) and writes the grid values.
+        long long* part = a.partial + ((int64_t)tile_id * split + ksub) * CELLS;
         for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
             const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
-            part[i] = tile[(zr * TY + yr) * ST::PXS + xr + 3];
+            part[i] = (long long)tile[(zr * TY + yr) * ST::PXS + xr + 3];
         }
+        if (ksub == 0 && threadIdx.x == 0) a.tile_shift[tile_id] = finite ? fshift : INT32_MIN;
         return;
     }
+    T* f = (T*)a.f;
+    const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
     for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
         const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
         if (xr >= ex || yr >= ey || zr >= ez) continue;
         const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
-        const T v = (T)(tile[(zr * TY + yr) * ST::PXS + xr + 3] * g.scale);
+        const T v = fx_value<T>(tile[(zr * TY + yr) * ST::PXS + xr + 3], fshift, finite, g.scale);
         T* dst = f + (int64_t)c * G + gi;
         *dst = a.accumulate ? *dst + v : v;
     }
 }
 
 // Grid values of split tiles, after the spreading kernel has published every block's
-// partial tile: one thread per tile cell (i < ncells, the tiles' cells) adds the partials
-// in block order and writes the cell's value.
+// partial sums: one thread per tile cell (i < ncells, the tiles' cells) adds the partials
+// and writes the cell's value.
 template <typename T, int DIM, int TX, int TY, int TZ>
 __device__ __forceinline__ void split_sum_body(const OpArgs& a, int64_t i, int64_t ncells)
 {
@@ -621,12 +625,13 @@ __device__ __forceinline__ void split_sum_body(const OpArgs& a, int64_t i, int64
     const int ez = (DIM == 3) ? min(TZ, g.n[2] - z0) : 1;
     if (xr >= ex || yr >= ey || zr >= ez) return;
     const int split = g.split;
-    const double* part = a.partial + (int64_t)tile_id * split * CELLS + cell;
-    double sum = 0.0;
-    for (int kk = 0; kk < split; ++kk) sum += part[(int64_t)kk * CELLS];
+    const long long* part = a.partial + (int64_t)tile_id * split * CELLS + cell;
+    unsigned long long sum = 0ull;
+    for (int kk = 0; kk < split; ++kk) sum += (unsigned long long)part[(int64_t)kk * CELLS];
+    const int fshift = a.tile_shift[tile_id];
     const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
     const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
-    const T v = (T)(sum * g.scale);
+    const T v = fx_value<T>(sum, fshift == INT32_MIN ? 0 : fshift, fshift != INT32_MIN, g.scale);
     T* dst = (T*)a.f + (int64_t)c * G + gi;
     *dst = a.accumulate ? *dst + v : v;
 }
@@ -637,18 +642,8 @@ __global__ __launch_bounds__(256) void split_sum_kernel(OpArgs a, int64_t ncells
     split_sum_body<T, DIM, TX, TY, TZ>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncells);
 }
 
-// Waves per SIMD a spreading kernel is compiled for.  FP32 with the 32x8x13 tile fits four
-// (its sums take half the registers of FP64, and four of its LDS tiles fit in a CU); the
-// others keep two, with the registers they need.
-template <typename T, int TX, int TY, int TZ>
-constexpr int spread_waves_per_eu()
-{
-    return (sizeof(T) == 4 && TX == 32 && TY == 8 && TZ == 13) ? 4 : 1;
-}
-
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(spread_waves_per_eu<T, TX, TY, TZ>()))) void spread_kernel(OpArgs a)
+__global__ __launch_bounds__(SPREAD_THREADS) void spread_kernel(OpArgs a)
 {
     spread_body<T, DIM, KERN, TX, TY, TZ>(a, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -1276,6 +1271,9 @@ void launch_split_sum(const OpArgs& a, hipStream_t st)
 template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 {
+    // the force maxima that set each tile's fixed-point scale
+    hipLaunchKernelGGL(fmax_kernel<T>, dim3(FMAX_PARTS), dim3(256), 0, st, (const T*)a.F, a.g.npts,
+                       a.g.ncomp, (unsigned long long*)a.fmax);
     spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles, &a.tile_slow);
     const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split);
     if (a.g.dim == 3) {
@@ -1283,7 +1281,7 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 #define IBK_SPREAD_SHAPE(i)                                                                       \
     case i:                                                                                       \
         hipLaunchKernelGGL((spread_kernel<T, 3, KERN, SP_SHAPE[i][0], SP_SHAPE[i][1], SP_SHAPE[i][2]>), \
-                           dim3(nb), dim3(256), 0, st, a);                                        \
+                           dim3(nb), dim3(SPREAD_THREADS), 0, st, a);                             \
         if (a.g.split > 1)                                                                        \
             launch_split_sum<T, 3, SP_SHAPE[i][0], SP_SHAPE[i][1], SP_SHAPE[i][2]>(a, st);         \
         break;
@@ -1294,8 +1292,8 @@ hipError_t spread_dispatch(OpArgs a, hipStream_t st)
         default: return hipErrorInvalidValue;
         }
     } else {
-        hipLaunchKernelGGL((spread_kernel<T, 2, KERN, SP2_TX, SP2_TY, 1>), dim3(nb), dim3(256),
-                           0, st, a);
+        hipLaunchKernelGGL((spread_kernel<T, 2, KERN, SP2_TX, SP2_TY, 1>), dim3(nb),
+                           dim3(SPREAD_THREADS), 0, st, a);
         if (a.g.split > 1) launch_split_sum<T, 2, SP2_TX, SP2_TY, 1>(a, st);
     }
     return hipGetLastError();
@@ -1329,10 +1327,23 @@ __device__ __forceinline__ int batch_job_of(const int32_t* starts, int njobs, in
     return lo;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void batch_fmax_kernel(const BatchJob* __restrict__ jobs,
+                                                         const BatchTable* __restrict__ bt)
+{
+    const int32_t* st = bt->starts[BS_FMAX];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job_of(st, nj, vb);
+        const OpArgs& a = jobs[j].op;
+        fmax_body<T>((const T*)a.F, a.g.npts, a.g.ncomp, (unsigned long long*)a.fmax, vb - st[j]);
+        __syncthreads();
+    }
+}
+
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    spread_waves_per_eu<T, TX, TY, TZ>()))) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
-                                                                     const BatchTable* __restrict__ bt)
+__global__ __launch_bounds__(SPREAD_THREADS) void batch_spread_kernel(const BatchJob* __restrict__ jobs,
+                                                           const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_SPREAD];
     const int nj = bt->njobs, total = st[nj];
@@ -1388,9 +1399,11 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
     constexpr int S = builtin_spread_shape(sizeof(T) == 4 ? IB_F32 : IB_F64);
     constexpr int TX = DIM == 3 ? SP_SHAPE[S][0] : SP2_TX, TY = DIM == 3 ? SP_SHAPE[S][1] : SP2_TY;
     constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
+    if (b.grid[BS_FMAX] > 0)
+        hipLaunchKernelGGL((batch_fmax_kernel<T>), dim3(b.grid[BS_FMAX]), dim3(256), 0, st, b.jobs, b.table);
     if (b.grid[BS_SPREAD] > 0)
         hipLaunchKernelGGL((batch_spread_kernel<T, DIM, KERN, TX, TY, TZ>), dim3(b.grid[BS_SPREAD]),
-                           dim3(256), 0, st, b.jobs, b.table);
+                           dim3(SPREAD_THREADS), 0, st, b.jobs, b.table);
     if (b.grid[BS_SPLITSUM] > 0)
         hipLaunchKernelGGL((batch_split_sum_kernel<T, DIM, TX, TY, TZ>), dim3(b.grid[BS_SPLITSUM]),
                            dim3(256), 0, st, b.jobs, b.table);

@@ -134,6 +134,14 @@ int32_t ib_plan_stagger_of(ib_plan plan, int32_t comp);
  * until the last spread/interpolate/gradient call that uses this update. */
 int32_t ib_plan_update(ib_plan plan, const void *X, void *stream);
 
+/* The plan of the positions that the last ib_interpolate_advect on this plan produced
+ * (written into its X), computed without reading X: the same keys, permutation, offsets
+ * and operator results as ib_plan_update(plan, X) with those positions.  The advanced
+ * positions are kept by the plan in its sorted order, so the sort reads its input nearly
+ * in order.  Needs an ib_interpolate_advect on this plan since its last update (else
+ * IB_ERR_ARG; walled plans: always IB_ERR_ARG, use ib_plan_update). */
+int32_t ib_plan_update_advected(ib_plan plan, void *stream);
+
 /* Copy one staggering's plan arrays into caller device buffers (any may be NULL):
  * keys[npts] (input order), sorted_keys[npts], perm[npts] (sorted position -> point index),
  * seg_off[q+1] (seg_off[q] = npts; buffer must hold npts+1), q[1]. */
@@ -178,8 +186,8 @@ int32_t ib_interpolate(ib_plan plan, const void *u, void *U, void *stream);
  * [0, length_k) exactly as ib_advect does (bitwise the same results as the two calls).
  * Needs ncomp == dim.  X (npts x dim, device) is the array of the last update (or any
  * array with the same values): it is overwritten in place, after which the plan still
- * serves spreading and interpolation at the update's positions, but ib_plan_export can no
- * longer key a staggering it had not sorted yet (IB_ERR_ARG). */
+ * serves spreading, interpolation and export at the update's positions.  The advanced
+ * positions are also kept by the plan (in its sorted order) for ib_plan_update_advected. */
 int32_t ib_interpolate_advect(ib_plan plan, const void *u, void *U, void *X, double dt,
                               void *stream);
 

@@ -257,17 +257,11 @@ __device__ __forceinline__ int floor_mod(double fy, int n, double inv_n)
     return (int)c;
 }
 
-__device__ __forceinline__ uint32_t fdiv(uint32_t x, FastDiv f)
+// Point index from a permutation entry, kept inside [0, n) so that no data can steer a
+// load or store out of bounds (a valid permutation is never changed by this).
+__device__ __forceinline__ int64_t clamp_index(int32_t p, int64_t n)
 {
-    return (uint32_t)(((uint64_t)x * f.m) >> f.s);
-}
-
-// Flat index of the cell-block table entry of a key (row * (nbx + 1) + cx / 4).
-__device__ __forceinline__ int64_t cblk_index(int32_t key, const GeomArgs& g)
-{
-    const uint32_t row = fdiv((uint32_t)key, g.div_n0);
-    const int cx = key - (int)row * g.n[0];
-    return (int64_t)row * (g.nbx + 1) + (cx >> CBLK_SHIFT);
+    return (uint32_t)p < (uint64_t)n ? (int64_t)p : 0;
 }
 
 }  // namespace ibk

@@ -1,6 +1,7 @@
 // Host runtime of libibops: argument checking, plan workspace layout and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -68,8 +69,26 @@ int32_t check_tuning(const ib_tuning* t)
 {
     if (!t) return IB_OK;
     if (t->spread_tile < 0 || t->spread_tile > SPREAD_TILE_SHAPES) return IB_ERR_ARG;
-    if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > MAX_RADIX_BITS)) return IB_ERR_ARG;
+    if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > MAX_BUCKET_BITS)) return IB_ERR_ARG;
     return IB_OK;
+}
+
+// Bucket digit bits of a plan: enough buckets that each spans at most BKT_CELLS cells (up
+// to 2^MAX_BUCKET_BITS buckets), and about one bucket per 2048 points, so that a bucket's
+// points usually fit its block's LDS; a tuning may ask for a width of its own.
+int bucket_bits(int64_t G, int64_t n, int tuned)
+{
+    const int bits = bits_for(G);
+    int rb;
+    if (tuned > 0) {
+        rb = tuned;
+    } else {
+        int want = 0;
+        while (want < MAX_BUCKET_BITS && (int64_t(2048) << want) < n) ++want;
+        rb = std::max(bits - 13, want);  // 2^13 = BKT_CELLS
+    }
+    rb = std::min(rb, MAX_BUCKET_BITS);
+    return std::max(0, std::min(rb, bits));
 }
 
 ib_grid_desc kernel_grid(const ib_grid_desc& g)
@@ -85,32 +104,19 @@ ib_grid_desc kernel_grid(const ib_grid_desc& g)
 }
 
 void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed, const ib_tuning* tuning, bool batch)
+                 const ib_tuning* tuning)
 {
     const ib_grid_desc kg = kernel_grid(*user);
     const ib_grid_desc* g = &kg;
-    if (rbits_fixed == 0 && tuning && tuning->radix_bits) rbits_fixed = tuning->radix_bits;
     L->nstag = nstag;
     L->G = 1;
     for (int k = 0; k < g->dim; ++k) L->G *= g->n[k];
     L->rows = (int)(L->G / g->n[0]);
-    L->nbx = (g->n[0] + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT;
-    const int bits = bits_for(L->G);
-    L->npass = (bits + MAX_RADIX_BITS - 1) / MAX_RADIX_BITS;
-    L->rbits = (bits + L->npass - 1) / L->npass;
-    if (L->rbits < 4) L->rbits = 4;
-    if (rbits_fixed > 0) {
-        L->rbits = rbits_fixed;
-        L->npass = (bits + rbits_fixed - 1) / rbits_fixed;
-        if (L->npass < 1) L->npass = 1;
-    }
+    L->rb = bucket_bits(L->G, n, tuning ? tuning->radix_bits : 0);
+    L->cb = bits_for(L->G) - L->rb;
     L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
-    // Batches keep the one segments tile size their shared kernel is built for.
-    L->seg_ipt = (!batch && n < SEG_SMALL_POINTS) ? SEG_IPT_SMALL : SEG_IPT;
-    const int64_t seg_tile = (int64_t)SORT_BLOCK * L->seg_ipt;
-    L->nseg_tiles = n > 0 ? (n + seg_tile - 1) / seg_tile : 1;
-    const int64_t R = int64_t(1) << L->rbits;
-    L->nscan_tiles = L->ntiles > 0 ? (R * L->ntiles + SCAN_TILE - 1) / SCAN_TILE : 1;
+    L->nseg_tiles = n > 0 ? (n + SORT_TILE - 1) / SORT_TILE : 1;
+    const int64_t R = int64_t(1) << L->rb;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -118,18 +124,19 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
         return o;
     };
     const size_t kn = (size_t)nstag * (size_t)n * sizeof(int32_t);
-    L->keys0 = take(kn);
+    L->kin = take(kn);
     L->kA = take(kn);
     L->vA = take(kn);
     L->kB = take(kn);
     L->vB = take(kn);
-    L->cblk = take((size_t)nstag * L->rows * (L->nbx + 1) * sizeof(int32_t));
+    L->cstart = take(((size_t)L->G + 1) * sizeof(int32_t));
     L->seg_off = take((size_t)nstag * (size_t)(n + 1) * sizeof(int32_t));
     L->q = take((size_t)nstag * sizeof(int32_t));
     const size_t b = dtype == IB_F64 ? 8 : 4;
     L->Xs = take((size_t)n * g->dim * b);
+    L->Xb = take((size_t)n * g->dim * b);
+    L->Xn = take((size_t)n * g->dim * b);
     L->Us = take(g->dim == 3 ? (size_t)n * 2 * b : 0);
-
     int tiles[3];
     // ib_tuning.spread_tile: 0 = the built-in shape of the precision, k = shape k - 1.
     L->sp_tile = g->dim != 3 ? 0
@@ -146,11 +153,9 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->fmax = take((size_t)3 * FMAX_PARTS * sizeof(unsigned long long));
     // Everything from here to zero_end is cleared at every update.
     L->zero_begin = off;
-    L->hist = take((size_t)nstag * L->npass * R * sizeof(uint32_t));
-    L->sort_status = take((size_t)L->npass * nstag * L->ntiles * R * sizeof(uint32_t));
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
-    L->scan_status = take((size_t)nstag * L->npass * L->nscan_tiles * sizeof(uint32_t));
-    L->counters = take((size_t)nstag * (L->npass + 1) * sizeof(uint32_t));
+    L->bhist = take((size_t)nstag * 3 * BKT_SHARDS * R * sizeof(uint32_t));
+    L->counters = take((size_t)nstag * PLAN_COUNTERS * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
     L->zero_end = off;
     L->gpad = take(user->walls ? (size_t)g->ncomp * (size_t)L->G * b : 0);
@@ -158,17 +163,6 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
 }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? IB_OK : IB_ERR_HIP; }
-
-FastDiv make_fastdiv(uint32_t d)
-{
-    uint32_t l = 0;
-    while ((uint64_t(1) << l) < d) ++l;
-    FastDiv f;
-    f.d = d;
-    f.s = 31 + l;
-    f.m = (uint32_t)(((uint64_t(1) << f.s) + d - 1) / d);
-    return f;
-}
 
 }  // namespace ibk
 
@@ -195,7 +189,7 @@ size_t ib_plan_workspace_bytes(const ib_grid_desc* grid, int32_t dtype, int64_t 
     double sx[3][3];
     if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
     Layout L;
-    make_layout(grid, dtype, nstag, npts, &L);
+    make_layout(grid, dtype, nstag, npts, &L, nullptr);
     return L.total;
 }
 
@@ -217,8 +211,6 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     g.ncomp = grid->ncomp;
     g.nstag = nstag;
     g.rows = L.rows;
-    g.nbx = L.nbx;
-    g.div_n0 = make_fastdiv((uint32_t)grid->n[0]);
     g.npts = npts;
     double hd = 1.0;
     for (int k = 0; k < 3; ++k) {
@@ -256,46 +248,40 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     char* base = (char*)workspace;
     p->gpad = user->walls ? (void*)(base + L.gpad) : nullptr;
     PlanDev& d = p->sa.d;
-    d.keys0 = (int32_t*)(base + L.keys0);
+    d.kin = (int32_t*)(base + L.kin);
     d.kA = (int32_t*)(base + L.kA);
     d.vA = (int32_t*)(base + L.vA);
     d.kB = (int32_t*)(base + L.kB);
     d.vB = (int32_t*)(base + L.vB);
-    d.cblk = (int32_t*)(base + L.cblk);
+    d.bhist = (uint32_t*)(base + L.bhist);
+    d.cstart = (int32_t*)(base + L.cstart);
     d.seg_off = (int32_t*)(base + L.seg_off);
     d.q = (int32_t*)(base + L.q);
     d.Xs = base + L.Xs;
+    d.Xb = base + L.Xb;
+    d.Xn = base + L.Xn;
     d.Us = base + L.Us;
-
     d.partial = (long long*)(base + L.partial);
     d.tile_shift = (int32_t*)(base + L.tile_shift);
     d.fmax = (unsigned long long*)(base + L.fmax);
-    d.hist = (uint32_t*)(base + L.hist);
-    d.sort_status = (uint32_t*)(base + L.sort_status);
     d.seg_status = (uint32_t*)(base + L.seg_status);
-    d.scan_status = (uint32_t*)(base + L.scan_status);
     d.counters = (uint32_t*)(base + L.counters);
     d.flag = (uint32_t*)(base + L.flag);
     d.zero_begin = (uint32_t*)(base + L.zero_begin);
     d.zero_words = (L.zero_end - L.zero_begin) / sizeof(uint32_t);
-    p->sa.npass = L.npass;
-    p->sa.rbits = L.rbits;
+    p->sa.rb = L.rb;
+    p->sa.cb = L.cb;
     p->sa.ntiles = L.ntiles;
     p->sa.nseg_tiles = L.nseg_tiles;
-    p->sa.seg_ipt = L.seg_ipt;
-    p->sa.nscan_tiles = L.nscan_tiles;
-    // Scanned passes pay three launches per pass for a short chained step; one-sweep passes
-    // one launch, but a look-back across all tiles per digit.  Scanned from
-    // SCANNED_MIN_POINTS points up.
-    p->sa.scanned = npts >= SCANNED_MIN_POINTS ? 1 : 0;
-    const bool in_a = (npts == 0) || (L.npass & 1);
-    p->sorted_keys = in_a ? d.kA : d.kB;
-    p->perm = in_a ? d.vA : d.vB;
+    p->sorted_keys = d.kB;
+    p->perm = d.vB;
     p->X = nullptr;
     p->last_stream = nullptr;
     p->updated = 0;
     p->x_moved = 0;
     p->sorted_mask = 0;
+    p->runs_mask = 0;
+    p->xn_valid = 0;
 }
 
 }  // namespace ibk
@@ -316,7 +302,7 @@ size_t ib_plan_workspace_bytes_tuned(const ib_grid_desc* grid, int32_t dtype, in
     if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
     if (check_tuning(tuning) != IB_OK) return 0;
     Layout L;
-    make_layout(grid, dtype, nstag, npts, &L, 0, tuning);
+    make_layout(grid, dtype, nstag, npts, &L, tuning);
     return L.total;
 }
 
@@ -333,7 +319,7 @@ int32_t ib_plan_create_tuned(const ib_grid_desc* grid, int32_t dtype, int64_t np
     st = check_tuning(tuning);
     if (st != IB_OK) return st;
     Layout L;
-    make_layout(grid, dtype, nstag, npts, &L, 0, tuning);
+    make_layout(grid, dtype, nstag, npts, &L, tuning);
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
     if (workspace_bytes < L.total) return IB_ERR_OOM;
 
@@ -358,10 +344,9 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     if (!X && p->npts > 0) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = launch_plan_reset(p->sa, st);
-    // The operators use the keys and sort of staggering 0 (with the positions gathered into
-    // that order); other staggerings get theirs when exported.
-    if (e == hipSuccess) e = launch_keys(p->sa, p->dtype, X, 0, st);
-    if (e == hipSuccess) e = launch_sort_stagger(p->sa, 0, p->dtype, X, true, st);
+    // The operators use the keys and sort of staggering 0, its cell-start table and the
+    // positions in that order; other staggerings are sorted when exported.
+    if (e == hipSuccess) e = launch_sort_stagger(p->sa, 0, p->dtype, X, nullptr, true, st);
     int32_t r = hip_status(e);
     if (r != IB_OK) return r;
     p->X = X;
@@ -369,6 +354,26 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     p->updated = 1;
     p->x_moved = 0;
     p->sorted_mask = 1u;
+    p->runs_mask = 0u;
+    p->xn_valid = 0;
+    return IB_OK;
+}
+
+int32_t ib_plan_update_advected(ib_plan p, void* stream)
+{
+    if (!p || !p->updated || !p->xn_valid) return IB_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    // The advanced positions, in the previous sorted order, with that order's point indices.
+    hipError_t e = launch_plan_reset(p->sa, st);
+    if (e == hipSuccess)
+        e = launch_sort_stagger(p->sa, 0, p->dtype, p->sa.d.Xn, p->perm, true, st);
+    int32_t r = hip_status(e);
+    if (r != IB_OK) return r;
+    p->last_stream = st;
+    p->x_moved = 0;
+    p->sorted_mask = 1u;
+    p->runs_mask = 0u;
+    p->xn_valid = 0;
     return IB_OK;
 }
 
@@ -378,17 +383,23 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
     if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (!(p->sorted_mask & (1u << sid))) {
-        if (p->x_moved) return IB_ERR_ARG;  // X was advanced in place since the update
-        hipError_t e0 = launch_keys(p->sa, p->dtype, p->X, sid, st);
-        if (e0 == hipSuccess) e0 = launch_sort_stagger(p->sa, sid, p->dtype, nullptr, false, st);
-        int32_t r = hip_status(e0);
+        // from the update's positions in staggering-0 sorted order (valid even after X was
+        // advanced in place)
+        int32_t r = hip_status(launch_sort_stagger(p->sa, sid, p->dtype, p->sa.d.Xs, p->perm, false, st));
         if (r != IB_OK) return r;
         p->sorted_mask |= 1u << sid;
     }
     const size_t n = (size_t)p->npts;
     const PlanDev& d = p->sa.d;
     hipError_t e = hipSuccess;
-    if (keys && n) e = hipMemcpyAsync(keys, d.keys0 + sid * n, n * 4, hipMemcpyDeviceToDevice, st);
+    if ((seg_off || q) && !(p->runs_mask & (1u << sid))) {
+        // run heads, q and offsets from the sorted keys (the look-back words and ticket
+        // of this staggering's runs chain were cleared by the update)
+        e = launch_runs(p->sa, sid, st);
+        if (e != hipSuccess) return IB_ERR_HIP;
+        p->runs_mask |= 1u << sid;
+    }
+    if (keys && n) e = launch_keys_out(p->sa, sid, keys, st);
     if (e == hipSuccess && sorted_keys && n)
         e = hipMemcpyAsync(sorted_keys, p->sorted_keys + sid * n, n * 4, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && perm && n)
@@ -424,7 +435,7 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->g = p->sa.g;
     a->sorted_keys = p->sorted_keys;  // staggering 0
     a->perm = p->perm;
-    a->cblk = p->sa.d.cblk;
+    a->cstart = p->sa.d.cstart;
     a->X = p->X;
     a->Xs = p->sa.d.Xs;
     a->Us = p->sa.d.Us;
@@ -487,8 +498,10 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     hipError_t e = hipSuccess;
     a.u = kernel_field(p, u, st, &e);
     a.U = U;
+    p->xn_valid = 0;
     if (!p->user.walls) {  // walled: interpolation, then the update without wrap along walls
         a.Xadv = X;
+        a.Xnext = p->sa.d.Xn;  // the advanced positions also in sorted order
         a.adv_dt = dt;
         for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
     }
@@ -499,6 +512,7 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     if (e == hipSuccess && p->user.walls)
         e = launch_advect(p->user.dim, p->user.ncomp, p->npts, p->user.length, p->user.walls,
                           p->dtype, X, U, dt, st);
+    if (e == hipSuccess && !p->user.walls) p->xn_valid = 1;
     return hip_status(e);
 }
 

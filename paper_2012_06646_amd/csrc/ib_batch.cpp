@@ -1,6 +1,6 @@
 // Batches of independent spread/interpolate jobs: one plan per job, carved from one
-// workspace, and one launch per stage covering every job (keys, radix passes, segments,
-// force gather, spreading, interpolation).
+// workspace, and one launch per stage covering every job (keys, count scan, bucket
+// scatter, bucket sort, force maxima, spreading, interpolation).
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -29,8 +29,7 @@ struct BatchLayout {
     std::vector<JobGeom> jobs;
 };
 
-// Validate the jobs and lay out their plan regions (radix digits of BATCH_RBITS bits for
-// all), one after another from offset 0.
+// Validate the jobs and lay out their plan regions, one after another from offset 0.
 int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayout* B)
 {
     if (!jobs || njobs < 1) return IB_ERR_ARG;
@@ -51,7 +50,7 @@ int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayo
         if (J.npts > 0 && !J.X) return IB_ERR_ARG;
         if (J.f && J.npts > 0 && !J.F) return IB_ERR_ARG;
         if (J.u && J.npts > 0 && !J.U) return IB_ERR_ARG;
-        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, BATCH_RBITS, nullptr, true);
+        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, nullptr);
         G.off = off;
         off += G.L.total;
     }
@@ -71,7 +70,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
     std::memset(host_header + batch_flags_offset(), 0, BATCH_MAX_JOBS * sizeof(uint32_t));
     ht->njobs = njobs;
     int counts[BS_COUNT];
-    size_t keys_lds = 0;
     uint32_t* flags_dev = (uint32_t*)(header_dev + batch_flags_offset());
     for (int j = 0; j < njobs; ++j) {
         const ib_job& J = jobs[j];
@@ -81,14 +79,13 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         BatchJob& b = hj[j];
         std::memset(&b, 0, sizeof b);
         b.sa = p.sa;
-        b.sa.scanned = 0;  // batched passes sort by one-sweep look-back (digit histograms)
         // All error flags of the batch sit in the table, so one copy reads them back.
         b.sa.d.flag = flags_dev + j;
         OpArgs& a = b.op;
         a.g = p.sa.g;
         a.sorted_keys = p.sorted_keys;
         a.perm = p.perm;
-        a.cblk = p.sa.d.cblk;
+        a.cstart = p.sa.d.cstart;
         a.X = J.X;
         a.Xs = p.sa.d.Xs;
         a.F = J.F;
@@ -108,9 +105,9 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         counts[BS_RESET] = reset_blocks(sa);
         counts[BS_FMAX] = J.f ? FMAX_PARTS : 0;
         counts[BS_KEYS] = keys_blocks(sa);
-        for (int q = 0; q < BATCH_MAX_PASSES; ++q)
-            counts[BS_SORT0 + q] = (n > 0 && q < sa.npass) ? (int)sa.ntiles : 0;
-        counts[BS_SEG] = (int)sa.nseg_tiles;
+        counts[BS_BASES] = n > 0 ? 1 : 0;
+        counts[BS_SCATTER] = n > 0 ? (int)sa.ntiles : 0;
+        counts[BS_BUCKET] = bucket_blocks(sa);
         counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;
         counts[BS_SPLITSUM] =
             (J.f && a.g.split > 1)
@@ -121,7 +118,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.interp_tiled = itiles > 0;
         counts[BS_INTERP] = J.u ? (itiles > 0 ? itiles : interp_blocks(n)) : 0;
         for (int s = 0; s < BS_COUNT; ++s) ht->starts[s][j + 1] = ht->starts[s][j] + counts[s];
-        if (counts[BS_KEYS] > 0 && keys_lds_bytes(sa) > keys_lds) keys_lds = keys_lds_bytes(sa);
     }
     bl->jobs = (const BatchJob*)(header_dev + batch_jobs_offset());
     bl->table = (const BatchTable*)header_dev;
@@ -129,7 +125,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
     bl->dim = jobs[0].grid.dim;
     bl->kernel = jobs[0].grid.kernel;
     for (int s = 0; s < BS_COUNT; ++s) bl->grid[s] = ht->starts[s][njobs];
-    bl->keys_lds = keys_lds;
 }
 
 }  // namespace
@@ -152,7 +147,7 @@ size_t batch_job_bytes(const ib_job* job, int32_t dtype)
     if (!job || check_grid(&job->grid, dtype, job->npts, &nstag, cs, sx) != IB_OK) return 0;
     if (job->grid.walls) return 0;
     Layout L;
-    make_layout(&job->grid, dtype, nstag, job->npts, &L, BATCH_RBITS, nullptr, true);
+    make_layout(&job->grid, dtype, nstag, job->npts, &L, nullptr);
     return L.total;
 }
 

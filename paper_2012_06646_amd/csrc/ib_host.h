@@ -15,13 +15,15 @@ struct ib_plan_s {
     int32_t dtype;
     int64_t npts;
     ibk::SortArgs sa;      // geometry, device pointers, radix configuration
-    int32_t* sorted_keys;  // final sort output (aliases kA or kB)
-    int32_t* perm;
+    int32_t* sorted_keys;  // final sort output (kB of staggering 0)
+    int32_t* perm;         // (vB of staggering 0)
     const void* X;         // positions of the last update
     hipStream_t last_stream;
     int updated;
     int x_moved;           // X advanced in place (ib_interpolate_advect) since the update
+    int xn_valid;          // Xn holds the positions of the last ib_interpolate_advect
     uint32_t sorted_mask;  // staggerings sorted since the last update
+    uint32_t runs_mask;    // staggerings whose run offsets were computed since the update
 };
 
 namespace ibk {
@@ -32,11 +34,11 @@ size_t align_up(size_t v);
 
 // Byte layout of one plan's workspace.
 struct Layout {
-    int nstag, npass, rbits, rows, nbx, seg_ipt;
-    int64_t ntiles, nseg_tiles, nscan_tiles, G;
+    int nstag, rb, cb, rows;
+    int64_t ntiles, nseg_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
-    size_t keys0, kA, vA, kB, vB, cblk, seg_off, q, Xs, Us, partial, tile_shift, fmax, zero_begin, hist,
-        sort_status, seg_status, scan_status, counters, flag, zero_end, gpad, total;
+    size_t kin, kA, vA, kB, vB, bhist, cstart, seg_off, q, Xs, Xb, Xn, Us, partial, tile_shift, fmax,
+        zero_begin, seg_status, counters, flag, zero_end, gpad, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,
@@ -45,11 +47,9 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
                    int comp_stag[3], double stag_xi[3][3]);
 
 // Workspace layout of a plan on the caller's descriptor g (sized for kernel_grid(*g), plus
-// one padded grid field when g has walls); rbits_fixed > 0 forces that radix digit width
-// (batched plans share one sort kernel), else the digit width spreads the key bits evenly
-// over passes.
+// one padded grid field when g has walls).
 void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Layout* L,
-                 int rbits_fixed = 0, const ib_tuning* tuning = nullptr, bool batch = false);
+                 const ib_tuning* tuning = nullptr);
 // The periodic grid a plan runs on: the caller's grid with IB_WALL_GHOSTS ghost indices
 // added along every walled dimension (same spacing), walls cleared.
 ib_grid_desc kernel_grid(const ib_grid_desc& g);

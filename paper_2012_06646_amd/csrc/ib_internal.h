@@ -10,23 +10,16 @@ namespace ibk {
 
 // Sort configuration: 256-thread blocks, SORT_IPT keys per thread.
 constexpr int SORT_BLOCK = 256;
-#ifndef IBK_SORT_IPT
-#define IBK_SORT_IPT 8
-#endif
-constexpr int SORT_IPT = IBK_SORT_IPT;
+constexpr int SORT_IPT = 8;
 constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
-// Sorted positions per thread of the segments kernel: 8, or 2 for plans below
-// SEG_SMALL_POINTS points (four times the blocks, where few tiles would leave most CUs idle).
-constexpr int SEG_IPT = 8;
-constexpr int SEG_IPT_SMALL = 2;
-constexpr int64_t SEG_SMALL_POINTS = int64_t(1) << 18;
-#ifndef IBK_SCANNED_MIN_POINTS
-#define IBK_SCANNED_MIN_POINTS (1 << 18)
-#endif
-constexpr int64_t SCANNED_MIN_POINTS = IBK_SCANNED_MIN_POINTS;  // plans: scanned passes from here
-constexpr int SCAN_VPT = 16;                      // counts per thread of the count scan
-constexpr int SCAN_TILE = SORT_BLOCK * SCAN_VPT;  // counts per scan block
-constexpr int MAX_RADIX_BITS = 8;
+// Bucket pass: the top rb key bits (rb <= MAX_BUCKET_BITS) choose the bucket of 2^cb cells.
+// A bucket block counts BKT_CELLS cells at a time in LDS and stages up to BKT_CAP points
+// there (more go through global memory).
+constexpr int MAX_BUCKET_BITS = 10;
+constexpr int BKT_CELLS = 8192;
+constexpr int BKT_CAP = 4096;
+constexpr int BKT_SHARDS = 16;   // shards of the bucket histogram and fill cursors
+constexpr int PLAN_COUNTERS = 2;  // tickets per staggering (the second: runs kernel)
 
 // Look-back status words: 2 flag bits over a 30-bit count.
 constexpr uint32_t LB_AGG = 1u << 30;
@@ -39,53 +32,43 @@ constexpr uint32_t FLAG_BAD_POINT = 1u;
 constexpr uint32_t FLAG_LOOKBACK_STALL = 2u;
 
 struct PlanDev {
-    int32_t* keys0;        // [nstag][n] keys in input order
-    int32_t* kA;           // ping-pong key/value buffers [nstag][n]
+    int32_t* kin;          // [nstag][n] keys in the source order of the last sort
+    int32_t* kA;           // [nstag][n] keys and indices in bucket order (input order per bucket)
     int32_t* vA;
-    int32_t* kB;
-    int32_t* vB;
-    uint32_t* hist;        // [nstag][npass][R] global digit counts
-    uint32_t* sort_status; // [nstag][npass][ntiles][R] look-back words
-    uint32_t* counters;    // [nstag][npass + 1] tile tickets (last: segments kernel)
+    int32_t* kB;           // [nstag][n] sorted keys
+    int32_t* vB;           // [nstag][n] permutation: sorted position -> point index
+    uint32_t* bhist;       // [nstag][3][BKT_SHARDS][R] bucket histogram, fill cursors, shard starts
+    uint32_t* counters;    // [nstag][PLAN_COUNTERS] tile tickets
     uint32_t* flag;        // device error flag
-    int32_t* cblk;         // [nstag][rows * (nbx + 1)] cell-block start table (see GeomArgs)
+    int32_t* cstart;       // [G + 1] first sorted position of each cell (staggering 0)
     int32_t* seg_off;      // [nstag][n + 1]
     int32_t* q;            // [nstag]
-    uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words
-    uint32_t* scan_status; // [nstag][npass][nscan_tiles] look-back words of the count scans
-    void* Xs;              // [n][dim] positions in the sorted order of staggering 0
+    uint32_t* seg_status;  // [nstag][nseg_tiles] look-back words of the runs kernel
+    void* Xs;              // [dim][n] positions in the sorted order of staggering 0 (columns)
+    void* Xb;              // [dim][n] positions in bucket order (carried by the sort)
+    void* Xn;              // [dim][n] positions advanced by interpolation, in sorted order
     void* Us;              // [n][2] interpolation: the first components in that order
     long long* partial;    // [tiles][split][tile cells] partial fixed-point tile sums (split > 1 only)
     int32_t* tile_shift;   // [tiles] fixed-point scale exponent of each split tile
-    unsigned long long* fmax;  // [3][FMAX_BLOCKS] partial maxima of |F| per component
+    unsigned long long* fmax;  // [3][FMAX_PARTS] partial maxima of |F| per component
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
 
-// Exact division of non-negative 31-bit integers by a fixed divisor d >= 1:
-// q = (n * m) >> s with s = 31 + ceil(log2 d) and m = ceil(2^s / d) (m < 2^32).
-struct FastDiv {
-    uint32_t d, m, s;
-};
-
 // Geometry and per-call arguments passed by value to every kernel.
 //
-// Cell-block start table: each x-row of cells is cut into blocks of 4 cells; entry
-// (row r, block b), at flat index r * (nbx + 1) + b, holds the first sorted position whose
-// cell lies in row r at x >= 4 b (b = nbx: the start of the next row).  A sorted range of
-// cells [xa, xb) of one row is then bracketed in O(1) by entries xa / 4 and ceil(xb / 4).
+// Cell-start table: entry c (0 <= c <= G) is the first sorted position whose key is at
+// least c, so the points of cells [ca, cb) of one x-row are the sorted range
+// [cstart[ca], cstart[cb]).
 //
 // Staggering 0 (that of component 0) orders the points for spreading and interpolation.
 // For component c, cell_c - cell_0 lies in [dlo, dhi] per dimension (each in {-1, 0, 1}).
-constexpr int CBLK_SHIFT = 2;
 struct GeomArgs {
     int dim;
     int ncomp;
     int nstag;
     int n[3];
     int rows;              // n1 * n2 (3-D) or n1 (2-D): number of x-rows
-    int nbx;               // ceil(n0 / 4): cell blocks per x-row
-    FastDiv div_n0;        // division by n0 (key -> row)
     double inv_n[3];       // 1 / n_k (periodic wrap of cell indices)
     int64_t npts;
     int comp_stag[3];      // component -> distinct-stagger index
@@ -105,22 +88,19 @@ struct GeomArgs {
 struct SortArgs {
     GeomArgs g;
     PlanDev d;
-    int npass;
-    int rbits;
-    int64_t ntiles;        // sort tiles per stagger
-    int64_t nseg_tiles;    // segment tiles per stagger
-    int64_t nscan_tiles;   // scan tiles of one pass's digit-major tile counts
-    int scanned;           // radix passes: count, scan, scatter (else one-sweep look-back)
-    int seg_ipt;           // sorted positions per thread of the segments kernel
+    int rb;                // bucket digit bits (bucket = key >> cb)
+    int cb;                // cell bits per bucket
+    int64_t ntiles;        // sort tiles (SORT_TILE points) per stagger
+    int64_t nseg_tiles;    // tiles of the runs kernel
 };
 
 struct OpArgs {
     GeomArgs g;
     const int32_t* sorted_keys;  // staggering 0: [n]
     const int32_t* perm;         // staggering 0: [n]
-    const int32_t* cblk;         // staggering 0: [rows * (nbx + 1)]
+    const int32_t* cstart;       // staggering 0: [G + 1] cell-start table
     const void* X;               // input order
-    const void* Xs;              // staggering-0 order
+    const void* Xs;              // staggering-0 order, columns [dim][n]
     const void* F;
     void* Us;
     void* f;
@@ -134,6 +114,7 @@ struct OpArgs {
     const unsigned long long* fmax;  // partial maxima of |F| per component (fmax_kernel)
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     void* Xadv;                  // interpolation: also advance these positions (or null)
+    void* Xnext;                 //   and write them in sorted order here, columns (or null)
     double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len
     double adv_len[3];
 };
@@ -146,14 +127,13 @@ struct OpArgs {
 // virtual blocks, so a launch of any size (e.g. a fixed grid replayed in a graph) covers a
 // batch of any shape.
 constexpr int BATCH_MAX_JOBS = 128;
-constexpr int BATCH_RBITS = 8;       // one radix digit width for every job of a batch
-constexpr int BATCH_MAX_PASSES = 4;  // ceil(31 / 8)
 enum BatchStage {
     BS_RESET = 0,
-    BS_FMAX,   // force maxima of every spreading job
-    BS_KEYS,
-    BS_SORT0,  // BS_SORT0 + p: radix pass p
-    BS_SEG = BS_SORT0 + BATCH_MAX_PASSES,
+    BS_FMAX,     // force maxima of every spreading job
+    BS_KEYS,     // keys and the bucket histogram
+    BS_BASES,    // bucket starts
+    BS_SCATTER,  // points into their buckets
+    BS_BUCKET,   // per bucket: counting sort, cell-start table, positions in sorted order
     BS_SPREAD,
     BS_SPLITSUM,  // partial tiles of split spreading tiles added
     BS_INTERP,
@@ -178,13 +158,12 @@ struct BatchLaunch {
     const BatchTable* table;   // device
     int dtype, dim, kernel;
     int grid[BS_COUNT];        // blocks to launch per stage (0: skip the stage)
-    size_t keys_lds;           // dynamic LDS of the keys stage (largest job)
 };
 
 // Virtual-block counts of one job (host side).
 int reset_blocks(const SortArgs& a);
 int keys_blocks(const SortArgs& a);
-size_t keys_lds_bytes(const SortArgs& a);
+int bucket_blocks(const SortArgs& a);
 int interp_blocks(int64_t npts);
 // Tiles of the LDS-staged interpolation of a 3-D plan, or 0 when its points should gather
 // directly: staging pays off with at least 256 tiles (one block each) and 200 points per tile
@@ -213,12 +192,16 @@ hipError_t launch_batch_ops(const BatchLaunch& b, hipStream_t st);
 
 // Host launchers (stream-ordered; return hipError_t).
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st);
-// Keys of staggering s and its digit histograms.
-hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, int s, hipStream_t st);
-// Sort staggering s, build its segments and cell-block table; with gather_x, also write
-// the positions in that order (used for staggering 0 only).
-hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,
-                               hipStream_t st);
+// Keys and sort of staggering s (sorted keys kB, permutation vB) of the points whose
+// positions X are read in a source order: row i of the caller's (n x dim) array is point i
+// (psrc null), or column entry i of a plan array ([dim][n]) is point psrc[i].  With outputs0, also the cell-start table and the positions in sorted
+// order (staggering 0).
+hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, const int32_t* psrc,
+                               bool outputs0, hipStream_t st);
+// keys[i] = the staggering-s key of point i (from the sorted keys and the permutation).
+hipError_t launch_keys_out(const SortArgs& a, int s, int32_t* keys, hipStream_t st);
+// Run heads, q and segment offsets of staggering s from its sorted keys.
+hipError_t launch_runs(const SortArgs& a, int s, hipStream_t st);
 // Spreading, preceded by the pass that finds the force maxima (fmax_kernel).
 hipError_t launch_spread(const OpArgs& a, int dtype, int kernel, hipStream_t st);
 constexpr int FMAX_PARTS = 1024;  // partial maxima per component (blocks of fmax_kernel)

@@ -193,7 +193,6 @@ struct ib_server_s {
             char* header = arena + (size_t)slot * header_bytes;
             BatchLaunch bl = exact;
             for (int s = 0; s < BS_COUNT; ++s) bl.grid[s] = GRAPH_GRID;
-            bl.keys_lds = (size_t)BATCH_MAX_PASSES * ((size_t)1 << BATCH_RBITS) * sizeof(uint32_t);
             const size_t nb = batch_jobs_offset() + (size_t)opts.max_jobs_per_batch * sizeof(BatchJob);
             hipGraph_t g = nullptr;
             if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)

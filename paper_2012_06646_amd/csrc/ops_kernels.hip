@@ -72,13 +72,6 @@ __device__ __forceinline__ void tile_coords(int b, const int tiles[3], int s, in
     iz = s == 2 ? i2 : s == 1 ? i0 : i1;
 }
 
-// Point index from a permutation entry, kept inside [0, n) so that no data can steer a
-// load or store out of bounds (a valid permutation is never changed by this).
-__device__ __forceinline__ int64_t clamp_index(int32_t p, int64_t n)
-{
-    return (uint32_t)p < (uint64_t)n ? (int64_t)p : 0;
-}
-
 // Position update of the IB step for one coordinate: x + dt u wrapped into [0, L).
 template <typename T>
 __device__ __forceinline__ T advect_coord(T x, T u, T dt, T L)
@@ -233,9 +226,7 @@ __device__ __forceinline__ unsigned long long fmax_of(const unsigned long long* 
 
 // A source slice (an x-y plane of staggering-0 cells in 3-D, one x-row in 2-D) as a list
 // of sorted ranges, one per x-row piece (at most 3 pieces per row, since a tile is never
-// wider than the grid).  A range may include a few points of neighbouring cells (the
-// cell-block table brackets ranges in blocks of 4 cells); such points map outside the
-// tile and are dropped.
+// wider than the grid), read exactly from the cell-start table.
 template <int MAXR>
 struct SliceTable {
     int32_t lo[MAXR];
@@ -261,7 +252,7 @@ struct SpreadTile {
     // Range table of source slice q (frame origin ox, oy, oz; lenx cells per row, nrows
     // rows); returns the slice's point count.  Afterwards lane r < 3 * nrows holds range r's
     // first slice position (*rp) and whether the range is non-empty (*rn).
-    __device__ static int build(const GeomArgs& g, const int32_t* __restrict__ cb, int q, int ox,
+    __device__ static int build(const GeomArgs& g, const int32_t* __restrict__ cs, int q, int ox,
                                 int oy, int oz, int lenx, int nrows, Table& tb, int* rp, bool* rn)
     {
         const int lane = lane_id();
@@ -277,7 +268,6 @@ struct SpreadTile {
                 uy = q;
                 r = wrap_small(oy + q, g.n[1]);
             }
-            const int64_t rb = (int64_t)r * (g.nbx + 1);
             const int32_t rowbase = r * n0;
             int done = 0;
 #pragma unroll
@@ -286,8 +276,8 @@ struct SpreadTile {
                 if (done < lenx) {
                     const int xa = wrap_small(ox + done, n0);
                     const int len = min(lenx - done, n0 - xa);
-                    lo = cb[rb + (xa >> CBLK_SHIFT)];
-                    hi = cb[rb + ((xa + len + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT)];
+                    lo = cs[rowbase + xa];
+                    hi = cs[rowbase + xa + len];
                     xo = done - xa - rowbase;
                     done += len;
                 }
@@ -319,9 +309,9 @@ struct SpreadTile {
     }
 
     // Visits of source slice q without building its table (the sum over its row pieces),
-    // and the most visits of any 4-cell block of those pieces.  Called by the whole wave;
-    // both results are uniform.
-    __device__ static void count(const GeomArgs& g, const int32_t* __restrict__ cb, int q, int ox,
+    // and the most points of any 4-cell block (cells 4b .. 4b + 3 of a row) those pieces
+    // touch.  Called by the whole wave; both results are uniform.
+    __device__ static void count(const GeomArgs& g, const int32_t* __restrict__ cs, int q, int ox,
                                  int oy, int oz, int lenx, int nrows, int* total, int* maxblk)
     {
         const int lane = lane_id();
@@ -331,23 +321,16 @@ struct SpreadTile {
             int r;
             if (DIM == 3) r = wrap_small(oz + q, g.n[2]) * g.n[1] + wrap_small(oy + lane, g.n[1]);
             else r = wrap_small(oy + q, g.n[1]);
-            const int64_t rb = (int64_t)r * (g.nbx + 1);
+            const int32_t rowbase = r * n0;
             int done = 0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 if (done < lenx) {
                     const int xa = wrap_small(ox + done, n0);
                     const int len = min(lenx - done, n0 - xa);
-                    const int b0 = xa >> CBLK_SHIFT;
-                    const int b1 = (xa + len + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT;
-                    int prev = cb[rb + b0];
-                    const int first = prev;
-                    for (int b = b0 + 1; b <= b1; ++b) {
-                        const int cur = cb[rb + b];
-                        mb = max(mb, cur - prev);
-                        prev = cur;
-                    }
-                    cnt += prev - first;
+                    cnt += cs[rowbase + xa + len] - cs[rowbase + xa];
+                    for (int x = xa & ~3; x < xa + len; x += 4)
+                        mb = max(mb, cs[rowbase + min(x + 4, n0)] - cs[rowbase + x]);
                     done += len;
                 }
             }
@@ -396,7 +379,7 @@ struct SpreadTile {
             const T* __restrict__ Xs = (const T*)a.Xs;
             key = sk[j];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+            for (int k = 0; k < DIM; ++k) x[k] = Xs[k * a.g.npts + j];  // columns
             // the force of the point, read through the permutation (its input-order row)
             F = ((const T*)a.F)[clamp_index(a.perm[j], a.g.npts) * a.g.ncomp + c];
         }
@@ -544,13 +527,13 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     // The most contributions any grid value of the tile can receive (every split block of
     // the tile finds the same), and the maximum force of component c: the scale of the
     // tile.  A grid value's stencil window holds (4 + hy)(4 + hz) source rows (3-D) of at
-    // most 5 cells each, which lie in at most two 4-cell blocks of the cell-block table, so
-    // it receives at most 2 (4 + hy)(4 + hz) maxblock contributions, and never more than the
-    // tile's visit count n_t.
+    // most 5 consecutive cells each (counted around the periodic wrap), which lie in at
+    // most three 4-cell blocks, so it receives at most 3 (4 + hy)(4 + hz) maxblock
+    // contributions, and never more than the tile's visit count n_t.
     int cnt = 0, mb = 0;
     for (int q = w; q < nslices; q += NW) {
         int t, m;
-        ST::count(g, a.cblk, q, ox, oy, oz, lenx, nrows, &t, &m);
+        ST::count(g, a.cstart, q, ox, oy, oz, lenx, nrows, &t, &m);
         cnt += t;
         mb = max(mb, m);
     }
@@ -565,7 +548,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
         mbt = max(mbt, (uint32_t)s_mb[i]);
     }
     const uint32_t rows_win = (DIM == 3) ? (uint32_t)((4 + hy) * (4 + hz)) : (uint32_t)(4 + hy);
-    const uint32_t mbound = (uint32_t)min((uint64_t)nt, (uint64_t)2u * rows_win * mbt);
+    const uint32_t mbound = (uint32_t)min((uint64_t)nt, (uint64_t)3u * rows_win * mbt);
     const bool finite = vmax < FX_NONFINITE;
     const int fshift = (vmax == 0ull || !finite) ? 0 : fx_shift(vmax, mbound);
 
@@ -575,7 +558,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
         for (int q = w; q < nslices; q += NW) {
             int rp;
             bool rn;
-            const int total = ST::build(g, a.cblk, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
+            const int total = ST::build(g, a.cstart, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
             if (total > 0)
                 ST::spread_slice(a, c, tb, marks[w], rp, rn, nranges, total, q, off, ex, ey, ez,
                                  fshift, tile, ksub, split);
@@ -715,7 +698,7 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
     for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)nblk * blockDim.x) {
         T x[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+        for (int k = 0; k < DIM; ++k) x[k] = Xs[k * n + j];  // columns
         const int64_t p = clamp_index(a.perm[j], n);
         T res[3] = {T(0), T(0), T(0)};
         if (sizeof(T) == 4 && unrolled) {
@@ -730,9 +713,13 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
         }
         if (a.Xadv) {  // fused position update (ncomp == DIM): the same arithmetic as advect
             T* __restrict__ Xa = (T*)a.Xadv;
+            T* __restrict__ Xn = (T*)a.Xnext;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k)
-                Xa[p * DIM + k] = advect_coord(x[k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+            for (int k = 0; k < DIM; ++k) {
+                const T y = advect_coord(x[k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                Xa[p * DIM + k] = y;
+                if (Xn) Xn[k * n + j] = y;
+            }
         }
     }
 }
@@ -781,15 +768,14 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     const int ex = min(TX, n0 - x0), ey = min(TY, n1 - y0), ez = min(TZ, n2 - z0);
     const int nrt = ey * ez;
 
-    // Sorted range of each x-row of the tile (exact: tiles start at multiples of the
-    // 4-cell blocks of the cell-block table), and their prefix counts.
+    // Sorted range of each x-row of the tile (from the cell-start table), and their prefix
+    // counts.
     uint32_t cnt = 0;
     int32_t lo = 0;
     if (tid < nrt) {
-        const int row = (z0 + tid / ey) * n1 + (y0 + tid % ey);
-        const int64_t rb = (int64_t)row * (g.nbx + 1);
-        lo = a.cblk[rb + (x0 >> CBLK_SHIFT)];
-        const int32_t hi = a.cblk[rb + ((x0 + ex + (1 << CBLK_SHIFT) - 1) >> CBLK_SHIFT)];
+        const int64_t rowbase = ((int64_t)(z0 + tid / ey) * n1 + (y0 + tid % ey)) * n0;
+        lo = a.cstart[rowbase + x0];
+        const int32_t hi = a.cstart[rowbase + x0 + ex];
         cnt = hi > lo ? (uint32_t)(hi - lo) : 0u;
     }
     uint32_t total_u;
@@ -872,7 +858,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                 s0[q][1] = ry_t;
                 s0[q][2] = rz_t;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) x[q][k] = Xs[j * 3 + k];
+                for (int k = 0; k < 3; ++k) x[q][k] = Xs[k * n + j];  // columns
                 pj[q] = clamp_index(a.perm[j], n);
                 jj[q] = j;
 #pragma unroll
@@ -920,20 +906,32 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                 }
                 const int64_t p = pj[q];
                 const T res[3] = {c == 0 ? sum : done[q][0], c == 1 ? sum : done[q][1], sum};
-                for (int k = 0; k < ncomp; ++k) U[p * ncomp + k] = res[k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < ncomp) U[p * ncomp + k] = res[k];
                 if (adv) {
                     T* __restrict__ Xa = (T*)a.Xadv;
+                    T* __restrict__ Xn = (T*)a.Xnext;
 #pragma unroll
-                    for (int k = 0; k < 3; ++k)
-                        Xa[p * 3 + k] = advect_coord(x[q][k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                    for (int k = 0; k < 3; ++k) {
+                        const T y = advect_coord(x[q][k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                        Xa[p * 3 + k] = y;
+                        if (Xn) Xn[k * n + jj[q]] = y;
+                    }
                 }
             }
         }
     }
 }
 
+// FP64 is built for four waves per SIMD (at most 128 VGPRs), which its body fits without
+// spilling; left to itself the compiler takes more registers and runs three.
+template <typename T>
+constexpr int interp_tile_waves() { return sizeof(T) == 8 ? 4 : 5; }
+
 template <typename T, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(256) void interp_tile_kernel(OpArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(interp_tile_waves<T>()))) void
+interp_tile_kernel(OpArgs a)
 {
     interp_tile_body<T, KERN, TX, TY, TZ>(a, xcd_block(blockIdx.x, gridDim.x));
 }
@@ -956,7 +954,7 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
     for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         T x[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) x[k] = Xs[j * DIM + k];
+        for (int k = 0; k < DIM; ++k) x[k] = Xs[k * n + j];  // columns
         const int64_t p = clamp_index(a.perm[j], n);
         T grad[DIM];
 #pragma unroll

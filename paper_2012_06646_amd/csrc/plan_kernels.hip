@@ -1,25 +1,35 @@
-// Plan kernels: cell keys, stable LSD radix sort of (key, index) pairs, and segments.
+// Plan kernels: cell keys, a stable sort of the point indices by key, and the table of
+// where each cell's points start in that order.
 //
-// These are the preparatory steps of the parallel spreading algorithm (Alg. 4, Sec. 3.3):
+// These are the preparatory steps of the parallel spreading algorithm (Alg. 4, Sec. 3.4):
 // one key per IB point from the cell it occupies, a key-value sort of the point indices
-// that groups equal keys, the count of distinct keys and where each run starts (Fig. 2).
-// The sort is stable, so the permutation is unique: ties keep input order.
+// that groups equal keys, and (Fig. 2) the count of distinct keys and where each run
+// starts.  The sort is stable, so the permutation is unique: ties keep input order.
 //
-// gfx950 design.  Only ceil(log2(#cells)) key bits are sorted, in passes of at most 8 bits,
-// over tiles of SORT_TILE (2048) keys.  Within a tile, keys are ranked stably with wave64
-// ballots and staged in LDS in digit order, so the global writes are contiguous runs per
-// digit.  Where a tile's run of a digit goes comes from one of two schemes:
-//   plans    three launches per pass: per-tile digit counts stored digit-major, one
-//            exclusive scan over them (its blocks chained by a wave-parallel look-back),
-//            and the ranked scatter;
-//   batches  one launch per pass ("one-sweep"): digit histograms of every pass from the
-//            keys kernel, and per digit a decoupled look-back over the earlier tiles.
-// Both give the same permutation.
+// gfx950 design.  Keys are cell indices below G, so the sort needs no comparison passes
+// over all key bits.  It runs as one bucket pass on the top key bits followed by a
+// counting sort of each bucket inside one block's LDS:
+//   keys_kernel      the key of every point, and the count of each bucket (key >> cb, the
+//                    top rb bits): per block in LDS, then added to a shard of the global
+//                    histogram;
+//   bases_kernel     where each bucket (and each shard of it) starts;
+//   radix_scatter_kernel  each tile's (key, index) pairs, grouped by bucket in LDS, written
+//                    to a range of their bucket that the tile reserves with one atomic per
+//                    bucket (so the order inside a bucket depends on timing);
+//   bucket_kernel    per bucket of 2^cb cells: a histogram of its cells in LDS, its scan
+//                    (the cell-start table of the bucket, written coalesced), placement of
+//                    every point at a slot of its cell, then each point's final place from
+//                    its rank among the cell's points by index.  Within a cell the order is
+//                    therefore ascending index whatever came before: the stable sort.  The
+//                    sorted keys, the permutation and the positions in sorted order are
+//                    written from there.
+// The run heads, q and segment offsets of Fig. 2 follow from the sorted keys
+// (runs_kernel), computed when a plan is exported: the operators use the cell-start table.
 #include "device_common.h"
 
 namespace ibk {
 
-// ---- reset: clear histograms, look-back words, tickets and the error flag -------------
+// ---- reset: clear look-back words, tickets and the error flag -------------------------
 __device__ __forceinline__ void plan_reset_body(uint32_t* __restrict__ p, size_t nwords, int bid, int nblk)
 {
     for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < nwords; i += (size_t)nblk * blockDim.x)
@@ -31,113 +41,119 @@ __global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
     plan_reset_body(p, nwords, blockIdx.x, gridDim.x);
 }
 
-// ---- keys: one per point and distinct staggering, plus all pass histograms ----------
-// Keys of staggerings [s0, s1) and their digit histograms for every pass.
-template <typename T>
-__device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict__ X, int bid, int nblk, int s0,
-                          int s1)
+// Bucket bookkeeping of staggering s, in three arrays of [BKT_SHARDS][R] words: the
+// histogram, the fill cursors and the first position of each (shard, bucket) range.  Tile
+// t counts and fills shard t mod BKT_SHARDS, so that no counter takes more than a
+// BKT_SHARDS-th of the tiles' atomic additions; a bucket's range is its shards' ranges in
+// shard order.
+__device__ __forceinline__ uint32_t* stag_hist(const SortArgs& a, int s)
 {
-    extern __shared__ uint32_t lhist[];  // [s1 - s0][npass][R]
+    return a.d.bhist + (int64_t)s * 3 * BKT_SHARDS * ((int64_t)1 << a.rb);
+}
+
+// Shard starts of staggering s: base[x][d] = (points of buckets below d) + (points of bucket
+// d in shards below x).  One block of BKT_THREADS threads; bucket d's shards by thread d.
+__device__ __forceinline__ void bases_body(const SortArgs& a, int s)
+{
+    __shared__ uint32_t s_red[1024 / 64 + 1];
+    const int R = 1 << a.rb;
+    const uint32_t* hist = stag_hist(a, s);
+    uint32_t* base = const_cast<uint32_t*>(hist) + 2 * BKT_SHARDS * R;
+    const int d = threadIdx.x;
+    uint32_t part[BKT_SHARDS], tot = 0;
+#pragma unroll
+    for (int x = 0; x < BKT_SHARDS; ++x) {
+        part[x] = d < R ? hist[x * R + d] : 0u;
+        tot += part[x];
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan_u32<1024>(tot, s_red, &all);
+    if (d < R) {
+#pragma unroll
+        for (int x = 0; x < BKT_SHARDS; ++x) {
+            base[x * R + d] = run;
+            run += part[x];
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void bases_kernel(SortArgs a, int s)
+{
+    bases_body(a, s);
+}
+
+// ---- keys: one per point, and the bucket histogram ----------------------------------
+// The pass reads the points in a source order: the caller's (rows of X, point i is i) or
+// a sorted order of the plan (columns of X, point i is psrc[i]).  Block `tile` keys source
+// positions [tile * SORT_TILE, ...) of staggering s into kin.
+template <typename T>
+__device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict__ X, bool soa, int s,
+                                          int tile)
+{
+    __shared__ uint32_t lh[1 << MAX_BUCKET_BITS];
     const GeomArgs& g = a.g;
-    const int R = 1 << a.rbits;
-    const int nh = (s1 - s0) * a.npass * R;
-    for (int i = threadIdx.x; i < nh; i += blockDim.x) lhist[i] = 0u;
+    const int R = 1 << a.rb;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) lh[i] = 0u;
     __syncthreads();
 
     const int64_t n = g.npts;
+    const int64_t base = (int64_t)tile * SORT_TILE;
     bool any_bad = false;
-    // Each thread takes KU points per round, all positions loaded before any is keyed, so
-    // the loads of a round are in flight together.
-    constexpr int KU = 4;
-    const int64_t step = (int64_t)nblk * blockDim.x;
-    for (int64_t j0 = (int64_t)bid * blockDim.x + threadIdx.x; j0 < n; j0 += KU * step) {
-        T xs[KU][3];
+    // All positions of this thread first, so their loads are in flight together: every
+    // load is unconditional at a clamped in-range index (values past the point count or the
+    // dimension are never used), so none waits behind a branch.
+    // Rows (n x dim, the caller's layout) or columns ([dim][n], the plan's own arrays).
+    const int64_t last = n * g.dim - 1;
+    const int64_t sr = soa ? 1 : g.dim, sc = soa ? n : 1;
+    T xs[SORT_IPT][3];
 #pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            const int64_t j = j0 + u * step;
+    for (int u = 0; u < SORT_IPT; ++u) {
+        const int64_t j = base + u * SORT_BLOCK + threadIdx.x;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) xs[u][k] = (j < n && k < g.dim) ? X[j * g.dim + k] : T(0);
-        }
+        for (int k = 0; k < 3; ++k) xs[u][k] = X[min(j * sr + k * sc, last)];
+    }
 #pragma unroll
-        for (int u = 0; u < KU; ++u) {
-            const int64_t j = j0 + u * step;
-            if (j >= n) break;
-            const T* x = xs[u];
-            bool bad = false;
-            for (int s = s0; s < s1; ++s) {
-                int key = 0, stride = 1;
-                for (int k = 0; k < g.dim; ++k) {
-                    const T y = shifted_scaled<T>(x[k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
-                    int c = 0;
-                    if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
-                    else bad = true;
-                    key += c * stride;
-                    stride *= g.n[k];
-                }
-                a.d.keys0[(int64_t)s * n + j] = key;
-                if (!a.scanned)  // one-sweep passes take digit histograms from here
-                    for (int p = 0; p < a.npass; ++p)
-                    atomicAdd(&lhist[((s - s0) * a.npass + p) * R + ((key >> (p * a.rbits)) & (R - 1))], 1u);
+    for (int u = 0; u < SORT_IPT; ++u) {
+        const int64_t j = base + u * SORT_BLOCK + threadIdx.x;
+        bool bad = false;
+        int key = 0, stride = 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {  // static indices: the coordinates stay in registers
+            if (k < g.dim) {
+                const T y = shifted_scaled<T>(xs[u][k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
+                int c = 0;
+                if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
+                else bad = true;
+                key += c * stride;
+                stride *= g.n[k];
             }
+        }
+        if (j < n) {
+            a.d.kin[(int64_t)s * n + j] = key;
+            atomicAdd(&lh[(uint32_t)key >> a.cb], 1u);
             any_bad |= bad;
         }
     }
     if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
     __syncthreads();
-    uint32_t* gh = a.d.hist + (size_t)s0 * a.npass * R;
-    if (!a.scanned)
-        for (int i = threadIdx.x; i < nh; i += blockDim.x)
-            if (lhist[i]) atomicAdd(&gh[i], lhist[i]);
+    uint32_t* hist = stag_hist(a, s) + (tile % BKT_SHARDS) * R;
+    for (int d = threadIdx.x; d < R; d += blockDim.x)
+        if (lh[d]) atomicAdd(&hist[d], lh[d]);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void keys_kernel(SortArgs a, const T* __restrict__ X, int s0, int s1)
+__global__ __launch_bounds__(SORT_BLOCK) void keys_kernel(SortArgs a, const T* __restrict__ X, int soa, int s)
 {
-    keys_body<T>(a, X, blockIdx.x, gridDim.x, s0, s1);
+    keys_body<T>(a, X, soa != 0, s, blockIdx.x);
 }
 
 // ---- decoupled look-back over one counter per tile ------------------------------------
-// Tile `t` of a chain publishes its own count first (flag AGG; tile 0 publishes INC), then
-// walks back over earlier tiles, summing AGG counts until it meets an INC prefix.  Every
-// earlier tile already holds a ticket, so it is running or done and publishes without
-// waiting: the walk always ends.  A bounded spin guards against the impossible case.
-__device__ __forceinline__ uint32_t lookback_strided(uint32_t* chain, int64_t stride, int64_t t,
-                                                     uint32_t mine, uint32_t* flag)
-{
-    if (t == 0) {
-        __hip_atomic_store(&chain[0], LB_INC | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return 0u;
-    }
-    __hip_atomic_store(&chain[t * stride], LB_AGG | mine, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t excl = 0;
-    int64_t j = t - 1;
-    uint32_t spins = 0;
-    while (true) {
-        uint32_t v = __hip_atomic_load(&chain[j * stride], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t f = v & ~LB_MASK;
-        if (f == 0u) {
-            if (++spins > (1u << 22)) {  // never expected; keep the kernel finite
-                atomicOr(flag, FLAG_LOOKBACK_STALL);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += v & LB_MASK;
-        if (f == LB_INC || j == 0) break;
-        --j;
-    }
-    __hip_atomic_store(&chain[t * stride], LB_INC | (excl + mine), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    return excl;
-}
-
-// The same over a chain of stride 1, walked by a whole wave: each round reads the words of
-// up to 64 earlier tiles at once and stops at the nearest one that holds an inclusive
-// prefix, so a chain of k tiles takes about k / 64 rounds instead of k reads one after
-// another.  Called by all 64 lanes of one wave; returns the exclusive prefix in every lane.
+// A chain of stride 1, walked by a whole wave: tile t publishes its own count (flag AGG;
+// tile 0 publishes INC), then each round reads the words of up to 64 earlier tiles at once
+// and stops at the nearest one that holds an inclusive prefix.  Every earlier tile already
+// holds a ticket, so it is running or done and publishes without waiting: the walk always
+// ends.  A bounded spin guards against the impossible case.  Called by all 64 lanes of one
+// wave; returns the exclusive prefix in every lane.
 __device__ __forceinline__ uint32_t lookback_wave(uint32_t* chain, int64_t t, uint32_t mine,
                                                   uint32_t* flag)
 {
@@ -181,327 +197,400 @@ __device__ __forceinline__ uint32_t lookback_wave(uint32_t* chain, int64_t t, ui
     return excl;
 }
 
-// ---- one LSD radix pass over RBITS bits of every staggering's keys --------------------
-// SCANNED: tile = block, and each digit's destination base for this tile comes from the
-// scanned digit-major tile counts (radix_count_kernel + radix_scan_kernel) instead of the
-// digit histogram plus a look-back over earlier tiles.  Both give the same stable order.
-template <int RBITS, bool SCANNED = false>
-__device__ __forceinline__ void radix_pass_body(const SortArgs& a, int s, int pass)
+// ---- a tile's (key, index, position) triples into their buckets -----------------------
+// The tile's points are counted per bucket and given slots in LDS, grouped by bucket in
+// LDS with their positions (when the pass produces positions in sorted order), and written
+// as one contiguous run per bucket into a range that the tile reserves
+// with one atomic addition on its shard's cursor of the bucket.  Points of a bucket
+// therefore arrive in an order that depends on timing; the bucket kernel restores the
+// stable order.
+template <typename T>
+__device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t, const T* __restrict__ X,
+                                             bool soa, const int32_t* __restrict__ psrc, T* __restrict__ Xb)
 {
-    constexpr int R = 1 << RBITS;
-    constexpr int NW = SORT_BLOCK / 64;
+    constexpr int R_MAX = 1 << MAX_BUCKET_BITS;
     __shared__ int32_t s_key[SORT_TILE];
     __shared__ int32_t s_val[SORT_TILE];
-    __shared__ uint32_t s_wcnt[NW][R];
-    __shared__ uint32_t s_tstart[R];
-    __shared__ uint32_t s_gbase[R];
-    __shared__ uint32_t s_excl[R];
-    __shared__ uint32_t s_scan[NW + 1];
-    __shared__ uint32_t s_ticket;
+    __shared__ T s_row[SORT_TILE * 3];
+    __shared__ uint32_t s_cnt[R_MAX];   // tile count per bucket
+    __shared__ uint32_t s_tstart[R_MAX];
+    __shared__ uint32_t s_gbase[R_MAX];
+    __shared__ uint32_t s_red[SORT_BLOCK / 64 + 1];
 
-    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    if (!SCANNED && tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
-    for (int i = tid; i < NW * R; i += SORT_BLOCK) (&s_wcnt[0][0])[i] = 0u;
-    __syncthreads();
-
+    const int tid = threadIdx.x;
+    const int rb = a.rb, R = 1 << rb, cb = a.cb;
+    const int dim = a.g.dim;
+    for (int i = tid; i < R; i += SORT_BLOCK) s_cnt[i] = 0u;
     const int64_t n = a.g.npts;
-    const int64_t t = SCANNED ? (int64_t)blockIdx.x : (int64_t)s_ticket;
     const int64_t base = t * SORT_TILE;
     const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
-    // The digit's global count (one-sweep) or this tile's destination base for the digit
-    // (scanned), loaded now so its latency overlaps the ranking.
-    const uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
-    const uint32_t gcount = tid >= R ? 0u
-                            : SCANNED ? counts[(int64_t)tid * a.ntiles + t]
-                                      : a.d.hist[((int64_t)s * a.npass + pass) * R + tid];
+    const int32_t* srck = a.d.kin + (int64_t)s * n;
+    int32_t* dstk = a.d.kA + (int64_t)s * n;
+    int32_t* dstv = a.d.vA + (int64_t)s * n;
+    const int shard = (int)(t % BKT_SHARDS);
+    uint32_t* cur = stag_hist(a, s) + (BKT_SHARDS + shard) * R;
+    const uint32_t* sbase = stag_hist(a, s) + (2 * BKT_SHARDS + shard) * R;
 
-    // Source and destination: pass 0 reads the unsorted keys and generates the indices.
-    const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
-    const int32_t* srcv = (pass & 1) ? a.d.vA : a.d.vB;
-    int32_t* dstk = (pass & 1) ? a.d.kB : a.d.kA;
-    int32_t* dstv = (pass & 1) ? a.d.vB : a.d.vA;
-    srck += (int64_t)s * n;
-    srcv += (int64_t)s * n;
-    dstk += (int64_t)s * n;
-    dstv += (int64_t)s * n;
-    const int shift = pass * RBITS;
-
-    // Stable in-tile ranking: wave w owns items [w*64*IPT, (w+1)*64*IPT) of the tile, in
-    // IPT steps of 64 consecutive items; the rank of an item among equal digits is the
-    // count in earlier steps of its wave plus the count of lower lanes in its step.
     int32_t key[SORT_IPT], val[SORT_IPT];
-    uint32_t rank[SORT_IPT];
-    const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {  // all loads first, so that they overlap
-        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
-        const bool valid = li < nvalid;
-        key[k] = valid ? srck[base + li] : 0;
-        val[k] = valid ? (pass == 0 ? (int32_t)(base + li) : srcv[base + li]) : 0;
-    }
+    uint32_t slot[SORT_IPT];
+    T row[SORT_IPT][3];
+    // all loads first, unconditional at clamped in-range indices, so that they overlap
+    const int64_t lastp = n - 1, lastx = n * dim - 1;
 #pragma unroll
     for (int k = 0; k < SORT_IPT; ++k) {
-        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
-        const bool valid = li < nvalid;
-        const uint32_t digit = ((uint32_t)key[k] >> shift) & (R - 1);
-        unsigned long long m = __ballot(valid);
+        const int64_t i = min(base + k * SORT_BLOCK + tid, lastp);
+        key[k] = srck[i];
+        val[k] = psrc != nullptr ? psrc[i] : (int32_t)i;
+    }
+    if (Xb != nullptr) {
+        const int64_t sr = soa ? 1 : dim, sc = soa ? n : 1;
 #pragma unroll
-        for (int b = 0; b < RBITS; ++b) {
-            const bool bit = (digit >> b) & 1u;
-            const unsigned long long bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+        for (int k = 0; k < SORT_IPT; ++k) {
+            const int64_t i = base + k * SORT_BLOCK + tid;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) row[k][d] = X[min(i * sr + d * sc, lastx)];
         }
-        uint32_t prior = 0;
-        if (valid) prior = s_wcnt[w][digit];
-        rank[k] = prior + (uint32_t)__popcll(m & below);
-        if (valid && lane == 63 - __clzll(m)) s_wcnt[w][digit] = prior + (uint32_t)__popcll(m);
     }
     __syncthreads();
-
-    // Per digit: wave offsets within the tile, the tile count, its exclusive prefix over
-    // earlier tiles (look-back), the digit's global base and its start inside the tile.
-    uint32_t cnt = 0;
-    if (tid < R) {
-        for (int v = 0; v < NW; ++v) {
-            const uint32_t c = s_wcnt[v][tid];
-            s_wcnt[v][tid] = cnt;
-            cnt += c;
-        }
+#pragma unroll
+    for (int k = 0; k < SORT_IPT; ++k)
+        if (k * SORT_BLOCK + tid < nvalid) slot[k] = atomicAdd(&s_cnt[(uint32_t)key[k] >> cb], 1u);
+    __syncthreads();
+    // the tile's start of each bucket in LDS (scan of the counts) and its reserved range
+    constexpr int DPT = R_MAX / SORT_BLOCK;  // buckets per thread, consecutive
+    uint32_t c[DPT], sum = 0;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const int d = tid * DPT + q;
+        c[q] = d < R ? s_cnt[d] : 0u;
+        sum += c[q];
     }
     uint32_t tot;
-    const uint32_t tstart = block_excl_scan_u32<SORT_BLOCK>(tid < R ? cnt : 0u, s_scan, &tot);
-    if (SCANNED) {
-        if (tid < R) {
-            s_tstart[tid] = tstart;
-            s_gbase[tid] = gcount;
-            s_excl[tid] = 0u;
+    uint32_t run = block_excl_scan_u32<SORT_BLOCK>(sum, s_red, &tot);
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const int d = tid * DPT + q;
+        if (d < R) {
+            s_tstart[d] = run;
+            s_gbase[d] = (c[q] ? atomicAdd(&cur[d], c[q]) : 0u) + sbase[d];
         }
-    } else {
-        const uint32_t gbase = block_excl_scan_u32<SORT_BLOCK>(tid < R ? gcount : 0u, s_scan, &tot);
-        if (tid < R) {
-            s_tstart[tid] = tstart;
-            s_gbase[tid] = gbase;
-            // Look-back column of this digit: tile-major, digit-minor words.
-            uint32_t* col = a.d.sort_status +
-                            (((int64_t)s * a.npass + pass) * a.ntiles) * R + tid;
-            const uint32_t excl = lookback_strided(col, R, t, cnt, a.d.flag);
-            s_excl[tid] = excl;
-        }
+        run += c[q];
     }
     __syncthreads();
-
-    // Stage the tile in digit order, then write contiguous runs per digit.
 #pragma unroll
     for (int k = 0; k < SORT_IPT; ++k) {
-        const int li = w * (64 * SORT_IPT) + k * 64 + lane;
+        const int li = k * SORT_BLOCK + tid;
         if (li < nvalid) {
-            const uint32_t digit = ((uint32_t)key[k] >> shift) & (R - 1);
-            const uint32_t pos = s_tstart[digit] + s_wcnt[w][digit] + rank[k];
+            const uint32_t pos = s_tstart[(uint32_t)key[k] >> cb] + slot[k];
             s_key[pos] = key[k];
             s_val[pos] = val[k];
+            if (Xb != nullptr) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s_row[pos * 3 + d] = row[k][d];
+            }
         }
     }
     __syncthreads();
     for (int i = tid; i < nvalid; i += SORT_BLOCK) {
         const int32_t kk = s_key[i];
-        const uint32_t digit = ((uint32_t)kk >> shift) & (R - 1);
-        const int64_t dst = (int64_t)s_gbase[digit] + s_excl[digit] + (i - (int64_t)s_tstart[digit]);
-        if (dst < n) {  // always true when the histograms and tile counts agree
+        const uint32_t d = (uint32_t)kk >> cb;
+        const int64_t dst = (int64_t)s_gbase[d] + (i - (int64_t)s_tstart[d]);
+        if (dst >= 0 && dst < n) {  // always true when the counts agree
             dstk[dst] = kk;
             dstv[dst] = s_val[i];
+            if (Xb != nullptr) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (e < dim) Xb[e * n + dst] = s_row[i * 3 + e];  // columns
+            }
         }
     }
 }
 
-template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_scatter_kernel(SortArgs a, int s, int pass)
+template <typename T>
+__global__ __launch_bounds__(SORT_BLOCK) void radix_scatter_kernel(SortArgs a, int s, const T* __restrict__ X,
+                                                                   int soa, const int32_t* __restrict__ psrc,
+                                                                   T* __restrict__ Xb)
 {
-    radix_pass_body<RBITS, true>(a, s, pass);
+    scatter_body<T>(a, s, blockIdx.x, X, soa != 0, psrc, Xb);
 }
 
-// A whole pass in one launch (plans with few points): digit bases from the keys kernel's
-// histograms and a decoupled look-back over earlier tiles.
-template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_onesweep_kernel(SortArgs a, int s, int pass)
-{
-    radix_pass_body<RBITS, false>(a, s, pass);
-}
+// ---- per bucket: counting sort in LDS, cell-start table, positions in sorted order ------
+// Bucket b holds the cells [b << cb, (b + 1) << cb) (up to G) and, after the scatter, its
+// points at positions [start, start + m) of kA / vA (and Xb).  The block counts its cells'
+// points in LDS, scans the counts into the cells' first sorted positions (the cell-start
+// table, written for staggering 0), places each point at a slot of its cell taken with an
+// LDS atomic, and then moves it to the cell's start plus its rank by index among the cell's
+// points.  The result is the stable sort whatever the order of arrival and of the atomics.
+constexpr int BKT_THREADS = 1024;
 
-// ---- scanned passes: per-tile digit counts, then one exclusive scan over them ---------
-// Counts are stored digit-major, counts[digit][tile], so the exclusive scan of the whole
-// array is, for each (digit, tile), the position of the tile's first key of that digit in
-// the pass's output: all keys of smaller digits, then those of the digit in earlier tiles.
-template <int RBITS>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_count_kernel(SortArgs a, int s, int pass)
+// Common case: at most BKT_CELLS cells and BKT_CAP points, all in LDS, four points per
+// thread held in registers throughout.
+template <typename T>
+__device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t start, int m, int64_t c0,
+                                            int nc, bool last, const T* __restrict__ Xb, T* __restrict__ Xs,
+                                            int32_t* __restrict__ cstart, uint32_t* hist, int32_t* sidx,
+                                            uint16_t* skey, uint32_t* s_red)
 {
-    constexpr int R = 1 << RBITS;
-    __shared__ uint32_t s_cnt[R];
+    constexpr int EPT = BKT_CAP / BKT_THREADS;
+    constexpr int CPT = BKT_CELLS / BKT_THREADS;
+    const GeomArgs& g = a.g;
+    const int dim = g.dim;
+    const int64_t n = g.npts;
     const int tid = threadIdx.x;
-    for (int i = tid; i < R; i += SORT_BLOCK) s_cnt[i] = 0u;
+    const int32_t* __restrict__ ka = a.d.kA + (int64_t)s * n + start;
+    const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
+    for (int i = tid; i <= nc; i += BKT_THREADS) hist[i] = 0u;
+    int32_t key[EPT], idx[EPT];
+    int cell[EPT];
+    uint32_t slot[EPT];
+    T row[EPT][3];
+    // loads unconditional at clamped in-range indices (so they overlap); m >= 1 here
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int e = k * BKT_THREADS + tid;
+        const int ec = min(e, m - 1);
+        key[k] = ka[ec];
+        idx[k] = va[ec];
+        // a key outside the bucket never comes from a consistent scatter; keep it in range
+        cell[k] = e < m ? (int)min(max((int64_t)key[k] - c0, (int64_t)0), (int64_t)nc - 1) : -1;
+        if (Xs != nullptr) {  // columns of the bucket-order positions
+#pragma unroll
+            for (int d = 0; d < 3; ++d) row[k][d] = Xb[min(d, dim - 1) * n + start + ec];
+        }
+    }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (cell[k] >= 0) slot[k] = atomicAdd(&hist[cell[k]], 1u);
+    __syncthreads();
+    uint32_t loc[CPT], sum = 0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int i = tid * CPT + q;
+        loc[q] = i < nc ? hist[i] : 0u;
+        sum += loc[q];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int i = tid * CPT + q;
+        if (i < nc) {
+            hist[i] = run;
+            if (cstart != nullptr) cstart[c0 + i] = (int32_t)(start + run);
+        }
+        run += loc[q];
+    }
+    if (tid == 0) {
+        hist[nc] = (uint32_t)m;
+        if (cstart != nullptr && last) cstart[c0 + nc] = (int32_t)n;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (cell[k] >= 0) {
+            const uint32_t pos = hist[cell[k]] + slot[k];
+            if (pos < (uint32_t)m) sidx[pos] = idx[k];
+        }
+    __syncthreads();
+    // final place: the cell's start plus the point's rank by index among the cell's points
+    int fin[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        fin[k] = -1;
+        if (cell[k] >= 0) {
+            const uint32_t lo = hist[cell[k]], hi = min(hist[cell[k] + 1], (uint32_t)m);
+            uint32_t rank = 0;
+            for (uint32_t p = lo; p < hi; ++p) rank += sidx[p] < idx[k] ? 1u : 0u;
+            fin[k] = (int)(lo + rank);
+        }
+    }
+    __syncthreads();  // every rank read from sidx before it is overwritten
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (fin[k] >= 0 && fin[k] < m) {
+            sidx[fin[k]] = idx[k];
+            skey[fin[k]] = (uint16_t)cell[k];
+            if (Xs != nullptr) {  // within the bucket's range of the output
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    if (d < dim) Xs[d * n + start + fin[k]] = row[k][d];
+            }
+        }
+    __syncthreads();
+    // keys and permutation from LDS in sorted order: coalesced writes
+    int32_t* ok = a.d.kB + (int64_t)s * n + start;
+    int32_t* ov = a.d.vB + (int64_t)s * n + start;
+    for (int e = tid; e < m; e += BKT_THREADS) {
+        ok[e] = (int32_t)(c0 + skey[e]);
+        ov[e] = sidx[e];
+    }
+}
+
+// General case: a bucket of more cells (BKT_CELLS at a time) or more points, staged in
+// place in the output arrays: the key array holds each slot's position in the bucket
+// order while each cell's slots are sorted by point index (one thread per cell).
+template <typename T>
+__device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t start, int64_t m,
+                                               int64_t cbeg, int64_t cend, bool last, const T* __restrict__ Xb,
+                                               T* __restrict__ Xs, int32_t* __restrict__ cstart,
+                                               uint32_t* hist, uint32_t* s_red)
+{
+    constexpr int CPT = BKT_CELLS / BKT_THREADS;
+    const GeomArgs& g = a.g;
+    const int dim = g.dim;
+    const int64_t n = g.npts;
+    const int32_t* __restrict__ ka = a.d.kA + (int64_t)s * n + start;
+    const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
+    int32_t* sorg = a.d.kB + (int64_t)s * n + start;  // bucket position of each sorted slot
+    int64_t sub_base = 0;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += BKT_CELLS) {
+        const int nc = (int)min((int64_t)BKT_CELLS, cend - c0);
+        for (int i = threadIdx.x; i < nc; i += BKT_THREADS) hist[i] = 0u;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < m; e += BKT_THREADS) {
+            const int64_t c = (int64_t)ka[e] - c0;
+            if (c >= 0 && c < nc) atomicAdd(&hist[c], 1u);
+        }
+        __syncthreads();
+        uint32_t loc[CPT];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int i = threadIdx.x * CPT + k;
+            loc[k] = i < nc ? hist[i] : 0u;
+            sum += loc[k];
+        }
+        uint32_t tot;
+        uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) {
+            const int i = threadIdx.x * CPT + k;
+            if (i < nc) {
+                hist[i] = (uint32_t)sub_base + run;  // next free slot of the cell
+                if (cstart != nullptr) cstart[c0 + i] = (int32_t)(start + sub_base + run);
+            }
+            run += loc[k];
+        }
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < m; e += BKT_THREADS) {
+            const int64_t c = (int64_t)ka[e] - c0;
+            if (c >= 0 && c < nc) {
+                const uint32_t pos = atomicAdd(&hist[c], 1u);
+                if (pos < (uint64_t)m) sorg[pos] = (int32_t)e;  // always in range when the counts agree
+            }
+        }
+        __syncthreads();
+        // hist[i] is now the end of cell i's slots, and hist[i - 1] its start.
+        for (int i = threadIdx.x; i < nc; i += BKT_THREADS) {
+            const int64_t hi = min((int64_t)hist[i], m);
+            const int64_t lo = i > 0 ? (int64_t)hist[i - 1] : sub_base;
+            for (int64_t p = lo + 1; p < hi; ++p) {  // insertion sort by point index
+                const int32_t v = sorg[p];
+                const int32_t vi = va[v];
+                int64_t q = p - 1;
+                while (q >= lo && va[sorg[q]] > vi) {
+                    sorg[q + 1] = sorg[q];
+                    --q;
+                }
+                sorg[q + 1] = v;
+            }
+        }
+        sub_base += tot;
+        __syncthreads();
+    }
+    if (cstart != nullptr && last && threadIdx.x == 0) cstart[cend] = (int32_t)n;
+    int32_t* ok = a.d.kB + (int64_t)s * n + start;
+    int32_t* ov = a.d.vB + (int64_t)s * n + start;
+    for (int64_t p = threadIdx.x; p < m; p += BKT_THREADS) {
+        const int64_t e = min((int64_t)(uint32_t)sorg[p], m - 1);  // this thread's own slot
+        const int32_t key = ka[e];
+        ov[p] = va[e];
+        if (Xs != nullptr)
+            for (int d = 0; d < dim; ++d) Xs[d * n + start + p] = Xb[d * n + start + e];
+        ok[p] = key;  // after the slot's bucket position was read
+    }
+}
+
+// Bucket b of staggering s (every bucket of the grid's cells has a block).
+template <typename T>
+__device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, const T* __restrict__ Xb,
+                                             T* __restrict__ Xs, int32_t* __restrict__ cstart)
+{
+    __shared__ uint32_t hist[BKT_CELLS + 1];
+    __shared__ int32_t sidx[BKT_CAP];
+    __shared__ uint16_t skey[BKT_CAP];  // cell within the bucket
+    __shared__ uint32_t s_red[BKT_THREADS / 64 + 1];
+    static_assert(BKT_CELLS <= 65536, "cells of a bucket fit 16 bits");
+    const GeomArgs& g = a.g;
+    const int64_t G = (int64_t)g.n[0] * g.n[1] * g.n[2];
+    const int R = 1 << a.rb;
+    const uint32_t* base0 = stag_hist(a, s) + 2 * BKT_SHARDS * R;  // shard 0 = bucket start
+    const int64_t n = g.npts;
+    const int64_t start = n > 0 ? (int64_t)base0[b] : 0;
+    const int64_t m = n > 0 ? (b + 1 < R ? (int64_t)base0[b + 1] : n) - start : 0;
+    const int64_t cbeg = (int64_t)b << a.cb;
+    const int64_t cend = min(G, (int64_t)(b + 1) << a.cb);
+    const bool last = cend == G;
+    if (m >= 1 && m <= BKT_CAP && cend - cbeg <= BKT_CELLS)
+        bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red);
+    else
+        bucket_general<T>(a, s, start, m, cbeg, cend, last, Xb, Xs, cstart, hist, s_red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BKT_THREADS) void bucket_kernel(SortArgs a, int s, const T* __restrict__ Xb,
+                                                             T* __restrict__ Xs, int32_t* __restrict__ cstart)
+{
+    bucket_entry<T>(a, s, blockIdx.x, Xb, Xs, cstart);
+}
+
+// Keys of staggering s in the order of the points (export): keys[perm[i]] = sorted_keys[i].
+__global__ __launch_bounds__(256) void keys_out_kernel(SortArgs a, int s, int32_t* __restrict__ keys)
+{
     const int64_t n = a.g.npts;
-    const int64_t t = blockIdx.x;
-    const int64_t base = t * SORT_TILE;
-    const int nvalid = (int)min((int64_t)SORT_TILE, n - base);
-    const int32_t* srck = (pass == 0) ? a.d.keys0 : ((pass & 1) ? a.d.kA : a.d.kB);
-    srck += (int64_t)s * n;
-    const int shift = pass * RBITS;
-    int32_t key[SORT_IPT];
-#pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k) {
-        const int li = k * SORT_BLOCK + tid;
-        key[k] = li < nvalid ? srck[base + li] : 0;
-    }
-#pragma unroll
-    for (int k = 0; k < SORT_IPT; ++k)
-        if (k * SORT_BLOCK + tid < nvalid) atomicAdd(&s_cnt[((uint32_t)key[k] >> shift) & (R - 1)], 1u);
-    __syncthreads();
-    uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
-    for (int d = tid; d < R; d += SORT_BLOCK) counts[(int64_t)d * a.ntiles + t] = s_cnt[d];
+    const int32_t* sk = a.d.kB + (int64_t)s * n;
+    const int32_t* pm = a.d.vB + (int64_t)s * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        keys[clamp_index(pm[i], n)] = sk[i];
 }
 
-// In-place exclusive scan of the R * ntiles counts of one pass: SCAN_TILE counts per block,
-// blocks in ticket order, the prefix over earlier blocks by look-back.
-__global__ __launch_bounds__(SORT_BLOCK) void radix_scan_kernel(SortArgs a, int s, int pass)
+// ---- runs: heads, q and seg_off from the sorted keys (export) --------------------------
+__device__ __forceinline__ void runs_body(const SortArgs& a, int s)
 {
-    __shared__ uint32_t s_scan[SORT_BLOCK / 64 + 1];
-    __shared__ uint32_t s_ticket;
-    __shared__ uint32_t s_excl;
-    const int tid = threadIdx.x;
-    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + pass], 1u);
-    __syncthreads();
-    const int64_t t = s_ticket;
-    const int64_t R = int64_t(1) << a.rbits;
-    const int64_t V = R * a.ntiles;
-    uint32_t* counts = a.d.sort_status + (((int64_t)s * a.npass + pass) * a.ntiles) * R;
-    const int64_t first = t * SCAN_TILE + (int64_t)tid * SCAN_VPT;
-    uint32_t v[SCAN_VPT];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_VPT; ++k) {
-        v[k] = first + k < V ? counts[first + k] : 0u;
-        sum += v[k];
-    }
-    uint32_t btot;
-    const uint32_t excl = block_excl_scan_u32<SORT_BLOCK>(sum, s_scan, &btot);
-    if (wave_id() == 0) {
-        uint32_t* chain = a.d.scan_status + ((int64_t)s * a.npass + pass) * a.nscan_tiles;
-        const uint32_t e = lookback_wave(chain, t, btot, a.d.flag);
-        if (lane_id() == 0) s_excl = e;
-    }
-    __syncthreads();
-    uint32_t run = s_excl + excl;
-#pragma unroll
-    for (int k = 0; k < SCAN_VPT; ++k) {
-        if (first + k < V) counts[first + k] = run;
-        run += v[k];
-    }
-}
-
-// ---- segments: run heads, q, seg_off and the cell-block start table -------------------
-// Rows base + t + k * SORT_BLOCK (k < SEG_IPT) of a tile: dst[i] = src[perm[i]] for rows
-// of D values, all permutation entries first, then all rows.
-template <typename T, int D, int SEG_IPT>
-__device__ __forceinline__ void gather_tile_rows(const int32_t* __restrict__ perm,
-                                                 const T* __restrict__ src, T* __restrict__ dst,
-                                                 int64_t base, int64_t n)
-{
-    // Rows past n are neither read nor written (with n == 0, src may be null).
-    int64_t p[SEG_IPT];
-#pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
-        const int32_t v = i < n ? perm[i] : 0;
-        p[k] = (uint32_t)v < (uint64_t)n ? v : 0;
-    }
-    T row[SEG_IPT][D];
-#pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
-        if (i < n) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) row[k][d] = src[p[k] * D + d];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + threadIdx.x + k * SORT_BLOCK;
-        if (i < n) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) dst[i * D + d] = row[k][d];
-        }
-    }
-}
-
-constexpr int CB_LANE_RUN = 16;  // table runs up to this long are written by their own lane
-
-template <typename T, int SEG_IPT>
-__device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T* __restrict__ X, T* __restrict__ Xs)
-{
-    // Sorted keys live in the buffer the last pass wrote (A after an odd pass count).
-    const bool in_a = (a.g.npts == 0) || (a.npass & 1);
-    const int32_t* sk_all = in_a ? a.d.kA : a.d.kB;
-    const int32_t* perm_all = in_a ? a.d.vA : a.d.vB;
     constexpr int NW = SORT_BLOCK / 64;
+    constexpr int IPT = SORT_IPT;
     __shared__ uint32_t s_wtot[NW];
     __shared__ uint32_t s_ticket;
     __shared__ uint32_t s_excl;
     const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
-    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * (a.npass + 1) + a.npass], 1u);
+    if (tid == 0) s_ticket = atomicAdd(&a.d.counters[s * PLAN_COUNTERS + 1], 1u);
     __syncthreads();
-
-    const GeomArgs& g = a.g;
-    const int64_t n = g.npts;
+    const int64_t n = a.g.npts;
     const int64_t t = s_ticket;
-    constexpr int SEG_TILE = SORT_BLOCK * SEG_IPT;
-    const int64_t base = t * SEG_TILE;
-    const int32_t* sk = sk_all + (int64_t)s * n;
+    const int64_t base = t * SORT_TILE;
+    const int32_t* sk = a.d.kB + (int64_t)s * n;
     int32_t* seg = a.d.seg_off + (int64_t)s * (n + 1);
-    const int64_t nent = (int64_t)g.rows * (g.nbx + 1);
-    int32_t* cb = a.d.cblk + (int64_t)s * nent;
-
-    uint32_t rank[SEG_IPT];
-    bool head[SEG_IPT];
+    uint32_t rank[IPT];
+    bool head[IPT];
     uint32_t wrun = 0;
     const unsigned long long below = (1ull << lane) - 1ull;
-    // All keys of this thread (and their predecessors) first, so their loads overlap rather
-    // than wait behind the table stores below.
-    int32_t kcs[SEG_IPT], kps[SEG_IPT];
+    int32_t kc[IPT], kp[IPT];
 #pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
-        kcs[k] = i < n ? sk[i] : 0;
-        kps[k] = (i < n && i > 0) ? sk[i - 1] : -1;
+    for (int k = 0; k < IPT; ++k) {
+        const int64_t i = base + w * (64 * IPT) + k * 64 + lane;
+        kc[k] = i < n ? sk[i] : 0;
+        kp[k] = (i < n && i > 0) ? sk[i - 1] : -1;
     }
 #pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
-        bool hd = false;
-        // Table entries (block(i-1), block(i)] start at sorted position i.  A lane writes a
-        // short run itself; longer runs (empty stretches of the grid, e.g. ghost planes or
-        // the space between clustered points) are written by the whole wave, one at a time.
-        int32_t bp = 0, bc = 0;
-        if (i < n) {
-            const int32_t kc = kcs[k];
-            const int32_t kp = kps[k];
-            hd = (i == 0) || (kc != kp);
-            bp = i > 0 ? (int32_t)min(cblk_index(kp, g), nent - 1) : -1;
-            bc = (int32_t)min(cblk_index(kc, g), nent - 1);
-            if (bc - bp <= CB_LANE_RUN)
-                for (int32_t e = bp + 1; e <= bc; ++e) cb[e] = (int32_t)i;
-        }
-        unsigned long long longs = __ballot(bc - bp > CB_LANE_RUN);
-        while (longs) {
-            const int src = __ffsll((long long)longs) - 1;
-            longs &= longs - 1ull;
-            const int32_t b0 = __shfl(bp, src, 64) + 1, b1 = __shfl(bc, src, 64);
-            const int32_t v = (int32_t)(base + w * (64 * SEG_IPT) + k * 64 + src);
-            for (int32_t e = b0 + lane; e <= b1; e += 64) cb[e] = v;
-        }
-        const unsigned long long m = __ballot(hd);
+    for (int k = 0; k < IPT; ++k) {
+        const int64_t i = base + w * (64 * IPT) + k * 64 + lane;
+        const bool hd = i < n && (i == 0 || kc[k] != kp[k]);
+        const unsigned long long msk = __ballot(hd);
         head[k] = hd;
-        rank[k] = wrun + (uint32_t)__popcll(m & below);
-        wrun += (uint32_t)__popcll(m);
+        rank[k] = wrun + (uint32_t)__popcll(msk & below);
+        wrun += (uint32_t)__popcll(msk);
     }
     if (lane == 0) s_wtot[w] = wrun;
     __syncthreads();
@@ -528,36 +617,21 @@ __device__ __forceinline__ void segments_body(const SortArgs& a, int s, const T*
             }
         }
     }
-    // The last tile fills the table entries after the last key with n.
-    if (t == a.nseg_tiles - 1) {
-        const int64_t blast = n > 0 ? min(cblk_index(sk[n - 1], g), nent - 1) : -1;
-        for (int64_t e = blast + 1 + tid; e < nent; e += SORT_BLOCK) cb[e] = (int32_t)n;
-    }
     __syncthreads();
     const uint32_t off = s_excl + s_wtot[w];
 #pragma unroll
-    for (int k = 0; k < SEG_IPT; ++k) {
-        const int64_t i = base + w * (64 * SEG_IPT) + k * 64 + lane;
+    for (int k = 0; k < IPT; ++k) {
+        const int64_t i = base + w * (64 * IPT) + k * 64 + lane;
         if (head[k]) seg[off + rank[k]] = (int32_t)i;
     }
-    // Positions in this sorted order (staggering 0 only): one row per sorted position, the
-    // tile's SEG_IPT rows of a thread loaded together so their random reads overlap.
-    if (Xs != nullptr) {
-        const int32_t* perm = perm_all + (int64_t)s * n;
-        if (g.dim == 3) gather_tile_rows<T, 3, SEG_IPT>(perm, X, Xs, base, n);
-        else gather_tile_rows<T, 2, SEG_IPT>(perm, X, Xs, base, n);
-    }
 }
 
-template <typename T, int SEG_IPT>
-__global__ __launch_bounds__(SORT_BLOCK) void segments_kernel(SortArgs a, int s, const T* __restrict__ X,
-                                                              T* __restrict__ Xs)
+__global__ __launch_bounds__(SORT_BLOCK) void runs_kernel(SortArgs a, int s)
 {
-    segments_body<T, SEG_IPT>(a, s, X, Xs);
+    runs_body(a, s);
 }
 
-// ---- host launchers ---------------------------------------------------------------------
-// ---- batched plan stages --------------------------------------------------------------
+// ---- batched plan stages ----------------------------------------------------------------
 
 // Job of virtual block vb: the last j with starts[j] <= vb (jobs without blocks in a stage
 // have starts[j] == starts[j + 1] and are passed over).
@@ -573,7 +647,7 @@ __device__ __forceinline__ int batch_job(const int32_t* starts, int njobs, int v
 }
 
 __global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* __restrict__ jobs,
-                                                                const BatchTable* __restrict__ bt)
+                                                          const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_RESET];
     const int nj = bt->njobs, total = st[nj];
@@ -585,43 +659,53 @@ __global__ __launch_bounds__(256) void batch_reset_kernel(const BatchJob* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_keys_kernel(const BatchJob* __restrict__ jobs,
+__global__ __launch_bounds__(SORT_BLOCK) void batch_keys_kernel(const BatchJob* __restrict__ jobs,
                                                                 const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_KEYS];
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
-        keys_body<T>(jobs[j].sa, (const T*)jobs[j].op.X, vb - st[j], st[j + 1] - st[j], 0, 1);
+        keys_body<T>(jobs[j].sa, (const T*)jobs[j].op.X, false, 0, vb - st[j]);
         __syncthreads();
     }
 }
 
-// Radix pass p of every job with more than p passes.  Blocks take tiles by ticket inside
-// the body, so only the number of virtual blocks per job (its tile count) matters.
-__global__ __launch_bounds__(SORT_BLOCK) void batch_sort_kernel(const BatchJob* __restrict__ jobs,
-                                                                const BatchTable* __restrict__ bt,
-                                                                int pass)
+__global__ __launch_bounds__(1024) void batch_bases_kernel(const BatchJob* __restrict__ jobs,
+                                                           const BatchTable* __restrict__ bt)
 {
-    const int32_t* st = bt->starts[BS_SORT0 + pass];
+    const int32_t* st = bt->starts[BS_BASES];
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        const int j = batch_job(st, nj, vb);
-        radix_pass_body<BATCH_RBITS>(jobs[j].sa, 0, pass);
+        bases_body(jobs[batch_job(st, nj, vb)].sa, 0);
         __syncthreads();
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(SORT_BLOCK) void batch_segments_kernel(
-    const BatchJob* __restrict__ jobs, const BatchTable* __restrict__ bt)
+__global__ __launch_bounds__(SORT_BLOCK) void batch_scatter_kernel(const BatchJob* __restrict__ jobs,
+                                                                   const BatchTable* __restrict__ bt)
 {
-    const int32_t* st = bt->starts[BS_SEG];
+    const int32_t* st = bt->starts[BS_SCATTER];
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
         const BatchJob& J = jobs[j];
-        segments_body<T, SEG_IPT>(J.sa, 0, (const T*)J.op.X, (T*)J.sa.d.Xs);
+        scatter_body<T>(J.sa, 0, vb - st[j], (const T*)J.op.X, false, nullptr, (T*)J.sa.d.Xb);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BKT_THREADS) void batch_bucket_kernel(const BatchJob* __restrict__ jobs,
+                                                                  const BatchTable* __restrict__ bt)
+{
+    const int32_t* st = bt->starts[BS_BUCKET];
+    const int nj = bt->njobs, total = st[nj];
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        const int j = batch_job(st, nj, vb);
+        const BatchJob& J = jobs[j];
+        bucket_entry<T>(J.sa, 0, vb - st[j], (const T*)J.sa.d.Xb, (T*)J.sa.d.Xs, J.sa.d.cstart);
         __syncthreads();
     }
 }
@@ -632,41 +716,46 @@ hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st)
         hipLaunchKernelGGL(batch_reset_kernel, dim3(b.grid[BS_RESET]), dim3(256), 0, st, b.jobs, b.table);
     if (b.grid[BS_KEYS] > 0) {
         if (b.dtype == IB_F64)
-            hipLaunchKernelGGL(batch_keys_kernel<double>, dim3(b.grid[BS_KEYS]), dim3(256), b.keys_lds,
+            hipLaunchKernelGGL(batch_keys_kernel<double>, dim3(b.grid[BS_KEYS]), dim3(SORT_BLOCK), 0, st,
+                               b.jobs, b.table);
+        else
+            hipLaunchKernelGGL(batch_keys_kernel<float>, dim3(b.grid[BS_KEYS]), dim3(SORT_BLOCK), 0, st,
+                               b.jobs, b.table);
+    }
+    if (b.grid[BS_BASES] > 0)
+        hipLaunchKernelGGL(batch_bases_kernel, dim3(b.grid[BS_BASES]), dim3(1024), 0, st, b.jobs, b.table);
+    if (b.grid[BS_SCATTER] > 0) {
+        if (b.dtype == IB_F64)
+            hipLaunchKernelGGL(batch_scatter_kernel<double>, dim3(b.grid[BS_SCATTER]), dim3(SORT_BLOCK), 0,
                                st, b.jobs, b.table);
         else
-            hipLaunchKernelGGL(batch_keys_kernel<float>, dim3(b.grid[BS_KEYS]), dim3(256), b.keys_lds,
+            hipLaunchKernelGGL(batch_scatter_kernel<float>, dim3(b.grid[BS_SCATTER]), dim3(SORT_BLOCK), 0,
                                st, b.jobs, b.table);
     }
-    for (int p = 0; p < BATCH_MAX_PASSES; ++p)
-        if (b.grid[BS_SORT0 + p] > 0)
-            hipLaunchKernelGGL(batch_sort_kernel, dim3(b.grid[BS_SORT0 + p]), dim3(SORT_BLOCK), 0, st,
-                               b.jobs, b.table, p);
-    if (b.grid[BS_SEG] > 0) {
+    if (b.grid[BS_BUCKET] > 0) {
         if (b.dtype == IB_F64)
-            hipLaunchKernelGGL(batch_segments_kernel<double>, dim3(b.grid[BS_SEG]), dim3(SORT_BLOCK), 0,
+            hipLaunchKernelGGL(batch_bucket_kernel<double>, dim3(b.grid[BS_BUCKET]), dim3(BKT_THREADS), 0,
                                st, b.jobs, b.table);
         else
-            hipLaunchKernelGGL(batch_segments_kernel<float>, dim3(b.grid[BS_SEG]), dim3(SORT_BLOCK), 0,
+            hipLaunchKernelGGL(batch_bucket_kernel<float>, dim3(b.grid[BS_BUCKET]), dim3(BKT_THREADS), 0,
                                st, b.jobs, b.table);
     }
     return hipGetLastError();
 }
+
+// ---- host side ---------------------------------------------------------------------------
 
 int reset_blocks(const SortArgs& a)
 {
     return (int)min((size_t)1024, (a.d.zero_words + 255) / 256);
 }
 
-// Few blocks: each adds its LDS histograms to the global ones with atomics.
-int keys_blocks(const SortArgs& a)
-{
-    return a.g.npts > 0 ? (int)min((int64_t)1024, (a.g.npts + 255) / 256) : 0;
-}
+int keys_blocks(const SortArgs& a) { return a.g.npts > 0 ? (int)a.ntiles : 0; }
 
-size_t keys_lds_bytes(const SortArgs& a)  // one staggering at a time
+int bucket_blocks(const SortArgs& a)
 {
-    return (size_t)a.npass * ((size_t)1 << a.rbits) * sizeof(uint32_t);
+    const int64_t G = (int64_t)a.g.n[0] * a.g.n[1] * a.g.n[2];
+    return (int)((G + ((int64_t)1 << a.cb) - 1) >> a.cb);
 }
 
 hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
@@ -678,68 +767,50 @@ hipError_t launch_plan_reset(const SortArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const SortArgs& a, int dtype, const void* X, int s, hipStream_t st)
+hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, const int32_t* psrc,
+                               bool outputs0, hipStream_t st)
 {
-    const int blocks = keys_blocks(a);
-    if (blocks == 0) return hipSuccess;
-    const size_t lds = keys_lds_bytes(a);
+    const int64_t n = a.g.npts;
+    void* Xb = outputs0 ? a.d.Xb : nullptr;  // positions carried into sorted order
+    const int soa = psrc != nullptr ? 1 : 0;  // the plan's own arrays are columns
+    if (n > 0) {
+        if (dtype == IB_F64) {
+            hipLaunchKernelGGL(keys_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
+                               (const double*)X, soa, s);
+            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s);
+            hipLaunchKernelGGL(radix_scatter_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
+                               a, s, (const double*)X, soa, psrc, (double*)Xb);
+        } else {
+            hipLaunchKernelGGL(keys_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
+                               (const float*)X, soa, s);
+            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s);
+            hipLaunchKernelGGL(radix_scatter_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
+                               a, s, (const float*)X, soa, psrc, (float*)Xb);
+        }
+    }
+    // The buckets write the cell-start table even without points (every cell starts at 0).
+    int32_t* cs = outputs0 ? a.d.cstart : nullptr;
+    const dim3 grid((unsigned)bucket_blocks(a));
     if (dtype == IB_F64)
-        hipLaunchKernelGGL(keys_kernel<double>, dim3(blocks), dim3(256), lds, st, a, (const double*)X,
-                           s, s + 1);
+        hipLaunchKernelGGL(bucket_kernel<double>, grid, dim3(BKT_THREADS), 0, st, a, s, (const double*)Xb,
+                           outputs0 ? (double*)a.d.Xs : nullptr, cs);
     else
-        hipLaunchKernelGGL(keys_kernel<float>, dim3(blocks), dim3(256), lds, st, a, (const float*)X,
-                           s, s + 1);
+        hipLaunchKernelGGL(bucket_kernel<float>, grid, dim3(BKT_THREADS), 0, st, a, s, (const float*)Xb,
+                           outputs0 ? (float*)a.d.Xs : nullptr, cs);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* X, bool gather_x,
-                               hipStream_t st)
+hipError_t launch_keys_out(const SortArgs& a, int s, int32_t* keys, hipStream_t st)
 {
-    const GeomArgs& g = a.g;
-    if (g.npts > 0) {  // scanned passes (three launches each) or one-sweep passes
-        const unsigned tiles = (unsigned)a.ntiles, sblocks = (unsigned)a.nscan_tiles;
-        for (int p = 0; p < a.npass; ++p) {
-            switch (a.rbits) {
-#define IBK_SCANNED_PASS(B)                                                                        \
-    case B:                                                                                        \
-        if (!a.scanned) {                                                                          \
-            hipLaunchKernelGGL(radix_onesweep_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, \
-                               p);                                                                 \
-            break;                                                                                 \
-        }                                                                                          \
-        hipLaunchKernelGGL(radix_count_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p);   \
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(sblocks), dim3(SORT_BLOCK), 0, st, a, s, p);     \
-        hipLaunchKernelGGL(radix_scatter_kernel<B>, dim3(tiles), dim3(SORT_BLOCK), 0, st, a, s, p); \
-        break;
-            IBK_SCANNED_PASS(4)
-            IBK_SCANNED_PASS(5)
-            IBK_SCANNED_PASS(6)
-            IBK_SCANNED_PASS(7)
-            IBK_SCANNED_PASS(8)
-#undef IBK_SCANNED_PASS
-            default: return hipErrorInvalidValue;
-            }
-        }
-    }
-    const dim3 grid((unsigned)a.nseg_tiles);
-    const bool small = a.seg_ipt == SEG_IPT_SMALL;
-    if (dtype == IB_F64) {
-        double* Xs = gather_x ? (double*)a.d.Xs : nullptr;
-        if (small)
-            hipLaunchKernelGGL((segments_kernel<double, SEG_IPT_SMALL>), grid, dim3(SORT_BLOCK), 0, st,
-                               a, s, (const double*)X, Xs);
-        else
-            hipLaunchKernelGGL((segments_kernel<double, SEG_IPT>), grid, dim3(SORT_BLOCK), 0, st, a,
-                               s, (const double*)X, Xs);
-    } else {
-        float* Xs = gather_x ? (float*)a.d.Xs : nullptr;
-        if (small)
-            hipLaunchKernelGGL((segments_kernel<float, SEG_IPT_SMALL>), grid, dim3(SORT_BLOCK), 0, st,
-                               a, s, (const float*)X, Xs);
-        else
-            hipLaunchKernelGGL((segments_kernel<float, SEG_IPT>), grid, dim3(SORT_BLOCK), 0, st, a, s,
-                               (const float*)X, Xs);
-    }
+    if (a.g.npts == 0) return hipSuccess;
+    const unsigned nb = (unsigned)min((int64_t)4096, (a.g.npts + 255) / 256);
+    hipLaunchKernelGGL(keys_out_kernel, dim3(nb), dim3(256), 0, st, a, s, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_runs(const SortArgs& a, int s, hipStream_t st)
+{
+    hipLaunchKernelGGL(runs_kernel, dim3((unsigned)a.nseg_tiles), dim3(SORT_BLOCK), 0, st, a, s);
     return hipGetLastError();
 }
 

@@ -63,6 +63,8 @@ _lib.ib_plan_stagger_of.restype = _i32
 _lib.ib_plan_stagger_of.argtypes = [_vp, _i32]
 _lib.ib_plan_update.restype = _i32
 _lib.ib_plan_update.argtypes = [_vp, _vp, _vp]
+_lib.ib_plan_update_advected.restype = _i32
+_lib.ib_plan_update_advected.argtypes = [_vp, _vp]
 _lib.ib_plan_export.restype = _i32
 _lib.ib_plan_export.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.ib_plan_status.restype = _i32
@@ -124,7 +126,7 @@ _lib.ib_tether_force.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64,
 EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
             "ib_advect", "ib_tether_force", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
-            "ib_plan_stagger_of", "ib_plan_update", "ib_plan_export", "ib_plan_status",
+            "ib_plan_stagger_of", "ib_plan_update", "ib_plan_update_advected", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate"]
 
 
@@ -228,6 +230,12 @@ class Plan:
         X = self._pts(X, self.dim, "X")
         _check(_lib.ib_plan_update(self._h, _ptr(X), _stream(stream)), "ib_plan_update")
         self.X = X  # the library references X; keep it alive
+        return self
+
+    def update_advected(self, stream=None):
+        """Plan of the positions the last interpolate_advect wrote (into its X), sorted from
+        the previous order: the same plan as update(X) of those positions."""
+        _check(_lib.ib_plan_update_advected(self._h, _stream(stream)), "ib_plan_update_advected")
         return self
 
     def export(self, stagger_id=0, stream=None):

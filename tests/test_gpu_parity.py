@@ -346,7 +346,7 @@ def check_plan_stagger0(ib, orc, g, X, dtype, label):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_interpolate_advect_equals_two_calls(ib, dtype):
+def test_interpolate_advect_equals_two_calls(ib, orc, dtype):
     """The fused interpolation + position update gives bitwise the results of
     ib_interpolate followed by ib_advect, including the periodic wrap."""
     g = wl.grid(3, [40, 36, 44], 1.0)
@@ -363,10 +363,47 @@ def test_interpolate_advect_equals_two_calls(ib, dtype):
     torch.cuda.synchronize()
     assert torch.equal(U1, U2) and torch.equal(X1, X2)
     assert bool(((X2 >= 0) & (X2 < 1.0)).all())
-    # the update's sorted staggering is still there; unsorted ones can no longer be keyed
-    assert p2.export(0)["q"] > 0
+    # every staggering can still be exported for the update's positions (the plan keeps
+    # them in sorted order), bit-exact against the oracle
+    Xh = np.asarray(X, dtype=_np_dtype(dtype)).astype(np.float64)
+    for c in range(3):
+        got = p2.export(p2.stagger_of(c))
+        k_ref, bad = orc.keys(g, Xh, g["stagger"][c], _prec(dtype))
+        sk_ref, perm_ref, seg_ref, q_ref = orc.plan(k_ref)
+        assert bad == 0 and np.array_equal(to_host(got["keys"]), k_ref)
+        assert np.array_equal(to_host(got["perm"]), perm_ref) and got["q"] == q_ref
+        assert np.array_equal(to_host(got["seg_off"]), seg_ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_update_advected_equals_fresh_update(ib, orc, dtype):
+    """ib_plan_update_advected (the plan of the positions the last interpolate_advect
+    wrote, sorted from the previous order) equals a fresh ib_plan_update of those
+    positions: every staggering's keys, permutation and offsets bit for bit, and the
+    spread and interpolated values bit for bit; also over several steps of clustering
+    trajectories, and it refuses to run without a preceding interpolate_advect."""
+    g = wl.grid(3, [48, 40, 36], [1.0, 0.9, 0.8])
+    X, F, u = wl.uniform_case(g, 90000, 71)
+    Xd, Fd, ud = to_dev(X, dtype), to_dev(F, dtype), to_dev(u, dtype)
+    p = ib.Plan(g, X.shape[0], dtype).update(Xd)
     with pytest.raises(ib.IBError):
-        p2.export(1)
+        p.update_advected()
+    dt = 4.0 / 48
+    for step in range(4):
+        p.interpolate_advect(ud, Xd, dt)
+        p.update_advected()
+        q = ib.Plan(g, X.shape[0], dtype).update(Xd.clone())
+        for sid in range(p.nstag):
+            a, b = p.export(sid), q.export(sid)
+            for key in ("keys", "sorted_keys", "perm", "seg_off"):
+                assert torch.equal(a[key], b[key]), (step, sid, key)
+            assert a["q"] == b["q"]
+        assert torch.equal(p.spread(Fd), q.spread(Fd))
+        assert torch.equal(p.interpolate(ud), q.interpolate(ud))
+    check = Xd.clone()
+    with pytest.raises(ib.IBError):  # consumed: a second call needs another advect
+        p.update_advected()
+    assert torch.equal(check, Xd)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

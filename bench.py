@@ -326,12 +326,12 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
     def closed_batched(graph=False):
         srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=128, use_graph=graph)
         for jb in pool:
-            srv.submit(jb)
+            srv.submit(jb, inputs_ready=True)
         srv.drain()
         c0 = srv.clock_us()
         for _ in range(2):
             for jb in pool:
-                srv.submit(jb)
+                srv.submit(jb, inputs_ready=True)
         srv.drain()
         tb = (srv.clock_us() - c0) / 1e6
         st = srv.stats()
@@ -355,7 +355,7 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
                     break
                 if target - now > 400.0:
                     time.sleep((target - now - 300.0) / 1e6)
-            tickets.append(srv.submit(pool[i % pool_size], arrival_us=target))
+            tickets.append(srv.submit(pool[i % pool_size], arrival_us=target, inputs_ready=True))
             targets.append(target)
         srv.drain()
         res = [srv.poll(t) for t in tickets]

@@ -10,7 +10,7 @@
  *                  f_c(x_i) = sum_j delta_h(x_i - X_j) F_{j,c}, delta_h = prod_k h_k^-1 phi(./h_k)
  *   interpolation  U = J(X) u, eq. (disc-interp):  U_{j,c} = sum_i delta_h(x_i - X_j) u_c(x_i) h^d
  *   plan           cell keys, stable key/index sort, unique-key count and segment offsets,
- *                  the preparatory steps of Alg. 4 (Sec. 3.3).
+ *                  the preparatory steps of Alg. 4 (Sec. 3.4).
  * Grid points of component c are x = h (i + xi_c), i taken modulo n (periodic box,
  * Sec. 3.1), except along walled dimensions (ib_grid_desc.walls); phi is Peskin's 4-point
  * kernel or the cosine kernel (Sec. 2).
@@ -96,10 +96,13 @@ typedef struct ib_plan_s *ib_plan;
  *                 whose partial tiles a second kernel adds in block order: > 0 = at least
  *                 that many points per block; 0 = about 512 blocks in all, with at least
  *                 128 points per block (batches use this rule too); < 0 = never share
- *   radix_bits    radix digit width of the key sort, 4..8: 0 = the key bits spread evenly
- *                 over the fewest passes of at most 8 bits
+ *   radix_bits    bucket bits of the key sort (its first pass groups the points by the top
+ *                 radix_bits bits of their keys; each bucket is then sorted by one block),
+ *                 4..10: 0 = enough buckets for about 2048 points each, and for at most
+ *                 8192 cells each
  * Results do not depend on the tuning beyond rounding: keys, permutations and offsets are
- * identical, and spread values may differ in the order of their additions. */
+ * identical, and spread values may differ in the scale of their fixed-point sums (the
+ * tile shape and sharing set it). */
 typedef struct {
     int32_t spread_tile;
     int32_t split_points;
@@ -109,7 +112,7 @@ typedef struct {
 /* Human-readable name of a status code (static string). */
 const char *ib_status_string(int32_t status);
 
-/* ---- plans: keys, stable sort, segments (Alg. 4, Sec. 3.3; Fig. 2) -------------------- */
+/* ---- plans: keys, stable sort, segments (Alg. 4, Sec. 3.4; Fig. 2) -------------------- */
 
 /* Bytes of device workspace a plan for `npts` points needs (0 on invalid arguments).
  * npts may be 0. */
@@ -127,11 +130,13 @@ int32_t ib_plan_create(const ib_grid_desc *grid, int32_t dtype, int64_t npts,
 int32_t ib_plan_num_staggers(ib_plan plan);
 int32_t ib_plan_stagger_of(ib_plan plan, int32_t comp);
 
-/* Recompute the plan for positions X (device, npts x dim, plan dtype): per distinct
- * staggering, the cell key of every point, the stable ascending sort of the point indices
- * by key (ties keep input order), the number q of distinct keys and the first sorted
- * position of each run.  X is referenced, not copied: it must stay valid and unchanged
- * until the last spread/interpolate/gradient call that uses this update. */
+/* Recompute the plan for positions X (device, npts x dim, plan dtype): the cell key of
+ * every point on the staggering of component 0, the stable ascending sort of the point
+ * indices by key (ties keep input order), the first sorted position of every cell, and
+ * the positions in that order, which the operators use.  The other staggerings are keyed
+ * and sorted, and the number q of distinct keys and the first sorted position of each run
+ * are computed, only when ib_plan_export asks for them (from the positions of this update,
+ * which the plan keeps).  X is read by this call only. */
 int32_t ib_plan_update(ib_plan plan, const void *X, void *stream);
 
 /* The plan of the positions that the last ib_interpolate_advect on this plan produced
@@ -307,8 +312,11 @@ int32_t ib_server_create(const ib_server_opts *opts, void *arena, size_t arena_b
 /* Microseconds since the server was created (the clock of arrival times and latencies). */
 double ib_server_clock_us(ib_server server);
 
-/* Queue a job (non-blocking).  arrival_us < 0 means now.  The job's buffers must stay valid
- * and unchanged until ib_batch_poll reports it finished.  Errors: IB_ERR_ARG (bad job),
+/* Queue a job (non-blocking).  arrival_us < 0 means now.  The job's input buffers must
+ * already hold their final values when this is called: the server reads them on its own
+ * stream without waiting for work queued on any other stream (synchronise the stream that
+ * produced them first).  The job's buffers must stay valid and unchanged until
+ * ib_batch_poll reports it finished.  Errors: IB_ERR_ARG (bad job),
  * IB_ERR_OOM (its footprint exceeds the whole arena), IB_ERR_BUSY (queue full). */
 int32_t ib_batch_submit(ib_server server, const ib_job *job, double arrival_us, uint64_t *ticket);
 

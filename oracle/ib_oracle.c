@@ -17,7 +17,7 @@
  *   - discrete interpolation and spreading, eqs. (disc-interp) and (disc-spread) of
  *     Sec. 2: U_j = sum_i delta_h(x_i - X_j) u_i h^d and f_i = sum_j delta_h(x_i - X_j) F_j,
  *     where F_j already carries the Lagrangian weight dtheta_j;
- *   - sort keys and the stable key/index sort of Alg. 4 (Sec. 3.3), keys numbered
+ *   - sort keys and the stable key/index sort of Alg. 4 (Sec. 3.4), keys numbered
  *     x-fastest as in Fig. 2, counted from 0;
  *   - the position update X + dt U of the IB time step (Sec. 2), rounded once and wrapped
  *     into the periodic box;

@@ -258,19 +258,29 @@ class Plan:
     def status(self):
         return _lib.ib_plan_status(self._h)
 
-    def _pts(self, t, cols, name):
-        if t.dtype != self.dtype or t.device.type != "cuda":
-            raise TypeError(f"{name} must be a {self.dtype} CUDA tensor")
-        if t.shape != (self.npts, cols):
-            raise ValueError(f"{name} must have shape ({self.npts}, {cols}), got {tuple(t.shape)}")
+    def _check(self, t, shape, name, output):
+        """An input (copied to contiguous memory if need be) or an output / in-place
+        buffer (which must already be contiguous: the library writes through its pointer)
+        of the plan's dtype, on the plan's device, with exactly this shape."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if t.device.type != "cuda" or (self.device.index is not None and t.device.index != self.device.index):
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if output:
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous (it is written in place)")
+            return t
         return t.contiguous()
 
-    def _grid(self, t, name):
-        if t.dtype != self.dtype or t.device.type != "cuda":
-            raise TypeError(f"{name} must be a {self.dtype} CUDA tensor")
-        if list(t.shape) != self.grid_shape:
-            raise ValueError(f"{name} must have shape {self.grid_shape}, got {list(t.shape)}")
-        return t.contiguous()
+    def _pts(self, t, cols, name, output=False):
+        return self._check(t, (self.npts, cols), name, output)
+
+    def _grid(self, t, name, output=False):
+        return self._check(t, self.grid_shape, name, output)
 
     def spread(self, F, f=None, accumulate=False, stream=None):
         F = self._pts(F, self.ncomp, "F")
@@ -278,7 +288,7 @@ class Plan:
             f = torch.empty(self.grid_shape, dtype=self.dtype, device=self.device)
             accumulate = False
         else:
-            f = self._grid(f, "f")
+            f = self._grid(f, "f", output=True)
         _check(_lib.ib_spread(self._h, _ptr(F), _ptr(f), int(bool(accumulate)), _stream(stream)),
                "ib_spread")
         return f
@@ -287,10 +297,11 @@ class Plan:
         """U = J(X) u, then X <- wrap(X + dt U) in place (one pass; same results as
         interpolate followed by advect)."""
         u = self._grid(u, "u")
-        if X.dtype != self.dtype or not X.is_contiguous() or tuple(X.shape) != (self.npts, self.dim):
-            raise ValueError(f"X must be a contiguous ({self.npts}, {self.dim}) {self.dtype} tensor")
+        X = self._pts(X, self.dim, "X", output=True)
         if U is None:
             U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
+        else:
+            U = self._pts(U, self.ncomp, "U", output=True)
         _check(_lib.ib_interpolate_advect(self._h, _ptr(u), _ptr(U), _ptr(X), float(dt), _stream(stream)),
                "ib_interpolate_advect")
         return U
@@ -299,6 +310,8 @@ class Plan:
         u = self._grid(u, "u")
         if U is None:
             U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
+        else:
+            U = self._pts(U, self.ncomp, "U", output=True)
         _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
         return U
 
@@ -309,6 +322,8 @@ def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None):
     if dX is None:
         dX = torch.empty((plan.npts, plan.dim), dtype=plan.dtype, device=plan.device)
         accumulate = False
+    else:
+        dX = plan._pts(dX, plan.dim, "dX", output=True)
     _check(_lib.ib_interpolate_grad(plan._h, _ptr(u), _ptr(W), _ptr(dX), int(bool(accumulate)),
                                     _stream(stream)), "ib_interpolate_grad")
     return dX
@@ -317,10 +332,34 @@ def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None):
 Plan.interpolate_grad = _interp_grad
 
 
+def _point_arrays(grid, **arrays):
+    """Point arrays of a grid-level call: same dtype (FP64 or FP32), all on one CUDA
+    device, contiguous, shape (n, dim) with one n."""
+    d = int(grid["dim"])
+    n = None
+    dev = None
+    dtype = None
+    for name, t in arrays.items():
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.dim() != 2 or t.shape[1] != d:
+            raise ValueError(f"{name} must have shape (n, {d}), got {tuple(t.shape)}")
+        n = t.shape[0] if n is None else n
+        dev = t.device if dev is None else dev
+        dtype = t.dtype if dtype is None else dtype
+        if t.shape[0] != n or t.device != dev or t.dtype != dtype:
+            raise ValueError("point arrays must agree in length, device and dtype")
+    _dtype_code(dtype)
+    return n
+
+
 def advect(grid, X, U, dt, stream=None):
     """In place: X <- X + dt U, wrapped into the periodic box (IB step position update)."""
-    if X.shape[0] != U.shape[0] or X.dtype != U.dtype or not X.is_contiguous() or not U.is_contiguous():
-        raise ValueError("X and U must be contiguous with matching rows and dtype")
+    _point_arrays(grid, X=X, U=U)
     _check(_lib.ib_advect(ctypes.byref(make_desc(grid)), _dtype_code(X.dtype), X.shape[0], _ptr(X),
                           _ptr(U), float(dt), _stream(stream)), "ib_advect")
     return X
@@ -329,12 +368,10 @@ def advect(grid, X, U, dt, stream=None):
 def tether_force(grid, X0, X, k, F=None, stream=None):
     """F = k (X0 - X), per coordinate to the nearest periodic image: the Hookean tether of the
     unstructured-point test (Sec. 4.1)."""
-    if X0.shape != X.shape or X0.dtype != X.dtype or not X0.is_contiguous() or not X.is_contiguous():
-        raise ValueError("X0 and X must be contiguous with matching shape and dtype")
     if F is None:
+        _point_arrays(grid, X0=X0, X=X)
         F = torch.empty_like(X)
-    if F.shape != X.shape or F.dtype != X.dtype or not F.is_contiguous():
-        raise ValueError("F must be contiguous, with the shape and dtype of X")
+    _point_arrays(grid, X0=X0, X=X, F=F)
     _check(_lib.ib_tether_force(ctypes.byref(make_desc(grid)), _dtype_code(X.dtype), X.shape[0],
                                 _ptr(X0), _ptr(X), float(k), _ptr(F), _stream(stream)),
            "ib_tether_force")
@@ -473,7 +510,13 @@ class Server:
     def clock_us(self):
         return _lib.ib_server_clock_us(self._h)
 
-    def submit(self, job, arrival_us=-1.0):
+    def submit(self, job, arrival_us=-1.0, inputs_ready=False):
+        """Queue a job.  The server reads the job's inputs on its own stream, so they must
+        be complete when the job is submitted: unless inputs_ready says they are, the
+        caller's current stream is synchronised first (inputs produced by torch kernels
+        just before the call are then seen whole)."""
+        if not inputs_ready:
+            torch.cuda.current_stream(self.device).synchronize()
         jd = job_desc(job, self.dtype)
         t = ctypes.c_uint64()
         _check(_lib.ib_batch_submit(self._h, ctypes.byref(jd), float(arrival_us), ctypes.byref(t)),

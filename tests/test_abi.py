@@ -128,3 +128,29 @@ def test_tuned_workspace_and_validation(ib):
         h = ctypes.c_void_p()
         assert ib._lib.ib_plan_create_tuned(ctypes.byref(g), 0, 1000, ctypes.byref(bad),
                                             ctypes.c_void_p(4096), 1 << 30, ctypes.byref(h)) == -1
+
+
+def test_binding_rejects_bad_buffers_before_any_launch(ib):
+    """Output and in-place buffers are checked (dtype, device, contiguity, exact shape)
+    before the library is called; a host tensor or a wrong shape raises instead of reaching
+    a kernel.  Runs on the CPU: the plan object is built without a device workspace."""
+    import torch
+    g = {"dim": 3, "n": [8, 8, 8], "length": [1.0, 1.0, 1.0],
+         "stagger": [[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]}
+    p = object.__new__(ib.Plan)  # no workspace: only the argument checks run
+    p.dtype, p.device, p.npts, p.dim, p.ncomp = torch.float64, torch.device("cuda", 0), 10, 3, 3
+    p.grid_shape = [3, 8, 8, 8]
+    ok_pts = torch.empty(10, 3, dtype=torch.float64)
+    with pytest.raises(ValueError):  # host tensor
+        p._pts(ok_pts, 3, "U", output=True)
+    with pytest.raises(TypeError):  # dtype
+        p._pts(ok_pts.float(), 3, "U", output=True)
+    meta = torch.empty(10, 4, dtype=torch.float64, device="meta")
+    with pytest.raises(ValueError):
+        p._pts(meta, 3, "U", output=True)
+    with pytest.raises(ValueError):  # grid shape
+        p._grid(torch.empty(3, 8, 8, 7, dtype=torch.float64), "f", output=True)
+    for bad in ({"X": ok_pts, "U": torch.empty(10, 2, dtype=torch.float64)},
+                {"X": torch.empty(10, 2, dtype=torch.float64), "U": ok_pts}):
+        with pytest.raises(ValueError):
+            ib._point_arrays(g, **bad)

@@ -121,3 +121,35 @@ def test_server_rejects_and_flags(ib):
     assert st == [0, 0, -6, 0]
     assert srv.poll(t[0])[0] == -1  # reported once
     srv.close()
+
+
+def test_server_sees_inputs_written_just_before_submit(ib):
+    """Inputs produced by torch kernels on the caller's stream right before submit: the
+    server (its own stream) sees them whole and gives the same results as the job run alone."""
+    dtype = torch.float64
+    jobs = serving_jobs(6, dtype, 6500, sizes=(32, 48), nmax=60000)
+    say("server: inputs written on the caller's stream before each submit")
+    srv = ib.Server(dtype, arena_bytes=512 << 20, max_jobs_per_batch=8)
+    final = []
+    tickets = []
+    for j in jobs:
+        X0, F0, u0 = j["X"].clone(), j["F"].clone(), j["u"].clone()
+        final.append((X0, F0, u0))
+        # stale contents first, then the real inputs written by a chain of kernels
+        j["X"].fill_(0.5)
+        j["F"].zero_()
+        j["u"].zero_()
+        for _ in range(20):
+            j["F"].mul_(1.0)
+        j["X"].copy_(X0)
+        j["F"].copy_(F0)
+        j["u"].copy_(u0)
+        tickets.append(srv.submit(j))
+    srv.drain()
+    out = [srv.poll(t)[0] for t in tickets]
+    srv.close()
+    assert out == [0] * len(jobs)
+    for j, (X0, F0, u0) in zip(jobs, final):
+        ref = {"grid": j["grid"], "X": X0, "F": F0, "u": u0}
+        f1, U1 = alone(ib, ref, dtype)
+        assert torch.equal(j["f"], f1) and torch.equal(j["U"], U1)

@@ -313,3 +313,93 @@ def test_interp_grad_matches_finite_differences(orc):
         Xm[:, k] -= e
         fd = ((orc.interp(g, Xp, u) - orc.interp(g, Xm, u)) * W).sum(1) / (2 * e)
         assert np.abs(fd - dX[:, k]).max() < 1e-6 * (np.abs(dX).max() + 1)
+
+
+# ---- spreading at sampled grid points ---------------------------------------------------
+
+@pytest.mark.parametrize("kernel", ["peskin4", "cosine4", "roma3"])
+@pytest.mark.parametrize("walls", [0, 0b101])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_spread_at_equals_full_spread(orc, kernel, walls, dim):
+    """or_spread_at (one grid value at a time, by a loop over all points) against the
+    full spread of both oracle tiers and the independent dense matrix, at sampled targets
+    on a grid whose sizes, spacings and staggerings all differ per dimension, with three
+    components carrying different forces: a wrong unflattening of the target index, a
+    component mix-up or a missing 1/h^d would each fail it."""
+    walls &= (1 << dim) - 1
+    n = [7, 5, 6][:dim]
+    length = [0.7, 1.25, 0.9][:dim]
+    g = wl.grid(dim, n, length, kernel=kernel)
+    g["walls"] = walls
+    r = wl.rng(300 + 10 * dim + walls)
+    X = r.uniform(-0.3, 1.3, (61, dim)) * np.array(length)  # outside the box too
+    F = r.standard_normal((61, dim)) * np.array([1.0, 10.0, 100.0])[:dim]
+    fa = orc.spread(g, X, F, tier=0)
+    fb = orc.spread(g, X, F, tier=1)
+    fd = allpairs.spread(g, X, F)
+    G = int(np.prod(n))
+    comp = np.repeat(np.arange(dim), 40).astype(np.int32)
+    target = np.concatenate([np.r_[0, G - 1, r.integers(0, G, 38)] for _ in range(dim)])
+    got = orc.spread_at(g, X, F, comp, target)
+    for ref in (fa, fb, fd):
+        want = ref.reshape(dim, -1)[comp, target]
+        scale = np.abs(ref).max()
+        assert np.abs(got - want).max() <= 1e-14 * scale
+
+
+# ---- keys at a scale that is not a power of two -----------------------------------------
+
+def _round_binary(q, bits):
+    """Exact rational q rounded to the nearest number with a `bits`-bit significand, ties
+    to even (IEEE round to nearest; normal range)."""
+    if q == 0:
+        return Fraction(0)
+    a = abs(q)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    ulp = Fraction(2) ** (e - bits + 1)
+    return (1 if q > 0 else -1) * round(a / ulp) * ulp
+
+
+@pytest.mark.parametrize("prec,bits", [("f32", 24), ("f64", 53)])
+@pytest.mark.parametrize("N,L", [(96, 1.0), (100, 0.9)])
+def test_keys_inexact_scale_exact_rational(orc, prec, bits, N, L):
+    """Keys where N / L is not a power of two, so the scaled coordinate t = X (N / L) is
+    rounded: the key rule rounds inv_h = N / L and then the product once in the job's
+    precision, subtracts the staggering in that precision and floors.  Checked with exact
+    rationals and IEEE rounding written out here, on random coordinates and on coordinates
+    just below cell faces, where a product rounded in double instead of the job's
+    precision floors differently (those cases must exist, and the oracle must side with
+    the rule)."""
+    nb = np.float32 if prec == "f32" else np.float64
+    r = wl.rng(400 + N)
+    X = r.uniform(-0.5, 1.5, 4000) * L
+    # coordinates just below a face k / inv_h: the rounded product lands on k
+    faces = np.arange(-40, 140) * (L / N)
+    near = []
+    for x in faces.astype(nb):
+        v = x
+        for _ in range(4):
+            v = np.nextafter(v, nb(-np.inf))
+            near.append(v)
+    X = np.concatenate([X.astype(nb), np.array(near, dtype=nb)]).astype(np.float64)
+    inv_h = _round_binary(Fraction(float(nb(N))) / Fraction(float(nb(L))), bits)
+    grid = wl.grid(2, [N, 8], [L, 1.0])
+    Xg = np.stack([X, np.full_like(X, 0.0625)], axis=1)
+    discriminating = 0
+    for xi in (0.0, 0.5):
+        k, bad = orc.keys(grid, Xg, [xi, 0.5], prec)
+        assert bad == 0
+        for j in range(len(X)):
+            t = _round_binary(Fraction(float(X[j])) * inv_h, bits)
+            y = _round_binary(t - Fraction(xi), bits)
+            want = math.floor(y) % N
+            assert k[j] % N == want, (j, X[j])
+            # the mutant: product rounded in double, staggering subtracted in double
+            tm = _round_binary(Fraction(float(X[j])) * inv_h, 53)
+            ym = _round_binary(tm - Fraction(xi), 53)
+            if math.floor(ym) % N != want:
+                discriminating += 1
+    if prec == "f32":
+        assert discriminating > 0  # the pin tells the rule from the double-product mutant

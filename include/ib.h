@@ -206,6 +206,25 @@ int32_t ib_interpolate_advect(ib_plan plan, const void *u, void *U, void *X, dou
 int32_t ib_interpolate_grad(ib_plan plan, const void *u, const void *W, void *dX,
                             int32_t accumulate, void *stream);
 
+/* Scaled operators, for the adjoints of Sec. 2's pair J = S^T taken in the grid inner
+ * product weighted by prod_k h_k (gradients through spreading and interpolation): each is
+ * the operator above with its result multiplied by scale inside the same kernels, with no
+ * extra pass over the grid or the points.
+ *   ib_spread_scaled:           f (+)= scale * S(X) F; the factor scale * (prod_k h_k)^-1 is
+ *                               formed once in FP64 and applied to the exact sums, so the
+ *                               result is bitwise reproducible as for ib_spread.
+ *   ib_interpolate_scaled:      U = scale * J(X) u, each result times scale (rounded to the
+ *                               plan's precision) after its sum.
+ *   ib_interpolate_grad_scaled: dX (+)= scale * (the gradient of ib_interpolate_grad), the
+ *                               product taken before any accumulation.
+ * Arguments, layouts and ownership as for the unscaled calls (which are these with scale 1,
+ * bit for bit).  Errors: IB_ERR_ARG for a non-finite scale, plus those of the unscaled calls. */
+int32_t ib_spread_scaled(ib_plan plan, const void *F, void *f, double scale, int32_t accumulate,
+                         void *stream);
+int32_t ib_interpolate_scaled(ib_plan plan, const void *u, void *U, double scale, void *stream);
+int32_t ib_interpolate_grad_scaled(ib_plan plan, const void *u, const void *W, void *dX,
+                                   double scale, int32_t accumulate, void *stream);
+
 /* Position update of the IB time step, steps (b)/(g) of Sec. 2 with the interpolated
  * velocity: X <- X + dt * U, each coordinate of a periodic dimension wrapped back into
  * [0, length_k) (walled dimensions: no wrap).  X (npts x dim)

@@ -7,7 +7,8 @@ weights of eqs. (disc-interp), (disc-spread)):
     f = S(X) F:   dL/dF = h^-d J(X) gf,             dL/dX_j = h^-d sum_c F_{j,c} d(J gf)_{j,c}/dX_j
 
 where h^d = prod_k h_k and the position terms use the derivative of the delta kernel
-(ib_interpolate_grad).  Every step runs in libibops kernels; torch only carries tensors.
+(ib_interpolate_grad).  Every step, the h^(+-d) factors included (the scaled entry
+points), runs in libibops kernels; torch only carries tensors.
 For L = 1/2 |J(X)u|^2 + <S(X)F, g>_h with <a, b>_h = h^d sum a b, this gives dL/dF = J g and
 dL/du = h^d S(J u), i.e. S v in the h-weighted grid inner product.
 """
@@ -46,7 +47,7 @@ class Interpolate(torch.autograd.Function):
         gU = gU.contiguous()
         dX = du = None
         if ctx.needs_input_grad[1]:
-            du = plan.spread(gU).mul_(ctx.hd)
+            du = plan.spread(gU, scale=ctx.hd)
         if ctx.needs_input_grad[0]:
             dX = plan.interpolate_grad(u, gU)
         return dX, du, None
@@ -72,9 +73,9 @@ class Spread(torch.autograd.Function):
         gf = gf.contiguous()
         dX = dF = None
         if ctx.needs_input_grad[1]:
-            dF = plan.interpolate(gf).div_(ctx.hd)
+            dF = plan.interpolate(gf, scale=1.0 / ctx.hd)
         if ctx.needs_input_grad[0]:
-            dX = plan.interpolate_grad(gf, F).div_(ctx.hd)
+            dX = plan.interpolate_grad(gf, F, scale=1.0 / ctx.hd)
         return dX, dF, None
 
 

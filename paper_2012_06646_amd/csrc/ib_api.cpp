@@ -443,6 +443,7 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->partial = p->sa.d.partial;
     a->tile_shift = p->sa.d.tile_shift;
     a->fmax = p->sa.d.fmax;
+    a->out_scale = 1.0;
 }
 
 // The caller's grid field u, or (walled plans) its copy padded with zero ghost values.
@@ -453,12 +454,14 @@ static const void* kernel_field(ib_plan p, const void* u, hipStream_t st, hipErr
     return p->gpad;
 }
 
-int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
+int32_t ib_spread_scaled(ib_plan p, const void* F, void* f, double scale, int32_t accumulate,
+                         void* stream)
 {
-    if (!p || !f || !p->updated) return IB_ERR_ARG;
+    if (!p || !f || !p->updated || !std::isfinite(scale)) return IB_ERR_ARG;
     if (!F && p->npts > 0) return IB_ERR_ARG;
     OpArgs a;
     fill_op_args(p, &a);
+    a.g.scale *= scale;  // one factor applied to the exact sums: (prod_k h_k)^-1 * scale
     a.F = F;
     a.f = p->user.walls ? p->gpad : f;  // walled: spread onto the padded grid, then drop ghosts
     a.accumulate = !p->user.walls && accumulate != 0;
@@ -470,13 +473,19 @@ int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* s
     return hip_status(e);
 }
 
-int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
+int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
 {
-    if (!p || !u || !p->updated) return IB_ERR_ARG;
+    return ib_spread_scaled(p, F, f, 1.0, accumulate, stream);
+}
+
+int32_t ib_interpolate_scaled(ib_plan p, const void* u, void* U, double scale, void* stream)
+{
+    if (!p || !u || !p->updated || !std::isfinite(scale)) return IB_ERR_ARG;
     if (!U && p->npts > 0) return IB_ERR_ARG;
     if (p->npts == 0) return IB_OK;
     OpArgs a;
     fill_op_args(p, &a);
+    a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     a.u = kernel_field(p, u, st, &e);
@@ -484,6 +493,11 @@ int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
     p->last_stream = st;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
     return hip_status(e);
+}
+
+int32_t ib_interpolate(ib_plan p, const void* u, void* U, void* stream)
+{
+    return ib_interpolate_scaled(p, u, U, 1.0, stream);
 }
 
 int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double dt, void* stream)
@@ -516,14 +530,15 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     return hip_status(e);
 }
 
-int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, int32_t accumulate,
-                            void* stream)
+int32_t ib_interpolate_grad_scaled(ib_plan p, const void* u, const void* W, void* dX, double scale,
+                                   int32_t accumulate, void* stream)
 {
-    if (!p || !u || !p->updated) return IB_ERR_ARG;
+    if (!p || !u || !p->updated || !std::isfinite(scale)) return IB_ERR_ARG;
     if ((!W || !dX) && p->npts > 0) return IB_ERR_ARG;
     if (p->npts == 0) return IB_OK;
     OpArgs a;
     fill_op_args(p, &a);
+    a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     a.u = kernel_field(p, u, st, &e);
@@ -531,6 +546,12 @@ int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, i
     if (e == hipSuccess)
         e = launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st);
     return hip_status(e);
+}
+
+int32_t ib_interpolate_grad(ib_plan p, const void* u, const void* W, void* dX, int32_t accumulate,
+                            void* stream)
+{
+    return ib_interpolate_grad_scaled(p, u, W, dX, 1.0, accumulate, stream);
 }
 
 int32_t ib_advect(const ib_grid_desc* grid, int32_t dtype, int64_t npts, void* X, const void* U,

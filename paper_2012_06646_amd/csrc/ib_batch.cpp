@@ -97,6 +97,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.f = J.f;
         a.u = J.u;
         a.U = J.U;
+        a.out_scale = 1.0;
         a.accumulate = 0;
         spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles, &a.tile_slow);
 

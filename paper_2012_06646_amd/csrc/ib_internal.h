@@ -113,6 +113,7 @@ struct OpArgs {
     int32_t* tile_shift;         //   and each split tile's scale exponent
     const unsigned long long* fmax;  // partial maxima of |F| per component (fmax_kernel)
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
+    double out_scale;            // interpolation and its gradient: results times this (1: none)
     void* Xadv;                  // interpolation: also advance these positions (or null)
     void* Xnext;                 //   and write them in sorted order here, columns (or null)
     double adv_dt;               //   X <- wrap(X + dt U) with box edges adv_len

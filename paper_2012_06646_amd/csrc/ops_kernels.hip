@@ -694,6 +694,7 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
     const T* __restrict__ Xs = (const T*)a.Xs;
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
+    const T os = (T)a.out_scale;
     const bool unrolled = sizeof(T) == 4 && ncomp == DIM;
     for (int64_t j = (int64_t)bid * blockDim.x + threadIdx.x; j < n; j += (int64_t)nblk * blockDim.x) {
         T x[DIM];
@@ -705,11 +706,11 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
 #pragma unroll
             for (int c = 0; c < DIM; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) U[p * DIM + c] = res[c];
+            for (int c = 0; c < DIM; ++c) U[p * DIM + c] = res[c] * os;
         } else {
 #pragma unroll 1
             for (int c = 0; c < ncomp; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
-            for (int c = 0; c < ncomp; ++c) U[p * ncomp + c] = res[c];
+            for (int c = 0; c < ncomp; ++c) U[p * ncomp + c] = res[c] * os;
         }
         if (a.Xadv) {  // fused position update (ncomp == DIM): the same arithmetic as advect
             T* __restrict__ Xa = (T*)a.Xadv;
@@ -792,6 +793,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
     T* __restrict__ Us = (T*)a.Us;
+    const T os = (T)a.out_scale;
     const int ncomp = g.ncomp;
     for (int c = 0; c < ncomp; ++c) {
         // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + 2) per axis, wrapped.
@@ -908,7 +910,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                 const T res[3] = {c == 0 ? sum : done[q][0], c == 1 ? sum : done[q][1], sum};
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
-                    if (k < ncomp) U[p * ncomp + k] = res[k];
+                    if (k < ncomp) U[p * ncomp + k] = res[k] * os;
                 if (adv) {
                     T* __restrict__ Xa = (T*)a.Xadv;
                     T* __restrict__ Xn = (T*)a.Xnext;
@@ -1016,7 +1018,8 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             T* d = dX + p * DIM + k;
-            *d = accumulate ? *d + grad[k] : grad[k];
+            const T v = grad[k] * (T)a.out_scale;
+            *d = accumulate ? *d + v : v;
         }
     }
 }
@@ -1413,7 +1416,7 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
 template <typename T>
 void batch_ops_by_shape(const BatchLaunch& b, hipStream_t st)
 {
-    with_kernel(b.kernel, [&](auto K) {
+    (void)with_kernel(b.kernel, [&](auto K) {
         if (b.dim == 3) batch_ops_dispatch<T, 3, decltype(K)::value>(b, st);
         else batch_ops_dispatch<T, 2, decltype(K)::value>(b, st);
         return hipSuccess;

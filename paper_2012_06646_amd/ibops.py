@@ -80,6 +80,12 @@ _lib.ib_interpolate_advect.restype = _i32
 _lib.ib_interpolate_advect.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp]
 _lib.ib_interpolate_grad.restype = _i32
 _lib.ib_interpolate_grad.argtypes = [_vp, _vp, _vp, _vp, _i32, _vp]
+_lib.ib_spread_scaled.restype = _i32
+_lib.ib_spread_scaled.argtypes = [_vp, _vp, _vp, ctypes.c_double, _i32, _vp]
+_lib.ib_interpolate_scaled.restype = _i32
+_lib.ib_interpolate_scaled.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp]
+_lib.ib_interpolate_grad_scaled.restype = _i32
+_lib.ib_interpolate_grad_scaled.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _i32, _vp]
 class JobDesc(ctypes.Structure):
     _fields_ = [("grid", GridDesc), ("npts", ctypes.c_int64), ("X", ctypes.c_void_p),
                 ("F", ctypes.c_void_p), ("f", ctypes.c_void_p), ("u", ctypes.c_void_p),
@@ -127,7 +133,8 @@ EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_c
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
             "ib_advect", "ib_tether_force", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_update_advected", "ib_plan_export", "ib_plan_status",
-            "ib_plan_destroy", "ib_spread", "ib_interpolate"]
+            "ib_plan_destroy", "ib_spread", "ib_interpolate", "ib_spread_scaled", "ib_interpolate_scaled",
+            "ib_interpolate_grad_scaled"]
 
 
 class IBError(RuntimeError):
@@ -282,15 +289,20 @@ class Plan:
     def _grid(self, t, name, output=False):
         return self._check(t, self.grid_shape, name, output)
 
-    def spread(self, F, f=None, accumulate=False, stream=None):
+    def spread(self, F, f=None, accumulate=False, stream=None, scale=None):
+        """f (+)= S(X) F, or scale * S(X) F (ib_spread_scaled) when scale is given."""
         F = self._pts(F, self.ncomp, "F")
         if f is None:
             f = torch.empty(self.grid_shape, dtype=self.dtype, device=self.device)
             accumulate = False
         else:
             f = self._grid(f, "f", output=True)
-        _check(_lib.ib_spread(self._h, _ptr(F), _ptr(f), int(bool(accumulate)), _stream(stream)),
-               "ib_spread")
+        if scale is None:
+            _check(_lib.ib_spread(self._h, _ptr(F), _ptr(f), int(bool(accumulate)), _stream(stream)),
+                   "ib_spread")
+        else:
+            _check(_lib.ib_spread_scaled(self._h, _ptr(F), _ptr(f), float(scale), int(bool(accumulate)),
+                                         _stream(stream)), "ib_spread_scaled")
         return f
 
     def interpolate_advect(self, u, X, dt, U=None, stream=None):
@@ -306,17 +318,23 @@ class Plan:
                "ib_interpolate_advect")
         return U
 
-    def interpolate(self, u, U=None, stream=None):
+    def interpolate(self, u, U=None, stream=None, scale=None):
+        """U = J(X) u, or scale * J(X) u (ib_interpolate_scaled) when scale is given."""
         u = self._grid(u, "u")
         if U is None:
             U = torch.empty((self.npts, self.ncomp), dtype=self.dtype, device=self.device)
         else:
             U = self._pts(U, self.ncomp, "U", output=True)
-        _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
+        if scale is None:
+            _check(_lib.ib_interpolate(self._h, _ptr(u), _ptr(U), _stream(stream)), "ib_interpolate")
+        else:
+            _check(_lib.ib_interpolate_scaled(self._h, _ptr(u), _ptr(U), float(scale), _stream(stream)),
+                   "ib_interpolate_scaled")
         return U
 
 
-def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None):
+def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None, scale=None):
+    """dX (+)= the position gradient of J(X) u against W (times scale when given)."""
     u = plan._grid(u, "u")
     W = plan._pts(W, plan.ncomp, "W")
     if dX is None:
@@ -324,8 +342,13 @@ def _interp_grad(plan, u, W, dX=None, accumulate=False, stream=None):
         accumulate = False
     else:
         dX = plan._pts(dX, plan.dim, "dX", output=True)
-    _check(_lib.ib_interpolate_grad(plan._h, _ptr(u), _ptr(W), _ptr(dX), int(bool(accumulate)),
-                                    _stream(stream)), "ib_interpolate_grad")
+    if scale is None:
+        _check(_lib.ib_interpolate_grad(plan._h, _ptr(u), _ptr(W), _ptr(dX), int(bool(accumulate)),
+                                        _stream(stream)), "ib_interpolate_grad")
+    else:
+        _check(_lib.ib_interpolate_grad_scaled(plan._h, _ptr(u), _ptr(W), _ptr(dX), float(scale),
+                                               int(bool(accumulate)), _stream(stream)),
+               "ib_interpolate_grad_scaled")
     return dX
 
 

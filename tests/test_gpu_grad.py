@@ -107,3 +107,41 @@ def test_rbc128_gradients(mods, orc, dtype):
         e = normwise(a, b)
         say(f"   {name} err {e:.3e}")
         assert e <= tol, (name, e)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("walls", [0, 0b100])
+def test_scaled_entry_points(mods, orc, dtype, walls):
+    """The scaled calls against the oracle's operators times the scale, and scale 1 against
+    the unscaled calls bit for bit.  Interpolation and its gradient round the product once
+    after the sum: bitwise the unscaled result times the scale in the plan's precision."""
+    ib, _ = mods
+    g = dict(wl.grid(3, [24, 20, 16], [1.2, 1.0, 0.8]), walls=walls)
+    X, F, u = wl.uniform_case(g, 5000, 77)
+    W = wl.rng(78).standard_normal(F.shape)
+    nd = np.float32 if dtype == torch.float32 else np.float64
+    X, F, u, W = (a.astype(nd) for a in (X, F, u, W))
+    say(f"scaled entry points {dtype} walls={walls}")
+    p = ib.Plan(g, X.shape[0], dtype).update(to_dev(X, dtype))
+    Fd, ud, Wd = to_dev(F, dtype), to_dev(u, dtype), to_dev(W, dtype)
+    tol = TOL[dtype]
+    for s in (1.0, 0.37, -2.5e3):
+        f = p.spread(Fd, scale=s)
+        U = p.interpolate(ud, scale=s)
+        dX = p.interpolate_grad(ud, Wd, scale=s)
+        assert normwise(to_host(f), s * orc.spread(g, X, F)) <= tol
+        assert normwise(to_host(U), s * orc.interp(g, X, u)) <= tol
+        assert normwise(to_host(dX), s * orc.interp_grad(g, X, u, W)) <= tol
+        assert torch.equal(U, p.interpolate(ud) * s)
+        assert torch.equal(dX, p.interpolate_grad(ud, Wd) * s)
+        if s == 1.0:
+            assert torch.equal(f, p.spread(Fd))
+        # accumulation adds the scaled result
+        acc = p.interpolate_grad(ud, Wd)
+        p.interpolate_grad(ud, Wd, dX=acc, accumulate=True, scale=s)
+        assert torch.equal(acc, p.interpolate_grad(ud, Wd) + dX)
+        facc = p.spread(Fd)
+        p.spread(Fd, f=facc, accumulate=True, scale=s)
+        assert torch.equal(facc, p.spread(Fd) + f)
+    with pytest.raises(ib.IBError):
+        p.interpolate(ud, scale=float("inf"))

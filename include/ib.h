@@ -290,6 +290,25 @@ int32_t ib_batch_run(const ib_job *jobs, int32_t njobs, int32_t dtype, void *wor
 int32_t ib_batch_status(const ib_job *jobs, int32_t njobs, int32_t dtype, const void *workspace,
                         int32_t *job_status, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ib_batch_run with the workspace taken
+ * from a fixed array of IB_STATIC_SCRATCH_BYTES bytes that the library holds in device memory
+ * (one per GPU, until the process ends).  Runs on the current device, whose stream `stream`
+ * must be; results equal those of ib_batch_run on the same jobs, bit for bit.  Calls no
+ * device or host memory allocator of HIP (no hipMalloc, hipFree, hipHostMalloc).
+ * job_flags: device array of njobs words, or NULL; once the batch has finished it holds each
+ * job's device error flag (0: none; else the job's positions were flagged as for
+ * ib_plan_status), written in stream order.  host_staging as for ib_batch_run.
+ * Every call on one GPU uses that GPU's one array, which keeps the last call's contents
+ * (each call sets up what it needs itself): calls whose work overlaps on one GPU (other
+ * streams, other threads) race and give wrong results; order them on one stream.
+ * Errors: IB_ERR_OOM when ib_batch_workspace_bytes(jobs, njobs, dtype) exceeds
+ * IB_STATIC_SCRATCH_BYTES (checked before any device work), IB_ERR_HIP if the array's
+ * address cannot be taken, and those of ib_batch_run. */
+#define IB_STATIC_SCRATCH_BYTES (64u << 20)
+int32_t ib_batch_run_static(const ib_job *jobs, int32_t njobs, int32_t dtype, void *host_staging,
+                            uint32_t *job_flags, void *stream);
+
 /* ---- serving loop ------------------------------------------------------------------- */
 
 /* A server takes independent jobs one at a time (ib_batch_submit), queues them, and runs

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "ib.h"
@@ -193,6 +194,37 @@ int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
 
 }  // namespace ibk
 
+// ---- the batch workspace of ib_batch_run_static -------------------------------------------
+//
+// A fixed array in device memory: each GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code the array's name is only a host-side
+// stand-in: the kernels and copies receive the device address taken once per device with
+// hipGetSymbolAddress (static_scratch), never the name.
+static __device__ __align__(256) unsigned char scratch[IB_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[SCRATCH_DEVICES];  // device address of scratch per device (null: not yet taken)
+
+// The current device's copy of scratch (taken on the first call on that device).
+int32_t static_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_DEVICES) return IB_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IB_ERR_HIP;
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return IB_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype)
@@ -214,6 +246,25 @@ int32_t ib_batch_run(const ib_job* jobs, int32_t njobs, int32_t dtype, void* wor
 {
     return ibk::batch_launch(jobs, njobs, dtype, workspace, workspace_bytes, host_staging,
                              (hipStream_t)stream);
+}
+
+int32_t ib_batch_run_static(const ib_job* jobs, int32_t njobs, int32_t dtype, void* host_staging,
+                            uint32_t* job_flags, void* stream)
+{
+    BatchLayout B;
+    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    if (st != IB_OK) return st;
+    if (B.header + B.plans > (size_t)IB_STATIC_SCRATCH_BYTES) return IB_ERR_OOM;
+    void* ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != IB_OK) return st;
+    hipStream_t hs = (hipStream_t)stream;
+    st = batch_launch(jobs, njobs, dtype, ws, IB_STATIC_SCRATCH_BYTES, host_staging, hs);
+    if (st == IB_OK && job_flags &&
+        hipMemcpyAsync(job_flags, (const char*)ws + batch_flags_offset(), njobs * sizeof(uint32_t),
+                       hipMemcpyDeviceToDevice, hs) != hipSuccess)
+        st = IB_ERR_HIP;
+    return st;
 }
 
 int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const void* workspace,

@@ -98,6 +98,8 @@ _lib.ib_batch_staging_bytes.restype = ctypes.c_size_t
 _lib.ib_batch_staging_bytes.argtypes = [_i32]
 _lib.ib_batch_run.restype = _i32
 _lib.ib_batch_run.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.ib_batch_run_static.restype = _i32
+_lib.ib_batch_run_static.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, _vp, _vp]
 _lib.ib_batch_status.restype = _i32
 _lib.ib_batch_status.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.POINTER(_i32), _vp]
 class ServerOpts(ctypes.Structure):
@@ -131,6 +133,7 @@ _lib.ib_tether_force.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64,
 
 EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
+            "ib_batch_run_static",
             "ib_advect", "ib_tether_force", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_update_advected", "ib_plan_export", "ib_plan_status",
             "ib_plan_destroy", "ib_spread", "ib_interpolate", "ib_spread_scaled", "ib_interpolate_scaled",
@@ -414,6 +417,7 @@ def interpolate(grid, X, u):
 
 
 BATCH_MAX_JOBS = 128
+STATIC_SCRATCH_BYTES = 64 << 20  # IB_STATIC_SCRATCH_BYTES: largest workspace of run_static
 
 
 class Batch:
@@ -421,9 +425,10 @@ class Batch:
     (ib_batch_run).  Each job is a dict with keys grid, X and optionally F (spread) and u
     (interpolate); all share a dtype, dimension and kernel.  Outputs (f and U per job) and
     the workspace are allocated once; `run()` may be called again after the inputs'
-    contents change (same shapes)."""
+    contents change (same shapes).  workspace=False allocates no workspace: such a batch runs
+    only through run_static (the library's fixed device array, ib_batch_run_static)."""
 
-    def __init__(self, jobs, dtype=torch.float64, device="cuda"):
+    def __init__(self, jobs, dtype=torch.float64, device="cuda", workspace=True):
         if not 1 <= len(jobs) <= BATCH_MAX_JOBS:
             raise ValueError(f"a batch holds 1..{BATCH_MAX_JOBS} jobs")
         self.dtype = dtype
@@ -465,17 +470,36 @@ class Batch:
         nbytes = int(_lib.ib_batch_workspace_bytes(arr, len(jobs), self.code))
         if nbytes == 0:
             _check(-4, "ib_batch_workspace_bytes")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.workspace_bytes = nbytes
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device) if workspace else None
         nst = int(_lib.ib_batch_staging_bytes(len(jobs)))
         self.staging = torch.empty(nst, dtype=torch.uint8, pin_memory=True)
 
     def run(self, stream=None):
+        if self.workspace is None:
+            raise ValueError("this batch has no workspace: use run_static")
         _check(_lib.ib_batch_run(self._arr, len(self.jobs), self.code, _ptr(self.workspace),
                                  self.workspace.numel(), ctypes.c_void_p(self.staging.data_ptr()),
                                  _stream(stream)), "ib_batch_run")
         return self
 
+    def run_static(self, flags=None, stream=None):
+        """Run without a workspace of its own (ib_batch_run_static); flags: None or a device
+        int32/uint32 tensor of one word per job, receiving the jobs' device error flags."""
+        on_dev = flags is not None and flags.device.type == "cuda" and (
+            self.device.index is None or flags.device.index == self.device.index)
+        if flags is not None and (not on_dev or flags.numel() < len(self.jobs)
+                                  or flags.element_size() != 4 or not flags.is_contiguous()):
+            raise ValueError(f"flags must be a contiguous device tensor of {len(self.jobs)} 32-bit words")
+        _check(_lib.ib_batch_run_static(self._arr, len(self.jobs), self.code,
+                                        ctypes.c_void_p(self.staging.data_ptr()),
+                                        None if flags is None else _ptr(flags), _stream(stream)),
+               "ib_batch_run_static")
+        return self
+
     def status(self, stream=None):
+        if self.workspace is None:
+            raise ValueError("this batch has no workspace: read the flags of run_static")
         out = (_i32 * len(self.jobs))()
         r = _lib.ib_batch_status(self._arr, len(self.jobs), self.code, _ptr(self.workspace), out,
                                  _stream(stream))

@@ -154,3 +154,21 @@ def test_binding_rejects_bad_buffers_before_any_launch(ib):
                 {"X": torch.empty(10, 2, dtype=torch.float64), "U": ok_pts}):
         with pytest.raises(ValueError):
             ib._point_arrays(g, **bad)
+
+
+def test_static_batch_refuses_oversize_before_device_work(ib):
+    """ib_batch_run_static checks the batch's workspace against IB_STATIC_SCRATCH_BYTES on the
+    host and returns IB_ERR_OOM before touching a device (no GPU needed); the size limit in
+    the header and the binding agree."""
+    import re
+    from paper_2012_06646_amd import workloads as wl
+    hdr = open(os.path.join(ROOT, "include", "ib.h")).read()
+    m = re.search(r"#define IB_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == ib.STATIC_SCRATCH_BYTES
+    arr = (ib.JobDesc * 1)()
+    arr[0].grid = ib.make_desc(wl.grid(3, 128, 1.0))
+    arr[0].npts = 3_000_000
+    arr[0].X = arr[0].F = arr[0].f = arr[0].u = arr[0].U = 4096  # never dereferenced
+    assert ib._lib.ib_batch_workspace_bytes(arr, 1, 0) > ib.STATIC_SCRATCH_BYTES
+    assert ib._lib.ib_batch_run_static(arr, 1, 0, None, None, None) == -2
+    assert ib._lib.ib_batch_run_static(arr, 0, 0, None, None, None) == -1  # no jobs

@@ -82,23 +82,6 @@ def device_facts(torch):
     return facts
 
 
-def cpu_baseline(g, X, F, u, sample):
-    """The CPU oracle as it stands (single thread) on the first `sample` points of the same
-    workload: keys + stable sort for each staggering, spreading, interpolation."""
-    from oracle import oracle as orc
-    Xs, Fs = np.asarray(X[:sample], np.float64), np.asarray(F[:sample], np.float64)
-    t0 = time.perf_counter()
-    for c in range(len(g["stagger"])):
-        k, _ = orc.keys(g, Xs, g["stagger"][c])
-        orc.plan(k)
-    orc.spread(g, Xs, Fs)
-    orc.interp(g, Xs, np.asarray(u, np.float64))
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} points of the same workload (one step: keys+sort per "
-                      f"staggering, spread, interpolate), single thread, {dt:.1f} s"}
-
-
 def cpu_baseline_threads(g, X, F, u, sample, threads):
     """The same oracle calls on the host's cores: the points split into `threads` contiguous
     chunks, one thread each (the oracle's C functions release the GIL).  Keys and
@@ -393,65 +376,81 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--npts", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tune", choices=["auto", "none"], default="auto",
-                    help="pick the plan tuning (spreading tile, tile sharing, radix digits) with "
-                         "the autotuner on the initial positions, or use the built-in choices")
-    ap.add_argument("--no-rbc", action="store_true",
-                    help="skip the red-blood-cell workload (256^3, 2.8 million clustered points)")
-    ap.add_argument("--no-serving", action="store_true",
-                    help="skip the batched-serving measurement (Poisson job stream)")
-    ap.add_argument("--no-unstructured", action="store_true",
-                    help="skip the paper's unstructured-point test (Sec. 4.1 grid and weak series)")
-    ap.add_argument("--no-walls", action="store_true",
-                    help="skip the walled-grid measurement (128^3 with walls along z)")
-    ap.add_argument("--no-kernels", action="store_true",
-                    help="skip the per-kernel measurements (4-point, cosine, 3-point; 128^3, periodic)")
-    ap.add_argument("--serving-only", action="store_true")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time the step captured once in a HIP graph and replayed")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 512 MiB device-to-device copy 5 times (the reference "
-                         "kernel for scaling HBM byte counters)")
-    args = ap.parse_args()
+def progress(msg):
+    """One line on stderr per finished part (the JSON line alone goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
-    if args.calibrate_copy:
-        import torch
-        nbytes = 512 << 20
-        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
-        a.fill_(1.0)
-        c = torch.empty_like(a)
-        for _ in range(5):
-            c.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
-        return
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); multi-GPU sharding is a design note, not implemented.",
-              file=sys.stderr)
-        sys.exit(2)
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Achieved HBM bandwidth of a plain device-to-device copy of nbytes (torch's copy
+    kernel): bytes read + written over the mean event time of reps copies.  The practical
+    ceiling beside the nominal 8 TB/s."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, c
+    return {"GB_per_s": round(2 * nbytes / sec / 1e9, 1), "bytes_per_copy": 2 * nbytes,
+            "kernel": "torch copy_ of a 1 GiB uint8 buffer", "reps": reps}
 
-    import torch
-    from paper_2012_06646_amd import ibops, workloads as wl
 
-    if args.serving_only:
-        torch.cuda.set_device(0)
-        print(json.dumps({"serving": serving_bench(torch, ibops, wl)}), flush=True)
-        return
+def host_facts():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
 
-    dtype = torch.float64 if args.dtype == "f64" else torch.float32
-    b = 8 if args.dtype == "f64" else 4
+
+def c1_bench(torch, ibops, wl, K):
+    """The small 2-D case: 32 x 32 collocated grid, two components, 1000 points, FP64.  A
+    step is plan update + spread + interpolate; launch-bound at this size."""
+    dev = torch.device("cuda:0")
+    g, X, F, u = wl.square32_1k()
+    Xd, Fd, ud = (torch.from_numpy(a).to(dev) for a in (X, F, u))
+    n = X.shape[0]
+    p = ibops.Plan(g, n, torch.float64, dev)
+    f = torch.empty(p.grid_shape, dtype=torch.float64, device=dev)
+    U = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    for _ in range(5):
+        p.update(Xd)
+        p.spread(Fd, f)
+        p.interpolate(ud, U)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(K):
+        p.update(Xd)
+        p.spread(Fd, f)
+        p.interpolate(ud, U)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    return {"workload": "2-D periodic unit square, 32^2 collocated grid, 2 components, 1000 "
+                        "uniform points, FP64; step = plan update + spread + interpolate",
+            "ms_per_step": round(ms, 5), "points_per_s": round(n / (ms / 1e3), 1)}
+
+
+def c2_leg(torch, ibops, wl, dt_name, args, snap_steps):
+    """The 128^3 / 10^6 step in one precision: K timed steps (per-stage events), the same
+    steps with cold caches, optionally replayed from a HIP graph, and (snap_steps) an
+    untimed pass that copies X_k and U_k = J(X_k) u to the host at the given steps."""
+    dtype = torch.float64 if dt_name == "f64" else torch.float32
+    b = 8 if dt_name == "f64" else 4
     g, X0, F, u = wl.cube128_1m(np.float64, args.npts)
     npts, dim, ncomp = X0.shape[0], 3, 3
     G = 128 ** 3
@@ -522,10 +521,8 @@ def main():
         print("bench.py: device flagged a data error", file=sys.stderr)
         sys.exit(1)
     ms_step = ev[0][0].elapsed_time(ev[K - 1][3]) / K
-    value = npts / (ms_step / 1e3)
     stage_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(K)]))
                 for i, name in enumerate(["plan", "spread", "interp_advect"])}
-
     per_step = np.array([ev[k][0].elapsed_time(ev[k][3]) for k in range(K)])
     step_pct = {f"p{q}": round(float(np.percentile(per_step, q)), 5) for q in (10, 50, 90)}
 
@@ -566,27 +563,147 @@ def main():
         torch.cuda.synchronize()
         graph_ms = g0.elapsed_time(g1) / K
 
+    snap = None
+    if snap_steps:
+        restart()
+        snap = {}
+        for k in range(K):
+            Xk = X.cpu().numpy() if k in snap_steps else None
+            step()
+            if Xk is not None:
+                snap[k] = (Xk, U.cpu().numpy())
+        torch.cuda.synchronize()
+
     algo = algorithmic_bytes(npts, dim, ncomp, G, b)
     dom = "spread" if stage_ms["spread"] >= stage_ms["interp_advect"] else "interp_advect"
     dom_bytes = algo["spread"] if dom == "spread" else algo["interp"] + 2 * dim * b * npts
     achieved = dom_bytes / (stage_ms[dom] / 1e3) / 1e9
-    traffic = measured_traffic("spread" if dom == "spread" else "interp", args.dtype)
+    traffic = measured_traffic("spread" if dom == "spread" else "interp", dt_name)
     roofline = {"bound": "hbm", "kernel": OP_KERNELS[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "algorithmic_bytes_per_launch": dom_bytes}
+    leg = {"dtype": dt_name, "value": npts / (ms_step / 1e3), "ms_per_step": ms_step,
+           "ms_per_step_graph": graph_ms, "step_ms_percentiles": step_pct,
+           "cold_cache_ms_per_step": round(cold_ms, 5),
+           "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()}, "tuning": tune_info,
+           "step_algorithmic_bytes": sum(algo.values()),
+           "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "host_wall_s": round(t_host, 4), "roofline": roofline}
+    del plan, X, Fd, ud, f, U, X0d
+    torch.cuda.empty_cache()
+    return leg, snap
+
+
+def oracle_at_steps(g, F, u, snap, sample, nrows=2000):
+    """The oracle at the positions the GPU produced at steps k (snap: k -> (X_k, U_k) on the
+    host): single-thread timing of one step (keys + sort per staggering, spread, interpolate)
+    on the first `sample` points of X_k, and the GPU's U_k against the oracle's at nrows
+    sampled points (normwise)."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(5)
+    total_pts, total_s, per = 0, 0.0, {}
+    for k, (Xk, Uk) in sorted(snap.items()):
+        Xh = Xk.astype(np.float64)
+        m = min(sample, Xh.shape[0])
+        Xs, Fs = Xh[:m], np.asarray(F[:m], np.float64)
+        t0 = time.perf_counter()
+        for c in range(len(g["stagger"])):
+            kk, _ = orc.keys(g, Xs, g["stagger"][c])
+            orc.plan(kk)
+        orc.spread(g, Xs, Fs)
+        orc.interp(g, Xs, np.asarray(u, np.float64))
+        dt = time.perf_counter() - t0
+        total_pts += m
+        total_s += dt
+        rows = rng.choice(Xh.shape[0], min(nrows, Xh.shape[0]), replace=False)
+        ref = orc.interp(g, Xh[rows], np.asarray(u, np.float64).astype(Uk.dtype).astype(np.float64))
+        err = float(np.abs(Uk[rows] - ref).max() / np.abs(ref).max())
+        per[str(k)] = {"oracle_s": round(dt, 3), "points": m, "interp_normwise_err": err}
+    return {"steps": per,
+            "cpu_baseline": {"value": total_pts / total_s, "unit": "points/s", "cores": 1,
+                             "kind": "oracle",
+                             "sample": f"first {sample} points of X_k for steps {sorted(snap)} as "
+                                       f"the GPU advanced them (one step each: keys + sort per "
+                                       f"staggering, spread, interpolate), single thread, "
+                                       f"{total_s:.1f} s"}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--npts", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="points per sampled step for the single-thread oracle timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", choices=["auto", "none"], default="auto",
+                    help="pick the plan tuning (spreading tile, tile sharing, radix digits) with "
+                         "the autotuner on the initial positions, or use the built-in choices")
+    ap.add_argument("--no-rbc", action="store_true",
+                    help="skip the red-blood-cell workload (256^3, 2.8 million clustered points)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the batched-serving measurement (Poisson job stream)")
+    ap.add_argument("--no-unstructured", action="store_true",
+                    help="skip the paper's unstructured-point test (Sec. 4.1 grid and weak series)")
+    ap.add_argument("--no-walls", action="store_true",
+                    help="skip the walled-grid measurement (128^3 with walls along z)")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the per-kernel measurements (4-point, cosine, 3-point; 128^3, periodic)")
+    ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the step captured once in a HIP graph and replayed")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy 5 times (the reference "
+                         "kernel for scaling HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        nbytes = 512 << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+        a.fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(5):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}))
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); multi-GPU sharding is a design note, not implemented.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_06646_amd import ibops, workloads as wl
+
+    if args.serving_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving_bench(torch, ibops, wl)}), flush=True)
+        return
+
+    dt_other = "f32" if args.dtype == "f64" else "f64"
+    snaps = sorted({0, 1, args.steps - 1})
+    leg, snap = c2_leg(torch, ibops, wl, args.dtype, args, snaps)
+    progress(f"128^3 step {args.dtype}: {leg['ms_per_step']:.4f} ms")
+    other, _ = c2_leg(torch, ibops, wl, dt_other, args, None)
+    progress(f"128^3 step {dt_other}: {other['ms_per_step']:.4f} ms")
+    g, X0, F, u = wl.cube128_1m(np.float64, args.npts)
+    npts = X0.shape[0]
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": leg["value"],
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "ms_per_step_graph": graph_ms,
-        "step_ms_percentiles": step_pct,
-        "cold_cache_ms_per_step": round(cold_ms, 5),
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -596,37 +713,42 @@ def main():
                                "N(0,1) forces and grid velocities, Peskin 4-point; step = plan + "
                                "spread + interpolate with the advection X += 0.1 h U fused in",
                    "grid": [128, 128, 128], "npts": npts, "seed": 1002},
-        "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
-        "tuning": tune_info,
-        "device": device_facts(torch),
-        "step_algorithmic_bytes": sum(algo.values()),
-        "step_hbm_frac": round(sum(algo.values()) / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        "host_wall_s": round(t_host, 4),
-        "roofline": roofline,
+        "roofline": leg["roofline"],
         "cpu_baseline": None,
-        "cpu_baseline_threads": None,
-        "rbc_256": None,
-        "paper_unstructured": None,
-        "walls_128": None,
-        "kernels_128": None,
-        "serving": None,
     }
+    out.update({k: v for k, v in leg.items() if k not in ("value", "ms_per_step", "roofline")})
+    out["c2_" + dt_other] = other
+    out["copy_bandwidth"] = copy_bandwidth(torch)
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / out["copy_bandwidth"]["GB_per_s"], 4)
+    out["device"] = device_facts(torch)
+    out["host"] = host_facts()
+    out["c1_2d_32"] = c1_bench(torch, ibops, wl, args.steps)
+    progress("copy bandwidth and 2-D 32^2 case done")
+    out.update({"cpu_baseline_threads": None, "oracle_at_gpu_steps": None, "rbc_256": None,
+                "paper_unstructured": None, "walls_128": None, "kernels_128": None, "serving": None})
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
     if not args.no_rbc:
         out["rbc_256"] = rbc_bench(torch, ibops, wl, args.steps)
+        progress("rbc 256^3 done")
     if not args.no_unstructured:
         out["paper_unstructured"] = unstructured_bench(torch, ibops, wl, args.steps)
+        progress("unstructured test done")
     if not args.no_walls:
         out["walls_128"] = variant_bench(torch, ibops, wl, args.steps, dtype, walls=4)
+        progress("walls done")
     if not args.no_kernels:
         out["kernels_128"] = {k: variant_bench(torch, ibops, wl, args.steps, dtype, kernel=k)
                               for k in ("peskin4", "cosine4", "roma3")}
     if not args.no_serving:
         out["serving"] = serving_bench(torch, ibops, wl)
+        progress("serving done")
     if not args.no_cpu_baseline:
-        Xh = X0.astype(np.float32 if b == 4 else np.float64).astype(np.float64)
-        out["cpu_baseline"] = cpu_baseline(g, Xh, F, u, min(args.cpu_sample, npts))
+        out["oracle_at_gpu_steps"] = oracle_at_steps(g, F, u, snap, args.cpu_sample)
+        out["cpu_baseline"] = out["oracle_at_gpu_steps"].pop("cpu_baseline")
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        Xh = snap[0][0].astype(np.float64)
         out["cpu_baseline_threads"] = cpu_baseline_threads(g, Xh, F, u, npts, threads)
+        progress("oracle timings done")
     print(json.dumps(out), flush=True)
 
 

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2012_06646_amd import workloads as wl
-from tests.gpu_util import TOL, normwise, say, to_dev, to_host
+from tests.gpu_util import TOL, normwise, oracle_errors, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -69,15 +69,21 @@ def test_batch_matches_one_by_one_bitwise(ib, dtype):
             assert torch.equal(U, U1), f"job {j}: interpolation differs"
 
 
-def test_batch_against_oracle(ib, orc):
-    dtype = torch.float64
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_against_oracle(ib, orc, dtype):
+    """Small jobs, a dense job whose spreading tiles are split over several blocks, and a
+    job dense enough to interpolate through LDS tiles, against the oracle."""
     specs = [(wl.grid(3, 24, 1.0), 3000, True, True), (wl.grid(3, [16, 20, 12], 1.0), 2500, True, True),
-             (wl.grid(3, 32, 2.0), 6000, True, True)]
+             (wl.grid(3, 32, 2.0), 6000, True, True),
+             (wl.grid(3, 32, 1.0), 150000, True, True),    # split spreading tiles
+             (wl.grid(3, 96, 1.0), 150000, True, True)]    # LDS-tiled interpolation
     jobs, host = make_jobs(specs, dtype, 4200)
+    say(f"batch against the oracle, dtype={dtype}")
     b = ib.Batch(jobs, dtype).run()
-    for (g, n, _, _), (f, U), (X, F, u) in zip(specs, b.results(), host):
-        ef = normwise(to_host(f), orc.spread(g, X, F))
-        eU = normwise(to_host(U), orc.interp(g, X, u))
+    nd = np.float32 if dtype == torch.float32 else np.float64
+    for i, ((g, n, _, _), (f, U), (X, F, u)) in enumerate(zip(specs, b.results(), host)):
+        X, F, u = (a.astype(nd) for a in (X, F, u))
+        ef, eU = oracle_errors(orc, g, X, F, u, f, U, 4250 + i)
         say(f"   grid {g['n']} n={n}: spread err {ef:.2e} interp err {eU:.2e}")
         assert ef <= TOL[dtype] and eU <= TOL[dtype]
 

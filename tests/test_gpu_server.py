@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2012_06646_amd import workloads as wl
-from tests.gpu_util import say, to_dev
+from tests.gpu_util import TOL, oracle_errors, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -153,3 +153,31 @@ def test_server_sees_inputs_written_just_before_submit(ib):
         ref = {"grid": j["grid"], "X": X0, "F": F0, "u": u0}
         f1, U1 = alone(ib, ref, dtype)
         assert torch.equal(j["f"], f1) and torch.equal(j["U"], U1)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_served_mix_against_oracle(ib, orc, graph):
+    """A serving mix in FP32 (grids 32^3..128^3, 10^3..2*10^5 points, log-uniform) run by
+    the server, every job against the oracle (the larger ones on sampled grid values and
+    points)."""
+    dtype = torch.float32
+    r = wl.rng(6600)
+    jobs, host = [], []
+    for i in range(10):
+        N = int(r.choice([32, 64, 96, 128]))
+        n = int(round(np.exp(r.uniform(np.log(1e3), np.log(2e5)))))
+        g = wl.grid(3, N, 1.0)
+        X, F, u = (a.astype(np.float32) for a in wl.uniform_case(g, n, 6600 + 1 + i))
+        host.append((g, X, F, u))
+        jobs.append({"grid": g, "X": to_dev(X, dtype), "F": to_dev(F, dtype), "u": to_dev(u, dtype),
+                     "f": torch.empty(wl.grid_shape(g), dtype=dtype, device="cuda"),
+                     "U": torch.empty((n, 3), dtype=dtype, device="cuda")})
+    say(f"served FP32 mix against the oracle, graph={graph}: {[j['X'].shape[0] for j in jobs]}")
+    srv = ib.Server(dtype, arena_bytes=1 << 30, max_jobs_per_batch=4, use_graph=graph)
+    out = run_all(srv, jobs)
+    srv.close()
+    assert all(st == 0 for st, _ in out)
+    for i, (job, (g, X, F, u)) in enumerate(zip(jobs, host)):
+        ef, eU = oracle_errors(orc, g, X, F, u, job["f"], job["U"], 6700 + i)
+        say(f"   job {i} grid {g['n'][0]} n={X.shape[0]}: spread {ef:.2e} interp {eU:.2e}")
+        assert ef <= TOL[dtype] and eU <= TOL[dtype], i

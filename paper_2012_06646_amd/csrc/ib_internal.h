@@ -51,6 +51,7 @@ struct PlanDev {
     long long* partial;    // [tiles][split][tile cells] partial fixed-point tile sums (split > 1 only)
     int32_t* tile_shift;   // [tiles] fixed-point scale exponent of each split tile
     unsigned long long* fmax;  // [3][FMAX_PARTS] partial maxima of |F| per component
+    uint32_t* cellmax;     // most points in any staggering-0 cell (bucket pass; zero region)
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
@@ -112,6 +113,7 @@ struct OpArgs {
     long long* partial;          // split spreading: partial fixed-point tile sums
     int32_t* tile_shift;         //   and each split tile's scale exponent
     const unsigned long long* fmax;  // partial maxima of |F| per component (fmax_kernel)
+    const uint32_t* cellmax;     // most points in any staggering-0 cell
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     double out_scale;            // interpolation and its gradient: results times this (1: none)
     void* Xadv;                  // interpolation: also advance these positions (or null)

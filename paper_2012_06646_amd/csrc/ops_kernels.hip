@@ -124,8 +124,9 @@ __device__ __forceinline__ void wave_sync()
 // of a contribution is the only error beyond those of the weights.
 //
 // The scale.  With vmax = max_j |F_{j,c}| < 2^e (all points) and M an upper bound on the
-// contributions any one grid value of the tile receives (from the cell-block counts of its
-// source frame, see spread_body), S = min(51 - e, 62 - ceil(log2 M) - e).  Then every
+// contributions any one grid value receives (the points of the staggering-0 cells that can
+// reach it, at most the largest cell count of the plan times the cells of that window, see
+// spread_body), S = min(51 - e, 62 - ceil(log2 M) - e).  Then every
 // contribution, scaled by 2^S, has magnitude below 2^51 (so one fused multiply-add with
 // 1.5 * 2^52 rounds it to an integer held in the low bits of its result), and no partial
 // sum reaches 2^62.  The rounding error of one contribution is at most
@@ -155,33 +156,53 @@ __device__ __forceinline__ int fx_shift(unsigned long long vmax_bits, uint32_t n
 
 // Largest |F_{j,c}| per component, as non-negative bit patterns (a NaN or infinity compares
 // above every finite value): FMAX_PARTS blocks each write the maxima of their share of the
-// rows (read in input order, coalesced), and a spreading block takes the maximum of those
-// partial maxima.
+// rows, and a spreading block takes the maximum of those partial maxima.  The rows are read
+// in input order as one flat array of n * NC elements (coalesced); element le of a pass
+// belongs to component le mod NC.
 constexpr int SPREAD_THREADS = 512;
+constexpr int FMAX_THREADS = 256;
+constexpr int FMAX_BATCH = 4;  // rows per thread per pass
+
+template <typename T, int NC>
+__device__ __forceinline__ void fmax_rows(const T* __restrict__ F, int64_t n, int bid,
+                                          unsigned long long m[3])
+{
+    constexpr int E = NC * FMAX_BATCH;
+    constexpr int64_t ROWS = (int64_t)FMAX_THREADS * FMAX_BATCH;
+    const int tid = threadIdx.x;
+    for (int64_t base = (int64_t)bid * ROWS; base < n; base += (int64_t)FMAX_PARTS * ROWS) {
+        const int64_t lim = (n - base) * NC;  // elements left from the pass's first one
+        const T* __restrict__ src = F + base * NC;
+        T v[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) v[k] = src[min((int64_t)(k * FMAX_THREADS + tid), lim - 1)];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int le = k * FMAX_THREADS + tid;
+            const int c = le % NC;
+            const unsigned long long b =
+                le < lim ? (unsigned long long)__double_as_longlong(fabs((double)v[k])) : 0ull;  // exact for FP32
+            m[0] = (c == 0 && b > m[0]) ? b : m[0];
+            m[1] = (c == 1 && b > m[1]) ? b : m[1];
+            m[2] = (c == 2 && b > m[2]) ? b : m[2];
+        }
+    }
+}
 
 template <typename T>
-__device__ __forceinline__ void fmax_body(const T* __restrict__ F, int64_t n, int ncomp,
-                                          unsigned long long* __restrict__ out, int bid)
+__device__ __forceinline__ void fmax_body(const OpArgs& a, int bid)
 {
-    __shared__ unsigned long long s_m[3][256 / 64];
+    __shared__ unsigned long long s_m[3][FMAX_THREADS / 64];
     unsigned long long m[3] = {0ull, 0ull, 0ull};
-    const int64_t total = n * ncomp;
-    // element e of F belongs to component e mod ncomp; each thread keeps its elements'
-    // components apart with a rotating index (ncomp <= 3)
-    for (int64_t e = (int64_t)bid * blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)FMAX_PARTS * blockDim.x) {
-        const int c = (int)(e % ncomp);
-        const double v = fabs((double)F[e]);  // exact for FP32
-        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-        m[0] = (c == 0 && b > m[0]) ? b : m[0];
-        m[1] = (c == 1 && b > m[1]) ? b : m[1];
-        m[2] = (c == 2 && b > m[2]) ? b : m[2];
-    }
+    const T* F = (const T*)a.F;
+    if (a.g.ncomp == 3) fmax_rows<T, 3>(F, a.g.npts, bid, m);
+    else if (a.g.ncomp == 2) fmax_rows<T, 2>(F, a.g.npts, bid, m);
+    else fmax_rows<T, 1>(F, a.g.npts, bid, m);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
-        for (int s = 32; s >= 1; s >>= 1) {
-            const unsigned long long o = __shfl_xor(m[c], s, 64);
+        for (int sh = 32; sh >= 1; sh >>= 1) {
+            const unsigned long long o = __shfl_xor(m[c], sh, 64);
             m[c] = o > m[c] ? o : m[c];
         }
         if (lane_id() == 0) s_m[c][wave_id()] = m[c];
@@ -189,16 +210,15 @@ __device__ __forceinline__ void fmax_body(const T* __restrict__ F, int64_t n, in
     __syncthreads();
     if (threadIdx.x < 3) {
         unsigned long long r = 0ull;
-        for (int w = 0; w < (int)(blockDim.x / 64); ++w) r = s_m[threadIdx.x][w] > r ? s_m[threadIdx.x][w] : r;
-        out[threadIdx.x * FMAX_PARTS + bid] = r;
+        for (int w = 0; w < FMAX_THREADS / 64; ++w) r = s_m[threadIdx.x][w] > r ? s_m[threadIdx.x][w] : r;
+        ((unsigned long long*)a.fmax)[threadIdx.x * FMAX_PARTS + bid] = r;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void fmax_kernel(const T* __restrict__ F, int64_t n, int ncomp,
-                                                   unsigned long long* __restrict__ out)
+__global__ __launch_bounds__(FMAX_THREADS) void fmax_kernel(OpArgs a)
 {
-    fmax_body<T>(F, n, ncomp, out, blockIdx.x);
+    fmax_body<T>(a, blockIdx.x);
 }
 
 // Maximum of the FMAX_PARTS partial maxima of component c, uniform over the block.
@@ -306,37 +326,6 @@ struct SpreadTile {
         *rn = lane < nranges && tb.hi[lane] > tb.lo[lane];
         wave_sync();
         return total_pts;
-    }
-
-    // Visits of source slice q without building its table (the sum over its row pieces),
-    // and the most points of any 4-cell block (cells 4b .. 4b + 3 of a row) those pieces
-    // touch.  Called by the whole wave; both results are uniform.
-    __device__ static void count(const GeomArgs& g, const int32_t* __restrict__ cs, int q, int ox,
-                                 int oy, int oz, int lenx, int nrows, int* total, int* maxblk)
-    {
-        const int lane = lane_id();
-        const int n0 = g.n[0];
-        int cnt = 0, mb = 0;
-        if (lane < nrows) {
-            int r;
-            if (DIM == 3) r = wrap_small(oz + q, g.n[2]) * g.n[1] + wrap_small(oy + lane, g.n[1]);
-            else r = wrap_small(oy + q, g.n[1]);
-            const int32_t rowbase = r * n0;
-            int done = 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                if (done < lenx) {
-                    const int xa = wrap_small(ox + done, n0);
-                    const int len = min(lenx - done, n0 - xa);
-                    cnt += cs[rowbase + xa + len] - cs[rowbase + xa];
-                    for (int x = xa & ~3; x < xa + len; x += 4)
-                        mb = max(mb, cs[rowbase + min(x + 4, n0)] - cs[rowbase + x]);
-                    done += len;
-                }
-            }
-        }
-        *total = (int)wave_last_u32(wave_incl_scan_u32((uint32_t)cnt));
-        *maxblk = wave_max_i32(mb);
     }
 
     // Range of slice position v0 + lane, for v0 < total.  The range holding v0 is the last
@@ -495,8 +484,6 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     __shared__ typename ST::Table tables[NW];
     __shared__ int32_t marks[NW][64];
     __shared__ unsigned long long s_red[NW];
-    __shared__ int s_cnt[NW];
-    __shared__ int s_mb[NW];
     const GeomArgs& g = a.g;
     // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
     // chunk of its points and publish their partial integer sums.  Tiles are numbered with
@@ -524,31 +511,13 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
     const int nranges = 3 * nrows;
     const int w = wave_id();
 
-    // The most contributions any grid value of the tile can receive (every split block of
-    // the tile finds the same), and the maximum force of component c: the scale of the
-    // tile.  A grid value's stencil window holds (4 + hy)(4 + hz) source rows (3-D) of at
-    // most 5 consecutive cells each (counted around the periodic wrap), which lie in at
-    // most three 4-cell blocks, so it receives at most 3 (4 + hy)(4 + hz) maxblock
-    // contributions, and never more than the tile's visit count n_t.
-    int cnt = 0, mb = 0;
-    for (int q = w; q < nslices; q += NW) {
-        int t, m;
-        ST::count(g, a.cstart, q, ox, oy, oz, lenx, nrows, &t, &m);
-        cnt += t;
-        mb = max(mb, m);
-    }
-    if (lane_id() == 0) {
-        s_cnt[w] = cnt;
-        s_mb[w] = mb;
-    }
+    // The most contributions any grid value can receive: its stencil window holds
+    // (4 + hx)(4 + hy)(4 + hz) staggering-0 cells (3-D), each with at most cellmax points.
+    // With the maximum force of component c it sets the tile's scale (every split block of
+    // the tile finds the same).
     const unsigned long long vmax = fmax_of<SPREAD_THREADS>(a.fmax, c, s_red);  // has barriers
-    uint32_t nt = 0, mbt = 0;
-    for (int i = 0; i < NW; ++i) {
-        nt += (uint32_t)s_cnt[i];
-        mbt = max(mbt, (uint32_t)s_mb[i]);
-    }
-    const uint32_t rows_win = (DIM == 3) ? (uint32_t)((4 + hy) * (4 + hz)) : (uint32_t)(4 + hy);
-    const uint32_t mbound = (uint32_t)min((uint64_t)nt, (uint64_t)3u * rows_win * mbt);
+    const uint64_t win = (uint64_t)(4 + hx) * (4 + hy) * ((DIM == 3) ? 4 + hz : 1);
+    const uint32_t mbound = (uint32_t)min(win * (uint64_t)*a.cellmax, (uint64_t)0xFFFFFFFFu);
     const bool finite = vmax < FX_NONFINITE;
     const int fshift = (vmax == 0ull || !finite) ? 0 : fx_shift(vmax, mbound);
 
@@ -1273,8 +1242,7 @@ template <typename T, int KERN>
 hipError_t spread_dispatch(OpArgs a, hipStream_t st)
 {
     // the force maxima that set each tile's fixed-point scale
-    hipLaunchKernelGGL(fmax_kernel<T>, dim3(FMAX_PARTS), dim3(256), 0, st, (const T*)a.F, a.g.npts,
-                       a.g.ncomp, (unsigned long long*)a.fmax);
+    hipLaunchKernelGGL(fmax_kernel<T>, dim3(FMAX_PARTS), dim3(FMAX_THREADS), 0, st, a);
     spread_tiles(a.g.dim, a.g.sp_tile, a.g.n, a.tiles, &a.tile_slow);
     const unsigned nb = (unsigned)(a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split);
     if (a.g.dim == 3) {
@@ -1329,15 +1297,14 @@ __device__ __forceinline__ int batch_job_of(const int32_t* starts, int njobs, in
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void batch_fmax_kernel(const BatchJob* __restrict__ jobs,
-                                                         const BatchTable* __restrict__ bt)
+__global__ __launch_bounds__(FMAX_THREADS) void batch_fmax_kernel(const BatchJob* __restrict__ jobs,
+                                                                const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_FMAX];
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job_of(st, nj, vb);
-        const OpArgs& a = jobs[j].op;
-        fmax_body<T>((const T*)a.F, a.g.npts, a.g.ncomp, (unsigned long long*)a.fmax, vb - st[j]);
+        fmax_body<T>(jobs[j].op, vb - st[j]);
         __syncthreads();
     }
 }
@@ -1401,7 +1368,8 @@ void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
     constexpr int TX = DIM == 3 ? SP_SHAPE[S][0] : SP2_TX, TY = DIM == 3 ? SP_SHAPE[S][1] : SP2_TY;
     constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
     if (b.grid[BS_FMAX] > 0)
-        hipLaunchKernelGGL((batch_fmax_kernel<T>), dim3(b.grid[BS_FMAX]), dim3(256), 0, st, b.jobs, b.table);
+        hipLaunchKernelGGL((batch_fmax_kernel<T>), dim3(b.grid[BS_FMAX]), dim3(FMAX_THREADS), 0, st,
+                           b.jobs, b.table);
     if (b.grid[BS_SPREAD] > 0)
         hipLaunchKernelGGL((batch_spread_kernel<T, DIM, KERN, TX, TY, TZ>), dim3(b.grid[BS_SPREAD]),
                            dim3(SPREAD_THREADS), 0, st, b.jobs, b.table);

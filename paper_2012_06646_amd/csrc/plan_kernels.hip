@@ -326,11 +326,19 @@ constexpr int BKT_THREADS = 1024;
 
 // Common case: at most BKT_CELLS cells and BKT_CAP points, all in LDS, four points per
 // thread held in registers throughout.
+// The largest of the threads' cell counts into *s_cmax (LDS, cleared before the block's
+// first barrier): one LDS atomic per wave.
+__device__ __forceinline__ void note_cell_max(uint32_t v, uint32_t* s_cmax)
+{
+    const int m = wave_max_i32((int)v);  // counts are below 2^30
+    if (lane_id() == 0 && m > 0) atomicMax(s_cmax, (uint32_t)m);
+}
+
 template <typename T>
 __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t start, int m, int64_t c0,
                                             int nc, bool last, const T* __restrict__ Xb, T* __restrict__ Xs,
                                             int32_t* __restrict__ cstart, uint32_t* hist, int32_t* sidx,
-                                            uint16_t* skey, uint32_t* s_red)
+                                            uint16_t* skey, uint32_t* s_red, uint32_t* s_cmax)
 {
     constexpr int EPT = BKT_CAP / BKT_THREADS;
     constexpr int CPT = BKT_CELLS / BKT_THREADS;
@@ -341,6 +349,7 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
     const int32_t* __restrict__ ka = a.d.kA + (int64_t)s * n + start;
     const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
     for (int i = tid; i <= nc; i += BKT_THREADS) hist[i] = 0u;
+    if (tid == 0) *s_cmax = 0u;
     int32_t key[EPT], idx[EPT];
     int cell[EPT];
     uint32_t slot[EPT];
@@ -364,13 +373,15 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
     for (int k = 0; k < EPT; ++k)
         if (cell[k] >= 0) slot[k] = atomicAdd(&hist[cell[k]], 1u);
     __syncthreads();
-    uint32_t loc[CPT], sum = 0;
+    uint32_t loc[CPT], sum = 0, lmax = 0;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
         const int i = tid * CPT + q;
         loc[q] = i < nc ? hist[i] : 0u;
         sum += loc[q];
+        lmax = max(lmax, loc[q]);
     }
+    if (cstart != nullptr) note_cell_max(lmax, s_cmax);
     uint32_t tot;
     uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
 #pragma unroll
@@ -387,6 +398,7 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
         if (cstart != nullptr && last) cstart[c0 + nc] = (int32_t)n;
     }
     __syncthreads();
+    if (cstart != nullptr && tid == 0) atomicMax(a.d.cellmax, *s_cmax);
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
         if (cell[k] >= 0) {
@@ -435,7 +447,7 @@ template <typename T>
 __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t start, int64_t m,
                                                int64_t cbeg, int64_t cend, bool last, const T* __restrict__ Xb,
                                                T* __restrict__ Xs, int32_t* __restrict__ cstart,
-                                               uint32_t* hist, uint32_t* s_red)
+                                               uint32_t* hist, uint32_t* s_red, uint32_t* s_cmax)
 {
     constexpr int CPT = BKT_CELLS / BKT_THREADS;
     const GeomArgs& g = a.g;
@@ -445,6 +457,8 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
     const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
     int32_t* sorg = a.d.kB + (int64_t)s * n + start;  // bucket position of each sorted slot
     int64_t sub_base = 0;
+    uint32_t lmax = 0;
+    if (threadIdx.x == 0) *s_cmax = 0u;
     for (int64_t c0 = cbeg; c0 < cend; c0 += BKT_CELLS) {
         const int nc = (int)min((int64_t)BKT_CELLS, cend - c0);
         for (int i = threadIdx.x; i < nc; i += BKT_THREADS) hist[i] = 0u;
@@ -461,6 +475,7 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
             const int i = threadIdx.x * CPT + k;
             loc[k] = i < nc ? hist[i] : 0u;
             sum += loc[k];
+            lmax = max(lmax, loc[k]);
         }
         uint32_t tot;
         uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
@@ -501,6 +516,11 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
         __syncthreads();
     }
     if (cstart != nullptr && last && threadIdx.x == 0) cstart[cend] = (int32_t)n;
+    if (cstart != nullptr) {
+        note_cell_max(lmax, s_cmax);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(a.d.cellmax, *s_cmax);
+    }
     int32_t* ok = a.d.kB + (int64_t)s * n + start;
     int32_t* ov = a.d.vB + (int64_t)s * n + start;
     for (int64_t p = threadIdx.x; p < m; p += BKT_THREADS) {
@@ -522,6 +542,7 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     __shared__ int32_t sidx[BKT_CAP];
     __shared__ uint16_t skey[BKT_CAP];  // cell within the bucket
     __shared__ uint32_t s_red[BKT_THREADS / 64 + 1];
+    __shared__ uint32_t s_cmax;
     static_assert(BKT_CELLS <= 65536, "cells of a bucket fit 16 bits");
     const GeomArgs& g = a.g;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -534,9 +555,10 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     const int64_t cend = min(G, (int64_t)(b + 1) << a.cb);
     const bool last = cend == G;
     if (m >= 1 && m <= BKT_CAP && cend - cbeg <= BKT_CELLS)
-        bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red);
+        bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red,
+                       &s_cmax);
     else
-        bucket_general<T>(a, s, start, m, cbeg, cend, last, Xb, Xs, cstart, hist, s_red);
+        bucket_general<T>(a, s, start, m, cbeg, cend, last, Xb, Xs, cstart, hist, s_red, &s_cmax);
 }
 
 template <typename T>

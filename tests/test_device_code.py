@@ -15,7 +15,7 @@ from paper_2012_06646_amd import build as B
 # every read-modify-write mnemonic: global/flat/buffer atomics and LDS atomics
 RMW = re.compile(r"^\s*((?:global|flat|buffer)_atomic_\w+|ds_(?:add|sub|rsub|min|max|inc|dec|and|or|xor|"
                  r"pk_add|cmpst|cmpswap|wrxchg|cond_sub|sub_clamp)\w*)", re.M)
-INTEGER_RMW = re.compile(r"^(ds_add(_rtn)?_u(32|64)|(global|flat)_atomic_(add|or)(_x2)?)$")
+INTEGER_RMW = re.compile(r"^(ds_(add|max)(_rtn)?_u(32|64)|(global|flat)_atomic_(add|or|umax)(_x2)?)$")
 FLOAT_SUFFIX = re.compile(r"_(f16|bf16|f32|f64)\b")
 
 

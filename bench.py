@@ -306,7 +306,7 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
     mu1 = 2 * pool_size / t1
     del plans
 
-    def closed_batched(graph=False):
+    def closed_batched(graph):
         srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=128, use_graph=graph)
         for jb in pool:
             srv.submit(jb, inputs_ready=True)
@@ -321,10 +321,30 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         srv.close()
         return 2 * pool_size / tb, st
 
-    muB, stB = closed_batched()
+    muB, stB = closed_batched(False)
     muG, _ = closed_batched(True)
 
-    def open_loop(max_batch, rate, graph=False):
+    def closed_by_batch(k, graph):
+        """Closed loop with batches of at most k jobs: the pool twice, after one warm pass."""
+        srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=k, use_graph=graph)
+        for jb in pool:
+            srv.submit(jb, inputs_ready=True)
+        srv.drain()
+        c0 = srv.clock_us()
+        for _ in range(2):
+            for jb in pool:
+                srv.submit(jb, inputs_ready=True)
+        srv.drain()
+        tb = (srv.clock_us() - c0) / 1e6
+        srv.close()
+        return round(2 * pool_size / tb, 1)
+
+    by_batch = {}
+    for k in (1, 2, 4, 8, 16, 32, 64, 128):
+        by_batch[str(k)] = {"direct_jobs_per_s": closed_by_batch(k, False),
+                            "graph_jobs_per_s": closed_by_batch(k, True)}
+
+    def open_loop(max_batch, rate, graph):
         srv = ibops.Server(dt, arena_bytes=16 << 30, max_jobs_per_batch=max_batch, use_graph=graph)
         total = warm + measured
         arr = wl.poisson_arrivals(total, rate)
@@ -358,9 +378,10 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
     for rho in rhos:
         rate = rho * mu1
         runs[str(rho)] = {"arrival_jobs_per_s": round(rate, 1),
-                          "one_job_per_launch": open_loop(1, rate),
-                          "batched": open_loop(128, rate),
-                          "batched_graph": open_loop(128, rate, True)}
+                          "one_job_per_launch": open_loop(1, rate, False),
+                          "batched": open_loop(128, rate, False),
+                          "batched_graph": open_loop(128, rate, True),
+                          "batched_default": open_loop(128, rate, None)}
     return {
         "workload": "independent FP32 jobs, N^3 MAC grid with N uniform on {32,64,96,128}, "
                     "n log-uniform in [1e3,1e6] uniform points, spread + interpolate each; "
@@ -372,6 +393,8 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         "batched_closed_loop_points_per_s": round(muB * pool_pts / pool_size, 1),
         "batched_closed_loop_mean_batch": round(stB["jobs_done"] / max(stB["batches"], 1), 2),
         "batched_graph_closed_loop_jobs_per_s": round(muG, 1),
+        "closed_loop_by_max_batch": by_batch,
+        "graph_max_jobs_default": ibops.GRAPH_MAX_JOBS,
         "open_loop_by_load": runs,
     }
 

@@ -90,8 +90,7 @@ typedef struct ib_plan_s *ib_plan;
 
 /* Tuning of a plan; all-zero fields select the built-in choices.
  *   spread_tile   3-D spreading tile (x*y*z cells owned by one block): 1 = 32x16x13,
- *                 2 = 32x8x13, 3 = 64x8x8; 0 = 32x16x13 for IB_F64 and 32x8x13 for
- *                 IB_F32 (2-D grids always use 64x32)
+ *                 2 = 32x8x13, 3 = 64x8x8; 0 = 64x8x8 (2-D grids always use 64x32)
  *   split_points  sharing of a spreading tile by several blocks (at most 256 per tile),
  *                 whose partial tiles a second kernel adds in block order: > 0 = at least
  *                 that many points per block; 0 = about 512 blocks in all, with at least
@@ -330,8 +329,9 @@ typedef struct {
     int32_t max_jobs_per_batch;  /* 1 .. IB_BATCH_MAX_JOBS (1: one job per launch sequence) */
     int32_t max_inflight;        /* 1 .. 4 batches queued on the GPU at once */
     int32_t max_queue;           /* jobs waiting; ib_batch_submit returns IB_ERR_BUSY beyond */
-    int32_t use_graph;           /* nonzero: each batch is one replay of a captured HIP graph
-                                    (fixed grids that loop over the batch's blocks) */
+    int32_t use_graph;           /* which batches replay a captured HIP graph (fixed grids that
+                                    loop over the batch's blocks) instead of direct launches:
+                                    0 none, k > 0 those of at most k jobs, < 0 all */
 } ib_server_opts;
 
 typedef struct {

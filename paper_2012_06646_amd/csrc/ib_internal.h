@@ -174,11 +174,13 @@ int interp_blocks(int64_t npts);
 // give bitwise-equal results.
 int interp_tiles(int dim, const int n[3], int64_t npts);
 // 3-D spreading tile shapes (index into the shape table of the spreading kernels):
-// 0 = 32x16x13, 1 = 32x8x13, 2 = 64x8x8.  FP32 plans and batches use 32x8x13 by default:
-// its kernel fits four waves per SIMD (FP32 sums need half the registers), and its LDS tile
-// lets four blocks share a CU.  FP64 plans use 32x16x13 (two waves per SIMD either way).
+// 0 = 32x16x13, 1 = 32x8x13, 2 = 64x8x8.  Plans and batches of both precisions use 64x8x8
+// by default: its long rows fill the 64-point chunks of a source slice best (fewer partial
+// chunks and table builds per point) and its small LDS tile lets three blocks share a CU,
+// which outweighs its larger halo (measured fastest of several shapes at 128^3 with 10^6
+// points, both precisions; the sums are 64-bit integers in either).
 constexpr int SPREAD_TILE_SHAPES = 3;
-constexpr int builtin_spread_shape(int32_t dtype) { return dtype == IB_F32 ? 1 : 0; }
+constexpr int builtin_spread_shape(int32_t) { return 2; }
 void spread_tiles(int dim, int shape, const int n[3], int tiles[3], int* slow);
 // Cells of one spreading tile, and the number of blocks that share a tile (1 .. SPLIT_MAX)
 // for npts points over ntiles (tiles x components) tiles: a dense point set on a small grid

@@ -151,7 +151,7 @@ struct ib_server_s {
         BatchLaunch bl;
         int32_t st = batch_prepare(jobs.data(), k, opts.dtype, header, plans + off, total, stage, &bl);
         if (st == IB_OK) {
-            if (opts.use_graph) {
+            if (opts.use_graph < 0 || (opts.use_graph > 0 && k <= opts.use_graph)) {
                 st = graph_launch(slot, bl);
             } else {
                 const size_t nb = batch_jobs_offset() + (size_t)k * sizeof(BatchJob);

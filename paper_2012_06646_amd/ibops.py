@@ -537,17 +537,27 @@ def job_desc(job, dtype):
     return jd
 
 
+# Batches of at most this many jobs replay a captured graph by default; larger ones launch
+# their stages directly (graph replay against direct launches, measured per batch size on the
+# serving mix of grids 32^3..128^3 with 10^3..10^6 points).
+GRAPH_MAX_JOBS = 0
+
+
 class Server:
     """The serving loop (ib_server_*): submit jobs one at a time, poll their tickets.  The
-    device arena (the server's HBM budget) is allocated here with torch and handed over."""
+    device arena (the server's HBM budget) is allocated here with torch and handed over.
+    use_graph: False (direct launches), True (every batch replays a captured graph), an int k
+    (batches of at most k jobs replay it), or None (GRAPH_MAX_JOBS)."""
 
     def __init__(self, dtype=torch.float32, arena_bytes=16 << 30, max_jobs_per_batch=BATCH_MAX_JOBS,
-                 max_inflight=2, max_queue=1 << 20, use_graph=False, device="cuda"):
+                 max_inflight=2, max_queue=1 << 20, use_graph=None, device="cuda"):
         self.dtype = dtype
         self.device = torch.device(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
-        o = ServerOpts(_dtype_code(dtype), int(max_jobs_per_batch), int(max_inflight), int(max_queue),
-                       int(bool(use_graph)))
+        if use_graph is None:
+            use_graph = GRAPH_MAX_JOBS
+        g = -1 if use_graph is True else 0 if use_graph is False else int(use_graph)
+        o = ServerOpts(_dtype_code(dtype), int(max_jobs_per_batch), int(max_inflight), int(max_queue), g)
         h = ctypes.c_void_p()
         _check(_lib.ib_server_create(ctypes.byref(o), _ptr(self.arena), self.arena.numel(),
                                      ctypes.byref(h)), "ib_server_create")

@@ -1,14 +1,17 @@
 """Autotuner for plan tunings (ib_tuning): the spreading tile shape, the number of points per
-block before a spreading tile is shared, and the radix digit width of the key sort.
+block before a spreading tile is shared, and the bucket bits of the key sort.
 
 For a representative point set, each candidate tuning builds a plan and times the step the
-plan serves -- plan update, spreading, interpolation -- with HIP events on the device; the
-fastest wins.  The search is coordinate-wise (tile shape, then splitting, then digit width),
-starting from the built-in choices, so a handful of candidates are timed; a candidate must
-beat the current choice by 2% to replace it, which keeps timing noise from deciding.  Results are kept
-in a JSON cache (``$IB_TUNE_CACHE``, default ``~/.cache/ibops_tune.json``) keyed by dtype,
-grid and the point count rounded to a power of two, where ``Plan(..., tuning="auto")``
-finds them.
+plan serves -- plan update, spreading, interpolation -- with HIP events on the device.  The
+search is coordinate-wise (tile shape, then splitting, then bucket bits), starting from the
+built-in choices.  Candidates that resolve to the same plan layout (the same tile shape and
+the same workspace size, which changes with the split count and the bucket bits) run the
+same kernels and are timed once.  The candidates of one axis are timed interleaved, one step
+each per round, and compared by their median step time, so drift of the device clock or of
+other work affects them alike; a candidate must beat the current choice by 2% to replace
+it.  Results are kept in a JSON cache (``$IB_TUNE_CACHE``, default
+``~/.cache/ibops_tune.json``) keyed by dtype, grid and the point count rounded to a power of
+two, where ``Plan(..., tuning="auto")`` finds them.
 """
 import json
 import math
@@ -18,9 +21,10 @@ import torch
 
 from . import ibops
 
-TILE_SHAPES = {1: "32x16x13", 2: "32x8x13", 3: "64x8x8"}  # 0: built-in (FP64 1, FP32 2)
+TILE_SHAPES = {1: "32x16x13", 2: "32x8x13", 3: "64x8x8"}  # 0: built-in (64x8x8)
+BUILTIN_TILE = 3
 SPLIT_CHOICES = (0, 256, 2048, -1)     # 0: built-in (~512 blocks, >= 128 points each); -1: never split
-RADIX_CHOICES = (0, 8, 6)              # 0: built-in (even digits of at most 8 bits)
+RADIX_CHOICES = (0, 8, 6)              # 0: built-in (about 2048 points, at most 8192 cells per bucket)
 MARGIN = 0.02                          # a candidate must be this much faster to be taken
 
 
@@ -61,55 +65,93 @@ def _store(k, entry):
     os.replace(tmp, path)
 
 
-def time_tuning(grid, X, F, u, tuning, reps=10):
-    """Average ms of one plan update + spread + interpolate with this tuning."""
-    dtype = X.dtype
-    p = ibops.Plan(grid, X.shape[0], dtype, X.device, tuning=tuning)
-    f = torch.empty(p.grid_shape, dtype=dtype, device=X.device)
-    U = torch.empty((X.shape[0], p.ncomp), dtype=dtype, device=X.device)
+def layout_key(grid, dtype, npts, tuning):
+    """Tunings with equal keys build the same plan layout and run the same kernels."""
+    tile = 0
+    if int(grid["dim"]) == 3:
+        tile = int(tuning.get("spread_tile", 0)) or BUILTIN_TILE
+    desc = ibops.make_desc(grid)
+    nbytes = ibops._lib.ib_plan_workspace_bytes_tuned(
+        ibops.ctypes.byref(desc), ibops._dtype_code(dtype), int(npts),
+        ibops.ctypes.byref(ibops.make_tuning(tuning)))
+    return (tile, int(nbytes))
 
-    def once():
-        p.update(X)
-        p.spread(F, f)
-        p.interpolate(u, U)
-    once()
-    torch.cuda.synchronize()
-    s0 = torch.cuda.Event(enable_timing=True)
-    s1 = torch.cuda.Event(enable_timing=True)
+
+def time_tunings(grid, X, F, u, tunings, reps=10):
+    """Median ms of one plan update + spread + interpolate for each tuning, timed
+    interleaved: round r times one step of every candidate in turn."""
+    dtype = X.dtype
     st = torch.cuda.current_stream()
-    s0.record(st)
-    for _ in range(reps):
-        once()
-    s1.record(st)
+    runs = []
+    for t in tunings:
+        p = ibops.Plan(grid, X.shape[0], dtype, X.device, tuning=t)
+        f = torch.empty(p.grid_shape, dtype=dtype, device=X.device)
+        U = torch.empty((X.shape[0], p.ncomp), dtype=dtype, device=X.device)
+
+        def once(p=p, f=f, U=U):
+            p.update(X)
+            p.spread(F, f)
+            p.interpolate(u, U)
+        once()  # first-use costs stay out of the timings
+        runs.append(once)
     torch.cuda.synchronize()
-    return s0.elapsed_time(s1) / reps
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in runs] for _ in range(reps)]
+    for r in range(reps):
+        for i, once in enumerate(runs):
+            ev[r][i][0].record(st)
+            once()
+            ev[r][i][1].record(st)
+    torch.cuda.synchronize()
+    out = []
+    for i in range(len(runs)):
+        ms = sorted(ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps))
+        out.append(ms[len(ms) // 2])
+    return out
+
+
+def time_tuning(grid, X, F, u, tuning, reps=10):
+    """Median ms of one plan update + spread + interpolate with this tuning."""
+    return time_tunings(grid, X, F, u, [tuning], reps)[0]
 
 
 def autotune(grid, X, F, u, reps=10, store=True, verbose=False):
     """Search the tunings for this point set and grid; return (best tuning, timings)."""
     best = {"spread_tile": 0, "split_points": 0, "radix_bits": 0}
-    timings = {}
+    timings = {}  # tuning key -> median ms (candidates of distinct layouts only)
+    seen = {}     # layout key -> tuning key timed for it
+    dtype, npts = X.dtype, X.shape[0]
 
-    def measure(t):
-        k = (t["spread_tile"], t["split_points"], t["radix_bits"])
-        if k not in timings:
-            timings[k] = time_tuning(grid, X, F, u, t, reps)
-            if verbose:
-                print(f"  tuning {t}: {timings[k]:.4f} ms", flush=True)
-        return timings[k]
+    def tkey(t):
+        return (t["spread_tile"], t["split_points"], t["radix_bits"])
 
-    time_tuning(grid, X, F, u, best, reps)  # warm-up: first-use costs stay out of the timings
-    cur = measure(best)
+    cur = time_tunings(grid, X, F, u, [best], reps)[0]
+    timings[tkey(best)] = cur
+    seen[layout_key(grid, dtype, npts, best)] = tkey(best)
     axes = [("split_points", SPLIT_CHOICES), ("radix_bits", RADIX_CHOICES)]
     if int(grid["dim"]) == 3:
-        builtin = 2 if X.dtype == torch.float32 else 1
-        axes.insert(0, ("spread_tile", tuple(k for k in TILE_SHAPES if k != builtin)))
+        axes.insert(0, ("spread_tile", tuple(k for k in TILE_SHAPES if k != BUILTIN_TILE)))
     for name, choices in axes:
+        cands = []
         for c in choices:
             cand = dict(best, **{name: c})
-            t = measure(cand)
-            if t < cur * (1.0 - MARGIN):
-                best, cur = cand, t
+            lk = layout_key(grid, dtype, npts, cand)
+            if lk in seen:
+                continue  # the same kernels as a candidate already timed
+            seen[lk] = tkey(cand)
+            cands.append(cand)
+        if not cands:
+            continue
+        ms = time_tunings(grid, X, F, u, [best] + cands, reps)  # the incumbent again, alongside
+        cur = ms[0]
+        timings[tkey(best)] = cur
+        for cand, t in zip(cands, ms[1:]):
+            timings[tkey(cand)] = t
+            if verbose:
+                print(f"  tuning {cand}: {t:.4f} ms (current {cur:.4f})", flush=True)
+        i = min(range(len(cands)), key=lambda k: ms[1 + k])
+        if ms[1 + i] < cur * (1.0 - MARGIN):
+            best, cur = cands[i], ms[1 + i]
     if store:
         _store(key(grid, X.dtype, X.shape[0]),
                {"tuning": best, "ms": round(cur, 5),

@@ -117,10 +117,10 @@ def test_tuned_workspace_and_validation(ib):
     assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(0, 0, 0))) == base
     # a dense point set shares tiles between blocks (partial tiles); never sharing needs less
     assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(0, -1, 0))) < base
-    # tile 0 is the built-in shape of the precision: 32x16x13 for FP64, 32x8x13 for FP32
-    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(1, 0, 0))) == base
+    # tile 0 is the built-in shape, 64x8x8, in both precisions
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(3, 0, 0))) == base
     base32 = ib._lib.ib_plan_workspace_bytes(ctypes.byref(g), 1, 10**6)
-    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 1, 10**6, ctypes.byref(T(2, 0, 0))) == base32
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 1, 10**6, ctypes.byref(T(3, 0, 0))) == base32
     for shape in (1, 2, 3):
         assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(shape, 0, 0))) > 0
     for bad in (T(4, 0, 0), T(-1, 0, 0), T(0, 0, 3), T(0, 0, 11)):

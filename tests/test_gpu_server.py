@@ -45,10 +45,11 @@ def run_all(srv, jobs):
 
 
 @pytest.mark.parametrize("max_batch,graph", [(1, False), (5, False), (128, False), (1, True),
-                                             (5, True), (128, True)])
+                                             (5, True), (128, True), (128, 3)])
 def test_server_results_match_jobs_run_alone(ib, max_batch, graph):
     """Every batch (with graphs: every replay of the slot's graph, with other work and
-    synchronisations between replays) against the same jobs run alone, bit for bit."""
+    synchronisations between replays; graph = 3: graphs for batches of at most 3 jobs, direct
+    launches for larger ones) against the same jobs run alone, bit for bit."""
     dtype = torch.float32
     jobs = serving_jobs(40, dtype, 6000)
     say(f"server max_batch={max_batch} graph={graph}: 40 jobs")

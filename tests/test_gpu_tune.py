@@ -58,7 +58,7 @@ def test_autotune_caches_and_plan_finds_it(ib, tmp_path, monkeypatch):
     Xd, Fd, ud = to_dev(X, dtype), to_dev(F, dtype), to_dev(u, dtype)
     best, timings = tune.autotune(g, Xd, Fd, ud, reps=3)
     say(f"autotune best {best} over {len(timings)} candidates")
-    assert len(timings) >= 8
+    assert len(timings) >= 3 and "(0, 0, 0)" in timings  # distinct layouts only
     data = json.load(open(tmp_path / "tune.json"))
     entry = data[tune.key(g, dtype, X.shape[0])]
     assert entry["tuning"] == best and entry["ms"] <= entry["default_ms"]

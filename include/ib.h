@@ -13,13 +13,18 @@
  *                  the preparatory steps of Alg. 4 (Sec. 3.4).
  * Grid points of component c are x = h (i + xi_c), i taken modulo n (periodic box,
  * Sec. 3.1), except along walled dimensions (ib_grid_desc.walls); phi is Peskin's 4-point
- * kernel or the cosine kernel (Sec. 2).
+ * kernel, the cosine kernel (Sec. 2) or the 3-point kernel (ib_kernel).
  *
  * Layouts:
  *   points X, forces F, velocities U : row-major (npts x dim) and (npts x ncomp)
  *   grid fields f, u                 : [ncomp][n2][n1][n0], x (index 0) fastest; 2-D: [ncomp][n1][n0]
  *   keys                             : key = c0 + n0 * (c1 + n1 * c2), the x-fastest cell index
  *                                      counted from 0 (Fig. 2 counts from 1)
+ * Cells (Sec. 3.1, Fig. 1): with y_k = t_k - xi_k, t_k = X_k * (n_k / L_k) rounded once in the
+ * plan's precision, c_k = floor(y_k) for the 4-point kernels (even support) and the nearest
+ * node floor(y_k + 1/2), half-way points going up, for the 3-point kernel (odd support,
+ * Fig. 1(b)); then taken modulo n_k.  A point's weights fall on the nodes c_k - 1 .. c_k + 2
+ * (even) or c_k - 1 .. c_k + 1 (odd) of each dimension.
  * Dtype: one per plan, IB_F64 or IB_F32, shared by X, F, f, u and U.  Keys, permutations
  * and offsets are int32.
  *
@@ -56,9 +61,8 @@ typedef enum {
     IB_KERNEL_PESKIN4 = 0,    /* Peskin's 4-point kernel */
     IB_KERNEL_COSINE4 = 1,    /* phi(r) = (1 + cos(pi r / 2)) / 4 on |r| <= 2 (the paper's choice) */
     IB_KERNEL_ROMA3 = 2       /* the 3-point kernel of Roma, Peskin & Berger (1999): odd support
-                                 s = 3, Fig. 1(b).  It runs on the same plan (cells and 4x4(x4)
-                                 shift window) as the 4-point kernels: the window's fourth weight
-                                 per dimension is zero, on the side away from the nearest node. */
+                                 s = 3, Fig. 1(b): its plans key points by their nearest node and
+                                 the operators take the 3^d shifts -1, 0, 1 around it */
 } ib_kernel;
 
 #define IB_KERNEL_COUNT 3

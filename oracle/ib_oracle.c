@@ -129,11 +129,15 @@ double or_dphi(int kernel, double r)
 
 /* ---- cell keys (Alg. 4 key step; Fig. 2 numbering, 0-based) ------------------------
  * For one grid staggering xi: t_k = X_k * (N_k / L_k), rounded once in the job precision
- * (prec 0 = double, 1 = float, never fused), y_k = t_k - xi_k, cell_k = floor(y_k) taken
+ * (prec 0 = double, 1 = float, never fused), y_k = t_k - xi_k.  The cell (Sec. 3.1, Fig. 1)
+ * is the region of points sharing one set of support points, named by its grid point: for
+ * an even support size (odd == 0) the cell whose lower corner is the node floor(y_k); for
+ * an odd support size (odd == 1, Fig. 1(b)) the cell centred on the nearest node,
+ * floor(y_k + 1/2), a point exactly half-way going to the upper node.  cell_k is taken
  * modulo N_k (Euclidean), key = cell_0 + N_0 * (cell_1 + N_1 * cell_2).
  * Returns the number of points whose scaled coordinate is not finite or too large
  * (|t| >= 2^30); their key is set to -1. */
-long or_keys(int dim, const int *n, const double *length, const double *xi, int prec,
+long or_keys(int dim, const int *n, const double *length, const double *xi, int prec, int odd,
              long np, const double *X, int32_t *keys)
 {
     long bad = 0;
@@ -154,6 +158,8 @@ long or_keys(int dim, const int *n, const double *length, const double *xi, int 
             }
             if (!isfinite(y) || fabs(y) >= 1073741824.0) { ok = 0; break; }
             long long c = (long long)floor(y);
+            /* y - floor(y) is exact; the nearest node is the upper one from 1/2 on */
+            if (odd && y - floor(y) >= 0.5) c += 1;
             c %= n[k];
             if (c < 0) c += n[k];
             key += c * stride;

@@ -41,7 +41,7 @@ def lib():
         L.or_dphi.restype = ctypes.c_double
         L.or_dphi.argtypes = [ctypes.c_int, ctypes.c_double]
         L.or_keys.restype = ctypes.c_long
-        L.or_keys.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_int, ctypes.c_long, _dp,
+        L.or_keys.argtypes = [ctypes.c_int, _ip, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp,
                               _i32p]
         L.or_plan.restype = ctypes.c_long
         L.or_plan.argtypes = [ctypes.c_long, _i32p, _i32p, _i32p, _i32p]
@@ -97,14 +97,17 @@ def dphi(r, kernel="peskin4"):
 
 
 def keys(grid, X, xi, prec="f64"):
-    """Cell keys of the points X (np x dim) on the staggering xi; -1 marks invalid points."""
-    dim, n, length, _, _, _, _ = _grid_args(grid)
+    """Cell keys of the points X (np x dim) on the staggering xi; -1 marks invalid points.
+    The cell rule follows the kernel's support size: the nearest node for the 3-point kernel
+    (odd support, Fig. 1(b)), the node at or below the point otherwise."""
+    dim, n, length, _, _, kernel, _ = _grid_args(grid)
     X = _f64(X).reshape(-1, dim)
     xi_a = np.zeros(3)
     xi_a[:dim] = xi
     out = np.empty(X.shape[0], dtype=np.int32)
+    odd = 1 if kernel == KERNELS["roma3"] else 0
     bad = lib().or_keys(dim, _ptr(n, _ip), _ptr(length, _dp), _ptr(xi_a, _dp),
-                        1 if prec == "f32" else 0, X.shape[0], _ptr(X, _dp), _ptr(out, _i32p))
+                        1 if prec == "f32" else 0, odd, X.shape[0], _ptr(X, _dp), _ptr(out, _i32p))
     return out, int(bad)
 
 

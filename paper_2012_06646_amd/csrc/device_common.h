@@ -157,12 +157,34 @@ __device__ __forceinline__ double weight_sqrt(double x)
 
 __device__ __forceinline__ float weight_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// ---- one-dimensional kernel weights for the four shifts sigma = -1, 0, 1, 2 --------------
-// w[k] = phi(sigma_k - r) for a point at fractional offset r in [0, 1) of its cell.
+// ---- support of the one-dimensional kernels -------------------------------------------
+// A point's cell along one axis, from y = fl(x inv_h) - xi, and the nodes its weights fall
+// on.  Even support (the 4-point kernels, s = 4): the cell is floor(y) and the nodes are
+// cell - 1 .. cell + 2.  Odd support (the 3-point kernel, s = 3): the de facto cell of
+// Fig. 1(b) is centred on a grid node -- the node nearest the point, floor(y + 1/2), ties
+// going up -- and the nodes are cell - 1 .. cell + 1 (shifts -1, 0, 1).
+template <int KERN>
+constexpr int support_width() { return KERN == IB_KERNEL_ROMA3 ? 3 : 4; }
 
+// Cell of y (as a double, not yet wrapped) and the point's offset from it: r = y - cell in
+// [0, 1) for even support, in [-1/2, 1/2) for odd support (odd = the kernel's support is
+// odd).  Both are exact: y - floor(y) is, and so is subtracting 1 from it.
+template <typename T>
+__device__ __forceinline__ double axis_cell(T y, bool odd, T* r)
+{
+    const T fy = floor(y);
+    T rr = y - fy;
+    const bool up = odd && rr >= T(0.5);
+    *r = up ? rr - T(1) : rr;
+    return (double)fy + (up ? 1.0 : 0.0);
+}
+
+// ---- one-dimensional kernel weights --------------------------------------------------
+// Even support: w[k] = phi(k - 1 - r) for the four nodes cell - 1 + k, r in [0, 1).
 template <typename T, int KERN>
 __device__ __forceinline__ void weights4(T r, T w[4])
 {
+    static_assert(support_width<KERN>() == 4, "even-support kernels only");
     if constexpr (KERN == IB_KERNEL_COSINE4) {
         T s, c;
         if constexpr (sizeof(T) == 8) sincospi(0.5 * r, &s, &c);
@@ -172,7 +194,7 @@ __device__ __forceinline__ void weights4(T r, T w[4])
         w[1] = q + q * c;
         w[2] = q + q * s;
         w[3] = q - q * c;
-    } else if constexpr (KERN == IB_KERNEL_PESKIN4) {
+    } else {
         // Peskin 4-point, with s = sqrt(1 + 4r - 4r^2): phi(-1-r) = (3 - 2r - s)/8,
         // phi(r) = (3 - 2r + s)/8, phi(1-r) = (1 + 2r + s)/8, phi(2-r) = (1 + 2r - s)/8.
         // The two differences lose relative (not absolute) accuracy when a weight is
@@ -184,28 +206,32 @@ __device__ __forceinline__ void weights4(T r, T w[4])
         w[1] = (a + s) * T(0.125);
         w[2] = (b + s) * T(0.125);
         w[3] = (b - s) * T(0.125);
-    } else {
-        // 3-point kernel.  With m the signed offset of the point from its nearest node
-        // (m = r or r - 1, |m| <= 1/2) and s = sqrt(1 - 3 m^2): the nearest node weighs
-        // (1 + s)/3, its lower neighbour (2 - 3m - s)/6, its upper neighbour (2 + 3m - s)/6.
-        // The nearest node is sigma = 0 for r < 1/2 and sigma = 1 otherwise; the remaining
-        // window entry (at distance >= 3/2) is zero.
-        const bool lo = r < T(0.5);
-        const T m = lo ? r : r - T(1);
-        const T s = weight_sqrt(T(1) - T(3) * m * m);
-        const T c = (T(1) + s) * T(1.0 / 3.0);
-        const T a = (T(2) - s - T(3) * m) * T(1.0 / 6.0);
-        const T b = (T(2) - s + T(3) * m) * T(1.0 / 6.0);
-        w[0] = lo ? a : T(0);
-        w[1] = lo ? c : a;
-        w[2] = lo ? b : c;
-        w[3] = lo ? T(0) : b;
     }
 }
 
-// Derivatives d w[k] / d r of the four weights of weights4 (r increases with X).
+// Odd support (3-point kernel): the three nodes cell - 1, cell, cell + 1 for the point at
+// signed offset m in [-1/2, 1/2] from its cell's node.  With s = sqrt(1 - 3 m^2): the node
+// weighs (1 + s)/3, its lower neighbour (2 - 3m - s)/6, its upper neighbour (2 + 3m - s)/6.
+template <typename T>
+__device__ __forceinline__ void weights3(T m, T w[3])
+{
+    const T s = weight_sqrt(T(1) - T(3) * m * m);
+    w[0] = (T(2) - s - T(3) * m) * T(1.0 / 6.0);
+    w[1] = (T(1) + s) * T(1.0 / 3.0);
+    w[2] = (T(2) - s + T(3) * m) * T(1.0 / 6.0);
+}
+
+// The weights of the SW = support_width<KERN>() nodes from the offset r of axis_cell.
 template <typename T, int KERN>
-__device__ __forceinline__ void dweights4(T r, T dw[4])
+__device__ __forceinline__ void weights_of(T r, T w[4])
+{
+    if constexpr (support_width<KERN>() == 3) weights3<T>(r, w);
+    else weights4<T, KERN>(r, w);
+}
+
+// Derivatives d w[k] / d r of the weights of weights_of (r increases with X).
+template <typename T, int KERN>
+__device__ __forceinline__ void dweights_of(T r, T dw[4])
 {
     if constexpr (KERN == IB_KERNEL_COSINE4) {
         T s, c;
@@ -225,17 +251,12 @@ __device__ __forceinline__ void dweights4(T r, T dw[4])
         dw[2] = (T(2) + ds) * T(0.125);
         dw[3] = (T(2) - ds) * T(0.125);
     } else {
-        // 3-point kernel (see weights4): dm/dr = 1 and ds/dm = -3m / s.
-        const bool lo = r < T(0.5);
-        const T m = lo ? r : r - T(1);
-        const T ds = T(-3) * m / sqrt(T(1) - T(3) * m * m);
-        const T dc = ds * T(1.0 / 3.0);
-        const T da = (T(-3) - ds) * T(1.0 / 6.0);
-        const T db = (T(3) - ds) * T(1.0 / 6.0);
-        dw[0] = lo ? da : T(0);
-        dw[1] = lo ? dc : da;
-        dw[2] = lo ? db : dc;
-        dw[3] = lo ? T(0) : db;
+        // 3-point kernel (see weights3), m = r: ds/dm = -3m / s.
+        const T ds = T(-3) * r / sqrt(T(1) - T(3) * r * r);
+        dw[0] = (T(-3) - ds) * T(1.0 / 6.0);
+        dw[1] = ds * T(1.0 / 3.0);
+        dw[2] = (T(3) - ds) * T(1.0 / 6.0);
+        dw[3] = T(0);
     }
 }
 

@@ -233,6 +233,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     g.scale = 1.0 / hd;
     g.split = L.split;
     g.sp_tile = L.sp_tile;
+    g.odd = grid->kernel == IB_KERNEL_ROMA3 ? 1 : 0;
     for (int c = 0; c < grid->ncomp; ++c) {
         g.comp_stag[c] = cs[c];
         for (int k = 0; k < 3; ++k) {

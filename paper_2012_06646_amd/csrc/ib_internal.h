@@ -84,6 +84,7 @@ struct GeomArgs {
     double scale;          // (prod_k h_k)^-1 for spreading
     int split;             // blocks per spreading tile (see spread_split)
     int sp_tile;           // spreading tile shape (ib_tuning.spread_tile)
+    int odd;               // odd-support kernel: a point's cell is its nearest node (Fig. 1(b))
 };
 
 struct SortArgs {

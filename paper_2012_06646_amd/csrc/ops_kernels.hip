@@ -12,13 +12,13 @@
 // owns a tile of one component's grid and produces every value of it exactly once.  It
 // reads the sorted points whose cells can reach the tile (contiguous sorted ranges per
 // x-row, since keys are x-fastest), one source plane at a time; a wave takes 64 of them,
-// one per lane, computes their separable weights and adds the 4^d products into the tile
-// held in LDS.  The sums are exact integer (fixed-point) sums, so their value does not
+// one per lane, computes their separable weights and adds the s^d products (s = 4, or 3
+// for the odd-support kernel) into the tile held in LDS.  The sums are exact integer (fixed-point) sums, so their value does not
 // depend on the order of the additions: waves and blocks need no ordering among
 // themselves, no floating-point atomics are used, and the result is bitwise reproducible.
 //
 // Interpolation (eq. disc-interp; Alg. 3, Sec. 3.3).  One thread per point in the sorted
-// order of staggering 0, gathering the 4^d grid values of each component directly
+// order of staggering 0, gathering the s^d grid values of each component directly
 // (neighbouring lanes hold neighbouring cells, so a wave's gathers share cache lines);
 // the point's components are accumulated in registers in tensor-product order and
 // written together.
@@ -84,25 +84,27 @@ __device__ __forceinline__ T advect_coord(T x, T u, T dt, T L)
 
 // Weights of a point at coordinates x for component c, and the offset of its component-c
 // cell from its staggering-0 cell per dimension.  The cells follow the key rule exactly
-// (t = x * inv_h rounded once, minus the staggering, floored).
+// (t = x * inv_h rounded once, minus the staggering; then axis_cell).
 template <typename T, int DIM, int KERN>
 __device__ __forceinline__ void comp_weights(const GeomArgs& g, int c, const T x[DIM],
                                              T w[DIM][4], int delta[DIM])
 {
+    constexpr bool odd = support_width<KERN>() == 3;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const T ih = Prec<T>::inv_h(g, k);
         const T yc = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
-        const T fc = floor(yc);
+        T r;
+        const double fc = axis_cell<T>(yc, odd, &r);
         if (g.dlo[c][k] == g.dhi[c][k]) {
             delta[k] = g.dlo[c][k];  // the same staggering as staggering 0 along this axis
         } else {
             const T y0 = shifted_scaled<T>(x[k], ih, (T)g.stag_xi[0][k]);
-            delta[k] = min(max((int)(fc - floor(y0)), g.dlo[c][k]), g.dhi[c][k]);
+            T r0;
+            delta[k] = min(max((int)(fc - axis_cell<T>(y0, odd, &r0)), g.dlo[c][k]), g.dhi[c][k]);
         }
-        T r = yc - fc;
         r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
-        weights4<T, KERN>(r, w[k]);
+        weights_of<T, KERN>(r, w[k]);
     }
 }
 
@@ -260,7 +262,8 @@ struct SliceTable {
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
 struct SpreadTile {
     static constexpr int PXS = TX + 6;  // padded row pitch of the LDS tile (x from -3 to TX + 2)
-    static constexpr int NZ = (DIM == 3) ? 4 : 1;            // stencil extent in z
+    static constexpr int SW = support_width<KERN>();         // stencil nodes per dimension
+    static constexpr int NZ = (DIM == 3) ? SW : 1;           // stencil extent in z
     static constexpr int MAXROWS = (DIM == 3) ? TY + 5 : 1;   // x-rows per slice
     static constexpr int MAXR = 3 * MAXROWS;
     static constexpr int CELLS = PXS * TY * TZ;               // LDS tile words
@@ -376,7 +379,7 @@ struct SpreadTile {
 
     __device__ static int chunk_pos(int lane) { return ((lane & 15) << 2) | (lane >> 4); }
 
-    // Add the 4^d contributions of every lane's point (lanes with has) into the tile, as
+    // Add the SW^d contributions of every lane's point (lanes with has) into the tile, as
     // fixed-point integers.  Tile rows are padded in x (PXS = TX + 6, target x from -3 to
     // TX + 2), so only whole rows can fall outside the tile; those are skipped.
     __device__ static void add_point(const T w[DIM][4], double Fs, bool has, int cx, int cy, int cz,
@@ -386,24 +389,24 @@ struct SpreadTile {
         const int base = (zb * TY + yb) * PXS + (cx + 2);
         double wz[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) wz[i] = (DIM == 3) ? (double)w[DIM - 1][i] * Fs : 0.0;
+        for (int i = 0; i < SW; ++i) wz[i] = (DIM == 3) ? (double)w[DIM - 1][i] * Fs : 0.0;
         bool oka[4], okb[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < SW; ++i) {
             oka[i] = has && ((DIM == 3) ? (unsigned)(zb + i) < (unsigned)ez
                                         : (unsigned)(yb + i) < (unsigned)ey);
             okb[i] = (DIM == 3) ? (unsigned)(yb + i) < (unsigned)ey : i == 0;
         }
 #pragma unroll
-        for (int ia = 0; ia < 4; ++ia)
+        for (int ia = 0; ia < SW; ++ia)
 #pragma unroll
-            for (int ib = 0; ib < ((DIM == 3) ? 4 : 1); ++ib) {
+            for (int ib = 0; ib < ((DIM == 3) ? SW : 1); ++ib) {
                 if (oka[ia] && okb[ib]) {
                     const double cyz = (DIM == 3) ? (double)w[1][ib] * wz[ia] : (double)w[1][ia] * Fs;
                     unsigned long long* row =
                         tile + base + ((DIM == 3) ? (ia * TY + ib) * PXS : ia * PXS);
 #pragma unroll
-                    for (int ix = 0; ix < 4; ++ix)
+                    for (int ix = 0; ix < SW; ++ix)
                         __hip_atomic_fetch_add(row + ix, fx_round((double)w[0][ix], cyz),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
@@ -411,7 +414,7 @@ struct SpreadTile {
     }
 
     // Add the slice's points, in chunks of 64 (one point per lane), into the tile.
-    // off[k] = 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
+    // off[k] = SW - 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
     // staggering-0 cell + delta - off.
     __device__ static void spread_slice(const OpArgs& a, int c, const Table& tb, int32_t* mark,
                                         int rp, bool rn, int nranges, int total, int q,
@@ -443,8 +446,8 @@ struct SpreadTile {
             const int cx = key + tb.xo[rr] + delta[0] - off[0];
             const int cy = tb.uy[rr] + delta[1] - off[1];
             const int cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
-            const bool has = valid && cx >= -2 && cx <= ex && cy >= -2 && cy <= ey &&
-                             (DIM == 2 || (cz >= -2 && cz <= ez));
+            const bool has = valid && cx >= 2 - SW && cx <= ex && cy >= 2 - SW && cy <= ey &&
+                             (DIM == 2 || (cz >= 2 - SW && cz <= ez));
             add_point(w, ldexp((double)Fc, fshift), has, cx, cy, cz, ey, ez, tile);
         }
     }
@@ -500,23 +503,26 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
 
     for (int i = threadIdx.x; i < ST::CELLS; i += blockDim.x) tile[i] = 0ull;
 
-    // Source frame: staggering-0 cells that can reach the tile for this component.
+    // Source frame: staggering-0 cells that can reach the tile for this component.  The
+    // nodes of a point with component-c cell i are i - 1 .. i + SW - 2, so a tile node m
+    // receives from cells m - SW + 2 .. m + 1, and staggering-0 cells lie delta below.
+    constexpr int SW = ST::SW;
     const int hx = g.dhi[c][0] - g.dlo[c][0], hy = g.dhi[c][1] - g.dlo[c][1];
     const int hz = (DIM == 3) ? g.dhi[c][2] - g.dlo[c][2] : 0;
-    const int off[3] = {2 + g.dhi[c][0], 2 + g.dhi[c][1], (DIM == 3) ? 2 + g.dhi[c][2] : 0};
+    const int off[3] = {SW - 2 + g.dhi[c][0], SW - 2 + g.dhi[c][1], (DIM == 3) ? SW - 2 + g.dhi[c][2] : 0};
     const int ox = x0 - off[0], oy = y0 - off[1], oz = (DIM == 3) ? z0 - off[2] : 0;
-    const int lenx = ex + 3 + hx;
-    const int nrows = (DIM == 3) ? ey + 3 + hy : 1;
-    const int nslices = (DIM == 3) ? ez + 3 + hz : ey + 3 + hy;
+    const int lenx = ex + SW - 1 + hx;
+    const int nrows = (DIM == 3) ? ey + SW - 1 + hy : 1;
+    const int nslices = (DIM == 3) ? ez + SW - 1 + hz : ey + SW - 1 + hy;
     const int nranges = 3 * nrows;
     const int w = wave_id();
 
     // The most contributions any grid value can receive: its stencil window holds
-    // (4 + hx)(4 + hy)(4 + hz) staggering-0 cells (3-D), each with at most cellmax points.
+    // (SW + hx)(SW + hy)(SW + hz) staggering-0 cells (3-D), each with at most cellmax points.
     // With the maximum force of component c it sets the tile's scale (every split block of
     // the tile finds the same).
     const unsigned long long vmax = fmax_of<SPREAD_THREADS>(a.fmax, c, s_red);  // has barriers
-    const uint64_t win = (uint64_t)(4 + hx) * (4 + hy) * ((DIM == 3) ? 4 + hz : 1);
+    const uint64_t win = (uint64_t)(SW + hx) * (SW + hy) * ((DIM == 3) ? SW + hz : 1);
     const uint32_t mbound = (uint32_t)min(win * (uint64_t)*a.cellmax, (uint64_t)0xFFFFFFFFu);
     const bool finite = vmax < FX_NONFINITE;
     const int fshift = (vmax == 0ull || !finite) ? 0 : fx_shift(vmax, mbound);
@@ -604,14 +610,15 @@ __global__ __launch_bounds__(SPREAD_THREADS) void spread_kernel(OpArgs a)
 // Interpolation
 // ---------------------------------------------------------------------------------------
 // One thread per point, in the sorted order of staggering 0: neighbouring lanes hold
-// neighbouring cells, so the 4^d gathers of a wave share cache lines.  All components of a
+// neighbouring cells, so the SW^d gathers of a wave share cache lines.  All components of a
 // point are accumulated in registers and written together.
 // Interpolated value of component c at point coordinates x: weights per axis, then the
-// 4^d gathers in tensor-product order.
+// SW^d gathers (SW = support_width<KERN>()) in tensor-product order.
 template <typename T, int DIM, int KERN>
 __device__ __forceinline__ T interp_component(const GeomArgs& g, const T* __restrict__ u, int c,
                                               const T x[DIM])
 {
+    constexpr int SW = support_width<KERN>();
     const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
     const int64_t G = (int64_t)n0 * n1 * n2;
     T w[DIM][4];
@@ -620,29 +627,28 @@ __device__ __forceinline__ T interp_component(const GeomArgs& g, const T* __rest
     for (int k = 0; k < DIM; ++k) {
         const T ih = Prec<T>::inv_h(g, k);
         const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
-        const T fy = floor(y);
-        T r = y - fy;
+        T r;
+        const double fyd = axis_cell<T>(y, SW == 3, &r);
         r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
-        weights4<T, KERN>(r, w[k]);
-        const double fyd = (double)fy;
+        weights_of<T, KERN>(r, w[k]);
         cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
     }
     int xi[4];
 #pragma unroll
-    for (int ix = 0; ix < 4; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+    for (int ix = 0; ix < SW; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
     const T* __restrict__ uc = u + (int64_t)c * G;
     T sum = T(0);
 #pragma unroll
-    for (int iz = 0; iz < ((DIM == 3) ? 4 : 1); ++iz) {
+    for (int iz = 0; iz < ((DIM == 3) ? SW : 1); ++iz) {
         const int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
         T sy = T(0);
 #pragma unroll
-        for (int iy = 0; iy < 4; ++iy) {
+        for (int iy = 0; iy < SW; ++iy) {
             const int yy = wrap_small(cell[1] - 1 + iy, n1);
             const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
             T sx = T(0);
 #pragma unroll
-            for (int ix = 0; ix < 4; ++ix) sx = fma(w[0][ix], line[xi[ix]], sx);
+            for (int ix = 0; ix < SW; ++ix) sx = fma(w[0][ix], line[xi[ix]], sx);
             sy = fma(w[1][iy], sx, sy);
         }
         sum = (DIM == 3) ? fma(w[DIM - 1][iz], sy, sum) : sy;
@@ -705,7 +711,7 @@ __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 // x-row of the tile).  For each component in turn it stages the grid values that the
 // stencils of those points can touch -- the tile widened by the stencil and by the offset
 // between the component's cells and staggering-0 cells -- in LDS with coalesced loads, and
-// every point then reads its 4^3 values from LDS instead of gathering them from L2.  The
+// every point then reads its s^3 values from LDS instead of gathering them from L2.  The
 // weights and the order of the multiply-adds are those of interp_component, so the values
 // are bitwise equal to the gather kernel's.  A point is handled by the same thread in every
 // pass: the first components wait in a sorted-order scratch (written and read coalesced),
@@ -717,7 +723,8 @@ template <typename T, int KERN, int TX, int TY, int TZ>
 __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
 {
     constexpr int KP = 4;
-    constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region
+    constexpr int SW = support_width<KERN>();
+    constexpr int RX = TX + 4, RY = TY + 4, RZ = TZ + 4;  // largest staged region (SW <= 4)
     constexpr int ROWS = TY * TZ;
     __shared__ T su[RX * RY * RZ];
     __shared__ int32_t s_rowoff[RY * RZ];  // grid offset of each staged row (wrapped y, z)
@@ -765,10 +772,10 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     const T os = (T)a.out_scale;
     const int ncomp = g.ncomp;
     for (int c = 0; c < ncomp; ++c) {
-        // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + 2) per axis, wrapped.
+        // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + SW - 2) per axis, wrapped.
         const int hx = g.dhi[c][0] - g.dlo[c][0], hy = g.dhi[c][1] - g.dlo[c][1];
         const int hz = g.dhi[c][2] - g.dlo[c][2];
-        const int lx = ex + 3 + hx, ly = ey + 3 + hy, lz = ez + 3 + hz;
+        const int lx = ex + SW - 1 + hx, ly = ey + SW - 1 + hy, lz = ez + SW - 1 + hz;
         const int rx = x0 + g.dlo[c][0] - 1, ry = y0 + g.dlo[c][1] - 1, rz = z0 + g.dlo[c][2] - 1;
         const int nr = ly * lz;
         if (tid < nr) {  // one thread per staged row (nr <= RY * RZ <= 256)
@@ -846,27 +853,28 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                 for (int k = 0; k < 3; ++k) {
                     const T ih = Prec<T>::inv_h(g, k);
                     const T y = shifted_scaled<T>(x[q][k], ih, (T)g.comp_xi[c][k]);
-                    const T fy = floor(y);
-                    T r = y - fy;
+                    T r;
+                    const double fy = axis_cell<T>(y, SW == 3, &r);
                     r += product_residual<T>(x[q][k], ih, Prec<T>::inv_lo(g, k));
-                    weights4<T, KERN>(r, w[k]);
+                    weights_of<T, KERN>(r, w[k]);
                     int d = g.dlo[c][k];
                     if (g.dhi[c][k] != d) {
                         const T y0s = shifted_scaled<T>(x[q][k], ih, (T)g.stag_xi[0][k]);
-                        d = min(max((int)(fy - floor(y0s)), g.dlo[c][k]), g.dhi[c][k]);
+                        T r0;
+                        d = min(max((int)(fy - axis_cell<T>(y0s, SW == 3, &r0)), g.dlo[c][k]), g.dhi[c][k]);
                     }
                     base[k] = s0[q][k] + d - g.dlo[c][k];  // first stencil cell, region-relative
                 }
                 T sum = T(0);
 #pragma unroll
-                for (int iz = 0; iz < 4; ++iz) {
+                for (int iz = 0; iz < SW; ++iz) {
                     T sy = T(0);
 #pragma unroll
-                    for (int iy = 0; iy < 4; ++iy) {
+                    for (int iy = 0; iy < SW; ++iy) {
                         const T* line = su + ((base[2] + iz) * ly + (base[1] + iy)) * lx + base[0];
                         T sx_ = T(0);
 #pragma unroll
-                        for (int ix = 0; ix < 4; ++ix) sx_ = fma(w[0][ix], line[ix], sx_);
+                        for (int ix = 0; ix < SW; ++ix) sx_ = fma(w[0][ix], line[ix], sx_);
                         sy = fma(w[1][iy], sx_, sy);
                     }
                     sum = fma(w[2][iz], sy, sum);
@@ -915,6 +923,7 @@ template <typename T, int DIM, int KERN>
 __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __restrict__ W,
                                                           T* __restrict__ dX, int accumulate)
 {
+    constexpr int SW = support_width<KERN>();
     const GeomArgs& g = a.g;
     const int64_t n = g.npts;
     const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
@@ -938,31 +947,30 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
             for (int k = 0; k < DIM; ++k) {
                 const T ih = Prec<T>::inv_h(g, k);
                 const T y = shifted_scaled<T>(x[k], ih, (T)g.comp_xi[c][k]);
-                const T fy = floor(y);
-                T r = y - fy;
+                T r;
+                const double fyd = axis_cell<T>(y, SW == 3, &r);
                 r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
-                weights4<T, KERN>(r, w[k]);
-                dweights4<T, KERN>(r, dw[k]);
-                const double fyd = (double)fy;
+                weights_of<T, KERN>(r, w[k]);
+                dweights_of<T, KERN>(r, dw[k]);
                 cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
             }
             int xi[4];
 #pragma unroll
-            for (int ix = 0; ix < 4; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+            for (int ix = 0; ix < SW; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
             const T* __restrict__ uc = a.u ? u + (int64_t)c * G : u;
             // s_* : sums with w in every axis except the one differentiated
             T gx = T(0), gy = T(0), gz = T(0);
 #pragma unroll
-            for (int iz = 0; iz < ((DIM == 3) ? 4 : 1); ++iz) {
+            for (int iz = 0; iz < ((DIM == 3) ? SW : 1); ++iz) {
                 const int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
                 T ay = T(0), by = T(0), cy = T(0);
 #pragma unroll
-                for (int iy = 0; iy < 4; ++iy) {
+                for (int iy = 0; iy < SW; ++iy) {
                     const int yy = wrap_small(cell[1] - 1 + iy, n1);
                     const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
                     T sx = T(0), dsx = T(0);
 #pragma unroll
-                    for (int ix = 0; ix < 4; ++ix) {
+                    for (int ix = 0; ix < SW; ++ix) {
                         const T v = line[xi[ix]];
                         sx = fma(w[0][ix], v, sx);
                         dsx = fma(dw[0][ix], v, dsx);

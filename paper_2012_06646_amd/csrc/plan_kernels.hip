@@ -122,7 +122,8 @@ __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict
             if (k < g.dim) {
                 const T y = shifted_scaled<T>(xs[u][k], Prec<T>::inv_h(g, k), (T)g.stag_xi[s][k]);
                 int c = 0;
-                if (fabs(y) < T(1073741824.0)) c = floor_mod((double)floor(y), g.n[k], g.inv_n[k]);
+                T r;
+                if (fabs(y) < T(1073741824.0)) c = floor_mod(axis_cell<T>(y, g.odd != 0, &r), g.n[k], g.inv_n[k]);
                 else bad = true;
                 key += c * stride;
                 stride *= g.n[k];

@@ -109,3 +109,31 @@ def test_roma3_batch_and_server_match_plans(ib):
             assert torch.equal(job["f"], f1), f"server rep {rep} job {j}: spread differs"
             assert torch.equal(job["U"], U1), f"server rep {rep} job {j}: interpolation differs"
     srv.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("walls", [0, 0b010])
+def test_roma3_keys_are_the_odd_support_cells(ib, orc, dtype, walls):
+    """Plans of the 3-point kernel key each point by its nearest node (the de facto cell of
+    Fig. 1(b)), for every staggering: keys, sorted keys, permutation, run offsets and q equal
+    the oracle's bit for bit.  Walled plans key on the padded grid."""
+    from tests.test_gpu_parity import check_plan
+    g = wl.grid(3, [20, 16, 12], [1.0, 0.8, 1.2], kernel="roma3")
+    X, _, _ = wl.uniform_case(g, 20000, 7300)
+    if not walls:
+        check_plan(ib, orc, g, X, dtype, "roma3 odd-support keys")
+        return
+    # h = 1 along every axis keeps n / L exact on both grids, so keys compare bit for bit
+    g = dict(wl.grid(3, [16, 12, 10], [16.0, 12.0, 10.0], kernel="roma3"), walls=walls)
+    gp = wl.grid(3, [16, 16, 10], [16.0, 16.0, 10.0], kernel="roma3")
+    X = wl.rng(7301).random((5000, 3)) * np.array([16.0, 12.0, 10.0])
+    nd = np.float32 if dtype == torch.float32 else np.float64
+    Xc = X.astype(nd)
+    say(f"roma3 walled keys dtype={dtype}")
+    p = ib.Plan(g, X.shape[0], dtype).update(to_dev(Xc, dtype))
+    got = p.export(0)
+    # the padded grid continues the caller's indices periodically (ghosts at n .. n + 3)
+    k_ref, bad = orc.keys(gp, Xc.astype(np.float64), g["stagger"][p.stagger_of(0)],
+                          "f32" if dtype == torch.float32 else "f64")
+    assert bad == 0
+    assert np.array_equal(to_host(got["keys"]), k_ref)

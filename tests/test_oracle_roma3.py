@@ -142,3 +142,45 @@ def test_roma3_midpoints_are_exact(orc):
                     z, y, x = (idx[j, 2] + sz) % 8, (idx[j, 1] + sy) % 8, (idx[j, 0] + sx) % 8
                     acc[z, y, x] += Fraction(1, 8) * int(F[j, 0]) * 512
     assert np.array_equal(f, acc.astype(np.float64))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("N,L,xi", [(32, 1.0, 0.5), (20, 1.3, 0.0), (96, 1.0, 0.0), (100, 0.9, 0.5)])
+def test_odd_support_keys_are_the_fig1b_cells(orc, prec, N, L, xi):
+    """Keys of the 3-point kernel name the de facto cells of Fig. 1(b): the region of points
+    that share one set of support points, identified by the grid point inside it.  So the
+    nodes key - 1, key, key + 1 carry every nonzero weight of the point (the oracle's own
+    phi decides which are nonzero), and the key's node lies within half a cell of the point.
+    The even rule (the node at or below the point) fails both for points past the half."""
+    g = wl.grid(1, N, L, stagger=[[xi]], kernel="roma3")
+    g = dict(g, dim=1)
+    X = wl.rng(70 + N).random(5000) * L
+    k, bad = orc.keys(g, X[:, None], [xi], prec)
+    assert bad == 0
+    ft = np.float32 if prec == "f32" else np.float64
+    inv_h = ft(ft(N) / ft(L))
+    y = np.array([float(Fraction(float(ft(ft(x) * inv_h))) - Fraction(xi)) for x in X])  # exact t - xi
+    # the node of the key, unwrapped next to y
+    node = k + N * np.round((y - k) / N)
+    for off in range(-3, 4):
+        w = orc.phi(y - (node + off), "roma3")
+        if abs(off) <= 1:
+            continue
+        assert np.all(w == 0.0), off
+    w3 = sum(orc.phi(y - (node + off), "roma3") for off in (-1, 0, 1))
+    assert np.abs(w3 - 1.0).max() < 1e-14
+    assert np.all(np.abs(y - node) <= 0.5)
+
+
+def test_odd_support_keys_ties_and_even_rule(orc):
+    """A point exactly half-way between two nodes belongs to the upper node's cell; the
+    4-point kernels keep the node at or below the point."""
+    N = 16
+    h = 1.0 / N
+    X = np.array([[2.5 * h], [3.0 * h], [3.25 * h], [3.75 * h], [15.5 * h]])  # dyadic: exact
+    g3 = dict(wl.grid(1, N, 1.0, stagger=[[0.0]], kernel="roma3"), dim=1)
+    g4 = dict(wl.grid(1, N, 1.0, stagger=[[0.0]], kernel="peskin4"), dim=1)
+    k3, _ = orc.keys(g3, X, [0.0])
+    k4, _ = orc.keys(g4, X, [0.0])
+    assert list(k3) == [3, 3, 3, 4, 0]   # 15.5 goes up to 16, wrapped to 0
+    assert list(k4) == [2, 3, 3, 3, 15]

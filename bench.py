@@ -569,6 +569,12 @@ def c2_leg(torch, ibops, wl, dt_name, args, snap_steps):
 
     graph_ms = None
     if args.graph:
+        # The graph holds one step that re-plans from the positions the previous step
+        # advanced (update_advected), so it is captured after one eager step from X_0; the
+        # timed replays are steps 1 .. K of the same trajectory.
+        restart()
+        step()
+        torch.cuda.synchronize()
         gr = torch.cuda.CUDAGraph()
         cap = torch.cuda.Stream()
         cap.wait_stream(stream)
@@ -577,6 +583,7 @@ def c2_leg(torch, ibops, wl, dt_name, args, snap_steps):
                 step()
         stream.wait_stream(cap)
         restart()
+        step()
         g0 = torch.cuda.Event(enable_timing=True)
         g1 = torch.cuda.Event(enable_timing=True)
         g0.record(stream)

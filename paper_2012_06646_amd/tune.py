@@ -24,7 +24,11 @@ from . import ibops
 TILE_SHAPES = {1: "32x16x13", 2: "32x8x13", 3: "64x8x8"}  # 0: built-in (64x8x8)
 BUILTIN_TILE = 3
 SPLIT_CHOICES = (0, 256, 2048, -1)     # 0: built-in (~512 blocks, >= 128 points each); -1: never split
-RADIX_CHOICES = (0, 8, 6)              # 0: built-in (about 2048 points, at most 8192 cells per bucket)
+# bucket bits: 0 = built-in (about 2048 points and at most 8192 cells per bucket), or 10, the
+# most buckets.  Fewer buckets than the built-in are not offered: their buckets start near
+# the 4096 points one block sorts in LDS, and once moving points crowd some cells those
+# buckets take the slower path through global memory.
+RADIX_CHOICES = (0, 10)
 MARGIN = 0.02                          # a candidate must be this much faster to be taken
 
 

@@ -27,8 +27,7 @@ __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 // ---- cross-lane steps on DPP lane moves ------------------------------------------------
 // A wave64 is four rows of 16 lanes.  DPP (data-parallel primitives) moves a VGPR between
 // lanes inside the VALU instruction, with no LDS round trip.  Encodings (GFX9 DPP_CTRL):
-// row_shr:n = 0x110 + n (lane l reads l - n within its row), wave_shr:1 = 0x138 (lane l
-// reads l - 1 across the wave), row_bcast:15 = 0x142 (lane 15 of a row to every lane of the
+// row_shr:n = 0x110 + n (lane l reads l - n within its row), row_bcast:15 = 0x142 (lane 15 of a row to every lane of the
 // next row) and row_bcast:31 = 0x143 (lane 31 to rows 2 and 3).  ROWS masks the rows that
 // are written; lanes that are not written, or whose source lane does not exist, get 0.
 template <int CTRL, int ROWS = 0xf>
@@ -36,9 +35,6 @@ __device__ __forceinline__ uint32_t dpp_move(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
 }
-
-// v of lane l - 1 (0 in lane 0).
-__device__ __forceinline__ uint32_t wave_shr1_u32(uint32_t v) { return dpp_move<0x138>(v); }
 
 // Inclusive prefix sum over the lanes of a wave (a Hillis-Steele scan within rows, then
 // the row totals carried across rows).

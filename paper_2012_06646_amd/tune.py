@@ -8,8 +8,8 @@ built-in choices.  Candidates that resolve to the same plan layout (the same til
 the same workspace size, which changes with the split count and the bucket bits) run the
 same kernels and are timed once.  The candidates of one axis are timed interleaved, one step
 each per round, and compared by their median step time, so drift of the device clock or of
-other work affects them alike; a candidate must beat the current choice by 2% to replace
-it.  Results are kept in a JSON cache (``$IB_TUNE_CACHE``, default
+other work affects them alike; a candidate must beat the current choice by 2%, and by more
+than the spread of the current choice's own repeats, to replace it.  Results are kept in a JSON cache (``$IB_TUNE_CACHE``, default
 ``~/.cache/ibops_tune.json``) keyed by dtype, grid and the point count rounded to a power of
 two, where ``Plan(..., tuning="auto")`` finds them.
 """
@@ -82,8 +82,8 @@ def layout_key(grid, dtype, npts, tuning):
 
 
 def time_tunings(grid, X, F, u, tunings, reps=10):
-    """Median ms of one plan update + spread + interpolate for each tuning, timed
-    interleaved: round r times one step of every candidate in turn."""
+    """(median ms, interquartile range in ms) of one plan update + spread + interpolate for
+    each tuning, timed interleaved: round r times one step of every candidate in turn."""
     dtype = X.dtype
     st = torch.cuda.current_stream()
     runs = []
@@ -110,13 +110,13 @@ def time_tunings(grid, X, F, u, tunings, reps=10):
     out = []
     for i in range(len(runs)):
         ms = sorted(ev[r][i][0].elapsed_time(ev[r][i][1]) for r in range(reps))
-        out.append(ms[len(ms) // 2])
+        out.append((ms[len(ms) // 2], ms[(3 * len(ms)) // 4] - ms[len(ms) // 4]))
     return out
 
 
 def time_tuning(grid, X, F, u, tuning, reps=10):
     """Median ms of one plan update + spread + interpolate with this tuning."""
-    return time_tunings(grid, X, F, u, [tuning], reps)[0]
+    return time_tunings(grid, X, F, u, [tuning], reps)[0][0]
 
 
 def autotune(grid, X, F, u, reps=10, store=True, verbose=False):
@@ -129,7 +129,7 @@ def autotune(grid, X, F, u, reps=10, store=True, verbose=False):
     def tkey(t):
         return (t["spread_tile"], t["split_points"], t["radix_bits"])
 
-    cur = time_tunings(grid, X, F, u, [best], reps)[0]
+    cur = time_tunings(grid, X, F, u, [best], reps)[0][0]
     timings[tkey(best)] = cur
     seen[layout_key(grid, dtype, npts, best)] = tkey(best)
     axes = [("split_points", SPLIT_CHOICES), ("radix_bits", RADIX_CHOICES)]
@@ -146,16 +146,18 @@ def autotune(grid, X, F, u, reps=10, store=True, verbose=False):
             cands.append(cand)
         if not cands:
             continue
-        ms = time_tunings(grid, X, F, u, [best] + cands, reps)  # the incumbent again, alongside
-        cur = ms[0]
+        res = time_tunings(grid, X, F, u, [best] + cands, reps)  # the incumbent again, alongside
+        cur, cur_iqr = res[0]
         timings[tkey(best)] = cur
-        for cand, t in zip(cands, ms[1:]):
+        for cand, (t, _) in zip(cands, res[1:]):
             timings[tkey(cand)] = t
             if verbose:
                 print(f"  tuning {cand}: {t:.4f} ms (current {cur:.4f})", flush=True)
-        i = min(range(len(cands)), key=lambda k: ms[1 + k])
-        if ms[1 + i] < cur * (1.0 - MARGIN):
-            best, cur = cands[i], ms[1 + i]
+        i = min(range(len(cands)), key=lambda k: res[1 + k][0])
+        # a candidate must win by the margin and by more than the incumbent's own spread
+        # between repeats (its interquartile range)
+        if res[1 + i][0] < cur - max(MARGIN * cur, cur_iqr):
+            best, cur = cands[i], res[1 + i][0]
     if store:
         _store(key(grid, X.dtype, X.shape[0]),
                {"tuning": best, "ms": round(cur, 5),

@@ -158,6 +158,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->counters = take((size_t)nstag * PLAN_COUNTERS * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
     L->cellmax = take(sizeof(uint32_t));
+    L->crowd = take(sizeof(uint32_t));
     L->zero_end = off;
     L->gpad = take(user->walls ? (size_t)g->ncomp * (size_t)L->G * b : 0);
     L->total = off;
@@ -270,6 +271,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     d.counters = (uint32_t*)(base + L.counters);
     d.flag = (uint32_t*)(base + L.flag);
     d.cellmax = (uint32_t*)(base + L.cellmax);
+    d.crowd = (uint32_t*)(base + L.crowd);
     d.zero_begin = (uint32_t*)(base + L.zero_begin);
     d.zero_words = (L.zero_end - L.zero_begin) / sizeof(uint32_t);
     p->sa.rb = L.rb;
@@ -447,6 +449,7 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->tile_shift = p->sa.d.tile_shift;
     a->fmax = p->sa.d.fmax;
     a->cellmax = p->sa.d.cellmax;
+    a->crowd = p->sa.d.crowd;
     a->out_scale = 1.0;
 }
 

@@ -38,7 +38,7 @@ struct Layout {
     int64_t ntiles, nseg_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t kin, kA, vA, kB, vB, bhist, cstart, seg_off, q, Xs, Xb, Xn, Us, partial, tile_shift, fmax,
-        zero_begin, seg_status, counters, flag, cellmax, zero_end, gpad, total;
+        zero_begin, seg_status, counters, flag, cellmax, crowd, zero_end, gpad, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

@@ -27,6 +27,13 @@ constexpr uint32_t LB_INC = 2u << 30;
 constexpr uint32_t LB_MASK = (1u << 30) - 1u;
 constexpr int64_t MAX_POINTS = (int64_t)LB_MASK;  // counts must fit in 30 bits
 
+// A cell of at least CROWD_CELL points puts two of its points into one 16-lane group of a
+// spreading chunk (consecutive sorted points go to different groups, four per round), so
+// their adds meet at one LDS address.  When at least 1/CROWD_DIV of the points lie in such
+// cells, spreading rotates each lane's order of adds (spread_kernel).
+constexpr uint32_t CROWD_CELL = 5;
+constexpr uint32_t CROWD_DIV = 12;
+
 // Device error flag bits.
 constexpr uint32_t FLAG_BAD_POINT = 1u;
 constexpr uint32_t FLAG_LOOKBACK_STALL = 2u;
@@ -52,6 +59,7 @@ struct PlanDev {
     int32_t* tile_shift;   // [tiles] fixed-point scale exponent of each split tile
     unsigned long long* fmax;  // [3][FMAX_PARTS] partial maxima of |F| per component
     uint32_t* cellmax;     // most points in any staggering-0 cell (bucket pass; zero region)
+    uint32_t* crowd;       // points in staggering-0 cells of at least CROWD_CELL points (likewise)
     uint32_t* zero_begin;  // region cleared at each update
     size_t zero_words;
 };
@@ -115,6 +123,7 @@ struct OpArgs {
     int32_t* tile_shift;         //   and each split tile's scale exponent
     const unsigned long long* fmax;  // partial maxima of |F| per component (fmax_kernel)
     const uint32_t* cellmax;     // most points in any staggering-0 cell
+    const uint32_t* crowd;       // points in cells of at least CROWD_CELL points (or null)
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
     double out_scale;            // interpolation and its gradient: results times this (1: none)
     void* Xadv;                  // interpolation: also advance these positions (or null)

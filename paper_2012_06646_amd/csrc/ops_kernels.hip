@@ -382,6 +382,10 @@ struct SpreadTile {
     // Add the SW^d contributions of every lane's point (lanes with has) into the tile, as
     // fixed-point integers.  Tile rows are padded in x (PXS = TX + 6, target x from -3 to
     // TX + 2), so only whole rows can fall outside the tile; those are skipped.
+    // ROT: lane l adds its x-nodes of a row starting at (l mod 4) mod SW, so up to four lanes
+    // of one 16-lane group that hold points of one cell (crowded cells) add to different
+    // addresses at each instruction; the set of adds, and so every sum, is the same.
+    template <bool ROT>
     __device__ static void add_point(const T w[DIM][4], double Fs, bool has, int cx, int cy, int cz,
                                      int ey, int ez, unsigned long long* tile)
     {
@@ -397,6 +401,19 @@ struct SpreadTile {
                                         : (unsigned)(yb + i) < (unsigned)ey);
             okb[i] = (DIM == 3) ? (unsigned)(yb + i) < (unsigned)ey : i == 0;
         }
+        double wx[4];
+        int xo[4];
+        const int rot = ROT ? (lane_id() & 3) % SW : 0;
+#pragma unroll
+        for (int ix = 0; ix < SW; ++ix) {
+            double v = (double)w[0][ix];
+            if (ROT) {
+#pragma unroll
+                for (int r = 1; r < SW; ++r) v = rot == r ? (double)w[0][(ix + r) % SW] : v;
+            }
+            wx[ix] = v;
+            xo[ix] = ROT ? (ix + rot) % SW : ix;
+        }
 #pragma unroll
         for (int ia = 0; ia < SW; ++ia)
 #pragma unroll
@@ -407,7 +424,7 @@ struct SpreadTile {
                         tile + base + ((DIM == 3) ? (ia * TY + ib) * PXS : ia * PXS);
 #pragma unroll
                     for (int ix = 0; ix < SW; ++ix)
-                        __hip_atomic_fetch_add(row + ix, fx_round((double)w[0][ix], cyz),
+                        __hip_atomic_fetch_add(row + xo[ix], fx_round(wx[ix], cyz),
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
@@ -416,6 +433,7 @@ struct SpreadTile {
     // Add the slice's points, in chunks of 64 (one point per lane), into the tile.
     // off[k] = SW - 2 + dhi[k]: a point's tile-relative component-c cell is its source-frame
     // staggering-0 cell + delta - off.
+    template <bool ROT>
     __device__ static void spread_slice(const OpArgs& a, int c, const Table& tb, int32_t* mark,
                                         int rp, bool rn, int nranges, int total, int q,
                                         const int off[3], int ex, int ey, int ez, int fshift,
@@ -448,7 +466,7 @@ struct SpreadTile {
             const int cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
             const bool has = valid && cx >= 2 - SW && cx <= ex && cy >= 2 - SW && cy <= ey &&
                              (DIM == 2 || (cz >= 2 - SW && cz <= ez));
-            add_point(w, ldexp((double)Fc, fshift), has, cx, cy, cz, ey, ez, tile);
+            add_point<ROT>(w, ldexp((double)Fc, fshift), has, cx, cy, cz, ey, ez, tile);
         }
     }
 };
@@ -478,15 +496,26 @@ __device__ __forceinline__ T fx_value(unsigned long long acc, int fshift, bool f
     return (T)(ldexp((double)(long long)acc, -fshift) * scale);
 }
 
-template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
+// LDS of a spreading block, declared once per kernel whichever order of adds it runs.
+template <typename ST>
+struct SpreadShared {
+    static constexpr int NW = SPREAD_THREADS / 64;  // waves per block
+    unsigned long long tile[ST::CELLS];
+    typename ST::Table tables[NW];
+    int32_t marks[NW][64];
+    unsigned long long s_red[NW];
+};
+
+template <typename T, int DIM, int KERN, int TX, int TY, int TZ, bool ROT>
+__device__ __forceinline__ void spread_body(const OpArgs& a, int bid,
+                                            SpreadShared<SpreadTile<T, DIM, KERN, TX, TY, TZ>>& sm)
 {
     using ST = SpreadTile<T, DIM, KERN, TX, TY, TZ>;
     constexpr int NW = SPREAD_THREADS / 64;  // waves per block
-    __shared__ unsigned long long tile[ST::CELLS];
-    __shared__ typename ST::Table tables[NW];
-    __shared__ int32_t marks[NW][64];
-    __shared__ unsigned long long s_red[NW];
+    unsigned long long* tile = sm.tile;
+    auto& tables = sm.tables;
+    auto& marks = sm.marks;
+    unsigned long long* s_red = sm.s_red;
     const GeomArgs& g = a.g;
     // Blocks bid = tile * split + k: the split blocks of a tile each take every split-th
     // chunk of its points and publish their partial integer sums.  Tiles are numbered with
@@ -535,7 +564,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid)
             bool rn;
             const int total = ST::build(g, a.cstart, q, ox, oy, oz, lenx, nrows, tb, &rp, &rn);
             if (total > 0)
-                ST::spread_slice(a, c, tb, marks[w], rp, rn, nranges, total, q, off, ex, ey, ez,
+                ST::template spread_slice<ROT>(a, c, tb, marks[w], rp, rn, nranges, total, q, off, ex, ey, ez,
                                  fshift, tile, ksub, split);
             wave_sync();
         }
@@ -600,10 +629,19 @@ __global__ __launch_bounds__(256) void split_sum_kernel(OpArgs a, int64_t ncells
     split_sum_body<T, DIM, TX, TY, TZ>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, ncells);
 }
 
+// The plan's count of points in crowded cells (bucket pass) picks the order of adds for
+// the whole launch: rotated when at least 1/CROWD_DIV of the points lie in cells of at least
+// CROWD_CELL points, where it removes most LDS bank conflicts between points of one cell;
+// plain otherwise, where the rotation's extra selects cost more than it saves.
 template <typename T, int DIM, int KERN, int TX, int TY, int TZ>
-__global__ __launch_bounds__(SPREAD_THREADS) void spread_kernel(OpArgs a)
+__global__ __launch_bounds__(SPREAD_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void
+spread_kernel(OpArgs a)
 {
-    spread_body<T, DIM, KERN, TX, TY, TZ>(a, xcd_block(blockIdx.x, gridDim.x));
+    __shared__ SpreadShared<SpreadTile<T, DIM, KERN, TX, TY, TZ>> sm;
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    const bool rot = a.crowd != nullptr && (uint64_t)*a.crowd * CROWD_DIV >= (uint64_t)a.g.npts;
+    if (rot) spread_body<T, DIM, KERN, TX, TY, TZ, true>(a, bid, sm);
+    else spread_body<T, DIM, KERN, TX, TY, TZ, false>(a, bid, sm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1323,9 +1361,10 @@ __global__ __launch_bounds__(SPREAD_THREADS) void batch_spread_kernel(const Batc
 {
     const int32_t* st = bt->starts[BS_SPREAD];
     const int nj = bt->njobs, total = st[nj];
+    __shared__ SpreadShared<SpreadTile<T, DIM, KERN, TX, TY, TZ>> sm;
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job_of(st, nj, vb);
-        spread_body<T, DIM, KERN, TX, TY, TZ>(jobs[j].op, vb - st[j]);
+        spread_body<T, DIM, KERN, TX, TY, TZ, false>(jobs[j].op, vb - st[j], sm);
         __syncthreads();
     }
 }

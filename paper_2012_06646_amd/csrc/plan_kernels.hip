@@ -327,19 +327,33 @@ constexpr int BKT_THREADS = 1024;
 
 // Common case: at most BKT_CELLS cells and BKT_CAP points, all in LDS, four points per
 // thread held in registers throughout.
-// The largest of the threads' cell counts into *s_cmax (LDS, cleared before the block's
-// first barrier): one LDS atomic per wave.
-__device__ __forceinline__ void note_cell_max(uint32_t v, uint32_t* s_cmax)
+// The largest of the threads' cell counts into s_cstat[0] and the sum of their counts of
+// points in cells of at least CROWD_CELL points into s_cstat[1] (LDS, cleared before the
+// block's first barrier): one LDS atomic each per wave.
+__device__ __forceinline__ void note_cell_stats(uint32_t vmax, uint32_t crowd, uint32_t* s_cstat)
 {
-    const int m = wave_max_i32((int)v);  // counts are below 2^30
-    if (lane_id() == 0 && m > 0) atomicMax(s_cmax, (uint32_t)m);
+    const int m = wave_max_i32((int)vmax);  // counts are below 2^30
+    const uint32_t c = wave_last_u32(wave_incl_scan_u32(crowd));  // below n < 2^31
+    if (lane_id() == 0) {
+        if (m > 0) atomicMax(&s_cstat[0], (uint32_t)m);
+        if (c > 0) atomicAdd(&s_cstat[1], c);
+    }
+}
+
+// The block's statistics into the plan's (staggering 0 only; after a barrier).
+__device__ __forceinline__ void publish_cell_stats(const SortArgs& a, const uint32_t* s_cstat)
+{
+    if (threadIdx.x == 0) {
+        if (s_cstat[0] > 0) atomicMax(a.d.cellmax, s_cstat[0]);
+        if (s_cstat[1] > 0) atomicAdd(a.d.crowd, s_cstat[1]);
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t start, int m, int64_t c0,
                                             int nc, bool last, const T* __restrict__ Xb, T* __restrict__ Xs,
                                             int32_t* __restrict__ cstart, uint32_t* hist, int32_t* sidx,
-                                            uint16_t* skey, uint32_t* s_red, uint32_t* s_cmax)
+                                            uint16_t* skey, uint32_t* s_red, uint32_t* s_cstat)
 {
     constexpr int EPT = BKT_CAP / BKT_THREADS;
     constexpr int CPT = BKT_CELLS / BKT_THREADS;
@@ -350,7 +364,7 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
     const int32_t* __restrict__ ka = a.d.kA + (int64_t)s * n + start;
     const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
     for (int i = tid; i <= nc; i += BKT_THREADS) hist[i] = 0u;
-    if (tid == 0) *s_cmax = 0u;
+    if (tid == 0) s_cstat[0] = s_cstat[1] = 0u;
     int32_t key[EPT], idx[EPT];
     int cell[EPT];
     uint32_t slot[EPT];
@@ -374,15 +388,16 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
     for (int k = 0; k < EPT; ++k)
         if (cell[k] >= 0) slot[k] = atomicAdd(&hist[cell[k]], 1u);
     __syncthreads();
-    uint32_t loc[CPT], sum = 0, lmax = 0;
+    uint32_t loc[CPT], sum = 0, lmax = 0, crowd = 0;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
         const int i = tid * CPT + q;
         loc[q] = i < nc ? hist[i] : 0u;
         sum += loc[q];
         lmax = max(lmax, loc[q]);
+        crowd += loc[q] >= CROWD_CELL ? loc[q] : 0u;
     }
-    if (cstart != nullptr) note_cell_max(lmax, s_cmax);
+    if (cstart != nullptr) note_cell_stats(lmax, crowd, s_cstat);
     uint32_t tot;
     uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
 #pragma unroll
@@ -399,7 +414,7 @@ __device__ __forceinline__ void bucket_fast(const SortArgs& a, int s, int64_t st
         if (cstart != nullptr && last) cstart[c0 + nc] = (int32_t)n;
     }
     __syncthreads();
-    if (cstart != nullptr && tid == 0) atomicMax(a.d.cellmax, *s_cmax);
+    if (cstart != nullptr) publish_cell_stats(a, s_cstat);
 #pragma unroll
     for (int k = 0; k < EPT; ++k)
         if (cell[k] >= 0) {
@@ -448,7 +463,7 @@ template <typename T>
 __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t start, int64_t m,
                                                int64_t cbeg, int64_t cend, bool last, const T* __restrict__ Xb,
                                                T* __restrict__ Xs, int32_t* __restrict__ cstart,
-                                               uint32_t* hist, uint32_t* s_red, uint32_t* s_cmax)
+                                               uint32_t* hist, uint32_t* s_red, uint32_t* s_cstat)
 {
     constexpr int CPT = BKT_CELLS / BKT_THREADS;
     const GeomArgs& g = a.g;
@@ -458,8 +473,8 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
     const int32_t* __restrict__ va = a.d.vA + (int64_t)s * n + start;
     int32_t* sorg = a.d.kB + (int64_t)s * n + start;  // bucket position of each sorted slot
     int64_t sub_base = 0;
-    uint32_t lmax = 0;
-    if (threadIdx.x == 0) *s_cmax = 0u;
+    uint32_t lmax = 0, crowd = 0;
+    if (threadIdx.x == 0) s_cstat[0] = s_cstat[1] = 0u;
     for (int64_t c0 = cbeg; c0 < cend; c0 += BKT_CELLS) {
         const int nc = (int)min((int64_t)BKT_CELLS, cend - c0);
         for (int i = threadIdx.x; i < nc; i += BKT_THREADS) hist[i] = 0u;
@@ -477,6 +492,7 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
             loc[k] = i < nc ? hist[i] : 0u;
             sum += loc[k];
             lmax = max(lmax, loc[k]);
+            crowd += loc[k] >= CROWD_CELL ? loc[k] : 0u;
         }
         uint32_t tot;
         uint32_t run = block_excl_scan_u32<BKT_THREADS>(sum, s_red, &tot);
@@ -518,9 +534,9 @@ __device__ __forceinline__ void bucket_general(const SortArgs& a, int s, int64_t
     }
     if (cstart != nullptr && last && threadIdx.x == 0) cstart[cend] = (int32_t)n;
     if (cstart != nullptr) {
-        note_cell_max(lmax, s_cmax);
+        note_cell_stats(lmax, crowd, s_cstat);
         __syncthreads();
-        if (threadIdx.x == 0) atomicMax(a.d.cellmax, *s_cmax);
+        publish_cell_stats(a, s_cstat);
     }
     int32_t* ok = a.d.kB + (int64_t)s * n + start;
     int32_t* ov = a.d.vB + (int64_t)s * n + start;
@@ -543,7 +559,7 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     __shared__ int32_t sidx[BKT_CAP];
     __shared__ uint16_t skey[BKT_CAP];  // cell within the bucket
     __shared__ uint32_t s_red[BKT_THREADS / 64 + 1];
-    __shared__ uint32_t s_cmax;
+    __shared__ uint32_t s_cstat[2];
     static_assert(BKT_CELLS <= 65536, "cells of a bucket fit 16 bits");
     const GeomArgs& g = a.g;
     const int64_t G = (int64_t)g.n[0] * g.n[1] * g.n[2];
@@ -557,9 +573,9 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     const bool last = cend == G;
     if (m >= 1 && m <= BKT_CAP && cend - cbeg <= BKT_CELLS)
         bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red,
-                       &s_cmax);
+                       s_cstat);
     else
-        bucket_general<T>(a, s, start, m, cbeg, cend, last, Xb, Xs, cstart, hist, s_red, &s_cmax);
+        bucket_general<T>(a, s, start, m, cbeg, cend, last, Xb, Xs, cstart, hist, s_red, s_cstat);
 }
 
 template <typename T>

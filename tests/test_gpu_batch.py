@@ -70,6 +70,28 @@ def test_batch_matches_one_by_one_bitwise(ib, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_crowded_job_rotated_adds_match_batch_bitwise(ib, dtype):
+    """Most points in cells of five or more points (2000 cells of 8, 20000 scattered), far
+    above the 1/12 share from which a plan's spreading rotates each lane's order of adds;
+    batches keep the plain order.  The fixed-point sums make the two bitwise equal."""
+    g = wl.grid(3, 48, 1.0)
+    r = wl.rng(4242)
+    h = 1.0 / 48
+    cells = r.integers(0, 48, (2000, 3)) * h
+    X = np.concatenate([np.repeat(cells, 8, axis=0) + r.random((16000, 3)) * h,
+                        r.random((20000, 3))]) % 1.0
+    X = X[r.permutation(X.shape[0])]
+    F = r.standard_normal(X.shape)
+    job = {"grid": g, "X": to_dev(X, dtype), "F": to_dev(F, dtype)}
+    say(f"crowded 48^3 job dtype={dtype}")
+    b = ib.Batch([job], dtype).run()
+    assert b.status() == [0]
+    f_batch = b.results()[0][0]
+    f_plan, _ = one_by_one(ib, job, dtype)
+    assert torch.equal(f_plan, f_batch)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_against_oracle(ib, orc, dtype):
     """Small jobs, a dense job whose spreading tiles are split over several blocks, and a
     job dense enough to interpolate through LDS tiles, against the oracle."""

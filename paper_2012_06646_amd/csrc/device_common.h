@@ -225,6 +225,28 @@ __device__ __forceinline__ void weights_of(T r, T w[4])
     else weights4<T, KERN>(r, w);
 }
 
+// The weights times 2^weight_shift<KERN>(): the Peskin kernel's four weights without their
+// common factor 1/8.  Scaling by a power of two is exact, so a product of scaled weights and
+// a value scaled by the inverse power has the same bits as the product of the weights.
+template <int KERN>
+constexpr int weight_shift() { return KERN == IB_KERNEL_PESKIN4 ? 3 : 0; }
+
+template <typename T, int KERN>
+__device__ __forceinline__ void weights_scaled(T r, T w[4])
+{
+    if constexpr (KERN == IB_KERNEL_PESKIN4) {
+        const T s = weight_sqrt(T(1) + T(4) * r * (T(1) - r));
+        const T a = T(3) - T(2) * r;
+        const T b = T(1) + T(2) * r;
+        w[0] = a - s;
+        w[1] = a + s;
+        w[2] = b + s;
+        w[3] = b - s;
+    } else {
+        weights_of<T, KERN>(r, w);
+    }
+}
+
 // Derivatives d w[k] / d r of the weights of weights_of (r increases with X).
 template <typename T, int KERN>
 __device__ __forceinline__ void dweights_of(T r, T dw[4])

@@ -82,8 +82,9 @@ __device__ __forceinline__ T advect_coord(T x, T u, T dt, T L)
     return y;
 }
 
-// Weights of a point at coordinates x for component c, and the offset of its component-c
-// cell from its staggering-0 cell per dimension.  The cells follow the key rule exactly
+// Weights of a point at coordinates x for component c, times 2^weight_shift<KERN>() each
+// (weights_scaled), and the offset of its component-c cell from its staggering-0 cell per
+// dimension.  The cells follow the key rule exactly
 // (t = x * inv_h rounded once, minus the staggering; then axis_cell).
 template <typename T, int DIM, int KERN>
 __device__ __forceinline__ void comp_weights(const GeomArgs& g, int c, const T x[DIM],
@@ -104,7 +105,7 @@ __device__ __forceinline__ void comp_weights(const GeomArgs& g, int c, const T x
             delta[k] = min(max((int)(fc - axis_cell<T>(y0, odd, &r0)), g.dlo[c][k]), g.dhi[c][k]);
         }
         r += product_residual<T>(x[k], ih, Prec<T>::inv_lo(g, k));
-        weights_of<T, KERN>(r, w[k]);
+        weights_scaled<T, KERN>(r, w[k]);
     }
 }
 
@@ -466,7 +467,8 @@ struct SpreadTile {
             const int cz = (DIM == 3) ? q + delta[DIM - 1] - off[2] : 0;
             const bool has = valid && cx >= 2 - SW && cx <= ex && cy >= 2 - SW && cy <= ey &&
                              (DIM == 2 || (cz >= 2 - SW && cz <= ez));
-            add_point<ROT>(w, ldexp((double)Fc, fshift), has, cx, cy, cz, ey, ez, tile);
+            add_point<ROT>(w, ldexp((double)Fc, fshift - DIM * weight_shift<KERN>()), has, cx, cy,
+                           cz, ey, ez, tile);
         }
     }
 };
@@ -807,7 +809,12 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
     T* __restrict__ Us = (T*)a.Us;
-    const T os = (T)a.out_scale;
+    // The sums use weights_scaled, 2^(3 ws) times the weights' product; the output scale and
+    // the time step of the position update take the inverse power, so U and the positions
+    // have the bits of the unscaled sums.
+    constexpr int WS3 = 3 * weight_shift<KERN>();
+    const T os = (T)ldexp(a.out_scale, -WS3);
+    const T adt = (T)ldexp(a.adv_dt, -WS3);
     const int ncomp = g.ncomp;
     for (int c = 0; c < ncomp; ++c) {
         // Staged region: cells [x0 + dlo - 1, x0 + ex + dhi + SW - 2) per axis, wrapped.
@@ -894,7 +901,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                     T r;
                     const double fy = axis_cell<T>(y, SW == 3, &r);
                     r += product_residual<T>(x[q][k], ih, Prec<T>::inv_lo(g, k));
-                    weights_of<T, KERN>(r, w[k]);
+                    weights_scaled<T, KERN>(r, w[k]);
                     int d = g.dlo[c][k];
                     if (g.dhi[c][k] != d) {
                         const T y0s = shifted_scaled<T>(x[q][k], ih, (T)g.stag_xi[0][k]);
@@ -931,7 +938,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
                     T* __restrict__ Xn = (T*)a.Xnext;
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
-                        const T y = advect_coord(x[q][k], res[k], (T)a.adv_dt, (T)a.adv_len[k]);
+                        const T y = advect_coord(x[q][k], res[k], adt, (T)a.adv_len[k]);
                         Xa[p * 3 + k] = y;
                         if (Xn) Xn[k * n + jj[q]] = y;
                     }

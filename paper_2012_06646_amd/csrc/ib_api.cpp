@@ -157,6 +157,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->bhist = take((size_t)nstag * 3 * BKT_SHARDS * R * sizeof(uint32_t));
     L->counters = take((size_t)nstag * PLAN_COUNTERS * sizeof(uint32_t));
     L->flag = take(sizeof(uint32_t));
+    L->bad = take(sizeof(uint32_t));
     L->cellmax = take(sizeof(uint32_t));
     L->crowd = take(sizeof(uint32_t));
     L->zero_end = off;
@@ -270,6 +271,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     d.seg_status = (uint32_t*)(base + L.seg_status);
     d.counters = (uint32_t*)(base + L.counters);
     d.flag = (uint32_t*)(base + L.flag);
+    d.bad = (uint32_t*)(base + L.bad);
     d.cellmax = (uint32_t*)(base + L.cellmax);
     d.crowd = (uint32_t*)(base + L.crowd);
     d.zero_begin = (uint32_t*)(base + L.zero_begin);
@@ -343,12 +345,24 @@ int32_t ib_plan_stagger_of(ib_plan p, int32_t comp)
     return p->sa.g.comp_stag[comp];
 }
 
+// The per-update region (bucket histograms, cursors, look-back words, tickets, flags) is
+// cleared by a kernel before a plan's first update; afterwards each sort's bases pass clears
+// what the next sort of its staggering counts into.  Without points there is no bases pass,
+// so such plans clear at every update.
+static hipError_t clear_once(ib_plan p, hipStream_t st)
+{
+    if (p->cleared && p->npts > 0) return hipSuccess;
+    const hipError_t e = launch_plan_reset(p->sa, st);
+    if (e == hipSuccess) p->cleared = 1;
+    return e;
+}
+
 int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
 {
     if (!p) return IB_ERR_ARG;
     if (!X && p->npts > 0) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_plan_reset(p->sa, st);
+    hipError_t e = clear_once(p, st);
     // The operators use the keys and sort of staggering 0, its cell-start table and the
     // positions in that order; other staggerings are sorted when exported.
     if (e == hipSuccess) e = launch_sort_stagger(p->sa, 0, p->dtype, X, nullptr, true, st);
@@ -369,7 +383,7 @@ int32_t ib_plan_update_advected(ib_plan p, void* stream)
     if (!p || !p->updated || !p->xn_valid) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     // The advanced positions, in the previous sorted order, with that order's point indices.
-    hipError_t e = launch_plan_reset(p->sa, st);
+    hipError_t e = clear_once(p, st);
     if (e == hipSuccess)
         e = launch_sort_stagger(p->sa, 0, p->dtype, p->sa.d.Xn, p->perm, true, st);
     int32_t r = hip_status(e);

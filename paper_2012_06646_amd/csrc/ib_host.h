@@ -24,6 +24,8 @@ struct ib_plan_s {
     int xn_valid;          // Xn holds the positions of the last ib_interpolate_advect
     uint32_t sorted_mask;  // staggerings sorted since the last update
     uint32_t runs_mask;    // staggerings whose run offsets were computed since the update
+    int cleared;           // the per-update region was cleared once (later updates clear it
+                           // through the bases pass)
 };
 
 namespace ibk {
@@ -38,7 +40,7 @@ struct Layout {
     int64_t ntiles, nseg_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t kin, kA, vA, kB, vB, bhist, cstart, seg_off, q, Xs, Xb, Xn, Us, partial, tile_shift, fmax,
-        zero_begin, seg_status, counters, flag, cellmax, crowd, zero_end, gpad, total;
+        zero_begin, seg_status, counters, flag, bad, cellmax, crowd, zero_end, gpad, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

@@ -53,7 +53,13 @@ __device__ __forceinline__ uint32_t* stag_hist(const SortArgs& a, int s)
 
 // Shard starts of staggering s: base[x][d] = (points of buckets below d) + (points of bucket
 // d in shards below x).  One block of BKT_THREADS threads; bucket d's shards by thread d.
-__device__ __forceinline__ void bases_body(const SortArgs& a, int s)
+//
+// The block also clears what this staggering's next passes count into, so that a plan
+// needs the reset kernel only once (before its first update): the histogram just read, the
+// scatter's fill cursors, the look-back words and tickets of its runs.  The keys pass marks
+// bad points in d.bad, which moves into the error flag here; an update (fresh) starts the
+// flag and the bucket pass's cell statistics afresh, an export adds to them.
+__device__ __forceinline__ void bases_body(const SortArgs& a, int s, bool fresh)
 {
     __shared__ uint32_t s_red[1024 / 64 + 1];
     const int R = 1 << a.rb;
@@ -75,11 +81,27 @@ __device__ __forceinline__ void bases_body(const SortArgs& a, int s)
             run += part[x];
         }
     }
+    // every histogram word was read before the scan's barriers
+    uint32_t* clear = const_cast<uint32_t*>(hist);
+    for (int i = threadIdx.x; i < 2 * BKT_SHARDS * R; i += blockDim.x) clear[i] = 0u;
+    for (int64_t i = threadIdx.x; i < a.nseg_tiles; i += blockDim.x) a.d.seg_status[(int64_t)s * a.nseg_tiles + i] = 0u;
+    if (threadIdx.x < PLAN_COUNTERS) a.d.counters[s * PLAN_COUNTERS + threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
+        const uint32_t bad = *a.d.bad ? FLAG_BAD_POINT : 0u;
+        *a.d.bad = 0u;
+        if (fresh) {
+            *a.d.flag = bad;
+            *a.d.cellmax = 0u;
+            *a.d.crowd = 0u;
+        } else if (bad) {
+            *a.d.flag |= bad;
+        }
+    }
 }
 
-__global__ __launch_bounds__(1024) void bases_kernel(SortArgs a, int s)
+__global__ __launch_bounds__(1024) void bases_kernel(SortArgs a, int s, int fresh)
 {
-    bases_body(a, s);
+    bases_body(a, s, fresh != 0);
 }
 
 // ---- keys: one per point, and the bucket histogram ----------------------------------
@@ -135,7 +157,7 @@ __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict
             any_bad |= bad;
         }
     }
-    if (any_bad) atomicOr(a.d.flag, FLAG_BAD_POINT);
+    if (any_bad) atomicOr(a.d.bad, 1u);
     __syncthreads();
     uint32_t* hist = stag_hist(a, s) + (tile % BKT_SHARDS) * R;
     for (int d = threadIdx.x; d < R; d += blockDim.x)
@@ -716,7 +738,7 @@ __global__ __launch_bounds__(1024) void batch_bases_kernel(const BatchJob* __res
     const int32_t* st = bt->starts[BS_BASES];
     const int nj = bt->njobs, total = st[nj];
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        bases_body(jobs[batch_job(st, nj, vb)].sa, 0);
+        bases_body(jobs[batch_job(st, nj, vb)].sa, 0, true);
         __syncthreads();
     }
 }
@@ -816,13 +838,13 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
         if (dtype == IB_F64) {
             hipLaunchKernelGGL(keys_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
                                (const double*)X, soa, s);
-            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s);
+            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s, outputs0 ? 1 : 0);
             hipLaunchKernelGGL(radix_scatter_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
                                a, s, (const double*)X, soa, psrc, (double*)Xb);
         } else {
             hipLaunchKernelGGL(keys_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
                                (const float*)X, soa, s);
-            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s);
+            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s, outputs0 ? 1 : 0);
             hipLaunchKernelGGL(radix_scatter_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
                                a, s, (const float*)X, soa, psrc, (float*)Xb);
         }

@@ -269,6 +269,35 @@ def test_dyadic_case_is_bit_exact(ib, orc, dtype):
     assert np.array_equal(U, orc.interp(g, X, u))
 
 
+def test_plan_flags_bad_points_per_update(ib):
+    """A position that is not finite sets the plan's device flag (status IB_ERR_DEVICE_FLAG,
+    read and cleared by the status call); an update with good positions starts clean, also
+    when the flag of an earlier update was never read; sorting another staggering at export
+    adds its own bad points to the flag."""
+    g = wl.grid(3, 16, 1.0)
+    X0, _, _ = wl.uniform_case(g, 3000, 4500)
+    Xbad = X0.copy()
+    Xbad[11, 2] = np.nan
+    good, bad = to_dev(X0, torch.float64), to_dev(Xbad, torch.float64)
+    p = ib.Plan(g, X0.shape[0], torch.float64)
+    for _ in range(2):
+        p.update(bad)
+        assert p.status() == -6
+        assert p.status() == 0
+        p.update(good)
+        assert p.status() == 0
+    p.update(bad)
+    p.update(good)
+    assert p.status() == 0
+    p.update(good)
+    p.export(1)
+    assert p.status() == 0
+    p.update(bad)
+    assert p.status() == -6
+    p.export(1)  # staggering 1 sorted from the same positions: flagged again
+    assert p.status() == -6
+
+
 def test_spread_accumulate_flag(ib, orc):
     g = wl.grid(3, [16, 12, 20], 1.0)
     X, F, u = wl.uniform_case(g, 5000, 27)

@@ -224,27 +224,30 @@ __global__ __launch_bounds__(FMAX_THREADS) void fmax_kernel(OpArgs a)
     fmax_body<T>(a, blockIdx.x);
 }
 
-// Maximum of the FMAX_PARTS partial maxima of component c, uniform over the block.
-template <int NT>
+// Maximum of the FMAX_PARTS partial maxima of component c, uniform over the block: the
+// first wave reads them all at once (FMAX_PARTS / 64 per lane) and reduces across its
+// lanes; one barrier publishes the result (and whatever the block wrote to LDS before it).
 __device__ __forceinline__ unsigned long long fmax_of(const unsigned long long* __restrict__ part,
                                                       int c, unsigned long long* s_red)
 {
-    unsigned long long m = 0ull;
-    for (int i = threadIdx.x; i < FMAX_PARTS; i += NT) {
-        const unsigned long long v = part[c * FMAX_PARTS + i];
-        m = v > m ? v : m;
-    }
+    static_assert(FMAX_PARTS % 64 == 0, "whole partial maxima per lane");
+    if (wave_id() == 0) {
+        constexpr int PER = FMAX_PARTS / 64;
+        unsigned long long v[PER];
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        const unsigned long long o = __shfl_xor(m, s, 64);
-        m = o > m ? o : m;
+        for (int i = 0; i < PER; ++i) v[i] = part[c * FMAX_PARTS + i * 64 + lane_id()];
+        unsigned long long m = 0ull;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) m = v[i] > m ? v[i] : m;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            const unsigned long long o = __shfl_xor(m, s, 64);
+            m = o > m ? o : m;
+        }
+        if (lane_id() == 0) s_red[0] = m;
     }
-    if (lane_id() == 0) s_red[wave_id()] = m;
     __syncthreads();
-    unsigned long long r = 0ull;
-    for (int w = 0; w < NT / 64; ++w) r = s_red[w] > r ? s_red[w] : r;
-    __syncthreads();
-    return r;
+    return s_red[0];
 }
 
 // A source slice (an x-y plane of staggering-0 cells in 3-D, one x-row in 2-D) as a list
@@ -552,7 +555,7 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid,
     // (SW + hx)(SW + hy)(SW + hz) staggering-0 cells (3-D), each with at most cellmax points.
     // With the maximum force of component c it sets the tile's scale (every split block of
     // the tile finds the same).
-    const unsigned long long vmax = fmax_of<SPREAD_THREADS>(a.fmax, c, s_red);  // has barriers
+    const unsigned long long vmax = fmax_of(a.fmax, c, s_red);  // has a barrier
     const uint64_t win = (uint64_t)(SW + hx) * (SW + hy) * ((DIM == 3) ? SW + hz : 1);
     const uint32_t mbound = (uint32_t)min(win * (uint64_t)*a.cellmax, (uint64_t)0xFFFFFFFFu);
     const bool finite = vmax < FX_NONFINITE;

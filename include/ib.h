@@ -122,7 +122,9 @@ const char *ib_status_string(int32_t status);
 size_t ib_plan_workspace_bytes(const ib_grid_desc *grid, int32_t dtype, int64_t npts);
 
 /* Create a plan.  `workspace` is caller-owned device memory of at least
- * ib_plan_workspace_bytes() bytes (256-byte aligned), kept alive until ib_plan_destroy.
+ * ib_plan_workspace_bytes() bytes (256-byte aligned), kept alive and left untouched by the
+ * caller until ib_plan_destroy: it holds the plan's state between calls (its first update
+ * clears the counters there; later updates find them cleared by the previous sort).
  * The library never allocates device memory.  The host-side plan object is freed by
  * ib_plan_destroy.  Errors: IB_ERR_ARG, IB_ERR_UNSUPPORTED, IB_ERR_OOM, IB_ERR_HIP. */
 int32_t ib_plan_create(const ib_grid_desc *grid, int32_t dtype, int64_t npts,

@@ -151,7 +151,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
                                    : 0);
     L->tile_shift = take(L->split > 1 ? (size_t)L->sp_tiles * sizeof(int32_t) : 0);
     L->fmax = take((size_t)3 * FMAX_PARTS * sizeof(unsigned long long));
-    // Everything from here to zero_end is cleared at every update.
+    // Everything from here to zero_end starts each update cleared (clear_once, bases pass).
     L->zero_begin = off;
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
     L->bhist = take((size_t)nstag * 3 * BKT_SHARDS * R * sizeof(uint32_t));

@@ -61,7 +61,7 @@ struct PlanDev {
     unsigned long long* fmax;  // [3][FMAX_PARTS] partial maxima of |F| per component
     uint32_t* cellmax;     // most points in any staggering-0 cell (bucket pass; zero region)
     uint32_t* crowd;       // points in staggering-0 cells of at least CROWD_CELL points (likewise)
-    uint32_t* zero_begin;  // region cleared at each update
+    uint32_t* zero_begin;  // per-update region: cleared before the first update, then by the sorts
     size_t zero_words;
 };
 

@@ -29,7 +29,7 @@
 
 namespace ibk {
 
-// ---- reset: clear look-back words, tickets and the error flag -------------------------
+// ---- reset: clear the per-update region (before a plan's first update) -----------------
 __device__ __forceinline__ void plan_reset_body(uint32_t* __restrict__ p, size_t nwords, int bid, int nblk)
 {
     for (size_t i = (size_t)bid * blockDim.x + threadIdx.x; i < nwords; i += (size_t)nblk * blockDim.x)

@@ -164,7 +164,7 @@ __device__ __forceinline__ int fx_shift(unsigned long long vmax_bits, uint32_t n
 // belongs to component le mod NC.
 constexpr int SPREAD_THREADS = 512;
 constexpr int FMAX_THREADS = 256;
-constexpr int FMAX_BATCH = 4;  // rows per thread per pass
+constexpr int FMAX_BATCH = 2;  // rows per thread per pass (measured 1.5 us faster than 4 at 10^6 rows)
 
 template <typename T, int NC>
 __device__ __forceinline__ void fmax_rows(const T* __restrict__ F, int64_t n, int bid,

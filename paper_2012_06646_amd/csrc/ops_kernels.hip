@@ -834,7 +834,7 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
         {
             // Thread tid stages x-column tid % lx of rows tid / lx, tid / lx + rstep, ...; SU
             // rows per round are loaded before any is stored, so their loads overlap.
-            constexpr int SU = 8;
+            constexpr int SU = 12;
             const int rstep = 256 / lx;
             const int xi = tid % lx;
             const int r = tid / lx;

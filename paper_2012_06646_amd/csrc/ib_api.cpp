@@ -65,29 +65,31 @@ int32_t check_grid(const ib_grid_desc* g, int32_t dtype, int64_t npts, int* nsta
     return IB_OK;
 }
 
-int32_t check_tuning(const ib_tuning* t)
+int32_t check_tuning(const ib_tuning* t, int32_t dtype)
 {
     if (!t) return IB_OK;
     if (t->spread_tile < 0 || t->spread_tile > SPREAD_TILE_SHAPES) return IB_ERR_ARG;
-    if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > MAX_BUCKET_BITS)) return IB_ERR_ARG;
+    if (t->radix_bits != 0 && (t->radix_bits < 4 || t->radix_bits > max_bucket_bits(dtype))) return IB_ERR_ARG;
     return IB_OK;
 }
 
 // Bucket digit bits of a plan: enough buckets that each spans at most BKT_CELLS cells (up
-// to 2^MAX_BUCKET_BITS buckets), and about one bucket per 2048 points, so that a bucket's
-// points usually fit its block's LDS; a tuning may ask for a width of its own.
-int bucket_bits(int64_t G, int64_t n, int tuned)
+// to 2^max_bucket_bits(dtype) buckets), and about one bucket per 2048 points up to 2^10
+// buckets, so that a bucket's points usually fit its block's LDS; a tuning may ask for a
+// width of its own.
+int bucket_bits(int64_t G, int64_t n, int tuned, int32_t dtype)
 {
     const int bits = bits_for(G);
+    const int cap = max_bucket_bits(dtype);
     int rb;
     if (tuned > 0) {
         rb = tuned;
     } else {
         int want = 0;
-        while (want < MAX_BUCKET_BITS && (int64_t(2048) << want) < n) ++want;
+        while (want < 10 && (int64_t(2048) << want) < n) ++want;
         rb = std::max(bits - 13, want);  // 2^13 = BKT_CELLS
     }
-    rb = std::min(rb, MAX_BUCKET_BITS);
+    rb = std::min(rb, cap);
     return std::max(0, std::min(rb, bits));
 }
 
@@ -112,7 +114,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->G = 1;
     for (int k = 0; k < g->dim; ++k) L->G *= g->n[k];
     L->rows = (int)(L->G / g->n[0]);
-    L->rb = bucket_bits(L->G, n, tuning ? tuning->radix_bits : 0);
+    L->rb = bucket_bits(L->G, n, tuning ? tuning->radix_bits : 0, dtype);
     L->cb = bits_for(L->G) - L->rb;
     L->ntiles = (n + SORT_TILE - 1) / SORT_TILE;
     L->nseg_tiles = n > 0 ? (n + SORT_TILE - 1) / SORT_TILE : 1;
@@ -307,7 +309,7 @@ size_t ib_plan_workspace_bytes_tuned(const ib_grid_desc* grid, int32_t dtype, in
     int nstag, cs[3];
     double sx[3][3];
     if (check_grid(grid, dtype, npts, &nstag, cs, sx) != IB_OK) return 0;
-    if (check_tuning(tuning) != IB_OK) return 0;
+    if (check_tuning(tuning, dtype) != IB_OK) return 0;
     Layout L;
     make_layout(grid, dtype, nstag, npts, &L, tuning);
     return L.total;
@@ -323,7 +325,7 @@ int32_t ib_plan_create_tuned(const ib_grid_desc* grid, int32_t dtype, int64_t np
     double sx[3][3] = {{0}};
     int32_t st = check_grid(grid, dtype, npts, &nstag, cs, sx);
     if (st != IB_OK) return st;
-    st = check_tuning(tuning);
+    st = check_tuning(tuning, dtype);
     if (st != IB_OK) return st;
     Layout L;
     make_layout(grid, dtype, nstag, npts, &L, tuning);

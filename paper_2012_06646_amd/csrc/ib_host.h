@@ -56,7 +56,7 @@ void make_layout(const ib_grid_desc* g, int32_t dtype, int nstag, int64_t n, Lay
 // added along every walled dimension (same spacing), walls cleared.
 ib_grid_desc kernel_grid(const ib_grid_desc& g);
 // IB_OK if every field of a (possibly null) tuning is in range.
-int32_t check_tuning(const ib_tuning* t);
+int32_t check_tuning(const ib_tuning* t, int32_t dtype);
 
 // Fill a plan object for a validated (caller's) descriptor over a workspace of layout L.
 // The kernels run on kernel_grid(*grid); keys and weights use the caller's spacing.

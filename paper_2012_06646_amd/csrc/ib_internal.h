@@ -17,9 +17,11 @@ constexpr int SORT_TILE = SORT_BLOCK * SORT_IPT;
 // Bucket pass: the top rb key bits (rb <= MAX_BUCKET_BITS) choose the bucket of 2^cb cells.
 // A bucket block counts BKT_CELLS cells at a time in LDS and stages up to BKT_CAP points
 // there (more go through global memory).
-constexpr int MAX_BUCKET_BITS = 10;
-static_assert((1 << MAX_BUCKET_BITS) % SORT_BLOCK == 0,
-              "the scatter's LDS scan gives every thread the same number of buckets");
+// FP32 sorts may use 2^11 buckets: at 256^3 cells a bucket of 2^10 would span more cells
+// than a block counts in LDS at once.  FP64 keeps 2^10, so that the scatter's LDS (which
+// carries the positions) still lets two blocks share a CU.
+constexpr int MAX_BUCKET_BITS = 11;
+constexpr int max_bucket_bits(int dtype) { return dtype == IB_F64 ? 10 : 11; }
 constexpr int BKT_CELLS = 8192;
 constexpr int BKT_CAP = 4096;
 constexpr int BKT_SHARDS = 16;   // shards of the bucket histogram and fill cursors

@@ -52,7 +52,8 @@ __device__ __forceinline__ uint32_t* stag_hist(const SortArgs& a, int s)
 }
 
 // Shard starts of staggering s: base[x][d] = (points of buckets below d) + (points of bucket
-// d in shards below x).  One block of BKT_THREADS threads; bucket d's shards by thread d.
+// d in shards below x).  One block of 1024 threads; bucket d (all its shards) by thread
+// d mod 1024, in rounds of 1024 buckets.
 //
 // The block also clears what this staggering's next passes count into, so that a plan
 // needs the reset kernel only once (before its first update): the histogram just read, the
@@ -65,21 +66,25 @@ __device__ __forceinline__ void bases_body(const SortArgs& a, int s, bool fresh)
     const int R = 1 << a.rb;
     const uint32_t* hist = stag_hist(a, s);
     uint32_t* base = const_cast<uint32_t*>(hist) + 2 * BKT_SHARDS * R;
-    const int d = threadIdx.x;
-    uint32_t part[BKT_SHARDS], tot = 0;
-#pragma unroll
-    for (int x = 0; x < BKT_SHARDS; ++x) {
-        part[x] = d < R ? hist[x * R + d] : 0u;
-        tot += part[x];
-    }
-    uint32_t all;
-    uint32_t run = block_excl_scan_u32<1024>(tot, s_red, &all);
-    if (d < R) {
+    uint32_t carry = 0;  // points of the buckets of earlier rounds
+    for (int d0 = 0; d0 < R; d0 += 1024) {  // rounds of 1024 buckets, bucket d0 + t by thread t
+        const int d = d0 + threadIdx.x;
+        uint32_t part[BKT_SHARDS], tot = 0;
 #pragma unroll
         for (int x = 0; x < BKT_SHARDS; ++x) {
-            base[x * R + d] = run;
-            run += part[x];
+            part[x] = d < R ? hist[x * R + d] : 0u;
+            tot += part[x];
         }
+        uint32_t all;
+        uint32_t run = carry + block_excl_scan_u32<1024>(tot, s_red, &all);
+        if (d < R) {
+#pragma unroll
+            for (int x = 0; x < BKT_SHARDS; ++x) {
+                base[x * R + d] = run;
+                run += part[x];
+            }
+        }
+        carry += all;
     }
     // every histogram word was read before the scan's barriers
     uint32_t* clear = const_cast<uint32_t*>(hist);
@@ -112,7 +117,7 @@ template <typename T>
 __device__ __forceinline__ void keys_body(const SortArgs& a, const T* __restrict__ X, bool soa, int s,
                                           int tile)
 {
-    __shared__ uint32_t lh[1 << MAX_BUCKET_BITS];
+    __shared__ uint32_t lh[1 << max_bucket_bits(sizeof(T) == 8 ? IB_F64 : IB_F32)];
     const GeomArgs& g = a.g;
     const int R = 1 << a.rb;
     for (int i = threadIdx.x; i < R; i += blockDim.x) lh[i] = 0u;
@@ -231,7 +236,7 @@ template <typename T>
 __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t, const T* __restrict__ X,
                                              bool soa, const int32_t* __restrict__ psrc, T* __restrict__ Xb)
 {
-    constexpr int R_MAX = 1 << MAX_BUCKET_BITS;
+    constexpr int R_MAX = 1 << max_bucket_bits(sizeof(T) == 8 ? IB_F64 : IB_F32);
     __shared__ int32_t s_key[SORT_TILE];
     __shared__ int32_t s_val[SORT_TILE];
     __shared__ T s_row[SORT_TILE * 3];
@@ -279,25 +284,19 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
     for (int k = 0; k < SORT_IPT; ++k)
         if (k * SORT_BLOCK + tid < nvalid) slot[k] = atomicAdd(&s_cnt[(uint32_t)key[k] >> cb], 1u);
     __syncthreads();
-    // the tile's start of each bucket in LDS (scan of the counts) and its reserved range
-    constexpr int DPT = R_MAX / SORT_BLOCK;  // buckets per thread, consecutive
-    uint32_t c[DPT], sum = 0;
-#pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-        const int d = tid * DPT + q;
-        c[q] = d < R ? s_cnt[d] : 0u;
-        sum += c[q];
-    }
-    uint32_t tot;
-    uint32_t run = block_excl_scan_u32<SORT_BLOCK>(sum, s_red, &tot);
-#pragma unroll
-    for (int q = 0; q < DPT; ++q) {
-        const int d = tid * DPT + q;
+    // the tile's start of each bucket in LDS (scan of the counts) and its reserved range, in
+    // rounds of SORT_BLOCK buckets (bucket d0 + t by thread t)
+    uint32_t carry = 0;
+    for (int d0 = 0; d0 < R; d0 += SORT_BLOCK) {
+        const int d = d0 + tid;
+        const uint32_t c = d < R ? s_cnt[d] : 0u;
+        uint32_t tot;
+        const uint32_t run = carry + block_excl_scan_u32<SORT_BLOCK>(c, s_red, &tot);
         if (d < R) {
             s_tstart[d] = run;
-            s_gbase[d] = (c[q] ? atomicAdd(&cur[d], c[q]) : 0u) + sbase[d];
+            s_gbase[d] = (c ? atomicAdd(&cur[d], c) : 0u) + sbase[d];
         }
-        run += c[q];
+        carry += tot;
     }
     __syncthreads();
 #pragma unroll

@@ -123,6 +123,9 @@ def test_tuned_workspace_and_validation(ib):
     assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 1, 10**6, ctypes.byref(T(3, 0, 0))) == base32
     for shape in (1, 2, 3):
         assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 10**6, ctypes.byref(T(shape, 0, 0))) > 0
+    # 2^11 buckets for FP32 plans only (FP64 sorts keep their positions in the scatter's LDS)
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 1, 10**6, ctypes.byref(T(0, 0, 11))) > 0
+    assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 1, 10**6, ctypes.byref(T(0, 0, 12))) == 0
     for bad in (T(4, 0, 0), T(-1, 0, 0), T(0, 0, 3), T(0, 0, 11)):
         assert ib._lib.ib_plan_workspace_bytes_tuned(ctypes.byref(g), 0, 1000, ctypes.byref(bad)) == 0
         h = ctypes.c_void_p()

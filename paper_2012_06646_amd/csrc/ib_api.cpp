@@ -469,10 +469,24 @@ static void fill_op_args(ib_plan p, OpArgs* a)
     a->out_scale = 1.0;
 }
 
-// The caller's grid field u, or (walled plans) its copy padded with zero ghost values.
-static const void* kernel_field(ib_plan p, const void* u, hipStream_t st, hipError_t* e)
+// Walled plans: kernels that can address the caller's unpadded field do so (direct).
+static void set_direct(ib_plan p, OpArgs* a)
+{
+    if (!p->user.walls) return;
+    a->direct = 1;
+    for (int k = 0; k < 3; ++k) a->user_n[k] = k < p->user.dim ? p->user.n[k] : 1;
+}
+
+// The caller's grid field u, or (walled plans) its copy padded with zero ghost values --
+// except for a tiled interpolation (tiled), whose tiles stage from u directly.
+static const void* kernel_field(ib_plan p, OpArgs* a, const void* u, bool tiled, hipStream_t st,
+                                hipError_t* e)
 {
     if (!p->user.walls) return u;
+    if (tiled && interp_tiles(a->g.dim, a->g.n, a->g.npts) > 0) {
+        set_direct(p, a);
+        return u;
+    }
     *e = launch_pad(p->user, p->grid, p->dtype, u, p->gpad, st);
     return p->gpad;
 }
@@ -486,14 +500,12 @@ int32_t ib_spread_scaled(ib_plan p, const void* F, void* f, double scale, int32_
     fill_op_args(p, &a);
     a.g.scale *= scale;  // one factor applied to the exact sums: (prod_k h_k)^-1 * scale
     a.F = F;
-    a.f = p->user.walls ? p->gpad : f;  // walled: spread onto the padded grid, then drop ghosts
-    a.accumulate = !p->user.walls && accumulate != 0;
+    a.f = f;
+    a.accumulate = accumulate != 0;
+    set_direct(p, &a);  // walled: the padded grid's tiles write the caller's cells, ghosts dropped
     hipStream_t st = (hipStream_t)stream;
     p->last_stream = st;
-    hipError_t e = launch_spread(a, p->dtype, p->grid.kernel, st);
-    if (e == hipSuccess && p->user.walls)
-        e = launch_unpad(p->user, p->grid, p->dtype, p->gpad, f, accumulate != 0, st);
-    return hip_status(e);
+    return hip_status(launch_spread(a, p->dtype, p->grid.kernel, st));
 }
 
 int32_t ib_spread(ib_plan p, const void* F, void* f, int32_t accumulate, void* stream)
@@ -511,7 +523,7 @@ int32_t ib_interpolate_scaled(ib_plan p, const void* u, void* U, double scale, v
     a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, u, st, &e);
+    a.u = kernel_field(p, &a, u, true, st, &e);
     a.U = U;
     p->last_stream = st;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
@@ -533,7 +545,7 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     fill_op_args(p, &a);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, u, st, &e);
+    a.u = kernel_field(p, &a, u, true, st, &e);
     a.U = U;
     p->xn_valid = 0;
     if (!p->user.walls) {  // walled: interpolation, then the update without wrap along walls
@@ -564,7 +576,7 @@ int32_t ib_interpolate_grad_scaled(ib_plan p, const void* u, const void* W, void
     a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, u, st, &e);
+    a.u = kernel_field(p, &a, u, false, st, &e);
     p->last_stream = st;
     if (e == hipSuccess)
         e = launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st);

@@ -97,6 +97,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         a.fmax = p.sa.d.fmax;
         a.cellmax = p.sa.d.cellmax;
         a.crowd = nullptr;  // batches keep one order of adds
+        a.direct = 0;       // and run periodic jobs only
         a.f = J.f;
         a.u = J.u;
         a.U = J.U;

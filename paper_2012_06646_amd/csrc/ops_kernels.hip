@@ -589,11 +589,15 @@ __device__ __forceinline__ void spread_body(const OpArgs& a, int bid,
         return;
     }
     T* f = (T*)a.f;
-    const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
+    // the output grid: the plan's own, or the caller's unpadded one (ghost cells dropped)
+    const int on0 = a.direct ? a.user_n[0] : g.n[0], on1 = a.direct ? a.user_n[1] : g.n[1];
+    const int on2 = (DIM == 3) ? (a.direct ? a.user_n[2] : g.n[2]) : 1;
+    const int64_t G = (int64_t)on0 * on1 * on2;
     for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
         const int xr = i % TX, yr = (i / TX) % TY, zr = i / (TX * TY);
         if (xr >= ex || yr >= ey || zr >= ez) continue;
-        const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
+        if (x0 + xr >= on0 || y0 + yr >= on1 || z0 + zr >= on2) continue;
+        const int64_t gi = ((int64_t)(z0 + zr) * on1 + (y0 + yr)) * on0 + (x0 + xr);
         const T v = fx_value<T>(tile[(zr * TY + yr) * ST::PXS + xr + 3], fshift, finite, g.scale);
         T* dst = f + (int64_t)c * G + gi;
         *dst = a.accumulate ? *dst + v : v;
@@ -621,8 +625,11 @@ __device__ __forceinline__ void split_sum_body(const OpArgs& a, int64_t i, int64
     unsigned long long sum = 0ull;
     for (int kk = 0; kk < split; ++kk) sum += (unsigned long long)part[(int64_t)kk * CELLS];
     const int fshift = a.tile_shift[tile_id];
-    const int64_t G = (int64_t)g.n[0] * g.n[1] * (DIM == 3 ? g.n[2] : 1);
-    const int64_t gi = ((int64_t)(z0 + zr) * g.n[1] + (y0 + yr)) * g.n[0] + (x0 + xr);
+    const int on0 = a.direct ? a.user_n[0] : g.n[0], on1 = a.direct ? a.user_n[1] : g.n[1];
+    const int on2 = (DIM == 3) ? (a.direct ? a.user_n[2] : g.n[2]) : 1;
+    if (x0 + xr >= on0 || y0 + yr >= on1 || z0 + zr >= on2) return;  // a ghost cell
+    const int64_t G = (int64_t)on0 * on1 * on2;
+    const int64_t gi = ((int64_t)(z0 + zr) * on1 + (y0 + yr)) * on0 + (x0 + xr);
     const T v = fx_value<T>(sum, fshift == INT32_MIN ? 0 : fshift, fshift != INT32_MIN, g.scale);
     T* dst = (T*)a.f + (int64_t)c * G + gi;
     *dst = a.accumulate ? *dst + v : v;
@@ -777,7 +784,6 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     __shared__ uint32_t s_scan[256 / 64 + 1];
     const GeomArgs& g = a.g;
     const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
-    const int64_t G = (int64_t)n0 * n1 * n2;
     const int64_t n = g.npts;
     const int tid = threadIdx.x;
     const int nt[3] = {(n0 + TX - 1) / TX, (n1 + TY - 1) / TY, (n2 + TZ - 1) / TZ};
@@ -812,6 +818,10 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
     const T* __restrict__ u = (const T*)a.u;
     T* __restrict__ U = (T*)a.U;
     T* __restrict__ Us = (T*)a.Us;
+    // the grid read: the plan's own, or the caller's unpadded field (direct)
+    const int un0 = a.direct ? a.user_n[0] : n0, un1 = a.direct ? a.user_n[1] : n1;
+    const int un2 = a.direct ? a.user_n[2] : n2;
+    const int64_t Gu = (int64_t)un0 * un1 * un2;
     // The sums use weights_scaled, 2^(3 ws) times the weights' product; the output scale and
     // the time step of the position update take the inverse power, so U and the positions
     // have the bits of the unscaled sums.
@@ -828,7 +838,10 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
         const int nr = ly * lz;
         if (tid < nr) {  // one thread per staged row (nr <= RY * RZ <= 256)
             const int iz = tid / ly, iy = tid - iz * ly;
-            s_rowoff[tid] = (wrap_small(rz + iz, n2) * n1 + wrap_small(ry + iy, n1)) * n0;
+            const int wz = wrap_small(rz + iz, n2), wy = wrap_small(ry + iy, n1);
+            // the caller's unpadded field: ghost rows (-1) read as zero
+            s_rowoff[tid] = !a.direct ? (wz * n1 + wy) * n0
+                          : (wz < un2 && wy < un1) ? (wz * un1 + wy) * un0 : -1;
         }
         __syncthreads();  // the previous component's points are done with su
         {
@@ -840,14 +853,16 @@ __device__ __forceinline__ void interp_tile_body(const OpArgs& a, int bid)
             const int r = tid / lx;
             if (r < rstep) {
                 const int gx = wrap_small(rx + xi, n0);
-                const T* __restrict__ uc = u + (int64_t)c * G;
+                const bool xin = gx < un0;  // not a ghost column of the caller's field
+                const T* __restrict__ uc = u + (int64_t)c * Gu;
                 for (int r0 = r; r0 < nr; r0 += SU * rstep) {
                     T val[SU];
 #pragma unroll
                     for (int q = 0; q < SU; ++q) {
                         const int rr = r0 + q * rstep;
                         val[q] = T(0);
-                        if (rr < nr) val[q] = uc[(int64_t)s_rowoff[rr] + gx];
+                        const int ro = rr < nr ? s_rowoff[rr] : -1;
+                        if (ro >= 0 && xin) val[q] = uc[(int64_t)ro + gx];
                     }
 #pragma unroll
                     for (int q = 0; q < SU; ++q) {
@@ -1115,9 +1130,11 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
 // ---------------------------------------------------------------------------------------
 // Walled plans run on a periodic grid with ghost indices n_k .. m_k - 1 added along walled
 // dimensions (m_k = n_k elsewhere).  The caller's field (n) sits at the same indices of the
-// padded field (m): pad copies it in with zero ghost values (ghost points are no grid
-// points, so interpolation reads nothing there), unpad copies the interior back out and
-// drops the ghost values that spreading wrote.
+// padded field (m).  Spreading writes the caller's cells straight from its tiles and drops
+// the ghost values; tiled interpolation stages the caller's cells and zero for ghosts
+// (OpArgs::direct).  The other interpolation kernels and the position gradient read a
+// padded copy: pad copies the field in with zero ghost values (ghost points are no grid
+// points, so interpolation reads nothing there).
 // ---------------------------------------------------------------------------------------
 // One wave per grid row (component, z, y), four rows per block, lanes along x with two
 // values in flight per lane: the row's indices are worked out once, not per value.
@@ -1148,38 +1165,10 @@ __global__ __launch_bounds__(256) void pad_kernel(int64_t rows, int n0, int n1, 
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void unpad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
-                                                    int m1, int m2, const T* __restrict__ src,
-                                                    T* __restrict__ dst, int accumulate)
-{
-    const int lane = lane_id();
-    for (int64_t r = (int64_t)blockIdx.x * PAD_ROWS_PER_BLOCK + wave_id(); r < rows;
-         r += (int64_t)gridDim.x * PAD_ROWS_PER_BLOCK) {  // rows of the caller's field
-        const int y = (int)(r % n1);
-        const int64_t cz = r / n1;
-        const int z = (int)(cz % n2);
-        const int64_t c = cz / n2;
-        const T* __restrict__ s = src + ((c * m2 + z) * m1 + y) * m0;
-        T* __restrict__ d = dst + r * n0;
-        for (int x = lane; x < n0; x += 128) {
-            const int x2 = x + 64;
-            const bool two = x2 < n0;
-            T v0 = s[x], v1 = two ? s[x2] : T(0);
-            if (accumulate) {
-                v0 += d[x];
-                if (two) v1 += d[x2];
-            }
-            d[x] = v0;
-            if (two) d[x2] = v1;
-        }
-    }
-}
-
 namespace {
 struct PadDims {
     int n[3], m[3];
-    int64_t user_rows, kernel_rows;  // x-rows of the caller's and the padded field (x ncomp)
+    int64_t kernel_rows;  // x-rows of the padded field (times ncomp)
 };
 
 PadDims pad_dims(const ib_grid_desc& user, const ib_grid_desc& kg)
@@ -1189,7 +1178,6 @@ PadDims pad_dims(const ib_grid_desc& user, const ib_grid_desc& kg)
         d.n[k] = k < user.dim ? user.n[k] : 1;
         d.m[k] = k < kg.dim ? kg.n[k] : 1;
     }
-    d.user_rows = (int64_t)user.ncomp * d.n[1] * d.n[2];
     d.kernel_rows = (int64_t)user.ncomp * d.m[1] * d.m[2];
     return d;
 }
@@ -1209,23 +1197,6 @@ hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtyp
         hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.kernel_rows,
                            d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
                            (float*)dst);
-    return hipGetLastError();
-}
-
-hipError_t launch_unpad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype,
-                        const void* src, void* dst, bool accumulate, hipStream_t st)
-{
-    const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)65536,
-                                          (d.user_rows + PAD_ROWS_PER_BLOCK - 1) / PAD_ROWS_PER_BLOCK);
-    if (dtype == IB_F64)
-        hipLaunchKernelGGL(unpad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.user_rows,
-                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
-                           (double*)dst, (int)accumulate);
-    else
-        hipLaunchKernelGGL(unpad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.user_rows,
-                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
-                           (float*)dst, (int)accumulate);
     return hipGetLastError();
 }
 

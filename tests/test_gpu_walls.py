@@ -41,7 +41,8 @@ CASES = [(wl.grid(3, [32, 24, 20], [1.0, 0.75, 0.625]), 4, 20000),
          (wl.grid(3, [40, 16, 16], [2.5, 1.0, 1.0]), 1, 15000),
          (wl.grid(2, [48, 40], [1.2, 1.0]), 2, 8000),
          (wl.grid(3, 64, 1.0), 4, 120000),
-         (wl.grid(3, 128, 1.0), 4, 250000)]  # dense enough for LDS-tiled interpolation
+         (wl.grid(3, 128, 1.0), 4, 250000),  # dense enough for LDS-tiled interpolation
+         (wl.grid(3, 128, 1.0), 3, 270000)]  # tiled, with ghost columns and rows (x, y walls)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

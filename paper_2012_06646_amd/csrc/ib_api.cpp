@@ -163,7 +163,6 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
     L->cellmax = take(sizeof(uint32_t));
     L->crowd = take(sizeof(uint32_t));
     L->zero_end = off;
-    L->gpad = take(user->walls ? (size_t)g->ncomp * (size_t)L->G * b : 0);
     L->total = off;
 }
 
@@ -252,7 +251,6 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
         for (int k = 0; k < 3; ++k) g.stag_xi[s][k] = sx[s][k];
 
     char* base = (char*)workspace;
-    p->gpad = user->walls ? (void*)(base + L.gpad) : nullptr;
     PlanDev& d = p->sa.d;
     d.kin = (int32_t*)(base + L.kin);
     d.kA = (int32_t*)(base + L.kA);
@@ -477,18 +475,12 @@ static void set_direct(ib_plan p, OpArgs* a)
     for (int k = 0; k < 3; ++k) a->user_n[k] = k < p->user.dim ? p->user.n[k] : 1;
 }
 
-// The caller's grid field u, or (walled plans) its copy padded with zero ghost values --
-// except for a tiled interpolation (tiled), whose tiles stage from u directly.
-static const void* kernel_field(ib_plan p, OpArgs* a, const void* u, bool tiled, hipStream_t st,
-                                hipError_t* e)
+// The caller's grid field u: walled plans' kernels read it as the padded grid's first
+// cells, with zero ghost values (set_direct).
+static const void* kernel_field(ib_plan p, OpArgs* a, const void* u)
 {
-    if (!p->user.walls) return u;
-    if (tiled && interp_tiles(a->g.dim, a->g.n, a->g.npts) > 0) {
-        set_direct(p, a);
-        return u;
-    }
-    *e = launch_pad(p->user, p->grid, p->dtype, u, p->gpad, st);
-    return p->gpad;
+    set_direct(p, a);
+    return u;
 }
 
 int32_t ib_spread_scaled(ib_plan p, const void* F, void* f, double scale, int32_t accumulate,
@@ -523,7 +515,7 @@ int32_t ib_interpolate_scaled(ib_plan p, const void* u, void* U, double scale, v
     a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, &a, u, true, st, &e);
+    a.u = kernel_field(p, &a, u);
     a.U = U;
     p->last_stream = st;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
@@ -545,7 +537,7 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
     fill_op_args(p, &a);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, &a, u, true, st, &e);
+    a.u = kernel_field(p, &a, u);
     a.U = U;
     p->xn_valid = 0;
     if (!p->user.walls) {  // walled: interpolation, then the update without wrap along walls
@@ -576,7 +568,7 @@ int32_t ib_interpolate_grad_scaled(ib_plan p, const void* u, const void* W, void
     a.out_scale = scale;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    a.u = kernel_field(p, &a, u, false, st, &e);
+    a.u = kernel_field(p, &a, u);
     p->last_stream = st;
     if (e == hipSuccess)
         e = launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st);

@@ -11,7 +11,6 @@
 struct ib_plan_s {
     ib_grid_desc grid;     // the grid the kernels run on (padded if the caller's has walls)
     ib_grid_desc user;     // the caller's grid
-    void* gpad;            // walled plans: one padded grid field (ncomp x padded cells)
     int32_t dtype;
     int64_t npts;
     ibk::SortArgs sa;      // geometry, device pointers, radix configuration
@@ -40,7 +39,7 @@ struct Layout {
     int64_t ntiles, nseg_tiles, G;
     int sp_tile, sp_tiles, split;  // tile shape, tiles (x components), blocks per tile
     size_t kin, kA, vA, kB, vB, bhist, cstart, seg_off, q, Xs, Xb, Xn, Us, partial, tile_shift, fmax,
-        zero_begin, seg_status, counters, flag, bad, cellmax, crowd, zero_end, gpad, total;
+        zero_begin, seg_status, counters, flag, bad, cellmax, crowd, zero_end, total;
 };
 
 // Validate a descriptor; find the distinct staggerings (count, component -> stagger index,

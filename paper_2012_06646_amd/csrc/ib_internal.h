@@ -132,9 +132,10 @@ struct OpArgs {
     const uint32_t* cellmax;     // most points in any staggering-0 cell
     const uint32_t* crowd;       // points in cells of at least CROWD_CELL points (or null)
     int interp_tiled;            // batches: interpolate through LDS tiles (see interp_tiles)
-    // Walled plans run on a grid padded with ghost cells at the top of each walled axis.
-    // direct = 1: f (spreading) or u (tiled interpolation) is the caller's field of
-    // user_n[0] x user_n[1] x user_n[2] cells per component, whose cells are the padded
+    // Walled plans run on a periodic grid with ghost cells added at the top of each walled
+    // axis (a point's stencil may reach them; they are no grid points).  direct = 1: f
+    // (spreading) or u (interpolation, the position gradient) is the caller's field of
+    // user_n[0] x user_n[1] x user_n[2] cells per component, whose cells are the kernel
     // grid's first user_n[k] along each axis: ghost values are dropped when spreading and
     // read as zero when interpolating, with no padded copy.
     int direct;
@@ -239,10 +240,6 @@ hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void
                               int accumulate, hipStream_t st);
 hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3], int walls, int dtype,
                          void* X, const void* U, double dt, hipStream_t st);
-// Walled plans: the caller's grid field (user grid) to the kernels' padded grid (zero ghost
-// values), for the kernels that read the padded grid.
-hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype, const void* src,
-                      void* dst, hipStream_t st);
 hipError_t launch_tether(int dim, int walls, int64_t npts, const double length[3], int dtype,
                          const void* X0, const void* X, double k, void* F, hipStream_t st);
 

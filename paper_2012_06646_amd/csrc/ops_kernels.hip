@@ -663,14 +663,18 @@ spread_kernel(OpArgs a)
 // neighbouring cells, so the SW^d gathers of a wave share cache lines.  All components of a
 // point are accumulated in registers and written together.
 // Interpolated value of component c at point coordinates x: weights per axis, then the
-// SW^d gathers (SW = support_width<KERN>()) in tensor-product order.
-template <typename T, int DIM, int KERN>
+// SW^d gathers (SW = support_width<KERN>()) in tensor-product order.  DIRECT: u is the
+// caller's unpadded field of un[0] x un[1] x un[2] cells per component (walled plans); the
+// stencil's ghost nodes read as zero.
+template <typename T, int DIM, int KERN, bool DIRECT>
 __device__ __forceinline__ T interp_component(const GeomArgs& g, const T* __restrict__ u, int c,
-                                              const T x[DIM])
+                                              const T x[DIM], const int un[3])
 {
     constexpr int SW = support_width<KERN>();
     const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
-    const int64_t G = (int64_t)n0 * n1 * n2;
+    const int f0 = DIRECT ? un[0] : n0, f1 = DIRECT ? un[1] : n1;  // the field read
+    const int f2 = (DIM == 3) ? (DIRECT ? un[2] : n2) : 1;
+    const int64_t G = (int64_t)f0 * f1 * f2;
     T w[DIM][4];
     int cell[DIM];
 #pragma unroll
@@ -684,21 +688,30 @@ __device__ __forceinline__ T interp_component(const GeomArgs& g, const T* __rest
         cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
     }
     int xi[4];
+    bool xok[4];
 #pragma unroll
-    for (int ix = 0; ix < SW; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+    for (int ix = 0; ix < SW; ++ix) {
+        xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+        xok[ix] = !DIRECT || xi[ix] < f0;
+        if (!xok[ix]) xi[ix] = 0;  // a ghost node: read an in-range value, use zero
+    }
     const T* __restrict__ uc = u + (int64_t)c * G;
     T sum = T(0);
 #pragma unroll
     for (int iz = 0; iz < ((DIM == 3) ? SW : 1); ++iz) {
-        const int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
+        int zz = (DIM == 3) ? wrap_small(cell[DIM - 1] - 1 + iz, n2) : 0;
         T sy = T(0);
 #pragma unroll
         for (int iy = 0; iy < SW; ++iy) {
-            const int yy = wrap_small(cell[1] - 1 + iy, n1);
-            const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
+            int yy = wrap_small(cell[1] - 1 + iy, n1);
+            const bool rok = !DIRECT || (yy < f1 && zz < f2);
+            const T* __restrict__ line = uc + (rok ? ((int64_t)zz * f1 + yy) * f0 : 0);
             T sx = T(0);
 #pragma unroll
-            for (int ix = 0; ix < SW; ++ix) sx = fma(w[0][ix], line[xi[ix]], sx);
+            for (int ix = 0; ix < SW; ++ix) {
+                const T v = line[xi[ix]];
+                sx = fma(w[0][ix], (rok && xok[ix]) ? v : T(0), sx);
+            }
             sy = fma(w[1][iy], sx, sy);
         }
         sum = (DIM == 3) ? fma(w[DIM - 1][iz], sy, sum) : sy;
@@ -710,7 +723,7 @@ __device__ __forceinline__ T interp_component(const GeomArgs& g, const T* __rest
 // loop, so all 3 x 4^d gathers of a point can be in flight together (measured faster, at
 // ~250 VGPRs); FP64 keeps one component at a time, since unrolling it would need ~360
 // VGPRs and leave one wave per SIMD.
-template <typename T, int DIM, int KERN>
+template <typename T, int DIM, int KERN, bool DIRECT>
 __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
 {
     const GeomArgs& g = a.g;
@@ -729,12 +742,12 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
         T res[3] = {T(0), T(0), T(0)};
         if (sizeof(T) == 4 && unrolled) {
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
+            for (int c = 0; c < DIM; ++c) res[c] = interp_component<T, DIM, KERN, DIRECT>(g, u, c, x, a.user_n);
 #pragma unroll
             for (int c = 0; c < DIM; ++c) U[p * DIM + c] = res[c] * os;
         } else {
 #pragma unroll 1
-            for (int c = 0; c < ncomp; ++c) res[c] = interp_component<T, DIM, KERN>(g, u, c, x);
+            for (int c = 0; c < ncomp; ++c) res[c] = interp_component<T, DIM, KERN, DIRECT>(g, u, c, x, a.user_n);
             for (int c = 0; c < ncomp; ++c) U[p * ncomp + c] = res[c] * os;
         }
         if (a.Xadv) {  // fused position update (ncomp == DIM): the same arithmetic as advect
@@ -750,10 +763,10 @@ __device__ __forceinline__ void interp_body(const OpArgs& a, int bid, int nblk)
     }
 }
 
-template <typename T, int DIM, int KERN>
+template <typename T, int DIM, int KERN, bool DIRECT>
 __global__ __launch_bounds__(256) void interp_kernel(OpArgs a)
 {
-    interp_body<T, DIM, KERN>(a, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
+    interp_body<T, DIM, KERN, DIRECT>(a, xcd_block(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // Interpolation through LDS (3-D plans).  A block owns a TX x TY x TZ tile of staggering-0
@@ -983,7 +996,7 @@ interp_tile_kernel(OpArgs a)
 // Position gradient of interpolation: dX_j += sum_c W_{j,c} dU_{j,c} / dX_j, U = J(X) u.
 // dW/dX_k = (1/h_k) dw_k(r_k) prod_{l != k} w_l(r_l); one thread per sorted point.
 // ---------------------------------------------------------------------------------------
-template <typename T, int DIM, int KERN>
+template <typename T, int DIM, int KERN, bool DIRECT>
 __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __restrict__ W,
                                                           T* __restrict__ dX, int accumulate)
 {
@@ -991,7 +1004,11 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
     const GeomArgs& g = a.g;
     const int64_t n = g.npts;
     const int n0 = g.n[0], n1 = g.n[1], n2 = (DIM == 3) ? g.n[2] : 1;
-    const int64_t G = (int64_t)n0 * n1 * n2;
+    // the field read: the plan's grid, or (DIRECT, walled plans) the caller's unpadded field,
+    // whose ghost nodes read as zero
+    const int f0 = DIRECT ? a.user_n[0] : n0, f1 = DIRECT ? a.user_n[1] : n1;
+    const int f2 = (DIM == 3) ? (DIRECT ? a.user_n[2] : n2) : 1;
+    const int64_t G = (int64_t)f0 * f1 * f2;
     const T* __restrict__ Xs = (const T*)a.Xs;
     const T* __restrict__ u = (const T*)a.u;
     const int bid = xcd_block(blockIdx.x, gridDim.x);
@@ -1019,8 +1036,13 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
                 cell[k] = fabs(fyd) < 1073741824.0 ? floor_mod(fyd, g.n[k], g.inv_n[k]) : 0;
             }
             int xi[4];
+            bool xok[4];
 #pragma unroll
-            for (int ix = 0; ix < SW; ++ix) xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+            for (int ix = 0; ix < SW; ++ix) {
+                xi[ix] = wrap_small(cell[0] - 1 + ix, n0);
+                xok[ix] = !DIRECT || xi[ix] < f0;
+                if (!xok[ix]) xi[ix] = 0;  // a ghost node: read an in-range value, use zero
+            }
             const T* __restrict__ uc = a.u ? u + (int64_t)c * G : u;
             // s_* : sums with w in every axis except the one differentiated
             T gx = T(0), gy = T(0), gz = T(0);
@@ -1031,11 +1053,12 @@ __global__ __launch_bounds__(256) void interp_grad_kernel(OpArgs a, const T* __r
 #pragma unroll
                 for (int iy = 0; iy < SW; ++iy) {
                     const int yy = wrap_small(cell[1] - 1 + iy, n1);
-                    const T* __restrict__ line = uc + ((int64_t)zz * n1 + yy) * n0;
+                    const bool rok = !DIRECT || (yy < f1 && zz < f2);
+                    const T* __restrict__ line = uc + (rok ? ((int64_t)zz * f1 + yy) * f0 : 0);
                     T sx = T(0), dsx = T(0);
 #pragma unroll
                     for (int ix = 0; ix < SW; ++ix) {
-                        const T v = line[xi[ix]];
+                        const T v = (rok && xok[ix]) ? line[xi[ix]] : T(0);
                         sx = fma(w[0][ix], v, sx);
                         dsx = fma(dw[0][ix], v, dsx);
                     }
@@ -1069,8 +1092,12 @@ template <typename T, int D, int K>
 void grad_launch(const OpArgs& a, const void* W, void* dX, int accumulate, unsigned nb,
                  hipStream_t st)
 {
-    hipLaunchKernelGGL((interp_grad_kernel<T, D, K>), dim3(nb), dim3(256), 0, st, a,
-                       (const T*)W, (T*)dX, accumulate);
+    if (a.direct)
+        hipLaunchKernelGGL((interp_grad_kernel<T, D, K, true>), dim3(nb), dim3(256), 0, st, a,
+                           (const T*)W, (T*)dX, accumulate);
+    else
+        hipLaunchKernelGGL((interp_grad_kernel<T, D, K, false>), dim3(nb), dim3(256), 0, st, a,
+                           (const T*)W, (T*)dX, accumulate);
 }
 
 hipError_t launch_interp_grad(const OpArgs& a, int dtype, int kernel, const void* W, void* dX,
@@ -1124,79 +1151,6 @@ hipError_t launch_advect(int dim, int ncomp, int64_t npts, const double length[3
         hipLaunchKernelGGL(advect_kernel<float>, dim3(blocks), dim3(256), 0, st, dim, ncomp, walls,
                            npts, (float)length[0], (float)length[1], (float)length[2], (float*)X,
                            (const float*)U, (float)dt);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------
-// Walled plans run on a periodic grid with ghost indices n_k .. m_k - 1 added along walled
-// dimensions (m_k = n_k elsewhere).  The caller's field (n) sits at the same indices of the
-// padded field (m).  Spreading writes the caller's cells straight from its tiles and drops
-// the ghost values; tiled interpolation stages the caller's cells and zero for ghosts
-// (OpArgs::direct).  The other interpolation kernels and the position gradient read a
-// padded copy: pad copies the field in with zero ghost values (ghost points are no grid
-// points, so interpolation reads nothing there).
-// ---------------------------------------------------------------------------------------
-// One wave per grid row (component, z, y), four rows per block, lanes along x with two
-// values in flight per lane: the row's indices are worked out once, not per value.
-constexpr int PAD_ROWS_PER_BLOCK = 4;
-
-template <typename T>
-__global__ __launch_bounds__(256) void pad_kernel(int64_t rows, int n0, int n1, int n2, int m0,
-                                                  int m1, int m2, const T* __restrict__ src,
-                                                  T* __restrict__ dst)
-{
-    const int lane = lane_id();
-    for (int64_t r = (int64_t)blockIdx.x * PAD_ROWS_PER_BLOCK + wave_id(); r < rows;
-         r += (int64_t)gridDim.x * PAD_ROWS_PER_BLOCK) {  // rows of the padded field
-        const int y = (int)(r % m1);
-        const int64_t cz = r / m1;
-        const int z = (int)(cz % m2);
-        const int64_t c = cz / m2;
-        const bool inside = y < n1 && z < n2;
-        const int64_t srow = inside ? ((c * n2 + z) * n1 + y) * n0 : 0;
-        T* __restrict__ d = dst + r * m0;
-        for (int x = lane; x < m0; x += 128) {
-            const int x2 = x + 64;
-            const T v0 = (inside && x < n0) ? src[srow + x] : T(0);
-            const T v1 = (inside && x2 < n0) ? src[srow + x2] : T(0);
-            d[x] = v0;
-            if (x2 < m0) d[x2] = v1;
-        }
-    }
-}
-
-namespace {
-struct PadDims {
-    int n[3], m[3];
-    int64_t kernel_rows;  // x-rows of the padded field (times ncomp)
-};
-
-PadDims pad_dims(const ib_grid_desc& user, const ib_grid_desc& kg)
-{
-    PadDims d;
-    for (int k = 0; k < 3; ++k) {
-        d.n[k] = k < user.dim ? user.n[k] : 1;
-        d.m[k] = k < kg.dim ? kg.n[k] : 1;
-    }
-    d.kernel_rows = (int64_t)user.ncomp * d.m[1] * d.m[2];
-    return d;
-}
-}  // namespace
-
-hipError_t launch_pad(const ib_grid_desc& user, const ib_grid_desc& kg, int dtype, const void* src,
-                      void* dst, hipStream_t st)
-{
-    const PadDims d = pad_dims(user, kg);
-    const unsigned blocks = (unsigned)min((int64_t)65536,
-                                          (d.kernel_rows + PAD_ROWS_PER_BLOCK - 1) / PAD_ROWS_PER_BLOCK);
-    if (dtype == IB_F64)
-        hipLaunchKernelGGL(pad_kernel<double>, dim3(blocks), dim3(256), 0, st, d.kernel_rows,
-                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const double*)src,
-                           (double*)dst);
-    else
-        hipLaunchKernelGGL(pad_kernel<float>, dim3(blocks), dim3(256), 0, st, d.kernel_rows,
-                           d.n[0], d.n[1], d.n[2], d.m[0], d.m[1], d.m[2], (const float*)src,
-                           (float*)dst);
     return hipGetLastError();
 }
 
@@ -1304,10 +1258,13 @@ hipError_t interp_dispatch(OpArgs a, hipStream_t st)
     if (nt > 0) {
         hipLaunchKernelGGL((interp_tile_kernel<T, KERN, IT_TX, IT_TY, IT_TZ>), dim3((unsigned)nt),
                            dim3(256), 0, st, a);
-    } else if (a.g.dim == 3)
-        hipLaunchKernelGGL((interp_kernel<T, 3, KERN>), dim3(nb), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((interp_kernel<T, 2, KERN>), dim3(nb), dim3(256), 0, st, a);
+    } else if (a.g.dim == 3) {
+        if (a.direct) hipLaunchKernelGGL((interp_kernel<T, 3, KERN, true>), dim3(nb), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((interp_kernel<T, 3, KERN, false>), dim3(nb), dim3(256), 0, st, a);
+    } else {
+        if (a.direct) hipLaunchKernelGGL((interp_kernel<T, 2, KERN, true>), dim3(nb), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((interp_kernel<T, 2, KERN, false>), dim3(nb), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -1368,7 +1325,7 @@ __global__ __launch_bounds__(256) void batch_interp_kernel(const BatchJob* __res
                 continue;
             }
         }
-        interp_body<T, DIM, KERN>(a, vb - st[j], nb);
+        interp_body<T, DIM, KERN, false>(a, vb - st[j], nb);
     }
 }
 

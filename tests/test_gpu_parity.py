@@ -269,6 +269,39 @@ def test_dyadic_case_is_bit_exact(ib, orc, dtype):
     assert np.array_equal(U, orc.interp(g, X, u))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_plan_reused_across_updates_and_exports(ib, orc, dtype):
+    """One plan, several updates with different point sets, every staggering exported after
+    each: the counters each sort leaves cleared for the next sort of its staggering give
+    the oracle's keys, permutation, offsets and q every time (only the first update runs
+    the reset kernel)."""
+    g = wl.grid(3, [48, 40, 36], [1.2, 1.0, 0.9])
+    n = 50000
+    nd = _np_dtype(dtype)
+    p = ib.Plan(g, n, dtype)
+    for it in range(3):
+        X = wl.uniform_case(g, n, 4600 + it)[0].astype(nd)
+        if it == 2:  # crowded: half of the points in 300 cells
+            r = wl.rng(4700)
+            h = np.array(g["length"]) / np.array(g["n"])
+            cells = r.integers(0, g["n"], (300, 3)) * h
+            X[: n // 2] = (np.repeat(cells, (n // 2) // 300 + 1, axis=0)[: n // 2]
+                           + r.random((n // 2, 3)) * h).astype(nd)
+        say(f"reused plan, update {it} dtype={dtype}")
+        p.update(to_dev(X, dtype))
+        assert p.status() == 0
+        Xh = X.astype(np.float64)
+        for c in range(len(g["stagger"])):
+            got = p.export(p.stagger_of(c))
+            k_ref, bad = orc.keys(g, Xh, g["stagger"][c], _prec(dtype))
+            assert bad == 0
+            sk_ref, perm_ref, seg_ref, q_ref = orc.plan(k_ref)
+            assert np.array_equal(to_host(got["keys"]), k_ref), (it, c)
+            assert np.array_equal(to_host(got["perm"]), perm_ref), (it, c)
+            assert np.array_equal(to_host(got["seg_off"]), seg_ref), (it, c)
+            assert got["q"] == q_ref, (it, c)
+
+
 def test_plan_flags_bad_points_per_update(ib):
     """A position that is not finite sets the plan's device flag (status IB_ERR_DEVICE_FLAG,
     read and cleared by the status call); an update with good positions starts clean, also

@@ -417,6 +417,16 @@ def interpolate(grid, X, u):
 
 
 BATCH_MAX_JOBS = 128
+
+
+def _on_device(t, name, device=None):
+    """A job tensor must live on the GPU (on `device` when given): the library hands its
+    pointer to kernels, so a host tensor would be read by the device."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or (device is not None and device.index is not None
+                                   and t.device.index != device.index):
+        raise ValueError(f"{name} must be a tensor on {device or 'a CUDA device'}, got {t.device}")
 STATIC_SCRATCH_BYTES = 64 << 20  # IB_STATIC_SCRATCH_BYTES: largest workspace of run_static
 
 
@@ -440,6 +450,9 @@ class Batch:
             g = job["grid"]
             d = make_desc(g)
             X = job["X"]
+            for name in ("X", "F", "u"):
+                if job.get(name) is not None:
+                    _on_device(job[name], f"job {j}: {name}", self.device)
             if X.dtype != dtype or X.dim() != 2 or X.shape[1] != d.dim:
                 raise ValueError(f"job {j}: X must be (n, {d.dim}) {dtype}")
             X = X.contiguous()
@@ -519,6 +532,9 @@ def job_desc(job, dtype):
     f and U are caller-allocated outputs."""
     d = make_desc(job["grid"])
     X = job["X"]
+    for name in ("X", "F", "f", "u", "U"):
+        if job.get(name) is not None:
+            _on_device(job[name], name)
     n = X.shape[0]
     if X.dtype != dtype or not X.is_contiguous() or X.shape[1] != d.dim:
         raise ValueError(f"X must be a contiguous (n, {d.dim}) {dtype} tensor")

@@ -159,6 +159,28 @@ def test_binding_rejects_bad_buffers_before_any_launch(ib):
             ib._point_arrays(g, **bad)
 
 
+def test_batch_and_server_jobs_reject_host_tensors(ib):
+    """Batch jobs and served jobs hand their tensors' pointers to kernels, so a host tensor
+    (or any input on the wrong kind of device) raises before anything is allocated or
+    launched.  Runs on the CPU."""
+    import torch
+    g = {"dim": 3, "n": [8, 8, 8], "length": [1.0, 1.0, 1.0],
+         "stagger": [[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]}
+    X = torch.rand(10, 3, dtype=torch.float64)
+    F = torch.rand(10, 3, dtype=torch.float64)
+    u = torch.rand(3, 8, 8, 8, dtype=torch.float64)
+    for job in ({"grid": g, "X": X, "F": F}, {"grid": g, "X": X, "u": u}):
+        with pytest.raises(ValueError, match="job 0: X"):
+            ib.Batch([job], dtype=torch.float64, device="cuda:0")
+        with pytest.raises(ValueError, match="X must be a tensor on"):
+            ib.job_desc(job, torch.float64)
+    meta = torch.empty(10, 3, dtype=torch.float64, device="meta")
+    with pytest.raises(ValueError, match="job 0: X"):
+        ib.Batch([{"grid": g, "X": meta, "F": F}], dtype=torch.float64, device="cuda:0")
+    with pytest.raises(TypeError):
+        ib.job_desc({"grid": g, "X": X.numpy()}, torch.float64)
+
+
 def test_static_batch_refuses_oversize_before_device_work(ib):
     """ib_batch_run_static checks the batch's workspace against IB_STATIC_SCRATCH_BYTES on the
     host and returns IB_ERR_OOM before touching a device (no GPU needed); the size limit in

@@ -153,7 +153,7 @@ void make_layout(const ib_grid_desc* user, int32_t dtype, int nstag, int64_t n, 
                                    : 0);
     L->tile_shift = take(L->split > 1 ? (size_t)L->sp_tiles * sizeof(int32_t) : 0);
     L->fmax = take((size_t)3 * FMAX_PARTS * sizeof(unsigned long long));
-    // Everything from here to zero_end starts each update cleared (clear_once, bases pass).
+    // Everything from here to zero_end starts each update cleared (clear_once, bucket pass).
     L->zero_begin = off;
     L->seg_status = take((size_t)nstag * L->nseg_tiles * sizeof(uint32_t));
     L->bhist = take((size_t)nstag * 3 * BKT_SHARDS * R * sizeof(uint32_t));
@@ -346,9 +346,10 @@ int32_t ib_plan_stagger_of(ib_plan p, int32_t comp)
 }
 
 // The per-update region (bucket histograms, cursors, look-back words, tickets, flags) is
-// cleared by a kernel before a plan's first update; afterwards each sort's bases pass clears
-// what the next sort of its staggering counts into.  Without points there is no bases pass,
-// so such plans clear at every update.
+// cleared by a kernel before a plan's first update; afterwards each sort's bucket pass clears
+// what the next sort of its staggering counts into, and its scatter pass absorbs the
+// bad-point mark.  Without points there is no scatter pass, so such plans clear at every
+// update.
 static hipError_t clear_once(ib_plan p, hipStream_t st)
 {
     if (p->cleared && p->npts > 0) return hipSuccess;

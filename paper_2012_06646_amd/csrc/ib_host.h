@@ -24,7 +24,7 @@ struct ib_plan_s {
     uint32_t sorted_mask;  // staggerings sorted since the last update
     uint32_t runs_mask;    // staggerings whose run offsets were computed since the update
     int cleared;           // the per-update region was cleared once (later updates clear it
-                           // through the bases pass)
+                           // through the bucket pass)
 };
 
 namespace ibk {

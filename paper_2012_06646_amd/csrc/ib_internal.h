@@ -53,7 +53,7 @@ struct PlanDev {
     uint32_t* bhist;       // [nstag][3][BKT_SHARDS][R] bucket histogram, fill cursors, shard starts
     uint32_t* counters;    // [nstag][PLAN_COUNTERS] tile tickets
     uint32_t* flag;        // device error flag
-    uint32_t* bad;         // keys pass: a point was bad (moved into flag by the bases pass)
+    uint32_t* bad;         // keys pass: a point was bad (moved into flag by the scatter pass)
     int32_t* cstart;       // [G + 1] first sorted position of each cell (staggering 0)
     int32_t* seg_off;      // [nstag][n + 1]
     int32_t* q;            // [nstag]

@@ -12,10 +12,11 @@
 //   keys_kernel      the key of every point, and the count of each bucket (key >> cb, the
 //                    top rb bits): per block in LDS, then added to a shard of the global
 //                    histogram;
-//   bases_kernel     where each bucket (and each shard of it) starts;
-//   radix_scatter_kernel  each tile's (key, index) pairs, grouped by bucket in LDS, written
-//                    to a range of their bucket that the tile reserves with one atomic per
-//                    bucket (so the order inside a bucket depends on timing);
+//   radix_scatter_kernel  where each bucket (and each shard of it) starts, found by every
+//                    block from the whole histogram; then each tile's (key, index) pairs,
+//                    grouped by bucket in LDS, written to a range of their bucket that the
+//                    tile reserves with one atomic per bucket (so the order inside a bucket
+//                    depends on timing);
 //   bucket_kernel    per bucket of 2^cb cells: a histogram of its cells in LDS, its scan
 //                    (the cell-start table of the bucket, written coalesced), placement of
 //                    every point at a slot of its cell, then each point's final place from
@@ -51,15 +52,27 @@ __device__ __forceinline__ uint32_t* stag_hist(const SortArgs& a, int s)
     return a.d.bhist + (int64_t)s * 3 * BKT_SHARDS * ((int64_t)1 << a.rb);
 }
 
-// Shard starts of staggering s: base[x][d] = (points of buckets below d) + (points of bucket
-// d in shards below x).  One block of 1024 threads; bucket d (all its shards) by thread
-// d mod 1024, in rounds of 1024 buckets.
-//
-// The block also clears what this staggering's next passes count into, so that a plan
-// needs the reset kernel only once (before its first update): the histogram just read, the
-// scatter's fill cursors, the look-back words and tickets of its runs.  The keys pass marks
-// bad points in d.bad, which moves into the error flag here; an update (fresh) starts the
-// flag and the bucket pass's cell statistics afresh, an export adds to them.
+// The keys pass marks bad points in d.bad, which moves into the error flag once the pass
+// is complete; an update (fresh) starts the flag and the bucket pass's cell statistics
+// afresh, an export adds to them.  One thread.
+__device__ __forceinline__ void absorb_bad_points(const SortArgs& a, bool fresh)
+{
+    const uint32_t bad = *a.d.bad ? FLAG_BAD_POINT : 0u;
+    *a.d.bad = 0u;
+    if (fresh) {
+        *a.d.flag = bad;
+        *a.d.cellmax = 0u;
+        *a.d.crowd = 0u;
+    } else if (bad) {
+        *a.d.flag |= bad;
+    }
+}
+
+// Shard starts of staggering s for batches: base[x][d] = (points of buckets below d) +
+// (points of bucket d in shards below x).  One block of 1024 threads; bucket d (all its
+// shards) by thread d mod 1024, in rounds of 1024 buckets.  (A plan's own sorts let every
+// scatter block find its shard's starts instead, scatter_body.)  The block also clears the
+// histogram just read and the fill cursors, and absorbs the bad-point mark.
 __device__ __forceinline__ void bases_body(const SortArgs& a, int s, bool fresh)
 {
     __shared__ uint32_t s_red[1024 / 64 + 1];
@@ -89,24 +102,7 @@ __device__ __forceinline__ void bases_body(const SortArgs& a, int s, bool fresh)
     // every histogram word was read before the scan's barriers
     uint32_t* clear = const_cast<uint32_t*>(hist);
     for (int i = threadIdx.x; i < 2 * BKT_SHARDS * R; i += blockDim.x) clear[i] = 0u;
-    for (int64_t i = threadIdx.x; i < a.nseg_tiles; i += blockDim.x) a.d.seg_status[(int64_t)s * a.nseg_tiles + i] = 0u;
-    if (threadIdx.x < PLAN_COUNTERS) a.d.counters[s * PLAN_COUNTERS + threadIdx.x] = 0u;
-    if (threadIdx.x == 0) {
-        const uint32_t bad = *a.d.bad ? FLAG_BAD_POINT : 0u;
-        *a.d.bad = 0u;
-        if (fresh) {
-            *a.d.flag = bad;
-            *a.d.cellmax = 0u;
-            *a.d.crowd = 0u;
-        } else if (bad) {
-            *a.d.flag |= bad;
-        }
-    }
-}
-
-__global__ __launch_bounds__(1024) void bases_kernel(SortArgs a, int s, int fresh)
-{
-    bases_body(a, s, fresh != 0);
+    if (threadIdx.x == 0) absorb_bad_points(a, fresh);
 }
 
 // ---- keys: one per point, and the bucket histogram ----------------------------------
@@ -232,9 +228,16 @@ __device__ __forceinline__ uint32_t lookback_wave(uint32_t* chain, int64_t t, ui
 // with one atomic addition on its shard's cursor of the bucket.  Points of a bucket
 // therefore arrive in an order that depends on timing; the bucket kernel restores the
 // stable order.
-template <typename T>
+//
+// OWN_BASES: the block finds its shard's start of every bucket from the complete
+// histogram itself (16 words per bucket, a scan of the bucket totals), so no pass between
+// the keys and the scatter is needed; tile 0 also publishes the bucket starts for the
+// bucket pass and absorbs the keys pass's bad-point mark (fresh: an update).  Otherwise
+// the starts come from bases_body.
+template <typename T, bool OWN_BASES>
 __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t, const T* __restrict__ X,
-                                             bool soa, const int32_t* __restrict__ psrc, T* __restrict__ Xb)
+                                             bool soa, const int32_t* __restrict__ psrc, T* __restrict__ Xb,
+                                             bool fresh)
 {
     constexpr int R_MAX = 1 << max_bucket_bits(sizeof(T) == 8 ? IB_F64 : IB_F32);
     __shared__ int32_t s_key[SORT_TILE];
@@ -256,8 +259,11 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
     int32_t* dstk = a.d.kA + (int64_t)s * n;
     int32_t* dstv = a.d.vA + (int64_t)s * n;
     const int shard = (int)(t % BKT_SHARDS);
+    const uint32_t* hist = stag_hist(a, s);
     uint32_t* cur = stag_hist(a, s) + (BKT_SHARDS + shard) * R;
-    const uint32_t* sbase = stag_hist(a, s) + (2 * BKT_SHARDS + shard) * R;
+    uint32_t* base_tab = stag_hist(a, s) + 2 * BKT_SHARDS * R;
+    const uint32_t* sbase = base_tab + shard * R;
+    if (OWN_BASES && t == 0 && tid == 0) absorb_bad_points(a, fresh);
 
     int32_t key[SORT_IPT], val[SORT_IPT];
     uint32_t slot[SORT_IPT];
@@ -279,6 +285,32 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
             for (int d = 0; d < 3; ++d) row[k][d] = X[min(i * sr + d * sc, lastx)];
         }
     }
+    if (OWN_BASES) {
+        // this shard's start of bucket d (into s_gbase): the points of the buckets below d,
+        // and of bucket d in the shards below this tile's; the histogram's loads are in
+        // flight with the tile's own
+        uint32_t bcarry = 0;
+        for (int d0 = 0; d0 < R; d0 += SORT_BLOCK) {
+            const int d = d0 + tid;
+            uint32_t h[BKT_SHARDS];
+#pragma unroll
+            for (int x = 0; x < BKT_SHARDS; ++x) h[x] = hist[x * R + min(d, R - 1)];
+            uint32_t btot = 0, below = 0;
+#pragma unroll
+            for (int x = 0; x < BKT_SHARDS; ++x) {
+                btot += h[x];
+                below += x < shard ? h[x] : 0u;
+            }
+            if (d >= R) btot = 0;
+            uint32_t ball;
+            const uint32_t bstart = bcarry + block_excl_scan_u32<SORT_BLOCK>(btot, s_red, &ball);
+            bcarry += ball;
+            if (d < R) {
+                s_gbase[d] = bstart + below;
+                if (t == 0) base_tab[d] = bstart;  // the bucket starts (shard 0)
+            }
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SORT_IPT; ++k)
@@ -294,7 +326,7 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
         const uint32_t run = carry + block_excl_scan_u32<SORT_BLOCK>(c, s_red, &tot);
         if (d < R) {
             s_tstart[d] = run;
-            s_gbase[d] = (c ? atomicAdd(&cur[d], c) : 0u) + sbase[d];
+            s_gbase[d] = (c ? atomicAdd(&cur[d], c) : 0u) + (OWN_BASES ? s_gbase[d] : sbase[d]);
         }
         carry += tot;
     }
@@ -329,12 +361,14 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
     }
 }
 
+// Built for eight waves per SIMD (at most 64 VGPRs), so that two blocks share a CU.
 template <typename T>
-__global__ __launch_bounds__(SORT_BLOCK) void radix_scatter_kernel(SortArgs a, int s, const T* __restrict__ X,
+__global__ __launch_bounds__(SORT_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
+radix_scatter_kernel(SortArgs a, int s, const T* __restrict__ X,
                                                                    int soa, const int32_t* __restrict__ psrc,
-                                                                   T* __restrict__ Xb)
+                                                                   T* __restrict__ Xb, int fresh)
 {
-    scatter_body<T>(a, s, blockIdx.x, X, soa != 0, psrc, Xb);
+    scatter_body<T, true>(a, s, blockIdx.x, X, soa != 0, psrc, Xb, fresh != 0);
 }
 
 // ---- per bucket: counting sort in LDS, cell-start table, positions in sorted order ------
@@ -592,6 +626,19 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     const int64_t cbeg = (int64_t)b << a.cb;
     const int64_t cend = min(G, (int64_t)(b + 1) << a.cb);
     const bool last = cend == G;
+    // Nothing reads this bucket's histogram words and fill cursors (every shard) after the
+    // scatter pass: clear them for the staggering's next sort, and (block 0) the look-back
+    // words and tickets of its runs, so that a plan needs the reset kernel only before its
+    // first update.  Buckets without a block hold no points, so their words stay zero.
+    {
+        uint32_t* counts = const_cast<uint32_t*>(stag_hist(a, s));
+        if ((int)threadIdx.x < 2 * BKT_SHARDS) counts[(int64_t)threadIdx.x * R + b] = 0u;
+        if (b == 0) {
+            for (int64_t i = threadIdx.x; i < a.nseg_tiles; i += blockDim.x)
+                a.d.seg_status[(int64_t)s * a.nseg_tiles + i] = 0u;
+            if ((int)threadIdx.x < PLAN_COUNTERS) a.d.counters[s * PLAN_COUNTERS + threadIdx.x] = 0u;
+        }
+    }
     if (m >= 1 && m <= BKT_CAP && cend - cbeg <= BKT_CELLS)
         bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red,
                        s_cstat);
@@ -751,7 +798,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void batch_scatter_kernel(const BatchJo
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
         const BatchJob& J = jobs[j];
-        scatter_body<T>(J.sa, 0, vb - st[j], (const T*)J.op.X, false, nullptr, (T*)J.sa.d.Xb);
+        scatter_body<T, false>(J.sa, 0, vb - st[j], (const T*)J.op.X, false, nullptr, (T*)J.sa.d.Xb, true);
         __syncthreads();
     }
 }
@@ -837,15 +884,13 @@ hipError_t launch_sort_stagger(const SortArgs& a, int s, int dtype, const void* 
         if (dtype == IB_F64) {
             hipLaunchKernelGGL(keys_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
                                (const double*)X, soa, s);
-            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s, outputs0 ? 1 : 0);
             hipLaunchKernelGGL(radix_scatter_kernel<double>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
-                               a, s, (const double*)X, soa, psrc, (double*)Xb);
+                               a, s, (const double*)X, soa, psrc, (double*)Xb, outputs0 ? 1 : 0);
         } else {
             hipLaunchKernelGGL(keys_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st, a,
                                (const float*)X, soa, s);
-            hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(1024), 0, st, a, s, outputs0 ? 1 : 0);
             hipLaunchKernelGGL(radix_scatter_kernel<float>, dim3((unsigned)a.ntiles), dim3(SORT_BLOCK), 0, st,
-                               a, s, (const float*)X, soa, psrc, (float*)Xb);
+                               a, s, (const float*)X, soa, psrc, (float*)Xb, outputs0 ? 1 : 0);
         }
     }
     // The buckets write the cell-start table even without points (every cell starts at 0).

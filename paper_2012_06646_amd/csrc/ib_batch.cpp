@@ -110,7 +110,6 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
         counts[BS_RESET] = reset_blocks(sa);
         counts[BS_FMAX] = J.f ? FMAX_PARTS : 0;
         counts[BS_KEYS] = keys_blocks(sa);
-        counts[BS_BASES] = n > 0 ? 1 : 0;
         counts[BS_SCATTER] = n > 0 ? (int)sa.ntiles : 0;
         counts[BS_BUCKET] = bucket_blocks(sa);
         counts[BS_SPREAD] = J.f ? a.tiles[0] * a.tiles[1] * a.tiles[2] * a.g.ncomp * a.g.split : 0;

@@ -50,7 +50,7 @@ struct PlanDev {
     int32_t* vA;
     int32_t* kB;           // [nstag][n] sorted keys
     int32_t* vB;           // [nstag][n] permutation: sorted position -> point index
-    uint32_t* bhist;       // [nstag][3][BKT_SHARDS][R] bucket histogram, fill cursors, shard starts
+    uint32_t* bhist;       // [nstag][3][BKT_SHARDS][R] bucket histogram, fill cursors, bucket starts
     uint32_t* counters;    // [nstag][PLAN_COUNTERS] tile tickets
     uint32_t* flag;        // device error flag
     uint32_t* bad;         // keys pass: a point was bad (moved into flag by the scatter pass)
@@ -159,8 +159,7 @@ enum BatchStage {
     BS_RESET = 0,
     BS_FMAX,     // force maxima of every spreading job
     BS_KEYS,     // keys and the bucket histogram
-    BS_BASES,    // bucket starts
-    BS_SCATTER,  // points into their buckets
+    BS_SCATTER,  // bucket starts, and points into their buckets
     BS_BUCKET,   // per bucket: counting sort, cell-start table, positions in sorted order
     BS_SPREAD,
     BS_SPLITSUM,  // partial tiles of split spreading tiles added

@@ -43,8 +43,8 @@ __global__ void plan_reset_kernel(uint32_t* __restrict__ p, size_t nwords)
 }
 
 // Bucket bookkeeping of staggering s, in three arrays of [BKT_SHARDS][R] words: the
-// histogram, the fill cursors and the first position of each (shard, bucket) range.  Tile
-// t counts and fills shard t mod BKT_SHARDS, so that no counter takes more than a
+// histogram, the fill cursors, and the bucket starts (the first R words of the third).
+// Tile t counts and fills shard t mod BKT_SHARDS, so that no counter takes more than a
 // BKT_SHARDS-th of the tiles' atomic additions; a bucket's range is its shards' ranges in
 // shard order.
 __device__ __forceinline__ uint32_t* stag_hist(const SortArgs& a, int s)
@@ -66,43 +66,6 @@ __device__ __forceinline__ void absorb_bad_points(const SortArgs& a, bool fresh)
     } else if (bad) {
         *a.d.flag |= bad;
     }
-}
-
-// Shard starts of staggering s for batches: base[x][d] = (points of buckets below d) +
-// (points of bucket d in shards below x).  One block of 1024 threads; bucket d (all its
-// shards) by thread d mod 1024, in rounds of 1024 buckets.  (A plan's own sorts let every
-// scatter block find its shard's starts instead, scatter_body.)  The block also clears the
-// histogram just read and the fill cursors, and absorbs the bad-point mark.
-__device__ __forceinline__ void bases_body(const SortArgs& a, int s, bool fresh)
-{
-    __shared__ uint32_t s_red[1024 / 64 + 1];
-    const int R = 1 << a.rb;
-    const uint32_t* hist = stag_hist(a, s);
-    uint32_t* base = const_cast<uint32_t*>(hist) + 2 * BKT_SHARDS * R;
-    uint32_t carry = 0;  // points of the buckets of earlier rounds
-    for (int d0 = 0; d0 < R; d0 += 1024) {  // rounds of 1024 buckets, bucket d0 + t by thread t
-        const int d = d0 + threadIdx.x;
-        uint32_t part[BKT_SHARDS], tot = 0;
-#pragma unroll
-        for (int x = 0; x < BKT_SHARDS; ++x) {
-            part[x] = d < R ? hist[x * R + d] : 0u;
-            tot += part[x];
-        }
-        uint32_t all;
-        uint32_t run = carry + block_excl_scan_u32<1024>(tot, s_red, &all);
-        if (d < R) {
-#pragma unroll
-            for (int x = 0; x < BKT_SHARDS; ++x) {
-                base[x * R + d] = run;
-                run += part[x];
-            }
-        }
-        carry += all;
-    }
-    // every histogram word was read before the scan's barriers
-    uint32_t* clear = const_cast<uint32_t*>(hist);
-    for (int i = threadIdx.x; i < 2 * BKT_SHARDS * R; i += blockDim.x) clear[i] = 0u;
-    if (threadIdx.x == 0) absorb_bad_points(a, fresh);
 }
 
 // ---- keys: one per point, and the bucket histogram ----------------------------------
@@ -229,12 +192,11 @@ __device__ __forceinline__ uint32_t lookback_wave(uint32_t* chain, int64_t t, ui
 // therefore arrive in an order that depends on timing; the bucket kernel restores the
 // stable order.
 //
-// OWN_BASES: the block finds its shard's start of every bucket from the complete
-// histogram itself (16 words per bucket, a scan of the bucket totals), so no pass between
-// the keys and the scatter is needed; tile 0 also publishes the bucket starts for the
-// bucket pass and absorbs the keys pass's bad-point mark (fresh: an update).  Otherwise
-// the starts come from bases_body.
-template <typename T, bool OWN_BASES>
+// The block finds its shard's start of every bucket from the complete histogram itself (16
+// words per bucket, a scan of the bucket totals), so no pass between the keys and the
+// scatter is needed; tile 0 also publishes the bucket starts for the bucket pass and
+// absorbs the keys pass's bad-point mark (fresh: an update).
+template <typename T>
 __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t, const T* __restrict__ X,
                                              bool soa, const int32_t* __restrict__ psrc, T* __restrict__ Xb,
                                              bool fresh)
@@ -261,9 +223,8 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
     const int shard = (int)(t % BKT_SHARDS);
     const uint32_t* hist = stag_hist(a, s);
     uint32_t* cur = stag_hist(a, s) + (BKT_SHARDS + shard) * R;
-    uint32_t* base_tab = stag_hist(a, s) + 2 * BKT_SHARDS * R;
-    const uint32_t* sbase = base_tab + shard * R;
-    if (OWN_BASES && t == 0 && tid == 0) absorb_bad_points(a, fresh);
+    uint32_t* base_tab = stag_hist(a, s) + 2 * BKT_SHARDS * R;  // [BKT_SHARDS][R]: shard 0 used
+    if (t == 0 && tid == 0) absorb_bad_points(a, fresh);
 
     int32_t key[SORT_IPT], val[SORT_IPT];
     uint32_t slot[SORT_IPT];
@@ -285,7 +246,7 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
             for (int d = 0; d < 3; ++d) row[k][d] = X[min(i * sr + d * sc, lastx)];
         }
     }
-    if (OWN_BASES) {
+    {
         // this shard's start of bucket d (into s_gbase): the points of the buckets below d,
         // and of bucket d in the shards below this tile's; the histogram's loads are in
         // flight with the tile's own
@@ -326,7 +287,7 @@ __device__ __forceinline__ void scatter_body(const SortArgs& a, int s, int64_t t
         const uint32_t run = carry + block_excl_scan_u32<SORT_BLOCK>(c, s_red, &tot);
         if (d < R) {
             s_tstart[d] = run;
-            s_gbase[d] = (c ? atomicAdd(&cur[d], c) : 0u) + (OWN_BASES ? s_gbase[d] : sbase[d]);
+            s_gbase[d] = (c ? atomicAdd(&cur[d], c) : 0u) + s_gbase[d];
         }
         carry += tot;
     }
@@ -368,7 +329,7 @@ radix_scatter_kernel(SortArgs a, int s, const T* __restrict__ X,
                                                                    int soa, const int32_t* __restrict__ psrc,
                                                                    T* __restrict__ Xb, int fresh)
 {
-    scatter_body<T, true>(a, s, blockIdx.x, X, soa != 0, psrc, Xb, fresh != 0);
+    scatter_body<T>(a, s, blockIdx.x, X, soa != 0, psrc, Xb, fresh != 0);
 }
 
 // ---- per bucket: counting sort in LDS, cell-start table, positions in sorted order ------
@@ -778,19 +739,8 @@ __global__ __launch_bounds__(SORT_BLOCK) void batch_keys_kernel(const BatchJob* 
     }
 }
 
-__global__ __launch_bounds__(1024) void batch_bases_kernel(const BatchJob* __restrict__ jobs,
-                                                           const BatchTable* __restrict__ bt)
-{
-    const int32_t* st = bt->starts[BS_BASES];
-    const int nj = bt->njobs, total = st[nj];
-    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        bases_body(jobs[batch_job(st, nj, vb)].sa, 0, true);
-        __syncthreads();
-    }
-}
-
 template <typename T>
-__global__ __launch_bounds__(SORT_BLOCK) void batch_scatter_kernel(const BatchJob* __restrict__ jobs,
+__global__ __launch_bounds__(SORT_BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void batch_scatter_kernel(const BatchJob* __restrict__ jobs,
                                                                    const BatchTable* __restrict__ bt)
 {
     const int32_t* st = bt->starts[BS_SCATTER];
@@ -798,7 +748,7 @@ __global__ __launch_bounds__(SORT_BLOCK) void batch_scatter_kernel(const BatchJo
     for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
         const int j = batch_job(st, nj, vb);
         const BatchJob& J = jobs[j];
-        scatter_body<T, false>(J.sa, 0, vb - st[j], (const T*)J.op.X, false, nullptr, (T*)J.sa.d.Xb, true);
+        scatter_body<T>(J.sa, 0, vb - st[j], (const T*)J.op.X, false, nullptr, (T*)J.sa.d.Xb, true);
         __syncthreads();
     }
 }
@@ -829,8 +779,6 @@ hipError_t launch_batch_plan(const BatchLaunch& b, hipStream_t st)
             hipLaunchKernelGGL(batch_keys_kernel<float>, dim3(b.grid[BS_KEYS]), dim3(SORT_BLOCK), 0, st,
                                b.jobs, b.table);
     }
-    if (b.grid[BS_BASES] > 0)
-        hipLaunchKernelGGL(batch_bases_kernel, dim3(b.grid[BS_BASES]), dim3(1024), 0, st, b.jobs, b.table);
     if (b.grid[BS_SCATTER] > 0) {
         if (b.dtype == IB_F64)
             hipLaunchKernelGGL(batch_scatter_kernel<double>, dim3(b.grid[BS_SCATTER]), dim3(SORT_BLOCK), 0,

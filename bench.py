@@ -374,6 +374,19 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
                 "jobs_per_s": round(measured / span, 1), "points_per_s": round(pts / span, 1),
                 "mean_batch": round(st["jobs_done"] / max(st["batches"], 1), 2), "errors": bad}
 
+    # one batch of the mix's first 64 jobs (ib_batch_run): the batch tuner's choice for it,
+    # and Batch.run with the built-in and the tuned choice, timed interleaved
+    from paper_2012_06646_amd import tune
+    bjobs = pool[:64]
+    best, cand = tune.autotune_batch(bjobs, dt, reps=5, store=False)
+    (t_def, _), (t_tuned, _) = tune.time_batch_tunings(bjobs, dt, [None, best], reps=10)
+    batch_tuning = {"jobs": len(bjobs), "points": int(sum(jb["X"].shape[0] for jb in bjobs)),
+                    "tuning": best, "candidates_ms": cand, "builtin_ms": round(t_def, 4),
+                    "tuned_ms": round(t_tuned, 4),
+                    "builtin_jobs_per_s": round(len(bjobs) / (t_def / 1e3), 1),
+                    "tuned_jobs_per_s": round(len(bjobs) / (t_tuned / 1e3), 1)}
+    progress("batch tuning done")
+
     runs = {}
     for rho in rhos:
         rate = rho * mu1
@@ -395,6 +408,7 @@ def serving_bench(torch, ibops, wl, pool_size=256, warm=200, measured=2000,
         "batched_graph_closed_loop_jobs_per_s": round(muG, 1),
         "closed_loop_by_max_batch": by_batch,
         "graph_max_jobs_default": ibops.GRAPH_MAX_JOBS,
+        "batch_tuning": batch_tuning,
         "open_loop_by_load": runs,
     }
 

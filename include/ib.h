@@ -289,6 +289,17 @@ size_t ib_batch_staging_bytes(int32_t njobs);
 int32_t ib_batch_run(const ib_job *jobs, int32_t njobs, int32_t dtype, void *workspace,
                      size_t workspace_bytes, void *host_staging, void *stream);
 
+/* A batch with one ib_tuning for all its jobs (NULL: the built-in choices, as above): each
+ * job's plan takes the tuning as ib_plan_create_tuned does, so a job's results equal those
+ * of a plan created with the same tuning, bit for bit.  The workspace size depends on the
+ * tuning; ib_batch_status works as for ib_batch_run.  Errors: those of
+ * ib_batch_workspace_bytes (0) and ib_batch_run, and IB_ERR_ARG for a tuning outside its
+ * documented ranges. */
+size_t ib_batch_workspace_bytes_tuned(const ib_job *jobs, int32_t njobs, int32_t dtype,
+                                      const ib_tuning *tuning);
+int32_t ib_batch_run_tuned(const ib_job *jobs, int32_t njobs, int32_t dtype, const ib_tuning *tuning,
+                           void *workspace, size_t workspace_bytes, void *host_staging, void *stream);
+
 /* Synchronise the stream, then report per job (job_status[j], may be NULL) whether the
  * device flagged a data error in its positions; returns IB_ERR_DEVICE_FLAG if any did.
  * The jobs and workspace must be those of the last ib_batch_run on that workspace. */

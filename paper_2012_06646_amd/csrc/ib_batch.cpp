@@ -30,12 +30,15 @@ struct BatchLayout {
     std::vector<JobGeom> jobs;
 };
 
-// Validate the jobs and lay out their plan regions, one after another from offset 0.
-int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayout* B)
+// Validate the jobs and lay out their plan regions, one after another from offset 0, each
+// with the batch's tuning (NULL: the built-in choices).
+int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, const ib_tuning* tuning,
+                     BatchLayout* B)
 {
     if (!jobs || njobs < 1) return IB_ERR_ARG;
     if (njobs > BATCH_MAX_JOBS) return IB_ERR_UNSUPPORTED;
     if (dtype != IB_F64 && dtype != IB_F32) return IB_ERR_UNSUPPORTED;
+    if (check_tuning(tuning, dtype) != IB_OK) return IB_ERR_ARG;
     B->jobs.resize(njobs);
     B->header = batch_header_bytes(njobs);
     size_t off = 0;
@@ -51,7 +54,7 @@ int32_t batch_layout(const ib_job* jobs, int32_t njobs, int32_t dtype, BatchLayo
         if (J.npts > 0 && !J.X) return IB_ERR_ARG;
         if (J.f && J.npts > 0 && !J.F) return IB_ERR_ARG;
         if (J.u && J.npts > 0 && !J.U) return IB_ERR_ARG;
-        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, nullptr);
+        make_layout(&J.grid, dtype, G.nstag, J.npts, &G.L, tuning);
         G.off = off;
         off += G.L.total;
     }
@@ -128,6 +131,7 @@ void batch_build(const ib_job* jobs, int32_t njobs, int32_t dtype, const BatchLa
     bl->dtype = dtype;
     bl->dim = jobs[0].grid.dim;
     bl->kernel = jobs[0].grid.kernel;
+    bl->sp_tile = B.jobs[0].L.sp_tile;  // one tuning for all jobs: one spreading tile shape
     for (int s = 0; s < BS_COUNT; ++s) bl->grid[s] = ht->starts[s][njobs];
 }
 
@@ -159,7 +163,7 @@ int32_t batch_prepare(const ib_job* jobs, int32_t njobs, int32_t dtype, void* he
                       void* plans_dev, size_t plans_bytes, void* host_header, BatchLaunch* bl)
 {
     BatchLayout B;
-    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    int32_t st = batch_layout(jobs, njobs, dtype, nullptr, &B);
     if (st != IB_OK) return st;
     if (!header_dev || !plans_dev || !host_header) return IB_ERR_ARG;
     if (((uintptr_t)header_dev % ALIGN) != 0 || ((uintptr_t)plans_dev % ALIGN) != 0) return IB_ERR_ARG;
@@ -168,11 +172,11 @@ int32_t batch_prepare(const ib_job* jobs, int32_t njobs, int32_t dtype, void* he
     return IB_OK;
 }
 
-int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
-                     size_t workspace_bytes, void* host_staging, hipStream_t hs)
+int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, const ib_tuning* tuning,
+                     void* workspace, size_t workspace_bytes, void* host_staging, hipStream_t hs)
 {
     BatchLayout B;
-    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    int32_t st = batch_layout(jobs, njobs, dtype, tuning, &B);
     if (st != IB_OK) return st;
     if (!workspace || ((uintptr_t)workspace % ALIGN) != 0) return IB_ERR_ARG;
     if (workspace_bytes < B.header + B.plans) return IB_ERR_OOM;
@@ -231,8 +235,14 @@ extern "C" {
 
 size_t ib_batch_workspace_bytes(const ib_job* jobs, int32_t njobs, int32_t dtype)
 {
+    return ib_batch_workspace_bytes_tuned(jobs, njobs, dtype, nullptr);
+}
+
+size_t ib_batch_workspace_bytes_tuned(const ib_job* jobs, int32_t njobs, int32_t dtype,
+                                      const ib_tuning* tuning)
+{
     BatchLayout B;
-    if (batch_layout(jobs, njobs, dtype, &B) != IB_OK) return 0;
+    if (batch_layout(jobs, njobs, dtype, tuning, &B) != IB_OK) return 0;
     return B.header + B.plans;
 }
 
@@ -246,7 +256,14 @@ size_t ib_batch_staging_bytes(int32_t njobs)
 int32_t ib_batch_run(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
                      size_t workspace_bytes, void* host_staging, void* stream)
 {
-    return ibk::batch_launch(jobs, njobs, dtype, workspace, workspace_bytes, host_staging,
+    return ibk::batch_launch(jobs, njobs, dtype, nullptr, workspace, workspace_bytes, host_staging,
+                             (hipStream_t)stream);
+}
+
+int32_t ib_batch_run_tuned(const ib_job* jobs, int32_t njobs, int32_t dtype, const ib_tuning* tuning,
+                           void* workspace, size_t workspace_bytes, void* host_staging, void* stream)
+{
+    return ibk::batch_launch(jobs, njobs, dtype, tuning, workspace, workspace_bytes, host_staging,
                              (hipStream_t)stream);
 }
 
@@ -254,14 +271,14 @@ int32_t ib_batch_run_static(const ib_job* jobs, int32_t njobs, int32_t dtype, vo
                             uint32_t* job_flags, void* stream)
 {
     BatchLayout B;
-    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    int32_t st = batch_layout(jobs, njobs, dtype, nullptr, &B);
     if (st != IB_OK) return st;
     if (B.header + B.plans > (size_t)IB_STATIC_SCRATCH_BYTES) return IB_ERR_OOM;
     void* ws = nullptr;
     st = static_scratch(&ws);
     if (st != IB_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
-    st = batch_launch(jobs, njobs, dtype, ws, IB_STATIC_SCRATCH_BYTES, host_staging, hs);
+    st = batch_launch(jobs, njobs, dtype, nullptr, ws, IB_STATIC_SCRATCH_BYTES, host_staging, hs);
     if (st == IB_OK && job_flags &&
         hipMemcpyAsync(job_flags, (const char*)ws + batch_flags_offset(), njobs * sizeof(uint32_t),
                        hipMemcpyDeviceToDevice, hs) != hipSuccess)
@@ -273,7 +290,7 @@ int32_t ib_batch_status(const ib_job* jobs, int32_t njobs, int32_t dtype, const 
                         int32_t* job_status, void* stream)
 {
     BatchLayout B;
-    int32_t st = batch_layout(jobs, njobs, dtype, &B);
+    int32_t st = batch_layout(jobs, njobs, dtype, nullptr, &B);  // validation only
     if (st != IB_OK) return st;
     if (!workspace) return IB_ERR_ARG;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return IB_ERR_HIP;

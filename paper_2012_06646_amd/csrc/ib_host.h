@@ -70,8 +70,8 @@ size_t batch_header_bytes(int32_t njobs);
 size_t batch_job_bytes(const ib_job* job, int32_t dtype);  // 0 for an invalid job
 size_t batch_flags_offset();                               // of the per-job flags in the header
 size_t batch_jobs_offset();                                // of the job array in the header
-int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, void* workspace,
-                     size_t workspace_bytes, void* host_staging, hipStream_t stream);
+int32_t batch_launch(const ib_job* jobs, int32_t njobs, int32_t dtype, const ib_tuning* tuning,
+                     void* workspace, size_t workspace_bytes, void* host_staging, hipStream_t stream);
 // Build a batch whose header lives at header_dev (batch_header_bytes(njobs)) and whose plan
 // regions start at plans_dev: writes the header's host copy (to be uploaded) and the launch
 // description with exact grids.  Launches nothing.

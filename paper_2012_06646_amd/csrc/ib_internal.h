@@ -184,6 +184,7 @@ struct BatchLaunch {
     const BatchJob* jobs;      // device
     const BatchTable* table;   // device
     int dtype, dim, kernel;
+    int sp_tile;               // spreading tile shape of every job (3-D)
     int grid[BS_COUNT];        // blocks to launch per stage (0: skip the stage)
 };
 

@@ -1346,11 +1346,10 @@ __global__ __launch_bounds__(256) void batch_split_sum_kernel(const BatchJob* __
     }
 }
 
-template <typename T, int DIM, int KERN>
-void batch_ops_dispatch(const BatchLaunch& b, hipStream_t st)
+// The stages of the operators for a batch whose jobs share spreading tile shape S.
+template <typename T, int DIM, int KERN, int S>
+void batch_ops_shape(const BatchLaunch& b, hipStream_t st)
 {
-    // the built-in tile of the precision (batches are never tuned)
-    constexpr int S = builtin_spread_shape(sizeof(T) == 4 ? IB_F32 : IB_F64);
     constexpr int TX = DIM == 3 ? SP_SHAPE[S][0] : SP2_TX, TY = DIM == 3 ? SP_SHAPE[S][1] : SP2_TY;
     constexpr int TZ = DIM == 3 ? SP_SHAPE[S][2] : 1;
     if (b.grid[BS_FMAX] > 0)
@@ -1371,8 +1370,17 @@ template <typename T>
 void batch_ops_by_shape(const BatchLaunch& b, hipStream_t st)
 {
     (void)with_kernel(b.kernel, [&](auto K) {
-        if (b.dim == 3) batch_ops_dispatch<T, 3, decltype(K)::value>(b, st);
-        else batch_ops_dispatch<T, 2, decltype(K)::value>(b, st);
+        constexpr int KV = decltype(K)::value;
+        if (b.dim != 3) {
+            batch_ops_shape<T, 2, KV, 0>(b, st);  // one 2-D tile shape
+        } else {
+            static_assert(SPREAD_TILE_SHAPES == 3, "a case per spreading tile shape");
+            switch (b.sp_tile) {
+            case 0: batch_ops_shape<T, 3, KV, 0>(b, st); break;
+            case 1: batch_ops_shape<T, 3, KV, 1>(b, st); break;
+            default: batch_ops_shape<T, 3, KV, 2>(b, st); break;
+            }
+        }
         return hipSuccess;
     });
 }

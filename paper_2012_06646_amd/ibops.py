@@ -98,6 +98,11 @@ _lib.ib_batch_staging_bytes.restype = ctypes.c_size_t
 _lib.ib_batch_staging_bytes.argtypes = [_i32]
 _lib.ib_batch_run.restype = _i32
 _lib.ib_batch_run.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, ctypes.c_size_t, _vp, _vp]
+_lib.ib_batch_workspace_bytes_tuned.restype = ctypes.c_size_t
+_lib.ib_batch_workspace_bytes_tuned.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, ctypes.POINTER(Tuning)]
+_lib.ib_batch_run_tuned.restype = _i32
+_lib.ib_batch_run_tuned.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, ctypes.POINTER(Tuning), _vp,
+                                    ctypes.c_size_t, _vp, _vp]
 _lib.ib_batch_run_static.restype = _i32
 _lib.ib_batch_run_static.argtypes = [ctypes.POINTER(JobDesc), _i32, _i32, _vp, _vp, _vp]
 _lib.ib_batch_status.restype = _i32
@@ -133,6 +138,7 @@ _lib.ib_tether_force.argtypes = [ctypes.POINTER(GridDesc), _i32, ctypes.c_int64,
 
 EXPORTED = ["ib_interpolate_advect", "ib_plan_workspace_bytes_tuned", "ib_plan_create_tuned", "ib_server_create", "ib_server_clock_us", "ib_batch_submit", "ib_batch_poll",
             "ib_server_drain", "ib_server_get_stats", "ib_server_destroy", "ib_batch_workspace_bytes", "ib_batch_staging_bytes", "ib_batch_run", "ib_batch_status",
+            "ib_batch_workspace_bytes_tuned", "ib_batch_run_tuned",
             "ib_batch_run_static",
             "ib_advect", "ib_tether_force", "ib_interpolate_grad", "ib_status_string", "ib_plan_workspace_bytes", "ib_plan_create", "ib_plan_num_staggers",
             "ib_plan_stagger_of", "ib_plan_update", "ib_plan_update_advected", "ib_plan_export", "ib_plan_status",
@@ -436,9 +442,12 @@ class Batch:
     (interpolate); all share a dtype, dimension and kernel.  Outputs (f and U per job) and
     the workspace are allocated once; `run()` may be called again after the inputs'
     contents change (same shapes).  workspace=False allocates no workspace: such a batch runs
-    only through run_static (the library's fixed device array, ib_batch_run_static)."""
+    only through run_static (the library's fixed device array, ib_batch_run_static).
+    tuning: None (built-in choices), a dict of ib_tuning fields applied to every job
+    (ib_batch_run_tuned), or "auto" (the autotuner's cached choice for this job mix, if
+    any); run_static always uses the built-in choices."""
 
-    def __init__(self, jobs, dtype=torch.float64, device="cuda", workspace=True):
+    def __init__(self, jobs, dtype=torch.float64, device="cuda", workspace=True, tuning=None):
         if not 1 <= len(jobs) <= BATCH_MAX_JOBS:
             raise ValueError(f"a batch holds 1..{BATCH_MAX_JOBS} jobs")
         self.dtype = dtype
@@ -480,9 +489,15 @@ class Batch:
             arr[j].U = rec["U"].data_ptr() if rec["U"] is not None and n else None
             self.jobs.append(rec)
         self._arr = arr
-        nbytes = int(_lib.ib_batch_workspace_bytes(arr, len(jobs), self.code))
+        if tuning == "auto":
+            from . import tune
+            tuning = tune.cached_batch(jobs, dtype)
+        self.tuning = tuning
+        self._tuning = make_tuning(tuning)
+        tp = ctypes.byref(self._tuning) if self._tuning is not None else None
+        nbytes = int(_lib.ib_batch_workspace_bytes_tuned(arr, len(jobs), self.code, tp))
         if nbytes == 0:
-            _check(-4, "ib_batch_workspace_bytes")
+            _check(-4, "ib_batch_workspace_bytes_tuned")
         self.workspace_bytes = nbytes
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device) if workspace else None
         nst = int(_lib.ib_batch_staging_bytes(len(jobs)))
@@ -491,9 +506,10 @@ class Batch:
     def run(self, stream=None):
         if self.workspace is None:
             raise ValueError("this batch has no workspace: use run_static")
-        _check(_lib.ib_batch_run(self._arr, len(self.jobs), self.code, _ptr(self.workspace),
-                                 self.workspace.numel(), ctypes.c_void_p(self.staging.data_ptr()),
-                                 _stream(stream)), "ib_batch_run")
+        tp = ctypes.byref(self._tuning) if self._tuning is not None else None
+        _check(_lib.ib_batch_run_tuned(self._arr, len(self.jobs), self.code, tp, _ptr(self.workspace),
+                                       self.workspace.numel(), ctypes.c_void_p(self.staging.data_ptr()),
+                                       _stream(stream)), "ib_batch_run_tuned")
         return self
 
     def run_static(self, flags=None, stream=None):

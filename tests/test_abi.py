@@ -108,6 +108,32 @@ def test_batch_workspace_sizing_and_validation(ib):
     assert ib._lib.ib_batch_run(arr, 3, 7, ctypes.c_void_p(4096), total, None, None) == -4
 
 
+def test_tuned_batch_workspace_and_validation(ib):
+    """ib_batch_workspace_bytes_tuned / ib_batch_run_tuned: a NULL or all-default tuning sizes
+    the batch like ib_batch_workspace_bytes, a tuning that splits spreading tiles needs more
+    room, and a tuning outside its ranges is refused before any device work."""
+    from paper_2012_06646_amd import workloads as wl
+    g3 = ib.make_desc(wl.grid(3, 32, 1.0))
+    arr = (ib.JobDesc * 3)()
+    for j in range(3):
+        arr[j].grid = g3
+        arr[j].npts = 1000 * (j + 1)
+        arr[j].X = arr[j].F = arr[j].f = 4096  # never dereferenced
+    base = ib._lib.ib_batch_workspace_bytes(arr, 3, 0)
+    assert base > 0
+    assert ib._lib.ib_batch_workspace_bytes_tuned(arr, 3, 0, None) == base
+    assert ib._lib.ib_batch_workspace_bytes_tuned(arr, 3, 0, ctypes.byref(ib.Tuning(0, 0, 0))) == base
+    split = ib._lib.ib_batch_workspace_bytes_tuned(arr, 3, 0, ctypes.byref(ib.Tuning(0, 16, 0)))
+    assert split > base  # partial integer tiles of the shared spreading tiles
+    for bad in (ib.Tuning(9, 0, 0), ib.Tuning(0, 0, 3), ib.Tuning(0, 0, 11)):  # FP64 sorts use <= 10 bits
+        assert ib._lib.ib_batch_workspace_bytes_tuned(arr, 3, 0, ctypes.byref(bad)) == 0
+        assert ib._lib.ib_batch_run_tuned(arr, 3, 0, ctypes.byref(bad), ctypes.c_void_p(4096), base,
+                                          None, None) == -1
+    assert ib._lib.ib_batch_workspace_bytes_tuned(arr, 3, 1, ctypes.byref(ib.Tuning(0, 0, 11))) > 0
+    assert ib._lib.ib_batch_run_tuned(arr, 3, 0, ctypes.byref(ib.Tuning(0, 16, 0)), ctypes.c_void_p(4096),
+                                      split - 1, None, None) == -2
+
+
 def test_tuned_workspace_and_validation(ib):
     from paper_2012_06646_amd import workloads as wl
     g = ib.make_desc(wl.grid(3, 32, 1.0))

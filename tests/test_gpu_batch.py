@@ -1,5 +1,7 @@
 """Batched jobs (ib_batch_run) against the same jobs run one by one through the plan API
 (bit for bit: the same kernels on the same data) and against the CPU oracle."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -147,3 +149,48 @@ def test_max_jobs_batch(ib):
     for j in (0, 1, 63, 127):
         f1, U1 = one_by_one(ib, jobs[j], dtype)
         assert torch.equal(res[j][0], f1) and torch.equal(res[j][1], U1)
+
+
+BATCH_TUNINGS = [{"spread_tile": 1}, {"spread_tile": 2}, {"split_points": 256}, {"split_points": -1},
+                 {"radix_bits": 10}, {"spread_tile": 1, "split_points": 2048, "radix_bits": 6}]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_tuned_batch_matches_tuned_plans_bitwise(ib, dtype):
+    """A batch run with one tuning for all its jobs gives each job the results of a plan
+    created with the same tuning, bit for bit (every spreading tile shape, shared and
+    unshared tiles, other bucket widths)."""
+    jobs, _ = make_jobs(MIXED_3D, dtype, 4300)
+    for t in BATCH_TUNINGS:
+        say(f"tuned batch {t} of {len(jobs)} mixed 3-D jobs dtype={dtype}")
+        b = ib.Batch(jobs, dtype, tuning=t).run()
+        assert b.status() == [0] * len(jobs)
+        for j, ((f, U), job) in enumerate(zip(b.results(), jobs)):
+            p = ib.Plan(job["grid"], job["X"].shape[0], dtype, tuning=t).update(job["X"])
+            if "F" in job:
+                assert torch.equal(f, p.spread(job["F"])), f"tuning {t}, job {j}: spread differs"
+            if "u" in job:
+                assert torch.equal(U, p.interpolate(job["u"])), f"tuning {t}, job {j}: interp differs"
+
+
+def test_autotune_batch_caches_and_batch_finds_it(ib, tmp_path, monkeypatch):
+    """The batch tuner times distinct layouts only, caches its choice under the job mix (in
+    any job order), and Batch(..., tuning="auto") runs with it."""
+    from paper_2012_06646_amd import tune
+    monkeypatch.setenv("IB_TUNE_CACHE", str(tmp_path / "tune.json"))
+    dtype = torch.float32
+    jobs, _ = make_jobs(MIXED_3D[:5], dtype, 4400)
+    say(f"autotune a batch of {len(jobs)} jobs")
+    best, timings = tune.autotune_batch(jobs, dtype, reps=3)
+    say(f"batch tuning {best} over {len(timings)} candidates")
+    assert len(timings) >= 3 and "(0, 0, 0)" in timings
+    entry = json.load(open(tmp_path / "tune.json"))[tune.batch_key(jobs, dtype)]
+    assert entry["tuning"] == best
+    assert tune.batch_key(list(reversed(jobs)), dtype) == tune.batch_key(jobs, dtype)
+    b = ib.Batch(jobs, dtype, tuning="auto")
+    assert b.tuning == best
+    b.run()
+    b2 = ib.Batch(jobs, dtype, tuning=best).run()
+    for (f, U), (f2, U2) in zip(b.results(), b2.results()):
+        assert (f is None and f2 is None) or torch.equal(f, f2)
+        assert (U is None and U2 is None) or torch.equal(U, U2)

@@ -26,6 +26,35 @@ def test_tune_cache_roundtrip(tmp_path, monkeypatch):
     assert list(data) == [k]
 
 
+def test_batch_tune_key_is_the_job_mix(tmp_path, monkeypatch):
+    """The batch tuning cache key depends on the jobs' grids, operators and point-count
+    buckets, not on their order; a stored choice is found for the same mix."""
+    from paper_2012_06646_amd import tune, workloads as wl
+    monkeypatch.setenv("IB_TUNE_CACHE", str(tmp_path / "t.json"))
+    g32, g64 = wl.grid(3, 32, 1.0), wl.grid(3, 64, 1.0)
+
+    def job(g, n, F=True, u=True):
+        j = {"grid": g, "X": torch.empty(n, 3)}
+        if F:
+            j["F"] = torch.empty(n, 3)
+        if u:
+            j["u"] = torch.empty(3, *g["n"][::-1])
+        return j
+    mix = [job(g32, 1000), job(g64, 50000), job(g64, 3000, u=False)]
+    k = tune.batch_key(mix, torch.float32)
+    assert k == tune.batch_key(mix[::-1], torch.float32)
+    assert k == tune.batch_key([job(g32, 1100), job(g64, 50000), job(g64, 3000, u=False)], torch.float32)
+    assert k != tune.batch_key(mix, torch.float64)
+    assert k != tune.batch_key([job(g32, 1000), job(g64, 50000), job(g64, 3000)], torch.float32)
+    assert k != tune.batch_key([job(g32, 1000), job(g32, 50000), job(g64, 3000, u=False)], torch.float32)
+    assert k != tune.batch_key([job(g32, 1000), job(g64, 200000), job(g64, 3000, u=False)], torch.float32)
+    assert k != tune.batch_key(mix[:2], torch.float32)
+    assert tune.cached_batch(mix, torch.float32) is None
+    tune._store(k, {"tuning": {"spread_tile": 1, "split_points": 0, "radix_bits": 0}, "ms": 1.0})
+    assert tune.cached_batch(mix[::-1], torch.float32) == {"spread_tile": 1, "split_points": 0,
+                                                          "radix_bits": 0}
+
+
 def test_algorithmic_bytes_of_the_benchmark_workload():
     bench = importlib.import_module("bench")
     a = bench.algorithmic_bytes(10 ** 6, 3, 3, 128 ** 3, 8)

@@ -173,6 +173,28 @@ def test_tuned_batch_matches_tuned_plans_bitwise(ib, dtype):
                 assert torch.equal(U, p.interpolate(job["u"])), f"tuning {t}, job {j}: interp differs"
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_tuned_2d_batch_matches_tuned_plans_and_oracle(ib, orc, dtype):
+    """2-D batches with tunings that share spreading tiles or change the bucket width: each
+    job equals a plan with the same tuning bit for bit, and the oracle within tolerance."""
+    specs = [(wl.grid(2, 32, 1.0, stagger=[[0.5, 0.5], [0.5, 0.5]]), 1000, True, True),
+             (wl.grid(2, [64, 40], 1.0), 7000, True, True),
+             (wl.grid(2, 48, 1.0), 30000, True, False)]
+    jobs, host = make_jobs(specs, dtype, 4500)
+    for t in ({"split_points": 32}, {"split_points": -1}, {"radix_bits": 6}):
+        say(f"tuned 2-D batch {t} dtype={dtype}")
+        b = ib.Batch(jobs, dtype, tuning=t).run()
+        assert b.status() == [0] * len(jobs)
+        for j, ((f, U), job, (g, n, sp, it), (X, F, u)) in enumerate(zip(b.results(), jobs, specs, host)):
+            p = ib.Plan(g, n, dtype, tuning=t).update(job["X"])
+            assert torch.equal(f, p.spread(job["F"])), f"tuning {t}, job {j}: spread differs"
+            nd = np.float64 if dtype == torch.float64 else np.float32
+            Xc = X.astype(nd).astype(np.float64)
+            assert normwise(to_host(f), orc.spread(g, Xc, F.astype(nd).astype(np.float64), tier=0)) <= TOL[dtype]
+            if it:
+                assert torch.equal(U, p.interpolate(job["u"])), f"tuning {t}, job {j}: interp differs"
+
+
 def test_autotune_batch_caches_and_batch_finds_it(ib, tmp_path, monkeypatch):
     """The batch tuner times distinct layouts only, caches its choice under the job mix (in
     any job order), and Batch(..., tuning="auto") runs with it."""

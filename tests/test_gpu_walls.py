@@ -86,6 +86,27 @@ def test_walled_ops_match_oracle(ib, orc, ci, dtype):
         assert torch.equal(Xd2, Xd)
 
 
+@pytest.mark.parametrize("tuning", [{"spread_tile": 1}, {"spread_tile": 2, "split_points": -1},
+                                    {"split_points": 64, "radix_bits": 6}])
+def test_walled_tunings_match_oracle(ib, orc, tuning):
+    """Walled plans with other spreading tiles, unshared or more widely shared tiles and
+    another bucket width still write and read only the caller's unpadded field."""
+    dtype = torch.float64
+    g = walled(wl.grid(3, 24, 1.0), 7)
+    n = 30000
+    say(f"walls=7 grid={g['n']} n={n} tuning={tuning}")
+    X = points_near_box(g, n, 97)
+    r = wl.rng(98)
+    F = r.standard_normal((n, 3))
+    u = r.standard_normal(wl.grid_shape(g))
+    p = ib.Plan(g, n, dtype, tuning=tuning).update(to_dev(X, dtype))
+    f = p.spread(to_dev(F, dtype))
+    U = p.interpolate(to_dev(u, dtype))
+    assert p.status() == 0
+    assert normwise(to_host(f), orc.spread(g, X, F)) <= TOL[dtype]
+    assert normwise(to_host(U), orc.interp(g, X, u)) <= TOL[dtype]
+
+
 def test_walled_keys_on_the_padded_grid(ib, orc):
     # h = 1 makes n / L exact on both grids, so the keys can be compared bit for bit
     g = walled(wl.grid(3, [16, 12, 10], [16.0, 12.0, 10.0]), 5)

@@ -98,14 +98,16 @@ typedef struct ib_plan_s *ib_plan;
  *   split_points  sharing of a spreading tile by several blocks (at most 256 per tile),
  *                 whose partial tiles a second kernel adds in block order: > 0 = at least
  *                 that many points per block; 0 = about 512 blocks in all, with at least
- *                 128 points per block (batches use this rule too); < 0 = never share
+ *                 128 points per block; < 0 = never share
  *   radix_bits    bucket bits of the key sort (its first pass groups the points by the top
  *                 radix_bits bits of their keys; each bucket is then sorted by one block),
- *                 4..10: 0 = enough buckets for about 2048 points each, and for at most
- *                 8192 cells each
- * Results do not depend on the tuning beyond rounding: keys, permutations and offsets are
- * identical, and spread values may differ in the scale of their fixed-point sums (the
- * tile shape and sharing set it). */
+ *                 4..10 for FP64 plans, 4..11 for FP32: 0 = enough buckets for about 2048
+ *                 points each, and for at most 8192 cells each
+ * Batches take the built-in choices, or one tuning for all their jobs (ib_batch_run_tuned).
+ * Results do not depend on the tuning: keys, permutations and offsets are identical, and
+ * so are spread and interpolated values, bit for bit (spreading's fixed-point scale depends
+ * on the forces and the plan's largest cell count only, and its integer sums on nothing
+ * else). */
 typedef struct {
     int32_t spread_tile;
     int32_t split_points;

@@ -29,6 +29,10 @@ def test_library_exports_every_declared_function(ib):
     for name in names:
         assert hasattr(ib._lib, name), f"{name} declared in include/ib.h but not exported"
     assert set(ib.EXPORTED) <= set(names)
+    # the binding declares every entry point's argument types, so ctypes converts each call
+    assert set(ib.EXPORTED) == set(names)
+    for name in names:
+        assert getattr(ib._lib, name).argtypes is not None, f"{name}: no argtypes in the binding"
 
 
 def test_status_strings(ib):

@@ -285,7 +285,6 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     p->X = nullptr;
     p->last_stream = nullptr;
     p->updated = 0;
-    p->x_moved = 0;
     p->sorted_mask = 0;
     p->runs_mask = 0;
     p->xn_valid = 0;
@@ -372,7 +371,6 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     p->X = X;
     p->last_stream = st;
     p->updated = 1;
-    p->x_moved = 0;
     p->sorted_mask = 1u;
     p->runs_mask = 0u;
     p->xn_valid = 0;
@@ -390,7 +388,6 @@ int32_t ib_plan_update_advected(ib_plan p, void* stream)
     int32_t r = hip_status(e);
     if (r != IB_OK) return r;
     p->last_stream = st;
-    p->x_moved = 0;
     p->sorted_mask = 1u;
     p->runs_mask = 0u;
     p->xn_valid = 0;
@@ -548,8 +545,6 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
         for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
     }
     p->last_stream = st;
-    // Positions of staggerings not yet sorted can no longer be derived from this update.
-    if (X == p->X) p->x_moved = 1;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
     if (e == hipSuccess && p->user.walls)
         e = launch_advect(p->user.dim, p->user.ncomp, p->npts, p->user.length, p->user.walls,

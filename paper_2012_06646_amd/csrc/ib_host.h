@@ -19,7 +19,6 @@ struct ib_plan_s {
     const void* X;         // positions of the last update
     hipStream_t last_stream;
     int updated;
-    int x_moved;           // X advanced in place (ib_interpolate_advect) since the update
     int xn_valid;          // Xn holds the positions of the last ib_interpolate_advect
     uint32_t sorted_mask;  // staggerings sorted since the last update
     uint32_t runs_mask;    // staggerings whose run offsets were computed since the update

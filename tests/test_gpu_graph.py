@@ -19,25 +19,26 @@ def ib():
     return ibops
 
 
-CASES = [(48, 60000, torch.float64),     # shared spreading tiles, gathered interpolation
-         (48, 60000, torch.float32),
-         (128, 1000000, torch.float64)]  # the benchmark's workload: LDS-tiled interpolation
+CASES = [(48, 60000, torch.float64, 0),     # shared spreading tiles, gathered interpolation
+         (48, 60000, torch.float32, 0),
+         (128, 1000000, torch.float64, 0),  # the benchmark's workload: LDS-tiled interpolation
+         (48, 60000, torch.float64, 4)]     # walls along z: a fresh plan every step
 
 
-@pytest.mark.parametrize("N,n,dtype", CASES)
-def test_captured_step_replays_match_eager(ib, N, n, dtype):
-    g = wl.grid(3, N, 1.0)
-    X0, F, u = wl.uniform_case(g, n, 61)
+@pytest.mark.parametrize("N,n,dtype,walls", CASES)
+def test_captured_step_replays_match_eager(ib, N, n, dtype, walls):
+    g = dict(wl.grid(3, N, 1.0), walls=walls)
+    X0, F, u = wl.uniform_case(wl.grid(3, N, 1.0), n, 61)
     dt = 0.1 / N
     Fd, ud = to_dev(F, dtype), to_dev(u, dtype)
     steps = 5
-    say(f"captured step N={N} n={n} dtype={dtype}")
+    say(f"captured step N={N} n={n} dtype={dtype} walls={walls}")
     # the eager reference: step 0 from the positions, then advected re-plans
     pe = ib.Plan(g, n, dtype)
     Xe = to_dev(X0, dtype)
     ref = []
     for k in range(steps):
-        if k == 0:
+        if k == 0 or walls:
             pe.update(Xe)
         else:
             pe.update_advected()
@@ -60,7 +61,10 @@ def test_captured_step_replays_match_eager(ib, N, n, dtype):
     cap.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(cap):
         with torch.cuda.graph(gr, stream=cap):
-            pg.update_advected()
+            if walls:
+                pg.update(Xg)  # walled plans re-plan from the positions
+            else:
+                pg.update_advected()
             pg.spread(Fd, fg)
             pg.interpolate_advect(ud, Xg, dt, Ug)
     torch.cuda.current_stream().wait_stream(cap)

@@ -156,11 +156,14 @@ int32_t ib_plan_update_advected(ib_plan plan, void *stream);
 
 /* Copy one staggering's plan arrays into caller device buffers (any may be NULL):
  * keys[npts] (input order), sorted_keys[npts], perm[npts] (sorted position -> point index),
- * seg_off[q+1] (seg_off[q] = npts; buffer must hold npts+1), q[1]. */
+ * seg_off[q+1] (seg_off[q] = npts; buffer must hold npts+1), q[1].  Stream-ordered after
+ * the plan's last update: another staggering is keyed and sorted, and the runs found, by
+ * every call that needs them, so a plan updated by a replayed graph exports that update. */
 int32_t ib_plan_export(ib_plan plan, int32_t stagger_id, int32_t *keys, int32_t *sorted_keys,
                        int32_t *perm, int32_t *seg_off, int32_t *q, void *stream);
 
-/* Synchronize the plan's last stream and report IB_ERR_DEVICE_FLAG if the last update
+/* Wait for all work on the current device (the plan's work may run on any stream, or
+ * replay from a captured graph), then report IB_ERR_DEVICE_FLAG if the last update
  * flagged a data error, else IB_OK (or IB_ERR_HIP).  Clears the flag. */
 int32_t ib_plan_status(ib_plan plan);
 

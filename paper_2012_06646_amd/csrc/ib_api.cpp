@@ -283,10 +283,7 @@ void plan_setup(ib_plan_s* p, const ib_grid_desc* user, int32_t dtype, int64_t n
     p->sorted_keys = d.kB;
     p->perm = d.vB;
     p->X = nullptr;
-    p->last_stream = nullptr;
     p->updated = 0;
-    p->sorted_mask = 0;
-    p->runs_mask = 0;
     p->xn_valid = 0;
 }
 
@@ -346,9 +343,9 @@ int32_t ib_plan_stagger_of(ib_plan p, int32_t comp)
 
 // The per-update region (bucket histograms, cursors, look-back words, tickets, flags) is
 // cleared by a kernel before a plan's first update; afterwards each sort's bucket pass clears
-// what the next sort of its staggering counts into, and its scatter pass absorbs the
-// bad-point mark.  Without points there is no scatter pass, so such plans clear at every
-// update.
+// what the next sort of its staggering counts into, its scatter pass absorbs the bad-point
+// mark, and each export clears the runs' words before its runs pass.  Without points there
+// is no scatter pass, so such plans clear at every update.
 static hipError_t clear_once(ib_plan p, hipStream_t st)
 {
     if (p->cleared && p->npts > 0) return hipSuccess;
@@ -369,10 +366,7 @@ int32_t ib_plan_update(ib_plan p, const void* X, void* stream)
     int32_t r = hip_status(e);
     if (r != IB_OK) return r;
     p->X = X;
-    p->last_stream = st;
     p->updated = 1;
-    p->sorted_mask = 1u;
-    p->runs_mask = 0u;
     p->xn_valid = 0;
     return IB_OK;
 }
@@ -387,9 +381,6 @@ int32_t ib_plan_update_advected(ib_plan p, void* stream)
         e = launch_sort_stagger(p->sa, 0, p->dtype, p->sa.d.Xn, p->perm, true, st);
     int32_t r = hip_status(e);
     if (r != IB_OK) return r;
-    p->last_stream = st;
-    p->sorted_mask = 1u;
-    p->runs_mask = 0u;
     p->xn_valid = 0;
     return IB_OK;
 }
@@ -399,22 +390,22 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
 {
     if (!p || sid < 0 || sid >= p->sa.g.nstag || !p->updated) return IB_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
-    if (!(p->sorted_mask & (1u << sid))) {
+    // Every export recomputes what it needs on the stream, with no host-side record of
+    // what is current: a plan whose updates are replayed from a captured graph exports the
+    // replayed update's arrays.
+    if (sid != 0) {
         // from the update's positions in staggering-0 sorted order (valid even after X was
         // advanced in place)
         int32_t r = hip_status(launch_sort_stagger(p->sa, sid, p->dtype, p->sa.d.Xs, p->perm, false, st));
         if (r != IB_OK) return r;
-        p->sorted_mask |= 1u << sid;
     }
     const size_t n = (size_t)p->npts;
     const PlanDev& d = p->sa.d;
     hipError_t e = hipSuccess;
-    if ((seg_off || q) && !(p->runs_mask & (1u << sid))) {
-        // run heads, q and offsets from the sorted keys (the look-back words and ticket
-        // of this staggering's runs chain were cleared by the update)
+    if (seg_off || q) {
+        // run heads, q and offsets from the sorted keys
         e = launch_runs(p->sa, sid, st);
         if (e != hipSuccess) return IB_ERR_HIP;
-        p->runs_mask |= 1u << sid;
     }
     if (keys && n) e = launch_keys_out(p->sa, sid, keys, st);
     if (e == hipSuccess && sorted_keys && n)
@@ -430,7 +421,8 @@ int32_t ib_plan_export(ib_plan p, int32_t sid, int32_t* keys, int32_t* sorted_ke
 int32_t ib_plan_status(ib_plan p)
 {
     if (!p) return IB_ERR_ARG;
-    if (hipStreamSynchronize(p->last_stream) != hipSuccess) return IB_ERR_HIP;
+    // the plan's work may run on any stream, or replay from a captured graph
+    if (hipDeviceSynchronize() != hipSuccess) return IB_ERR_HIP;
     if (!p->updated) return IB_OK;
     uint32_t flag = 0;
     if (hipMemcpy(&flag, p->sa.d.flag, sizeof flag, hipMemcpyDeviceToHost) != hipSuccess)
@@ -494,7 +486,6 @@ int32_t ib_spread_scaled(ib_plan p, const void* F, void* f, double scale, int32_
     a.accumulate = accumulate != 0;
     set_direct(p, &a);  // walled: the padded grid's tiles write the caller's cells, ghosts dropped
     hipStream_t st = (hipStream_t)stream;
-    p->last_stream = st;
     return hip_status(launch_spread(a, p->dtype, p->grid.kernel, st));
 }
 
@@ -515,7 +506,6 @@ int32_t ib_interpolate_scaled(ib_plan p, const void* u, void* U, double scale, v
     hipError_t e = hipSuccess;
     a.u = kernel_field(p, &a, u);
     a.U = U;
-    p->last_stream = st;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
     return hip_status(e);
 }
@@ -544,7 +534,6 @@ int32_t ib_interpolate_advect(ib_plan p, const void* u, void* U, void* X, double
         a.adv_dt = dt;
         for (int k = 0; k < 3; ++k) a.adv_len[k] = k < p->grid.dim ? p->grid.length[k] : 1.0;
     }
-    p->last_stream = st;
     if (e == hipSuccess) e = launch_interp(a, p->dtype, p->grid.kernel, st);
     if (e == hipSuccess && p->user.walls)
         e = launch_advect(p->user.dim, p->user.ncomp, p->npts, p->user.length, p->user.walls,
@@ -565,7 +554,6 @@ int32_t ib_interpolate_grad_scaled(ib_plan p, const void* u, const void* W, void
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     a.u = kernel_field(p, &a, u);
-    p->last_stream = st;
     if (e == hipSuccess)
         e = launch_interp_grad(a, p->dtype, p->grid.kernel, W, dX, accumulate != 0, st);
     return hip_status(e);

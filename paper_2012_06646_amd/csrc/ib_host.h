@@ -17,11 +17,8 @@ struct ib_plan_s {
     int32_t* sorted_keys;  // final sort output (kB of staggering 0)
     int32_t* perm;         // (vB of staggering 0)
     const void* X;         // positions of the last update
-    hipStream_t last_stream;
     int updated;
     int xn_valid;          // Xn holds the positions of the last ib_interpolate_advect
-    uint32_t sorted_mask;  // staggerings sorted since the last update
-    uint32_t runs_mask;    // staggerings whose run offsets were computed since the update
     int cleared;           // the per-update region was cleared once (later updates clear it
                            // through the bucket pass)
 };

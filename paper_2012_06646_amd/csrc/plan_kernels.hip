@@ -588,18 +588,10 @@ __device__ __forceinline__ void bucket_entry(const SortArgs& a, int s, int b, co
     const int64_t cend = min(G, (int64_t)(b + 1) << a.cb);
     const bool last = cend == G;
     // Nothing reads this bucket's histogram words and fill cursors (every shard) after the
-    // scatter pass: clear them for the staggering's next sort, and (block 0) the look-back
-    // words and tickets of its runs, so that a plan needs the reset kernel only before its
-    // first update.  Buckets without a block hold no points, so their words stay zero.
-    {
-        uint32_t* counts = const_cast<uint32_t*>(stag_hist(a, s));
-        if ((int)threadIdx.x < 2 * BKT_SHARDS) counts[(int64_t)threadIdx.x * R + b] = 0u;
-        if (b == 0) {
-            for (int64_t i = threadIdx.x; i < a.nseg_tiles; i += blockDim.x)
-                a.d.seg_status[(int64_t)s * a.nseg_tiles + i] = 0u;
-            if ((int)threadIdx.x < PLAN_COUNTERS) a.d.counters[s * PLAN_COUNTERS + threadIdx.x] = 0u;
-        }
-    }
+    // scatter pass: clear them for the staggering's next sort, so that a plan needs the reset
+    // kernel only before its first update.  Buckets without a block hold no points, so their
+    // words stay zero.
+    if ((int)threadIdx.x < 2 * BKT_SHARDS) const_cast<uint32_t*>(stag_hist(a, s))[(int64_t)threadIdx.x * R + b] = 0u;
     if (m >= 1 && m <= BKT_CAP && cend - cbeg <= BKT_CELLS)
         bucket_fast<T>(a, s, start, (int)m, cbeg, (int)(cend - cbeg), last, Xb, Xs, cstart, hist, sidx, skey, s_red,
                        s_cstat);
@@ -622,6 +614,16 @@ __global__ __launch_bounds__(256) void keys_out_kernel(SortArgs a, int s, int32_
     const int32_t* pm = a.d.vB + (int64_t)s * n;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         keys[clamp_index(pm[i], n)] = sk[i];
+}
+
+// The look-back words and the tile tickets of staggering s's runs, cleared before every
+// runs pass (grid-stride).
+__global__ __launch_bounds__(256) void runs_clear_kernel(SortArgs a, int s)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nseg_tiles;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a.d.seg_status[(int64_t)s * a.nseg_tiles + i] = 0u;
+    if (blockIdx.x == 0 && (int)threadIdx.x < PLAN_COUNTERS) a.d.counters[s * PLAN_COUNTERS + threadIdx.x] = 0u;
 }
 
 // ---- runs: heads, q and seg_off from the sorted keys (export) --------------------------
@@ -863,6 +865,9 @@ hipError_t launch_keys_out(const SortArgs& a, int s, int32_t* keys, hipStream_t 
 
 hipError_t launch_runs(const SortArgs& a, int s, hipStream_t st)
 {
+    const int64_t nc64 = (a.nseg_tiles + 255) / 256;
+    const unsigned nc = (unsigned)(nc64 < 64 ? (nc64 > 0 ? nc64 : 1) : 64);
+    hipLaunchKernelGGL(runs_clear_kernel, dim3(nc), dim3(256), 0, st, a, s);
     hipLaunchKernelGGL(runs_kernel, dim3((unsigned)a.nseg_tiles), dim3(SORT_BLOCK), 0, st, a, s);
     return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 """A plan step -- the re-plan from the advanced positions, spreading, and interpolation
 with the position update -- captured once in a HIP graph and replayed: every replay, with
 eager work and synchronisations between the replays, gives the bits of the same step run
-eagerly, step after step along the advected trajectory."""
+eagerly, step after step along the advected trajectory, and exports between the replays
+return the replayed update's plan arrays (every export recomputes on the stream)."""
 import pytest
 import torch
 
@@ -25,6 +26,23 @@ CASES = [(48, 60000, torch.float64, 0),     # shared spreading tiles, gathered i
          (48, 60000, torch.float64, 4)]     # walls along z: a fresh plan every step
 
 
+KEYS = ("keys", "sorted_keys", "perm", "seg_off")
+
+
+def exports(p):
+    """Plan arrays of staggerings 0 and 1 (host copies)."""
+    out = []
+    for sid in (0, 1):
+        e = p.export(sid)
+        out.append([e[k].cpu() for k in KEYS] + [e["q"]])
+    return out
+
+
+def same_exports(a, b):
+    return all(torch.equal(x, y) if torch.is_tensor(x) else x == y
+               for ea, eb in zip(a, b) for x, y in zip(ea, eb))
+
+
 @pytest.mark.parametrize("N,n,dtype,walls", CASES)
 def test_captured_step_replays_match_eager(ib, N, n, dtype, walls):
     g = dict(wl.grid(3, N, 1.0), walls=walls)
@@ -44,7 +62,7 @@ def test_captured_step_replays_match_eager(ib, N, n, dtype, walls):
             pe.update_advected()
         f = pe.spread(Fd)
         U = pe.interpolate_advect(ud, Xe, dt)
-        ref.append((f.clone(), U.clone(), Xe.clone()))
+        ref.append((f.clone(), U.clone(), Xe.clone(), exports(pe)))
     del pe
     # step 0 eagerly, then one captured step replayed for steps 1 ..
     pg = ib.Plan(g, n, dtype)
@@ -78,4 +96,6 @@ def test_captured_step_replays_match_eager(ib, N, n, dtype, walls):
         assert torch.equal(fg, ref[k][0]), f"replay {k}: spreading differs"
         assert torch.equal(Ug, ref[k][1]), f"replay {k}: interpolation differs"
         assert torch.equal(Xg, ref[k][2]), f"replay {k}: positions differ"
+        assert same_exports(exports(pg), ref[k][3]), f"replay {k}: exports differ"
+        assert same_exports(exports(pg), ref[k][3]), f"replay {k}: a second export differs"
     assert pg.status() == 0
